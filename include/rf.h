@@ -1,0 +1,188 @@
+/*
+ * rf.h -- C ABI of the MI355X (gfx950) sketch-powered range finder.
+ *
+ * Implements the method of Chenakkod & Derezinski, "Accelerating Power Method
+ * with Fast Sketching for Stronger Low-Rank Approximation" (arXiv 2605.09755):
+ *
+ *   Algorithm 1 (Sketch-Powered Range Finder, Section 2):
+ *       Q = orth((At At^T)^q At Omega),   At = A S,
+ *       S  n x r1 sparse sign sketch, s nonzeros +-1/sqrt(s) per row (Lemma 3.2(2)),
+ *       Omega r1 x r2 Gaussian, r1 = sketch size l, r2 = target rank k (Section 4).
+ *   Randomised SVD finisher (Section 2, "Sketch-Powered Low-Rank Factorization"):
+ *       B = Q^T A = Ub Sigma V^T,  U = Q Ub.
+ *   Algorithm 2 (Sketch-Powered Low-Rank Factorization):
+ *       X = (S2^T Y)^+ (S2^T A),  S2 m x r1 second sparse sketch.
+ *   Algorithm 3 (Sketch-Powered Nystrom Approximation, PSD A):
+ *       Ct = A S, Wt = S^T A S, Y = Wt^q Omega, C = Ct Y, W = Y^T Wt Y.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Matrices are ROW-MAJOR.  Element (i, j) of a matrix with leading dimension
+ *   ld is at offset i*ld + j.  ld >= cols.
+ * - Every matrix pointer (A data, block scales, outputs, workspace, info) is a
+ *   DEVICE pointer owned by the caller.  The library never allocates, frees or
+ *   copies host memory, and never synchronises: calls only enqueue work on
+ *   `stream` (a hipStream_t passed as void*; NULL = the null stream).
+ * - Argument checking is synchronous: on any error status nothing has been
+ *   enqueued.  RF_EINVAL: bad sizes / null pointers / inconsistent dtype.
+ *   RF_EWORKSPACE: ws_bytes < rf_workspace_size(...).  RF_EUNSUPPORTED: valid
+ *   request this build does not implement.  RF_EHIP: a HIP launch failed.
+ * - Conditions found on the device (Cholesky breakdown handled by column
+ *   refill, non-finite values) are written to *info (device memory, may be
+ *   NULL) and are readable after the stream has been synchronised.
+ * - Randomness: S, S2 and Omega are pure functions of (seed, stream id, matrix
+ *   index b = 0) through Philox4x32-10 (Salmon et al., SC'11); stream ids:
+ *   0 = S (S1), 1 = Omega, 2 = S2, 3 = refill vectors.
+ * - Sizes: 1 <= k <= sketch <= min(m, n) (Theorem 2.1 / 2.3 hypotheses;
+ *   sketch <= n for Nystrom, Theorem 2.5), q >= 0, 1 <= nnz_per_col <= sketch.
+ */
+#ifndef RF_H
+#define RF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RF_OK = 0,
+  RF_EINVAL = 1,
+  RF_EWORKSPACE = 2,
+  RF_EUNSUPPORTED = 3,
+  RF_EHIP = 4
+} rf_status;
+
+/* storage type of A */
+typedef enum {
+  RF_F32 = 0,           /* float */
+  RF_F64 = 1,           /* reserved (not accepted for A) */
+  RF_BF16 = 2,          /* bfloat16 bits (uint16), round-to-nearest-even from FP32 */
+  RF_FP8E4M3_B128 = 3   /* OCP e4m3 bytes with one FP32 scale per 128x128 block:
+                           value(i,j) = fp8(i,j) * block_scales[(i/128)*ceil(cols/128) + j/128] */
+} rf_dtype;
+
+/* arithmetic form of the big products (A S, At Z, At^T Q, Q^T A) */
+typedef enum {
+  RF_PREC_FP32 = 0,     /* plain: FP32 operands on FP32 MFMA */
+  RF_PREC_MIXED = 1     /* BF16 operands on BF16 MFMA (FP8 A: FP8 MFMA for Q^T A),
+                           FP32 accumulate, last power product in FP32 */
+} rf_precision;
+/* In both forms the Gram matrices of CholeskyQR2, the Cholesky factors, the
+   triangular inverses and the Rayleigh-Ritz eigenproblem are FP64. */
+
+enum { RF_OP_RANGE_FINDER = 0, RF_OP_SVD = 1, RF_OP_LOWRANK = 2, RF_OP_NYSTROM = 3 };
+
+/* flags */
+#define RF_FLAG_ORTH_ERR 1u   /* compute info->orth_err = max |Q^T Q - I| (one extra FP64 Gram) */
+
+typedef struct {
+  const void* data;           /* device, row-major rows x cols, leading dim ld (elements) */
+  const float* block_scales;  /* device; required iff dtype == RF_FP8E4M3_B128, else NULL */
+  int64_t rows, cols, ld;
+  int32_t dtype;              /* rf_dtype */
+  int32_t reserved;           /* must be 0 */
+} rf_matrix;
+
+typedef struct {
+  int32_t k;            /* target rank r2 (columns of Q) */
+  int32_t sketch;       /* sketch size r1 = l */
+  int32_t q;            /* power steps: 2q+1 products with At */
+  int32_t nnz_per_col;  /* s: nonzeros per row of S (per column of A) */
+  uint64_t seed;
+  int32_t precision;    /* rf_precision */
+  uint32_t flags;       /* RF_FLAG_* */
+} rf_params;
+
+typedef struct {
+  int32_t status;       /* 0 = ok; bit 1 = Cholesky breakdown repaired; bit 2 = non-finite seen */
+  int32_t rank_found;   /* k minus columns refilled during orthonormalisation (last call) */
+  int32_t chol_retries; /* number of CholeskyQR passes that needed column refill */
+  int32_t nonfinite;    /* 1 if a NaN/Inf was seen in a Gram matrix */
+  double orth_err;      /* max |Q^T Q - I| if RF_FLAG_ORTH_ERR, else -1 */
+} rf_info;
+
+/* Bytes of device workspace op (RF_OP_*) needs for A and p; 0 if the arguments
+   are invalid.  Workspace must be 256-byte aligned. */
+size_t rf_workspace_size(int op, const rf_matrix* A, const rf_params* p);
+
+/* Algorithm 1.  Q: m x k FP32 (ldq >= k), orthonormal columns spanning
+   (At At^T)^q At Omega, computed by subspace iteration with CholeskyQR
+   re-orthonormalisation (exact-arithmetic span unchanged, remark after
+   Algorithm 1) and a final CholeskyQR2. */
+rf_status rf_range_finder(const rf_matrix* A, const rf_params* p, float* Q, int64_t ldq,
+                          void* ws, size_t ws_bytes, rf_info* info, void* stream);
+
+/* Randomised SVD on top of Algorithm 1 (Section 2; Section 4 uses r2 = k):
+   U m x k FP32, sigma k FP64 descending, Vt k x n FP32 with A ~= U diag(sigma) Vt
+   = Q Q^T A.  Sign convention: the largest-magnitude entry of each column of U
+   is positive (lowest row index on ties). */
+rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, double* sigma,
+                 float* Vt, int64_t ldvt, void* ws, size_t ws_bytes, rf_info* info, void* stream);
+
+/* Algorithm 2.  Y m x k FP32 is returned orthonormalised (Y X is invariant
+   under Y -> Y M), X k x n FP32 = (S2^T Y)^+ (S2^T A) by FP64 normal equations
+   (S2^T Y is a well-conditioned sketch of an orthonormal basis). */
+rf_status rf_lowrank(const rf_matrix* A, const rf_params* p, float* Y, int64_t ldy, float* X,
+                     int64_t ldx, void* ws, size_t ws_bytes, rf_info* info, void* stream);
+
+/* Algorithm 3 for square PSD A (n x n).  C n x k FP32, W k x k FP64 (symmetric),
+   F n x k FP32 optional (NULL to skip): F = C V+ Lambda+^{-1/2} from the
+   eigenpairs of W with eigenvalues > k * 2^-52 * lambda_max, so that
+   C W^+ C^T = F F^T (dropped columns are zero).  For q >= 1 the power iterate
+   Y is re-orthonormalised after every product with Wt. */
+rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t ldc, double* W,
+                     int64_t ldw, float* F, int64_t ldf, void* ws, size_t ws_bytes,
+                     rf_info* info, void* stream);
+
+/* ---- parity hooks (same kernels as the entry points above) ---------------- */
+
+/* Sketch table: out[j*s + t] = bucket | (negative << 31) for j < n, t < s, with
+   bucket in block t = [floor(t*r1/s), floor((t+1)*r1/s)).  out: device int32[n*s]. */
+rf_status rf_sketch_table(int64_t n, int32_t s, int32_t r1, uint64_t seed, uint32_t stream_id,
+                          uint32_t b, int32_t* out, void* stream);
+
+/* Gaussian fill: out (rows x cols, row-major, device float) with entry e
+   from Philox counter e/4 via Box-Muller in FP64, rounded to FP32. */
+rf_status rf_gaussian(int64_t rows, int64_t cols, uint64_t seed, uint32_t stream_id, uint32_t b,
+                      float* out, void* stream);
+
+/* At = A S for the sketch given by (s = p->nnz_per_col, r1 = p->sketch, seed,
+   stream id 0): out m x r1 FP32 (ldo >= r1).  Any r1 >= s is accepted (p->k,
+   p->q ignored).  ws >= rf_sketch_apply_ws(A, p) bytes. */
+size_t rf_sketch_apply_ws(const rf_matrix* A, const rf_params* p);
+rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, int64_t ldo,
+                          void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel-level hooks used by the parity tests (same kernels as above).
+   rf_test_gemm: C (M x N FP32, ldc) = op(A) op(B); dtype 0 = FP32 operands,
+     2 = BF16 operands (uint16 bits); a_kc != 0: op(A)(i,k) = A[i*lda+k] else
+     A[k*lda+i]; b_kc != 0: op(B)(k,j) = B[j*ldb+k] else B[k*ldb+j];
+     b_upper != 0 promises op(B)(k,j) = 0 for k > j.  ws: >= rf_test_gemm_ws(M,N,K)
+     bytes (split-K partials), may be NULL to disable split-K.
+   rf_test_gram: C (M x N FP64) = X^T Y, X (K x M) and Y (K x N) row-major FP32;
+     sym != 0 requires X == Y.  ws >= rf_test_gram_ws(K,M,N) bytes or NULL.
+   rf_test_cholqr_factor: in place upper Cholesky of G (N x N FP64, ld N) and
+     Rinv (N x N FP64, ld N) = R^{-1}; counters: device int32[16] ([0] = number
+     of pivots declared dependent).  ws >= rf_test_chol_ws(N) bytes.
+   rf_test_eig: eigenpairs of symmetric G (N x N FP64, ld N, preserved): lam
+     (N, descending), V (N x N, ld N).  ws >= rf_test_eig_ws(N) bytes; N <= 4096. */
+size_t rf_test_gemm_ws(int64_t M, int64_t N, int64_t K);
+rf_status rf_test_gemm(int dtype, int a_kc, int b_kc, const void* A, int64_t lda, const void* B, int64_t ldb,
+                       float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, int b_upper, void* ws,
+                       void* stream);
+size_t rf_test_gram_ws(int64_t K, int64_t M, int64_t N);
+rf_status rf_test_gram(const float* X, const float* Y, int64_t K, int64_t M, int64_t N, int sym, double* C,
+                       void* ws, void* stream);
+size_t rf_test_chol_ws(int64_t N);
+rf_status rf_test_cholqr_factor(double* G, int64_t N, double* Rinv, int32_t* counters, void* ws, void* stream);
+size_t rf_test_eig_ws(int64_t N);
+rf_status rf_test_eig(const double* G, int64_t N, double* lam, double* V, void* ws, void* stream);
+
+const char* rf_status_string(rf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RF_H */

@@ -1,0 +1,304 @@
+"""Thin Python binding of librf.so, the MI355X (gfx950) sketch-powered range finder.
+
+Every function here only marshals arguments (torch tensors on the GPU ->
+device pointers, sizes, the current HIP stream) and calls the C ABI declared in
+include/rf.h; every step of the computation runs in the library's HIP kernels.
+There is no CPU fallback: if librf.so is missing or cannot be loaded, the
+functions raise.
+
+Method: Chenakkod & Derezinski, "Accelerating Power Method with Fast Sketching
+for Stronger Low-Rank Approximation" (arXiv 2605.09755) -- Algorithm 1
+(range_finder), the randomised SVD finisher of Section 2 (svd), Algorithm 2
+(lowrank) and Algorithm 3 (nystrom).
+"""
+import ctypes
+import os
+import struct
+
+import torch
+
+__all__ = [
+    "RF_F32", "RF_BF16", "RF_FP8E4M3_B128", "RF_PREC_FP32", "RF_PREC_MIXED",
+    "RF_OP_RANGE_FINDER", "RF_OP_SVD", "RF_OP_LOWRANK", "RF_OP_NYSTROM",
+    "lib", "library_path", "rf_status_string", "rf_workspace_size", "rf_sketch_table", "rf_gaussian",
+    "rf_sketch_apply", "rf_range_finder", "rf_svd", "rf_lowrank", "rf_nystrom", "RFError",
+]
+
+RF_OK, RF_EINVAL, RF_EWORKSPACE, RF_EUNSUPPORTED, RF_EHIP = 0, 1, 2, 3, 4
+RF_F32, RF_F64, RF_BF16, RF_FP8E4M3_B128 = 0, 1, 2, 3
+RF_PREC_FP32, RF_PREC_MIXED = 0, 1
+RF_OP_RANGE_FINDER, RF_OP_SVD, RF_OP_LOWRANK, RF_OP_NYSTROM = 0, 1, 2, 3
+RF_FLAG_ORTH_ERR = 1
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+library_path = os.path.join(_HERE, "librf.so")
+
+
+class RfMatrix(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("block_scales", ctypes.c_void_p), ("rows", ctypes.c_int64),
+                ("cols", ctypes.c_int64), ("ld", ctypes.c_int64), ("dtype", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class RfParams(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("sketch", ctypes.c_int32), ("q", ctypes.c_int32),
+                ("nnz_per_col", ctypes.c_int32), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
+                ("flags", ctypes.c_uint32)]
+
+
+INFO_BYTES = 24  # int32 x 4 + double
+
+
+class RFError(RuntimeError):
+    def __init__(self, fn, status):
+        super().__init__("%s failed: %s (%d)" % (fn, _status_name(status), status))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load librf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(library_path):
+            raise RuntimeError("librf.so not found at %s: build it with "
+                               "`python -m paper_2605_09755_amd.build` (no CPU fallback exists)" % library_path)
+        L = ctypes.CDLL(library_path)
+        vp, i64, i32, u32, u64, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32,
+                                      ctypes.c_uint64, ctypes.c_size_t)
+        M, P = ctypes.POINTER(RfMatrix), ctypes.POINTER(RfParams)
+        L.rf_status_string.restype = ctypes.c_char_p
+        L.rf_status_string.argtypes = [i32]
+        L.rf_workspace_size.restype = sz
+        L.rf_workspace_size.argtypes = [ctypes.c_int, M, P]
+        L.rf_sketch_table.restype = i32
+        L.rf_sketch_table.argtypes = [i64, i32, i32, u64, u32, u32, vp, vp]
+        L.rf_gaussian.restype = i32
+        L.rf_gaussian.argtypes = [i64, i64, u64, u32, u32, vp, vp]
+        L.rf_sketch_apply_ws.restype = sz
+        L.rf_sketch_apply_ws.argtypes = [M, P]
+        L.rf_sketch_apply.restype = i32
+        L.rf_sketch_apply.argtypes = [M, P, vp, i64, vp, sz, vp]
+        L.rf_range_finder.restype = i32
+        L.rf_range_finder.argtypes = [M, P, vp, i64, vp, sz, vp, vp]
+        L.rf_svd.restype = i32
+        L.rf_svd.argtypes = [M, P, vp, i64, vp, vp, i64, vp, sz, vp, vp]
+        L.rf_lowrank.restype = i32
+        L.rf_lowrank.argtypes = [M, P, vp, i64, vp, i64, vp, sz, vp, vp]
+        L.rf_nystrom.restype = i32
+        L.rf_nystrom.argtypes = [M, P, vp, i64, vp, i64, vp, i64, vp, sz, vp, vp]
+        L.rf_test_gemm_ws.restype = sz
+        L.rf_test_gemm_ws.argtypes = [i64, i64, i64]
+        L.rf_test_gemm.restype = i32
+        L.rf_test_gemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, vp, i64, i64, i64,
+                                   i64, ctypes.c_int, vp, vp]
+        L.rf_test_gram_ws.restype = sz
+        L.rf_test_gram_ws.argtypes = [i64, i64, i64]
+        L.rf_test_gram.restype = i32
+        L.rf_test_gram.argtypes = [vp, vp, i64, i64, i64, ctypes.c_int, vp, vp, vp]
+        L.rf_test_chol_ws.restype = sz
+        L.rf_test_chol_ws.argtypes = [i64]
+        L.rf_test_cholqr_factor.restype = i32
+        L.rf_test_cholqr_factor.argtypes = [vp, i64, vp, vp, vp, vp]
+        L.rf_test_eig_ws.restype = sz
+        L.rf_test_eig_ws.argtypes = [i64]
+        L.rf_test_eig.restype = i32
+        L.rf_test_eig.argtypes = [vp, i64, vp, vp, vp, vp]
+        _lib = L
+    return _lib
+
+
+def _status_name(s):
+    return {0: "ok", 1: "invalid argument", 2: "workspace too small", 3: "unsupported", 4: "HIP launch error"}.get(
+        s, "unknown")
+
+
+def rf_status_string(s):
+    return lib().rf_status_string(int(s)).decode()
+
+
+def _check(fn, st):
+    if st != RF_OK:
+        raise RFError(fn, st)
+
+
+def _stream(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def matrix(A, scales=None):
+    """rf_matrix descriptor for a 2-D row-major device tensor (float32, bfloat16,
+    or uint8 holding OCP e4m3 bytes together with 128x128 block `scales`)."""
+    if A.dim() != 2 or A.stride(1) != 1:
+        raise ValueError("A must be a 2-D tensor with unit column stride")
+    if A.dtype == torch.float32:
+        dt = RF_F32
+    elif A.dtype == torch.bfloat16:
+        dt = RF_BF16
+    elif A.dtype in (torch.uint8, getattr(torch, "float8_e4m3fn", torch.uint8)):
+        dt = RF_FP8E4M3_B128
+        if scales is None:
+            raise ValueError("FP8 storage needs block scales")
+    else:
+        raise ValueError("unsupported dtype %s" % A.dtype)
+    return RfMatrix(A.data_ptr(), scales.data_ptr() if scales is not None else None, A.shape[0], A.shape[1],
+                    max(A.stride(0), A.shape[1]), dt, 0)
+
+
+def params(k, sketch, q=0, nnz_per_col=8, seed=0, precision=RF_PREC_FP32, flags=0):
+    if isinstance(precision, str):
+        precision = {"fp32": RF_PREC_FP32, "mixed": RF_PREC_MIXED}[precision]
+    return RfParams(int(k), int(sketch), int(q), int(nnz_per_col), int(seed) & 0xFFFFFFFFFFFFFFFF, int(precision),
+                    int(flags))
+
+
+def rf_workspace_size(op, A, p, scales=None):
+    return int(lib().rf_workspace_size(int(op), ctypes.byref(matrix(A, scales)), ctypes.byref(p)))
+
+
+def _workspace(op, A, p, scales):
+    n = rf_workspace_size(op, A, p, scales)
+    if n == 0:
+        raise RFError("rf_workspace_size", RF_EINVAL)
+    return torch.empty(n, dtype=torch.uint8, device=A.device), n
+
+
+def _info(buf):
+    raw = bytes(buf.cpu().numpy().tobytes())
+    status, rank, retries, nonf, orth = struct.unpack("<iiiid", raw)
+    return {"status": status, "rank_found": rank, "chol_retries": retries, "nonfinite": nonf, "orth_err": orth}
+
+
+def rf_sketch_table(n, s, r1, seed, stream_id=0, b=0, device="cuda"):
+    out = torch.empty((n, s), dtype=torch.int32, device=device)
+    _check("rf_sketch_table", lib().rf_sketch_table(n, s, r1, seed, stream_id, b, _ptr(out), _stream(out.device)))
+    return out
+
+
+def rf_gaussian(rows, cols, seed, stream_id=1, b=0, device="cuda"):
+    out = torch.empty((rows, cols), dtype=torch.float32, device=device)
+    _check("rf_gaussian", lib().rf_gaussian(rows, cols, seed, stream_id, b, _ptr(out), _stream(out.device)))
+    return out
+
+
+def rf_sketch_apply(A, sketch, nnz_per_col, seed, scales=None):
+    p = params(1, sketch, 0, nnz_per_col, seed)
+    nws = int(lib().rf_sketch_apply_ws(ctypes.byref(matrix(A, scales)), ctypes.byref(p)))
+    if nws == 0:
+        raise RFError("rf_sketch_apply_ws", RF_EINVAL)
+    ws = torch.empty(nws, dtype=torch.uint8, device=A.device)
+    out = torch.empty((A.shape[0], sketch), dtype=torch.float32, device=A.device)
+    _check("rf_sketch_apply", lib().rf_sketch_apply(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(out),
+                                                    sketch, _ptr(ws), nws, _stream(A.device)))
+    return out
+
+
+def rf_range_finder(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, orth_err=False,
+                    workspace=None):
+    p = params(k, sketch, q, nnz_per_col, seed, precision, RF_FLAG_ORTH_ERR if orth_err else 0)
+    ws, nws = workspace if workspace is not None else _workspace(RF_OP_RANGE_FINDER, A, p, scales)
+    Q = torch.empty((A.shape[0], k), dtype=torch.float32, device=A.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    _check("rf_range_finder", lib().rf_range_finder(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(Q), k,
+                                                    _ptr(ws), nws, _ptr(info), _stream(A.device)))
+    return Q, info
+
+
+def rf_svd(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, orth_err=False,
+           workspace=None, out=None):
+    p = params(k, sketch, q, nnz_per_col, seed, precision, RF_FLAG_ORTH_ERR if orth_err else 0)
+    ws, nws = workspace if workspace is not None else _workspace(RF_OP_SVD, A, p, scales)
+    m, n = A.shape
+    if out is None:
+        U = torch.empty((m, k), dtype=torch.float32, device=A.device)
+        sig = torch.empty(k, dtype=torch.float64, device=A.device)
+        Vt = torch.empty((k, n), dtype=torch.float32, device=A.device)
+        info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    else:
+        U, sig, Vt, info = out
+    _check("rf_svd", lib().rf_svd(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(U), k, _ptr(sig), _ptr(Vt),
+                                  n, _ptr(ws), nws, _ptr(info), _stream(A.device)))
+    return U, sig, Vt, info
+
+
+def rf_lowrank(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, workspace=None):
+    p = params(k, sketch, q, nnz_per_col, seed, precision)
+    ws, nws = workspace if workspace is not None else _workspace(RF_OP_LOWRANK, A, p, scales)
+    m, n = A.shape
+    Y = torch.empty((m, k), dtype=torch.float32, device=A.device)
+    X = torch.empty((k, n), dtype=torch.float32, device=A.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    _check("rf_lowrank", lib().rf_lowrank(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(Y), k, _ptr(X), n,
+                                          _ptr(ws), nws, _ptr(info), _stream(A.device)))
+    return Y, X, info
+
+
+def rf_nystrom(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, want_F=True,
+               workspace=None):
+    p = params(k, sketch, q, nnz_per_col, seed, precision)
+    ws, nws = workspace if workspace is not None else _workspace(RF_OP_NYSTROM, A, p, scales)
+    n = A.shape[0]
+    C = torch.empty((n, k), dtype=torch.float32, device=A.device)
+    W = torch.empty((k, k), dtype=torch.float64, device=A.device)
+    F = torch.empty((n, k), dtype=torch.float32, device=A.device) if want_F else None
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    _check("rf_nystrom", lib().rf_nystrom(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(C), k, _ptr(W), k,
+                                          _ptr(F), k, _ptr(ws), nws, _ptr(info), _stream(A.device)))
+    return C, W, F, info
+
+
+# ---- kernel-level parity hooks -------------------------------------------------------
+def rf_test_gemm(A, B, M, N, K, a_kc, b_kc, b_upper=False, split=True):
+    """C = op(A) op(B) (FP32 out) with the library's MFMA GEMM.  A, B: float32 or
+    bfloat16 device tensors in the layouts described in include/rf.h."""
+    dtype = 0 if A.dtype == torch.float32 else 2
+    lda = A.stride(0)
+    ldb = B.stride(0)
+    C = torch.empty((M, N), dtype=torch.float32, device=A.device)
+    ws = torch.empty(int(lib().rf_test_gemm_ws(M, N, K)), dtype=torch.uint8, device=A.device) if split else None
+    _check("rf_test_gemm", lib().rf_test_gemm(dtype, int(a_kc), int(b_kc), _ptr(A), lda, _ptr(B), ldb, _ptr(C), N, M,
+                                              N, K, int(b_upper), _ptr(ws), _stream(A.device)))
+    return C
+
+
+def rf_test_gram(X, Y=None, sym=False, split=True):
+    Y = X if Y is None else Y
+    K, M = X.shape
+    N = Y.shape[1]
+    C = torch.zeros((M, N), dtype=torch.float64, device=X.device)
+    ws = torch.empty(int(lib().rf_test_gram_ws(K, M, N)), dtype=torch.uint8, device=X.device) if split else None
+    _check("rf_test_gram", lib().rf_test_gram(_ptr(X), _ptr(Y), K, M, N, int(sym), _ptr(C), _ptr(ws),
+                                              _stream(X.device)))
+    return C
+
+
+def rf_test_cholqr_factor(G):
+    N = G.shape[0]
+    G = G.clone().contiguous()
+    Rinv = torch.zeros_like(G)
+    counters = torch.zeros(16, dtype=torch.int32, device=G.device)
+    ws = torch.empty(int(lib().rf_test_chol_ws(N)), dtype=torch.uint8, device=G.device)
+    _check("rf_test_cholqr_factor", lib().rf_test_cholqr_factor(_ptr(G), N, _ptr(Rinv), _ptr(counters), _ptr(ws),
+                                                                _stream(G.device)))
+    return G, Rinv, counters
+
+
+def rf_test_eig(G):
+    N = G.shape[0]
+    G = G.contiguous()
+    lam = torch.empty(N, dtype=torch.float64, device=G.device)
+    V = torch.empty((N, N), dtype=torch.float64, device=G.device)
+    ws = torch.empty(int(lib().rf_test_eig_ws(N)), dtype=torch.uint8, device=G.device)
+    _check("rf_test_eig", lib().rf_test_eig(_ptr(G), N, _ptr(lam), _ptr(V), _ptr(ws), _stream(G.device)))
+    return lam, V
+
+
+def info_dict(info):
+    """Decode an rf_info device buffer (synchronises)."""
+    return _info(info)

@@ -1,0 +1,398 @@
+// K5/K6: dense products on MFMA.  C = alpha * op(A) op(B), FP32 accumulation.
+//
+// These are the tall-skinny contractions of the power loop (At Z over r1,
+// At^T Q over m -- Algorithm 1, line 1), the randomised-SVD product Q^T A
+// (Section 2), the CholeskyQR apply Y R^{-1}, and the small Ritz products.
+//
+// Tile: 128 x 128 per workgroup, 4 waves in 2 x 2, each wave 64 x 64 as 2 x 2
+// MFMA 32x32 blocks.  FP32 operands use v_mfma_f32_32x32x2f32 (one value per
+// lane per block), BF16 operands use v_mfma_f32_32x32x16_bf16 (eight k-consecutive
+// values per lane).  Operands are staged global -> registers -> LDS with double
+// buffering and one barrier per k-step.  Either operand may be k-contiguous
+// ("K" layout) or m/n-contiguous ("T" layout); BF16 T-layout tiles are transposed
+// in registers (2 x 8 blocks) on their way into LDS, which always stores BF16
+// k-contiguous.  Split-K writes FP32 partials that a second kernel sums in
+// fixed order (deterministic).
+#include "common.h"
+#include "kernels.h"
+
+namespace rf {
+
+constexpr int GBM = 128, GBN = 128;
+
+RF_DEV void tile_coords(int id, int ntm, int ntn, int& tm, int& tn) {
+  // XCD-aware order: consecutive workgroup ids go to different XCDs (id % 8);
+  // give each XCD whole M-panels and walk their N tiles back to back so the
+  // panel stays in that XCD's L2.
+  if (ntm % 8 == 0 && ntn > 1) {
+    int xcd = id & 7, local = id >> 3;
+    tn = local % ntn;
+    tm = (local / ntn) * 8 + xcd;
+  } else {
+    tn = id % ntn;
+    tm = id / ntn;
+  }
+}
+
+RF_DEV void store_out(const GemmArgs& g, int64_t i, int64_t j, float v) {
+  if (i >= g.M || j >= g.N) return;
+  v *= g.alpha;
+  if (g.colscale) v *= g.colscale[j];
+  if (g.c_bf16) {
+    uint16_t* C = reinterpret_cast<uint16_t*>(g.C);
+    C[g.c_trans ? j * g.ldc + i : i * g.ldc + j] = f32_to_bf16_rne(v);
+  } else {
+    float* C = reinterpret_cast<float*>(g.C);
+    C[g.c_trans ? j * g.ldc + i : i * g.ldc + j] = v;
+  }
+}
+
+// ---------------- FP32 operands -------------------------------------------------------
+template <bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
+  constexpr int BK = 16;
+  constexpr int AST = AKC ? (BK + 1) : GBM;  // LDS row stride (floats)
+  constexpr int BST = BKC ? (BK + 1) : GBN;
+  constexpr int ASZ = AKC ? GBM * (BK + 1) : BK * GBM;
+  constexpr int BSZ = BKC ? GBN * (BK + 1) : BK * GBN;
+  __shared__ float As[2][ASZ];
+  __shared__ float Bs[2][BSZ];
+
+  const int ntm = (int)((g.M + GBM - 1) / GBM), ntn = (int)((g.N + GBN - 1) / GBN);
+  int tm, tn;
+  tile_coords(blockIdx.x, ntm, ntn, tm, tn);
+  const int64_t i0 = (int64_t)tm * GBM, j0 = (int64_t)tn * GBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int64_t kbeg = (int64_t)blockIdx.y * g.kps;
+  int64_t kend = min(g.K, kbeg + g.kps);
+  if (g.b_upper) kend = min(kend, j0 + GBN);
+  const float* A = reinterpret_cast<const float*>(g.A);
+  const float* B = reinterpret_cast<const float*>(g.B);
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  float ra[2][4], rb[2][4];
+  auto gload = [&](int64_t k0) {
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+      if (AKC) {
+        int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 4;
+        int64_t i = i0 + row;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int64_t k = k0 + kc + e;
+          ra[ps][e] = (i < g.M && k < kend) ? A[i * g.lda + k] : 0.f;
+        }
+      } else {
+        int kr = (tid >> 5) + 8 * ps, ic = (tid & 31) * 4;
+        int64_t k = k0 + kr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int64_t i = i0 + ic + e;
+          ra[ps][e] = (i < g.M && k < kend) ? A[k * g.lda + i] : 0.f;
+        }
+      }
+      if (BKC) {
+        int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 4;
+        int64_t j = j0 + row;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int64_t k = k0 + kc + e;
+          rb[ps][e] = (j < g.N && k < kend) ? B[j * g.ldb + k] : 0.f;
+        }
+      } else {
+        int kr = (tid >> 5) + 8 * ps, jc = (tid & 31) * 4;
+        int64_t k = k0 + kr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          int64_t j = j0 + jc + e;
+          rb[ps][e] = (j < g.N && k < kend) ? B[k * g.ldb + j] : 0.f;
+        }
+      }
+    }
+  };
+  auto sstore = [&](int buf) {
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+      if (AKC) {
+        int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) As[buf][row * AST + kc + e] = ra[ps][e];
+      } else {
+        int kr = (tid >> 5) + 8 * ps, ic = (tid & 31) * 4;
+        *reinterpret_cast<float4*>(&As[buf][kr * AST + ic]) = make_float4(ra[ps][0], ra[ps][1], ra[ps][2], ra[ps][3]);
+      }
+      if (BKC) {
+        int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 4;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) Bs[buf][row * BST + kc + e] = rb[ps][e];
+      } else {
+        int kr = (tid >> 5) + 8 * ps, jc = (tid & 31) * 4;
+        *reinterpret_cast<float4*>(&Bs[buf][kr * BST + jc]) = make_float4(rb[ps][0], rb[ps][1], rb[ps][2], rb[ps][3]);
+      }
+    }
+  };
+
+  const int nk = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload(kbeg + (int64_t)(kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 2; ++kk) {
+      const int kidx = 2 * kk + (lane >> 5);
+      float af[2], bf[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        int ii = wm * 64 + a * 32 + (lane & 31);
+        af[a] = AKC ? As[buf][ii * AST + kidx] : As[buf][kidx * AST + ii];
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        int jj = wn * 64 + b * 32 + (lane & 31);
+        bf[b] = BKC ? Bs[buf][jj * BST + kidx] : Bs[buf][kidx * BST + jj];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        int64_t i = i0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        int64_t j = j0 + wn * 64 + b * 32 + (lane & 31);
+        if (g.partial) {
+          if (i < g.M && j < g.N) g.partial[((int64_t)blockIdx.y * g.M + i) * g.N + j] = acc[a][b][r];
+        } else {
+          store_out(g, i, j, acc[a][b][r]);
+        }
+      }
+}
+
+// ---------------- BF16 operands -------------------------------------------------------
+RF_DEV uint32_t pack_lo(uint32_t a, uint32_t b) { return (a & 0xffffu) | (b << 16); }
+RF_DEV uint32_t pack_hi(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
+
+template <bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  constexpr int BK = 32;
+  constexpr int ST = BK + 8;  // bf16 elements per LDS row (80 B)
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][GBM * ST];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][GBN * ST];
+
+  const int ntm = (int)((g.M + GBM - 1) / GBM), ntn = (int)((g.N + GBN - 1) / GBN);
+  int tm, tn;
+  tile_coords(blockIdx.x, ntm, ntn, tm, tn);
+  const int64_t i0 = (int64_t)tm * GBM, j0 = (int64_t)tn * GBN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int64_t kbeg = (int64_t)blockIdx.y * g.kps;
+  int64_t kend = min(g.K, kbeg + g.kps);
+  if (g.b_upper) kend = min(kend, j0 + GBN);
+  const uint16_t* A = reinterpret_cast<const uint16_t*>(g.A);
+  const uint16_t* B = reinterpret_cast<const uint16_t*>(g.B);
+
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  // staging registers: 2 x uint4 per operand (16 bf16)
+  uint4 sa[2], sb[2];
+
+  // K layout: 128 rows x 32 k; thread: row (tid>>2)+64ps, k chunk (tid&3)*8.
+  auto load_kc = [&](const uint16_t* P, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, uint4* dst, bool vec) {
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+      int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 8;
+      int64_t r = r0 + row, k = k0 + kc;
+      if (vec && r < rmax && k + 8 <= kend) {
+        dst[ps] = *reinterpret_cast<const uint4*>(P + r * ld + k);
+      } else {
+        uint32_t w[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          uint32_t lo = (r < rmax && k + 2 * e < kend) ? P[r * ld + k + 2 * e] : 0u;
+          uint32_t hi = (r < rmax && k + 2 * e + 1 < kend) ? P[r * ld + k + 2 * e + 1] : 0u;
+          w[e] = lo | (hi << 16);
+        }
+        dst[ps] = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+  };
+  // T layout: element (r, k) at P[k*ld + r].  Wave w covers k rows 8w..8w+7,
+  // lane covers r pair (2 lane, 2 lane + 1); produces two k-vectors of 8.
+  auto load_tc = [&](const uint16_t* P, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, uint4* dst, bool vec) {
+    uint32_t w[8];
+    int64_t r = r0 + 2 * lane;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      int64_t k = k0 + 8 * wave + e;
+      if (vec && k < kend && r + 1 < rmax) {
+        w[e] = *reinterpret_cast<const uint32_t*>(P + k * ld + r);
+      } else {
+        uint32_t lo = (k < kend && r < rmax) ? P[k * ld + r] : 0u;
+        uint32_t hi = (k < kend && r + 1 < rmax) ? P[k * ld + r + 1] : 0u;
+        w[e] = lo | (hi << 16);
+      }
+    }
+    dst[0] = make_uint4(pack_lo(w[0], w[1]), pack_lo(w[2], w[3]), pack_lo(w[4], w[5]), pack_lo(w[6], w[7]));
+    dst[1] = make_uint4(pack_hi(w[0], w[1]), pack_hi(w[2], w[3]), pack_hi(w[4], w[5]), pack_hi(w[6], w[7]));
+  };
+  auto store_kc = [&](uint16_t* S, const uint4* src) {
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+      int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 8;
+      *reinterpret_cast<uint4*>(S + row * ST + kc) = src[ps];
+    }
+  };
+  auto store_tc = [&](uint16_t* S, const uint4* src) {
+    *reinterpret_cast<uint4*>(S + (2 * lane) * ST + 8 * wave) = src[0];
+    *reinterpret_cast<uint4*>(S + (2 * lane + 1) * ST + 8 * wave) = src[1];
+  };
+  const bool avec = AKC ? ((((uintptr_t)A) & 15) == 0 && (g.lda & 7) == 0) : ((((uintptr_t)A) & 3) == 0 && (g.lda & 1) == 0);
+  const bool bvec = BKC ? ((((uintptr_t)B) & 15) == 0 && (g.ldb & 7) == 0) : ((((uintptr_t)B) & 3) == 0 && (g.ldb & 1) == 0);
+  auto gload = [&](int64_t k0) {
+    if (AKC) load_kc(A, g.lda, i0, g.M, k0, sa, avec); else load_tc(A, g.lda, i0, g.M, k0, sa, avec);
+    if (BKC) load_kc(B, g.ldb, j0, g.N, k0, sb, bvec); else load_tc(B, g.ldb, j0, g.N, k0, sb, bvec);
+  };
+  auto sstore = [&](int buf) {
+    if (AKC) store_kc(As[buf], sa); else store_tc(As[buf], sa);
+    if (BKC) store_kc(Bs[buf], sb); else store_tc(Bs[buf], sb);
+  };
+
+  const int nk = kend > kbeg ? (int)((kend - kbeg + BK - 1) / BK) : 0;
+  if (nk > 0) {
+    gload(kbeg);
+    sstore(0);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) gload(kbeg + (int64_t)(kt + 1) * BK);
+#pragma unroll
+    for (int kk = 0; kk < BK / 16; ++kk) {
+      const int koff = 16 * kk + 8 * (lane >> 5);
+      bf16x8 af[2], bfr[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) {
+        int ii = wm * 64 + a * 32 + (lane & 31);
+        af[a] = *reinterpret_cast<const bf16x8*>(&As[buf][ii * ST + koff]);
+      }
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        int jj = wn * 64 + b * 32 + (lane & 31);
+        bfr[b] = *reinterpret_cast<const bf16x8*>(&Bs[buf][jj * ST + koff]);
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nk) sstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        int64_t i = i0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        int64_t j = j0 + wn * 64 + b * 32 + (lane & 31);
+        if (g.partial) {
+          if (i < g.M && j < g.N) g.partial[((int64_t)blockIdx.y * g.M + i) * g.N + j] = acc[a][b][r];
+        } else {
+          store_out(g, i, j, acc[a][b][r]);
+        }
+      }
+}
+
+__global__ void k_gemm_reduce(GemmArgs g, int splits) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= g.M * g.N) return;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += g.partial[(int64_t)z * g.M * g.N + idx];
+  store_out(g, idx / g.N, idx % g.N, s);
+}
+
+static int cu_count() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    if (n <= 0) n = 256;
+  }
+  return n;
+}
+
+int gemm_splits(int64_t M, int64_t N, int64_t K) {
+  int64_t tiles = ((M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
+  int s = 1;
+  while (tiles * s < 2 * cu_count() && K / (s * 2) >= 512 && s < 64) s *= 2;
+  return s;
+}
+
+size_t gemm_partial_floats(int64_t M, int64_t N, int64_t K) {
+  int s = gemm_splits(M, N, K);
+  return s > 1 ? (size_t)s * M * N : 0;
+}
+
+hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
+  if (g.M == 0 || g.N == 0) return hipSuccess;
+  int splits = partial ? gemm_splits(g.M, g.N, g.K) : 1;
+  if (g.b_upper) splits = 1;
+  int64_t bk = 32;
+  g.kps = ((g.K + splits - 1) / splits + bk - 1) / bk * bk;
+  if (g.kps == 0) g.kps = bk;
+  splits = (int)((g.K + g.kps - 1) / g.kps);
+  if (splits < 1) splits = 1;
+  g.partial = splits > 1 ? partial : nullptr;
+  int64_t tiles = ((g.M + GBM - 1) / GBM) * ((g.N + GBN - 1) / GBN);
+  dim3 grid((unsigned)tiles, (unsigned)splits);
+  auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, g); };
+  if (dtype == 0) {
+    if (g.a_kc && g.b_kc) go(k_gemm_f32<true, true>);
+    else if (g.a_kc && !g.b_kc) go(k_gemm_f32<true, false>);
+    else if (!g.a_kc && g.b_kc) go(k_gemm_f32<false, true>);
+    else go(k_gemm_f32<false, false>);
+  } else if (dtype == 2) {
+    if (g.a_kc && g.b_kc) go(k_gemm_bf16<true, true>);
+    else if (g.a_kc && !g.b_kc) go(k_gemm_bf16<true, false>);
+    else if (!g.a_kc && g.b_kc) go(k_gemm_bf16<false, true>);
+    else go(k_gemm_bf16<false, false>);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  if (splits > 1) {
+    int64_t tot = g.M * g.N;
+    hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, g, splits);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rf

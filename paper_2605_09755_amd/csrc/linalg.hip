@@ -1,0 +1,1074 @@
+// FP64 small dense linear algebra on the device: the Gram matrices, Cholesky
+// factors and triangular inverses of CholeskyQR2 (re-orthonormalisation after
+// each power step, remark after Algorithm 1; "orth" of Algorithm 1, line 2),
+// and the symmetric eigensolver of the Rayleigh-Ritz step of the randomised SVD
+// (SVD of B = Q^T A through the eigenpairs of B B^T, Section 2) and of the
+// Nystrom core W (Algorithm 3).  Everything stays on the stream: no host
+// round-trips, conditions are written to device counters.
+#include "common.h"
+#include "kernels.h"
+
+namespace rf {
+
+// ============================== Gram: C = X^T Y (FP64) ==============================
+template <typename T>
+RF_DEV double ldd(const T* p) { return (double)*p; }
+
+constexpr int GT = 64;  // output tile
+constexpr int GK = 16;  // k rows per step
+
+RF_DEV void upper_tile(int id, int nt, int& tm, int& tn) {
+  // enumerate tm <= tn row by row
+  int r = 0, rem = id;
+  while (rem >= nt - r) { rem -= nt - r; ++r; }
+  tm = r;
+  tn = r + rem;
+}
+
+template <typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int64_t ldx, const TY* __restrict__ Y,
+                                              int64_t ldy, int64_t K, int64_t M, int64_t N, int sym,
+                                              double* __restrict__ C, int64_t ldc, double* __restrict__ partial,
+                                              int64_t kps, const int* run_if) {
+  if (run_if && *run_if == 0) return;
+  __shared__ double Xs[GK][GT];
+  __shared__ double Ys[GK][GT];
+  const int ntm = (int)((M + GT - 1) / GT), ntn = (int)((N + GT - 1) / GT);
+  int tm, tn;
+  if (sym) upper_tile(blockIdx.x, ntm, tm, tn);
+  else { tm = blockIdx.x / ntn; tn = blockIdx.x % ntn; }
+  const int64_t i0 = (int64_t)tm * GT, j0 = (int64_t)tn * GT;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
+  const int64_t kbeg = (int64_t)blockIdx.y * kps, kend = min(K, kbeg + kps);
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
+  for (int64_t k0 = kbeg; k0 < kend; k0 += GK) {
+    {
+      int r = tid >> 4, c = (tid & 15) * 4;
+      int64_t k = k0 + r;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int64_t i = i0 + c + e, j = j0 + c + e;
+        Xs[r][c + e] = (k < kend && i < M) ? ldd(X + k * ldx + i) : 0.0;
+        Ys[r][c + e] = (k < kend && j < N) ? ldd(Y + k * ldy + j) : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK / 4; ++kk) {
+      int kr = 4 * kk + (lane >> 4);
+      double af[2], bf[2];
+#pragma unroll
+      for (int a = 0; a < 2; ++a) af[a] = Xs[kr][wm * 32 + a * 16 + (lane & 15)];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) bf[b] = Ys[kr][wn * 32 + b * 16 + (lane & 15)];
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // v_mfma_f64_16x16x4f64 output: register r of lane l holds row (l/16) + 4r, column l%16
+        int64_t i = i0 + wm * 32 + a * 16 + (lane >> 4) + 4 * r;
+        int64_t j = j0 + wn * 32 + b * 16 + (lane & 15);
+        if (i >= M || j >= N) continue;
+        if (sym && i > j) continue;
+        double v = acc[a][b][r];
+        if (partial) {
+          partial[((int64_t)blockIdx.y * M + i) * N + j] = v;
+        } else {
+          C[i * ldc + j] = v;
+          if (sym && i != j) C[j * ldc + i] = v;
+        }
+      }
+}
+
+__global__ void k_gram_reduce(const double* __restrict__ partial, int splits, int64_t M, int64_t N, int sym,
+                              double* __restrict__ C, int64_t ldc, const int* run_if) {
+  if (run_if && *run_if == 0) return;
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= M * N) return;
+  int64_t i = idx / N, j = idx % N;
+  if (sym && i > j) return;
+  double s = 0.0;
+  for (int z = 0; z < splits; ++z) s += partial[(int64_t)z * M * N + idx];
+  C[i * ldc + j] = s;
+  if (sym && i != j) C[j * ldc + i] = s;
+}
+
+static int cus() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    if (n <= 0) n = 256;
+  }
+  return n;
+}
+
+static int gram_splits(int64_t K, int64_t M, int64_t N, int sym) {
+  int64_t ntm = (M + GT - 1) / GT, ntn = (N + GT - 1) / GT;
+  int64_t tiles = sym ? ntm * (ntm + 1) / 2 : ntm * ntn;
+  int s = 1;
+  while (tiles * s < 2 * cus() && K / (2 * s) >= 256 && s < 128) s *= 2;
+  return s;
+}
+
+size_t gram_partial_doubles(int64_t K, int64_t M, int64_t N) {
+  int s = gram_splits(K, M, N, 0);
+  int s2 = gram_splits(K, M, N, 1);
+  if (s2 > s) s = s2;
+  return s > 1 ? (size_t)s * M * N : 0;
+}
+
+hipError_t launch_gram(const void* X, int64_t ldx, int xdt, const void* Y, int64_t ldy, int ydt, int64_t K, int64_t M,
+                       int64_t N, int sym, double* C, int64_t ldc, double* partial, const int* run_if,
+                       hipStream_t st) {
+  if (M == 0 || N == 0) return hipSuccess;
+  int splits = partial ? gram_splits(K, M, N, sym) : 1;
+  int64_t kps = ((K + splits - 1) / splits + GK - 1) / GK * GK;
+  if (kps == 0) kps = GK;
+  splits = (int)((K + kps - 1) / kps);
+  if (splits < 1) splits = 1;
+  int64_t ntm = (M + GT - 1) / GT, ntn = (N + GT - 1) / GT;
+  int64_t tiles = sym ? ntm * (ntm + 1) / 2 : ntm * ntn;
+  double* part = splits > 1 ? partial : nullptr;
+  dim3 grid((unsigned)tiles, (unsigned)splits);
+  if (xdt == 0 && ydt == 0)
+    hipLaunchKernelGGL((k_gram<float, float>), grid, dim3(256), 0, st, (const float*)X, ldx, (const float*)Y, ldy, K,
+                       M, N, sym, C, ldc, part, kps, run_if);
+  else if (xdt == 1 && ydt == 1)
+    hipLaunchKernelGGL((k_gram<double, double>), grid, dim3(256), 0, st, (const double*)X, ldx, (const double*)Y,
+                       ldy, K, M, N, sym, C, ldc, part, kps, run_if);
+  else if (xdt == 0 && ydt == 1)
+    hipLaunchKernelGGL((k_gram<float, double>), grid, dim3(256), 0, st, (const float*)X, ldx, (const double*)Y, ldy,
+                       K, M, N, sym, C, ldc, part, kps, run_if);
+  else
+    hipLaunchKernelGGL((k_gram<double, float>), grid, dim3(256), 0, st, (const double*)X, ldx, (const float*)Y, ldy,
+                       K, M, N, sym, C, ldc, part, kps, run_if);
+  if (splits > 1) {
+    int64_t tot = M * N;
+    hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, partial, splits, M, N,
+                       sym, C, ldc, run_if);
+  }
+  return hipGetLastError();
+}
+
+// ============================== Cholesky (upper, in place) ==============================
+constexpr int CB = 64;
+
+__global__ void k_chol_prep(const double* __restrict__ G, int64_t ld, int64_t N, double* __restrict__ d0,
+                            int* __restrict__ flags, int* count, const int* run_if) {
+  if (run_if && *run_if == 0) return;
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *count = 0;
+  if (i < N) {
+    d0[i] = G[i * ld + i];
+    flags[i] = 0;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ G, int64_t ld, int64_t N, int kb,
+                                                   double tol, const double* __restrict__ d0, int* __restrict__ flags,
+                                                   int* count, int* nonfinite, const int* run_if) {
+  if (run_if && *run_if == 0) return;
+  __shared__ double A[CB][CB + 1];
+  __shared__ double piv;
+  __shared__ int bad;
+  const int64_t b0 = (int64_t)kb * CB;
+  const int nb = (int)min((int64_t)CB, N - b0);
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    int i = e / CB, j = e % CB;
+    A[i][j] = (i < nb && j < nb) ? G[(b0 + i) * ld + b0 + j] : 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < nb; ++c) {
+    if (threadIdx.x == 0) {
+      double d = A[c][c];
+      double ref = d0[b0 + c];
+      bool fin = isfinite(d);
+      if (!fin) *nonfinite = 1;
+      if (fin && d > tol * ref && d > 0.0) {
+        piv = sqrt(d);
+        bad = 0;
+      } else {
+        piv = 1.0;
+        bad = 1;
+        flags[b0 + c] = 1;
+        atomicAdd(count, 1);
+      }
+    }
+    __syncthreads();
+    for (int j = c + 1 + threadIdx.x; j < nb; j += blockDim.x) A[c][j] = bad ? 0.0 : A[c][j] / piv;
+    if (threadIdx.x == 0) A[c][c] = piv;
+    __syncthreads();
+    int w = nb - c - 1;
+    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+      int i = c + 1 + e / w, j = c + 1 + e % w;
+      if (j >= i) A[i][j] -= A[c][i] * A[c][j];
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+    int i = e / nb, j = e % nb;
+    G[(b0 + i) * ld + b0 + j] = (j >= i) ? A[i][j] : 0.0;
+  }
+}
+
+// R12 = R11^{-T} G12 for every block column right of kb.
+__global__ __launch_bounds__(64) void k_chol_panel(double* __restrict__ G, int64_t ld, int64_t N, int kb,
+                                                   const int* __restrict__ flags, const int* run_if) {
+  if (run_if && *run_if == 0) return;
+  __shared__ double R[CB][CB + 1];
+  const int64_t b0 = (int64_t)kb * CB;
+  const int nb = (int)min((int64_t)CB, N - b0);
+  const int64_t c0 = b0 + CB + (int64_t)blockIdx.x * CB;
+  const int nc = (int)min((int64_t)CB, N - c0);
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    int i = e / CB, j = e % CB;
+    R[i][j] = (i < nb && j < nb) ? G[(b0 + i) * ld + b0 + j] : 0.0;
+  }
+  __syncthreads();
+  const int j = threadIdx.x;
+  if (j >= nc) return;
+  double x[CB];
+#pragma unroll
+  for (int r = 0; r < CB; ++r) x[r] = (r < nb) ? G[(b0 + r) * ld + c0 + j] : 0.0;
+#pragma unroll
+  for (int r = 0; r < CB; ++r) {
+    if (r < nb) {
+      double s = x[r];
+#pragma unroll
+      for (int t = 0; t < r; ++t) s -= R[t][r] * x[t];
+      x[r] = flags[b0 + r] ? 0.0 : s / R[r][r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < CB; ++r)
+    if (r < nb) G[(b0 + r) * ld + c0 + j] = x[r];
+}
+
+// Trailing update of upper tiles (ib <= jb) right/below of block kb.
+__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int64_t ld, int64_t N, int kb,
+                                                     const int* run_if) {
+  if (run_if && *run_if == 0) return;
+  __shared__ double P[CB][CB];
+  __shared__ double Qm[CB][CB];
+  const int64_t b0 = (int64_t)kb * CB;
+  const int nb = (int)min((int64_t)CB, N - b0);
+  const int nt = (int)((N - b0 - CB + CB - 1) / CB);
+  int ti, tj;
+  upper_tile(blockIdx.x, nt, ti, tj);
+  const int64_t r0 = b0 + CB + (int64_t)ti * CB, q0 = b0 + CB + (int64_t)tj * CB;
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    int k = e / CB, c = e % CB;
+    P[k][c] = (k < nb && r0 + c < N) ? G[(b0 + k) * ld + r0 + c] : 0.0;
+    Qm[k][c] = (k < nb && q0 + c < N) ? G[(b0 + k) * ld + q0 + c] : 0.0;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4] = {};
+  for (int k = 0; k < nb; ++k) {
+    double p[4], qv[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) p[a] = P[k][ty + 16 * a];
+#pragma unroll
+    for (int b = 0; b < 4; ++b) qv[b] = Qm[k][tx + 16 * b];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[a][b] += p[a] * qv[b];
+  }
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) {
+      int64_t i = r0 + ty + 16 * a, j = q0 + tx + 16 * b;
+      if (i < N && j < N && j >= i) G[i * ld + j] -= acc[a][b];
+    }
+}
+
+hipError_t launch_cholesky(double* G, int64_t ld, int64_t N, double tol_ratio, double* d0, int* flags, int* count,
+                           int* nonfinite, const int* run_if, hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_chol_prep, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, G, ld, N, d0, flags, count,
+                     run_if);
+  int nblk = (int)((N + CB - 1) / CB);
+  for (int kb = 0; kb < nblk; ++kb) {
+    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, G, ld, N, kb, tol_ratio, d0, flags, count, nonfinite,
+                       run_if);
+    int nt = nblk - kb - 1;
+    if (nt > 0) {
+      hipLaunchKernelGGL(k_chol_panel, dim3(nt), dim3(64), 0, st, G, ld, N, kb, flags, run_if);
+      hipLaunchKernelGGL(k_chol_update, dim3(nt * (nt + 1) / 2), dim3(256), 0, st, G, ld, N, kb, run_if);
+    }
+  }
+  return hipGetLastError();
+}
+
+// ============================== triangular inverse ==============================
+__global__ void k_zero64(double* p, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0.0;
+}
+
+// X_bb = R_bb^{-1} for every diagonal block; X is N x N with ld N.
+__global__ __launch_bounds__(64) void k_trinv_diag(const double* __restrict__ R, int64_t ld, int64_t N,
+                                                   double* __restrict__ X) {
+  __shared__ double Rs[CB][CB + 1];
+  const int64_t b0 = (int64_t)blockIdx.x * CB;
+  const int nb = (int)min((int64_t)CB, N - b0);
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    int i = e / CB, j = e % CB;
+    Rs[i][j] = (i < nb && j < nb) ? R[(b0 + i) * ld + b0 + j] : 0.0;
+  }
+  __syncthreads();
+  const int j = threadIdx.x;  // column of the inverse
+  if (j >= nb) return;
+  double x[CB];
+#pragma unroll
+  for (int r = CB - 1; r >= 0; --r) {
+    if (r < nb) {
+      double s = (r == j) ? 1.0 : 0.0;
+#pragma unroll
+      for (int c = r + 1; c < CB; ++c)
+        if (c < nb) s -= Rs[r][c] * x[c];
+      x[r] = (r > j) ? 0.0 : s / Rs[r][r];
+    } else {
+      x[r] = 0.0;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < CB; ++r)
+    if (r < nb) X[(b0 + r) * N + b0 + j] = x[r];
+}
+
+// Block diagonal d: X_ij = -X_ii * sum_{l=i+1..j} R_il X_lj, j = i + d.
+__global__ __launch_bounds__(256) void k_trinv_off(const double* __restrict__ R, int64_t ld, int64_t N, int d,
+                                                   double* __restrict__ X) {
+  __shared__ double Ta[CB][CB];
+  __shared__ double Tb[CB][CB];
+  const int ib = blockIdx.x, jb = ib + d;
+  const int64_t i0 = (int64_t)ib * CB, j0 = (int64_t)jb * CB;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double acc[4][4] = {};
+  for (int lb = ib + 1; lb <= jb; ++lb) {
+    const int64_t l0 = (int64_t)lb * CB;
+    __syncthreads();
+    for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+      int r = e / CB, c = e % CB;
+      Ta[r][c] = (i0 + r < N && l0 + c < N) ? R[(i0 + r) * ld + l0 + c] : 0.0;
+      Tb[r][c] = (l0 + r < N && j0 + c < N) ? X[(l0 + r) * N + j0 + c] : 0.0;
+    }
+    __syncthreads();
+    for (int k = 0; k < CB; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = Ta[ty + 16 * u][k];
+#pragma unroll
+      for (int v = 0; v < 4; ++v) b[v] = Tb[k][tx + 16 * v];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+    }
+  }
+  __syncthreads();
+  // T -> Tb, X_ii -> Ta
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) Tb[ty + 16 * u][tx + 16 * v] = acc[u][v];
+  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
+    int r = e / CB, c = e % CB;
+    Ta[r][c] = (i0 + r < N && i0 + c < N) ? X[(i0 + r) * N + i0 + c] : 0.0;
+  }
+  __syncthreads();
+  double o[4][4] = {};
+  for (int k = 0; k < CB; ++k) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = Ta[ty + 16 * u][k];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b[v] = Tb[k][tx + 16 * v];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) o[u][v] += a[u] * b[v];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int64_t r = i0 + ty + 16 * u, c = j0 + tx + 16 * v;
+      if (r < N && c < N) X[r * N + c] = -o[u][v];
+    }
+}
+
+__global__ void k_trinv_out(const double* __restrict__ X, int64_t N, double* out64, int64_t ld64, float* out32,
+                            int64_t ld32) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * N) return;
+  int64_t i = idx / N, j = idx % N;
+  double v = X[idx];
+  if (out64) out64[i * ld64 + j] = v;
+  if (out32) out32[i * ld32 + j] = (float)v;
+}
+
+size_t tri_inverse_work_doubles(int64_t N) { return (size_t)N * N; }
+
+hipError_t launch_tri_inverse(const double* R, int64_t ld, int64_t N, double* out64, int64_t ld64, float* out32,
+                              int64_t ld32, double* work, hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  int64_t tot = N * N;
+  hipLaunchKernelGGL(k_zero64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, work, tot);
+  int nblk = (int)((N + CB - 1) / CB);
+  hipLaunchKernelGGL(k_trinv_diag, dim3(nblk), dim3(64), 0, st, R, ld, N, work);
+  for (int d = 1; d < nblk; ++d)
+    hipLaunchKernelGGL(k_trinv_off, dim3(nblk - d), dim3(256), 0, st, R, ld, N, d, work);
+  hipLaunchKernelGGL(k_trinv_out, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, work, N, out64, ld64, out32,
+                     ld32);
+  return hipGetLastError();
+}
+
+// ============================== block-Jacobi eigensolver ==============================
+// G (K x K, K = 2 p JB, padded with decoupled -1e300 diagonal) is driven to
+// diagonal form by rounds of p independent 64 x 64 subproblems (pairs of 32-wide
+// blocks, round-robin "circle" schedule).  Each subproblem is diagonalised in
+// LDS by cyclic two-sided Jacobi rotations (Golub & Van Loan, sym.schur2) and
+// its rotation V (64 x 64) is applied to the rows/columns of G and to Z in a
+// second kernel, tile by tile, in place.  Converged when every off-diagonal
+// entry is <= tol * sqrt(|G_ii G_jj| + floor^2).
+constexpr int JB = 32, JS = 64;
+
+struct EigWork {
+  double* Gp;      // K x K
+  double* Z;       // K x K
+  double* V;       // p x 64 x 64
+  int* perm;       // K
+  unsigned long long* maxoff;  // 1
+  int* conv;       // 1
+  double* floor2;  // 1
+  int64_t K;
+  int p;
+};
+
+static EigWork eig_layout(void* work, int64_t N) {
+  EigWork w;
+  int64_t K = ((N + 2 * JB - 1) / (2 * JB)) * (2 * JB);
+  if (K < 2 * JB) K = 2 * JB;
+  w.K = K;
+  w.p = (int)(K / (2 * JB));
+  char* p = (char*)work;
+  w.Gp = (double*)p; p += K * K * 8;
+  w.Z = (double*)p; p += K * K * 8;
+  w.V = (double*)p; p += (size_t)w.p * JS * JS * 8;
+  w.perm = (int*)p; p += ((K * 4 + 255) / 256) * 256;
+  w.maxoff = (unsigned long long*)p; p += 256;
+  w.conv = (int*)p; p += 256;
+  w.floor2 = (double*)p; p += 256;
+  return w;
+}
+
+size_t eig_work_bytes(int64_t N) {
+  int64_t K = ((N + 2 * JB - 1) / (2 * JB)) * (2 * JB);
+  if (K < 2 * JB) K = 2 * JB;
+  int64_t p = K / (2 * JB);
+  return (size_t)(2 * K * K * 8 + p * JS * JS * 8 + ((K * 4 + 255) / 256) * 256 + 3 * 256);
+}
+
+RF_DEV int circle(int round, int i, int n) {  // position i of round in an n-player circle schedule
+  return i == 0 ? 0 : 1 + (i - 1 + round) % (n - 1);
+}
+
+__global__ void k_eig_init(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx == 0) {
+    *w.maxoff = 0ull;
+    *w.conv = 0;
+  }
+  if (idx >= w.K * w.K) return;
+  int64_t i = idx / w.K, j = idx % w.K;
+  double v;
+  if (i < N && j < N) v = G[i * ld + j];
+  else v = (i == j) ? -1e300 : 0.0;
+  w.Gp[idx] = v;
+  w.Z[idx] = (i == j) ? 1.0 : 0.0;
+}
+
+__global__ void k_eig_floor(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
+  // floor^2 = (1e-15 * trace|.| / N)^2, single workgroup
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) s += fabs(G[i * ld + i]);
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double f = 1e-15 * red[0] / (double)(N > 0 ? N : 1);
+    *w.floor2 = f * f + 1e-300;
+  }
+}
+
+RF_DEV void jacobi_rot(double app, double aqq, double apq, double floor2, double& c, double& s) {
+  double scale = sqrt(fabs(app) * fabs(aqq) + floor2);
+  if (!(fabs(apq) > 1e-17 * scale)) {
+    c = 1.0;
+    s = 0.0;
+    return;
+  }
+  double tau = (aqq - app) / (2.0 * apq);
+  double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+  c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+}
+
+__global__ __launch_bounds__(256) void k_eig_solve(EigWork w, int round, int inner_sweeps) {
+  if (*w.conv) return;
+  extern __shared__ double sm[];
+  double(*M)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm);
+  double(*V)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm + JS * (JS + 1));
+  __shared__ double cs[JS / 2], sn[JS / 2];
+  __shared__ int pa[JS / 2], pb[JS / 2];
+  __shared__ int done;
+  const int x = blockIdx.x, np = 2 * w.p;
+  const int P = circle(round, x, np), Q = circle(round, np - 1 - x, np);
+  const double floor2 = *w.floor2;
+  auto gidx = [&](int a) -> int64_t { return a < JB ? (int64_t)P * JB + a : (int64_t)Q * JB + (a - JB); };
+  for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
+    int a = e / JS, b = e % JS;
+    M[a][b] = w.Gp[gidx(a) * w.K + gidx(b)];
+    V[a][b] = (a == b) ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int sw = 0; sw < inner_sweeps; ++sw) {
+    if (threadIdx.x == 0) done = 1;
+    __syncthreads();
+    for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
+      int a = e / JS, b = e % JS;
+      if (a < b && fabs(M[a][b]) > 1e-15 * sqrt(fabs(M[a][a]) * fabs(M[b][b]) + floor2)) done = 0;
+    }
+    __syncthreads();
+    if (done) break;
+    for (int rr = 0; rr < JS - 1; ++rr) {
+      if (threadIdx.x < JS / 2) {
+        int u = threadIdx.x;
+        int a = circle(rr, u, JS), b = circle(rr, JS - 1 - u, JS);
+        if (a > b) { int t = a; a = b; b = t; }
+        pa[u] = a;
+        pb[u] = b;
+        double c, s;
+        jacobi_rot(M[a][a], M[b][b], M[a][b], floor2, c, s);
+        cs[u] = c;
+        sn[u] = s;
+      }
+      __syncthreads();
+      // two-sided update of 2x2 blocks (u, v): M' = J_u^T M J_v
+      for (int e = threadIdx.x; e < (JS / 2) * (JS / 2); e += blockDim.x) {
+        int u = e / (JS / 2), v = e % (JS / 2);
+        int a = pa[u], b = pb[u], cc = pa[v], d = pb[v];
+        double cu = cs[u], su = sn[u], cv = cs[v], sv = sn[v];
+        double m00 = M[a][cc], m01 = M[a][d], m10 = M[b][cc], m11 = M[b][d];
+        double t00 = cu * m00 - su * m10, t01 = cu * m01 - su * m11;
+        double t10 = su * m00 + cu * m10, t11 = su * m01 + cu * m11;
+        double r00 = cv * t00 - sv * t01, r01 = sv * t00 + cv * t01;
+        double r10 = cv * t10 - sv * t11, r11 = sv * t10 + cv * t11;
+        if (u == v) { r01 = 0.0; r10 = 0.0; }
+        M[a][cc] = r00; M[a][d] = r01; M[b][cc] = r10; M[b][d] = r11;
+      }
+      for (int e = threadIdx.x; e < JS * (JS / 2); e += blockDim.x) {
+        int row = e / (JS / 2), u = e % (JS / 2);
+        int a = pa[u], b = pb[u];
+        double c = cs[u], s = sn[u];
+        double va = V[row][a], vb = V[row][b];
+        V[row][a] = c * va - s * vb;
+        V[row][b] = s * va + c * vb;
+      }
+      __syncthreads();
+    }
+  }
+  // Order the subproblem's eigenpairs: the larger half goes to the block with the
+  // lower index, so eigenvalues settle in descending order along the diagonal
+  // (speeds up convergence on clustered spectra; the padding sinks to the end).
+  __shared__ int rnk[JS];
+  if (threadIdx.x < JS) {
+    const int a = threadIdx.x;
+    const double d = M[a][a];
+    int r = 0;
+    for (int b = 0; b < JS; ++b) {
+      const double e = M[b][b];
+      r += (e > d || (e == d && b < a)) ? 1 : 0;
+    }
+    rnk[a] = (P < Q) ? r : (r + JB) % JS;
+  }
+  __syncthreads();
+  double* out = w.V + (int64_t)x * JS * JS;
+  for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) out[(e / JS) * JS + rnk[e % JS]] = V[e / JS][e % JS];
+}
+
+// Tiles (x, y): G[I_x, I_y] <- V_x^T G[I_x, I_y] V_y ; tiles for Z: Z[rows, I_x] <- Z[rows, I_x] V_x.
+__global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
+  if (*w.conv) return;
+  extern __shared__ double sm[];
+  double(*T)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm);
+  double(*Va)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm + JS * (JS + 1));
+  double(*Vb)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm + 2 * JS * (JS + 1));
+  const int np = 2 * w.p;
+  const int ntile = w.p * w.p;
+  const int id = blockIdx.x;
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  if (id < ntile) {
+    const int x = id / w.p, y = id % w.p;
+    const int Px = circle(round, x, np), Qx = circle(round, np - 1 - x, np);
+    const int Py = circle(round, y, np), Qy = circle(round, np - 1 - y, np);
+    auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
+    auto iy = [&](int a) -> int64_t { return a < JB ? (int64_t)Py * JB + a : (int64_t)Qy * JB + (a - JB); };
+    const double* vx = w.V + (int64_t)x * JS * JS;
+    const double* vy = w.V + (int64_t)y * JS * JS;
+    for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
+      int a = e / JS, b = e % JS;
+      T[a][b] = w.Gp[ix(a) * w.K + iy(b)];
+      Va[a][b] = vx[e];
+      Vb[a][b] = vy[e];
+    }
+    __syncthreads();
+    double acc[4][4] = {};
+    for (int k = 0; k < JS; ++k) {  // U = T Vy
+      double t[4], v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) t[u] = T[ty + 16 * u][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = Vb[k][tx + 16 * c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[u][c] += t[u] * v[c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) T[ty + 16 * u][tx + 16 * c] = acc[u][c];
+    __syncthreads();
+    double o[4][4] = {};
+    for (int k = 0; k < JS; ++k) {  // Vx^T U
+      double a[4], t[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) a[u] = Va[k][ty + 16 * u];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) t[c] = T[k][tx + 16 * c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) o[u][c] += a[u] * t[c];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        int a = ty + 16 * u, b = tx + 16 * c;
+        w.Gp[ix(a) * w.K + iy(b)] = o[u][c];
+      }
+  } else {
+    const int zid = id - ntile;
+    const int x = zid % w.p, rb = zid / w.p;
+    const int Px = circle(round, x, np), Qx = circle(round, np - 1 - x, np);
+    auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
+    const double* vx = w.V + (int64_t)x * JS * JS;
+    const int64_t r0 = (int64_t)rb * JS;
+    for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
+      int a = e / JS, b = e % JS;
+      T[a][b] = (r0 + a < w.K) ? w.Z[(r0 + a) * w.K + ix(b)] : 0.0;
+      Va[a][b] = vx[e];
+    }
+    __syncthreads();
+    double acc[4][4] = {};
+    for (int k = 0; k < JS; ++k) {
+      double t[4], v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) t[u] = T[ty + 16 * u][k];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) v[c] = Va[k][tx + 16 * c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+#pragma unroll
+        for (int c = 0; c < 4; ++c) acc[u][c] += t[u] * v[c];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        int64_t r = r0 + ty + 16 * u;
+        if (r < w.K) w.Z[r * w.K + ix(tx + 16 * c)] = acc[u][c];
+      }
+  }
+}
+
+__global__ void k_eig_check(EigWork w) {
+  if (*w.conv) return;
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double r = 0.0;
+  if (idx < w.K * w.K) {
+    int64_t i = idx / w.K, j = idx % w.K;
+    if (i != j) {
+      double g = w.Gp[idx];
+      double d = sqrt(fabs(w.Gp[i * w.K + i])) * sqrt(fabs(w.Gp[j * w.K + j]));
+      r = fabs(g) / sqrt(d * d + *w.floor2);
+      if (!(r == r)) r = 1.0;  // NaN: keep iterating (and never claim convergence)
+    }
+  }
+  r = wave_max(r);
+  if ((threadIdx.x & 63) == 0 && r > 0.0) atomicMax(w.maxoff, (unsigned long long)__double_as_longlong(r));
+}
+
+__global__ void k_eig_decide(EigWork w, double tol) {
+  if (*w.conv) return;
+  double m = __longlong_as_double((long long)*w.maxoff);
+  if (m <= tol) *w.conv = 1;
+  *w.maxoff = 0ull;
+}
+
+// Sort diag(Gp) descending (bitonic, one workgroup, K <= 4096), gather outputs.
+__global__ __launch_bounds__(1024) void k_eig_sort(EigWork w, int64_t N, double* lam) {
+  __shared__ double key[4096];
+  __shared__ int idx[4096];
+  int Kp = 1;
+  while (Kp < w.K) Kp <<= 1;
+  for (int i = threadIdx.x; i < Kp; i += blockDim.x) {
+    key[i] = (i < w.K) ? w.Gp[(int64_t)i * w.K + i] : -INFINITY;
+    idx[i] = i;
+  }
+  __syncthreads();
+  for (int size = 2; size <= Kp; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int i = threadIdx.x; i < Kp; i += blockDim.x) {
+        int j = i ^ stride;
+        if (j > i) {
+          bool desc = ((i & size) == 0);
+          double a = key[i], b = key[j];
+          bool sw = desc ? (a < b || (a == b && idx[i] > idx[j])) : (a > b || (a == b && idx[i] < idx[j]));
+          if (sw) {
+            key[i] = b; key[j] = a;
+            int t = idx[i]; idx[i] = idx[j]; idx[j] = t;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    lam[i] = key[i];
+    w.perm[i] = idx[i];
+  }
+}
+
+__global__ void k_eig_gather(EigWork w, int64_t N, double* V, int64_t ldv) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= N * N) return;
+  int64_t r = e / N, c = e % N;
+  V[r * ldv + c] = w.Z[r * w.K + w.perm[c]];
+}
+
+hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
+                      hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  EigWork w = eig_layout(work, N);
+  if (w.K > 4096) return hipErrorInvalidValue;
+  int64_t KK = w.K * w.K;
+  hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, st, G, ld, N, w);
+  hipLaunchKernelGGL(k_eig_floor, dim3(1), dim3(256), 0, st, G, ld, N, w);
+  size_t lds_solve = 2 * JS * (JS + 1) * sizeof(double);
+  size_t lds_apply = 3 * JS * (JS + 1) * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    hipFuncSetAttribute((const void*)k_eig_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_solve);
+    hipFuncSetAttribute((const void*)k_eig_apply, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_apply);
+    attr = true;
+  }
+  const int rounds = 2 * w.p - 1;
+  const int max_sweeps = 20;
+  const int ntile = w.p * w.p + (int)(w.K / JS) * w.p;
+  for (int sw = 0; sw < max_sweeps; ++sw) {
+    for (int r = 0; r < rounds; ++r) {
+      hipLaunchKernelGGL(k_eig_solve, dim3(w.p), dim3(256), lds_solve, st, w, r, sw < 2 ? 2 : 1);
+      hipLaunchKernelGGL(k_eig_apply, dim3(ntile), dim3(256), lds_apply, st, w, r);
+    }
+    hipLaunchKernelGGL(k_eig_check, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, st, w);
+    hipLaunchKernelGGL(k_eig_decide, dim3(1), dim3(1), 0, st, w, 1e-12);
+  }
+  hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, st, w, N, lam);
+  hipLaunchKernelGGL(k_eig_gather, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, w, N, V, ldv);
+  return hipGetLastError();
+}
+
+// ============================== utilities ==============================
+__global__ void k_cast_f32_bf16(const float* __restrict__ in, int64_t ldi, uint16_t* __restrict__ out, int64_t ldo,
+                                int64_t rows, int64_t cols) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  int64_t i = idx / cols, j = idx % cols;
+  out[i * ldo + j] = f32_to_bf16_rne(in[i * ldi + j]);
+}
+__global__ void k_cast_f64_f32(const double* __restrict__ in, int64_t ldi, float* __restrict__ out, int64_t ldo,
+                               int64_t rows, int64_t cols) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  int64_t i = idx / cols, j = idx % cols;
+  out[i * ldo + j] = (float)in[i * ldi + j];
+}
+__global__ void k_copy_f32(const float* __restrict__ in, int64_t ldi, float* __restrict__ out, int64_t ldo,
+                           int64_t rows, int64_t cols) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  int64_t i = idx / cols, j = idx % cols;
+  out[i * ldo + j] = in[i * ldi + j];
+}
+__global__ void k_fill_i32(int* p, int64_t n, int v) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+static inline dim3 g1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
+
+hipError_t launch_cast_f32_bf16(const float* in, int64_t ldi, uint16_t* out, int64_t ldo, int64_t rows, int64_t cols,
+                                hipStream_t st) {
+  if (rows * cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_f32_bf16, g1(rows * cols), dim3(256), 0, st, in, ldi, out, ldo, rows, cols);
+  return hipGetLastError();
+}
+hipError_t launch_cast_f64_f32(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
+                               hipStream_t st) {
+  if (rows * cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_f64_f32, g1(rows * cols), dim3(256), 0, st, in, ldi, out, ldo, rows, cols);
+  return hipGetLastError();
+}
+hipError_t launch_copy_f32(const float* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
+                           hipStream_t st) {
+  if (rows * cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_f32, g1(rows * cols), dim3(256), 0, st, in, ldi, out, ldo, rows, cols);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t st) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32, g1(n), dim3(256), 0, st, p, n, v);
+  return hipGetLastError();
+}
+
+__global__ void k_refill(float* __restrict__ X, int64_t ldx, int64_t rows, int64_t k, const int* __restrict__ flags,
+                         const int* count, const double* __restrict__ d0, uint64_t seed) {
+  if (*count == 0) return;
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * k) return;
+  int64_t i = idx / k, j = idx % k;
+  if (!flags[j]) return;
+  double dm = 0.0;
+  for (int64_t c = 0; c < k; ++c) dm = fmax(dm, d0[c]);
+  double sc = sqrt(dm / (double)rows);
+  if (!(sc > 0.0) || !isfinite(sc)) sc = 1.0 / sqrt((double)rows);
+  // entry (i, j) of a rows x k Gaussian on stream 3
+  int64_t e = i * k + j;
+  u32x4 x = philox((uint64_t)(e >> 2), 3u, 0u, seed);
+  uint32_t w[4] = {x.x, x.y, x.z, x.w};
+  int q = (int)(e & 3);
+  const double s32 = 2.3283064365386963e-10;
+  double ua = ((double)w[(q >> 1) * 2] + 0.5) * s32, ub = ((double)w[(q >> 1) * 2 + 1] + 0.5) * s32;
+  double rad = sqrt(-2.0 * log(ua));
+  double z = (q & 1) ? rad * sin(6.283185307179586 * ub) : rad * cos(6.283185307179586 * ub);
+  X[i * ldx + j] = (float)(z * sc);
+}
+
+hipError_t launch_refill(float* X, int64_t ldx, int64_t rows, int64_t k, const int* flags, const int* count,
+                         const double* d0, uint64_t seed, hipStream_t st) {
+  if (rows * k == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_refill, g1(rows * k), dim3(256), 0, st, X, ldx, rows, k, flags, count, d0, seed);
+  return hipGetLastError();
+}
+
+__global__ void k_sigma(const double* lam, int64_t k, double* sigma, float* inv32) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  double l = lam[i];
+  double s = l > 0.0 ? sqrt(l) : 0.0;
+  if (sigma) sigma[i] = s;
+  if (inv32) inv32[i] = s > 0.0 ? (float)(1.0 / s) : 0.f;
+}
+hipError_t launch_sigma(const double* lam, int64_t k, double* sigma, float* inv32, hipStream_t st) {
+  if (k == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sigma, g1(k), dim3(256), 0, st, lam, k, sigma, inv32);
+  return hipGetLastError();
+}
+
+// key = |u| bits << 32 | (0xffffffff - row): max key = largest |u|, lowest row on ties
+__global__ void k_sign_key(const float* __restrict__ U, int64_t ldu, int64_t m, int64_t k,
+                           unsigned long long* __restrict__ keys, int64_t rows_per) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  int64_t r0 = (int64_t)blockIdx.y * rows_per, r1 = min(m, r0 + rows_per);
+  unsigned long long best = 0ull;
+  for (int64_t r = r0; r < r1; ++r) {
+    float v = fabsf(U[r * ldu + c]);
+    unsigned long long key = ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)r);
+    best = key > best ? key : best;
+  }
+  atomicMax(keys + c, best);
+}
+__global__ void k_sign_decide(const float* __restrict__ U, int64_t ldu, int64_t k,
+                              const unsigned long long* __restrict__ keys, float* __restrict__ sgn) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= k) return;
+  int64_t rr = 0xffffffffll - (int64_t)(keys[c] & 0xffffffffull);
+  sgn[c] = (U[rr * ldu + c] < 0.f) ? -1.f : 1.f;
+}
+__global__ void k_sign_apply(float* __restrict__ U, int64_t ldu, int64_t m, int64_t k, float* __restrict__ Vt,
+                             int64_t ldvt, int64_t n, const float* __restrict__ sgn) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < m * k) {
+    int64_t r = idx / k, c = idx % k;
+    U[r * ldu + c] *= sgn[c];
+  } else if (Vt && idx < m * k + k * n) {
+    int64_t e = idx - m * k;
+    int64_t c = e / n, j = e % n;
+    Vt[c * ldvt + j] *= sgn[c];
+  }
+}
+
+// work: 3 k ints (keys: 2k, signs: k)
+hipError_t launch_sign_fix(float* U, int64_t ldu, int64_t m, int64_t k, float* Vt, int64_t ldvt, int64_t n, int* work,
+                           hipStream_t st) {
+  if (m * k == 0) return hipSuccess;
+  unsigned long long* keys = reinterpret_cast<unsigned long long*>(work);
+  float* sgn = reinterpret_cast<float*>(work + 2 * k);
+  hipLaunchKernelGGL(k_fill_i32, g1(2 * k), dim3(256), 0, st, work, 2 * k, 0);
+  int64_t rows_per = 256;
+  dim3 grid((unsigned)((k + 255) / 256), (unsigned)((m + rows_per - 1) / rows_per));
+  hipLaunchKernelGGL(k_sign_key, grid, dim3(256), 0, st, U, ldu, m, k, keys, rows_per);
+  hipLaunchKernelGGL(k_sign_decide, g1(k), dim3(256), 0, st, U, ldu, k, keys, sgn);
+  int64_t tot = m * k + (Vt ? k * n : 0);
+  hipLaunchKernelGGL(k_sign_apply, g1(tot), dim3(256), 0, st, U, ldu, m, k, Vt, ldvt, n, sgn);
+  return hipGetLastError();
+}
+
+__global__ void k_note_first(int* counters) {
+  // after the first factorisation of a pass: remember whether a refill happened
+  int c = counters[0];
+  counters[4] = c > 0 ? 1 : 0;
+  if (c > 0) counters[1] += 1;
+}
+__global__ void k_note_final(int* counters) { counters[3] = counters[0]; }
+hipError_t launch_note(int* counters, int final_, hipStream_t st) {
+  if (final_) hipLaunchKernelGGL(k_note_final, dim3(1), dim3(1), 0, st, counters);
+  else hipLaunchKernelGGL(k_note_first, dim3(1), dim3(1), 0, st, counters);
+  return hipGetLastError();
+}
+
+__global__ void k_nystrom_scale(const double* lam, int64_t k, float* scale) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k) return;
+  double lmax = lam[0] > 0.0 ? lam[0] : 0.0;
+  double cut = (double)k * 2.220446049250313e-16 * lmax;
+  double l = lam[i];
+  scale[i] = (l > cut && l > 0.0) ? (float)(1.0 / sqrt(l)) : 0.f;
+}
+hipError_t launch_nystrom_scale(const double* lam, int64_t k, float* scale, hipStream_t st) {
+  if (k == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_nystrom_scale, g1(k), dim3(256), 0, st, lam, k, scale);
+  return hipGetLastError();
+}
+
+struct InfoOut {
+  int32_t status, rank_found, chol_retries, nonfinite;
+  double orth_err;
+};
+__global__ void k_info(InfoOut* info, const int* counters, int k, const double* orth) {
+  int retries = counters[1], nonf = counters[2], last = counters[3];
+  info->status = (retries > 0 ? 1 : 0) | (nonf ? 2 : 0);
+  info->rank_found = k - last;
+  info->chol_retries = retries;
+  info->nonfinite = nonf;
+  info->orth_err = orth ? *orth : -1.0;
+}
+hipError_t launch_info(void* info, const int* counters, int k, const double* orth, hipStream_t st) {
+  if (!info) return hipSuccess;
+  hipLaunchKernelGGL(k_info, dim3(1), dim3(1), 0, st, (InfoOut*)info, counters, k, orth);
+  return hipGetLastError();
+}
+
+__global__ void k_orth_err(const double* __restrict__ G, int64_t ld, int64_t N, unsigned long long* out) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double r = 0.0;
+  if (idx < N * N) {
+    int64_t i = idx / N, j = idx % N;
+    r = fabs(G[i * ld + j] - (i == j ? 1.0 : 0.0));
+    if (!(r == r)) r = INFINITY;
+  }
+  r = wave_max(r);
+  if ((threadIdx.x & 63) == 0 && r > 0.0) atomicMax(out, (unsigned long long)__double_as_longlong(r));
+}
+hipError_t launch_orth_err(const double* G, int64_t ld, int64_t N, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(256), 0, st, (int*)out, 2, 0);
+  if (N == 0) return hipGetLastError();
+  hipLaunchKernelGGL(k_orth_err, g1(N * N), dim3(256), 0, st, G, ld, N, (unsigned long long*)out);
+  return hipGetLastError();
+}
+
+__global__ void k_symmetrize(float* X, int64_t ld, int64_t N) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * N) return;
+  int64_t i = idx / N, j = idx % N;
+  if (i < j) {
+    float a = X[i * ld + j], b = X[j * ld + i];
+    float m = 0.5f * (a + b);
+    X[i * ld + j] = m;
+    X[j * ld + i] = m;
+  }
+}
+hipError_t launch_symmetrize(float* X, int64_t ld, int64_t N, hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_symmetrize, g1(N * N), dim3(256), 0, st, X, ld, N);
+  return hipGetLastError();
+}
+
+__global__ void k_symmetrize64(double* X, int64_t ld, int64_t N) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * N) return;
+  int64_t i = idx / N, j = idx % N;
+  if (i < j) {
+    double m = 0.5 * (X[i * ld + j] + X[j * ld + i]);
+    X[i * ld + j] = m;
+    X[j * ld + i] = m;
+  }
+}
+hipError_t launch_symmetrize64(double* X, int64_t ld, int64_t N, hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_symmetrize64, g1(N * N), dim3(256), 0, st, X, ld, N);
+  return hipGetLastError();
+}
+__global__ void k_copy_f64(const double* __restrict__ in, int64_t ldi, double* __restrict__ out, int64_t ldo,
+                           int64_t rows, int64_t cols) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  int64_t i = idx / cols, j = idx % cols;
+  out[i * ldo + j] = in[i * ldi + j];
+}
+hipError_t launch_copy_f64(const double* in, int64_t ldi, double* out, int64_t ldo, int64_t rows, int64_t cols,
+                           hipStream_t st) {
+  if (rows * cols == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_copy_f64, g1(rows * cols), dim3(256), 0, st, in, ldi, out, ldo, rows, cols);
+  return hipGetLastError();
+}
+
+}  // namespace rf

@@ -1,0 +1,541 @@
+// C ABI of the range finder: argument checks, workspace carving and the
+// stream-ordered schedule of kernels for Algorithms 1-3 and the randomised
+// SVD finisher.  No allocation, no synchronisation, no host round trips.
+#include <math.h>
+#include <string.h>
+
+#include "../../include/rf.h"
+#include "common.h"
+#include "kernels.h"
+
+using namespace rf;
+
+namespace {
+
+// ------------------------------------------------------------------ workspace
+struct Arena {
+  char* base;
+  size_t off = 0;
+  explicit Arena(void* b) : base((char*)b) {}
+  template <typename T>
+  T* get(size_t count) {
+    size_t bytes = ((count * sizeof(T)) + 255) / 256 * 256;
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+struct Dims {
+  int64_t m, n;
+  int k, r1, s, q;
+  int dtype, prec;
+};
+
+struct RFBufs {
+  int32_t* table; uint32_t* ready;
+  float* om; uint16_t* om16;
+  float* At; uint16_t* At16;
+  float* Ya; float* Yb; uint16_t* Q16;
+  float* Zh; float* Z; uint16_t* Z16;
+  double* G; double* d0; int* flags; int* counters; float* Rinv; double* triwork;
+  double* gpart; float* mpart; double* orth;
+};
+
+static size_t max3(size_t a, size_t b, size_t c) { return a > b ? (a > c ? a : c) : (b > c ? b : c); }
+
+// Buffers of Algorithm 1 (shared by every op).
+static RFBufs carve_rf(Arena& ar, const Dims& d) {
+  RFBufs b;
+  const bool mixed = d.prec == RF_PREC_MIXED;
+  b.table = ar.get<int32_t>((size_t)d.n * d.s);
+  b.ready = ar.get<uint32_t>((size_t)d.n * d.s);
+  b.om = ar.get<float>((size_t)d.r1 * d.k);
+  b.om16 = mixed ? ar.get<uint16_t>((size_t)d.r1 * d.k) : nullptr;
+  b.At = ar.get<float>((size_t)d.m * d.r1);
+  b.At16 = mixed ? ar.get<uint16_t>((size_t)d.m * d.r1) : nullptr;
+  b.Ya = ar.get<float>((size_t)d.m * d.k);
+  b.Yb = ar.get<float>((size_t)d.m * d.k);
+  b.Q16 = mixed ? ar.get<uint16_t>((size_t)d.m * d.k) : nullptr;
+  b.Zh = ar.get<float>((size_t)d.r1 * d.k);
+  b.Z = ar.get<float>((size_t)d.r1 * d.k);
+  b.Z16 = mixed ? ar.get<uint16_t>((size_t)d.r1 * d.k) : nullptr;
+  b.G = ar.get<double>((size_t)d.k * d.k);
+  b.d0 = ar.get<double>((size_t)d.k);
+  b.flags = ar.get<int>((size_t)d.k);
+  b.counters = ar.get<int>(16);
+  b.Rinv = ar.get<float>((size_t)d.k * d.k);
+  b.triwork = ar.get<double>(tri_inverse_work_doubles(d.k));
+  b.gpart = ar.get<double>(gram_partial_doubles(d.m > d.r1 ? d.m : d.r1, d.k, d.k));
+  b.mpart = ar.get<float>(gemm_partial_floats(d.r1, d.k, d.m));
+  b.orth = ar.get<double>(2);
+  return b;
+}
+
+struct Ctx {
+  hipStream_t st;
+  hipError_t err = hipSuccess;
+  void chk(hipError_t e) {
+    if (e != hipSuccess && err == hipSuccess) err = e;
+  }
+};
+
+static void gemm(Ctx& c, int dtype, const void* A, int64_t lda, int a_kc, const void* B, int64_t ldb, int b_kc, void* C,
+                 int64_t ldc, int64_t M, int64_t N, int64_t K, float* partial, const float* colscale = nullptr,
+                 int c_trans = 0, int b_upper = 0, int c_bf16 = 0) {
+  GemmArgs g;
+  memset(&g, 0, sizeof(g));
+  g.A = A; g.lda = lda; g.a_kc = a_kc;
+  g.B = B; g.ldb = ldb; g.b_kc = b_kc;
+  g.C = C; g.ldc = ldc; g.c_trans = c_trans; g.c_bf16 = c_bf16;
+  g.M = M; g.N = N; g.K = K;
+  g.alpha = 1.f;
+  g.colscale = colscale;
+  g.b_upper = b_upper;
+  c.chk(launch_gemm(g, dtype, partial, c.st));
+}
+
+// Tolerance on Cholesky pivots relative to the original diagonal: a column whose
+// residual is below ~4 sqrt(k) FP32 ulps of its norm is numerically dependent.
+static double chol_tol(int k) {
+  const double u = 5.9604644775390625e-08;  // 2^-24
+  return 16.0 * (double)k * u * u;
+}
+
+// One CholeskyQR pass: out = X R^{-1}, X^T X = R^T R.  Dependent columns of X are
+// replaced (stream-3 Gaussians) and the factorisation repeated.
+static void cholqr_pass(Ctx& c, RFBufs& b, float* X, float* out, int64_t rows, int k, uint64_t seed) {
+  c.chk(launch_gram(X, k, 0, X, k, 0, rows, k, k, 1, b.G, k, b.gpart, nullptr, c.st));
+  c.chk(launch_cholesky(b.G, k, k, chol_tol(k), b.d0, b.flags, &b.counters[0], &b.counters[2], nullptr, c.st));
+  c.chk(launch_note(b.counters, 0, c.st));
+  c.chk(launch_refill(X, k, rows, k, b.flags, &b.counters[4], b.d0, seed, c.st));
+  c.chk(launch_gram(X, k, 0, X, k, 0, rows, k, k, 1, b.G, k, b.gpart, &b.counters[4], c.st));
+  c.chk(launch_cholesky(b.G, k, k, chol_tol(k), b.d0, b.flags, &b.counters[0], &b.counters[2], &b.counters[4], c.st));
+  c.chk(launch_note(b.counters, 1, c.st));
+  c.chk(launch_tri_inverse(b.G, k, k, nullptr, 0, b.Rinv, k, b.triwork, c.st));
+  gemm(c, 0, X, k, 1, b.Rinv, k, 0, out, k, rows, k, k, nullptr, nullptr, 0, 1);
+}
+
+// Algorithm 1.  Result (m x k FP32, ld k) in `Qout`; b.Ya/b.Yb are used as scratch.
+static void range_finder_core(Ctx& c, const rf_matrix* A, const Dims& d, uint64_t seed, RFBufs& b, float* Qout,
+                              const int32_t* table_in = nullptr, const float* om_in = nullptr) {
+  const bool mixed = d.prec == RF_PREC_MIXED;
+  const int k = d.k, r1 = d.r1;
+  c.chk(launch_fill_i32(b.counters, 16, 0, c.st));
+  const int32_t* table = table_in;
+  if (!table) {
+    c.chk(launch_sketch_table(d.n, d.s, r1, seed, 0, 0, b.table, c.st));
+    table = b.table;
+  }
+  const bool fast = sketch_right_fast_ok(d.s);
+  if (fast) c.chk(launch_sketch_ready(table, d.n, d.s, r1, sketch_right_cpl(d.s), b.ready, c.st));
+  const float* om = om_in;
+  if (!om) {
+    c.chk(launch_gaussian(r1, k, seed, 1, 0, b.om, k, c.st));
+    om = b.om;
+  }
+  // At = A S  (one pass over A)
+  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, table, fast ? b.ready : nullptr, d.s, d.m, d.n,
+                            r1, b.At, r1, c.st));
+  if (mixed) {
+    c.chk(launch_cast_f32_bf16(b.At, r1, b.At16, r1, d.m, r1, c.st));
+    c.chk(launch_cast_f32_bf16(om, k, b.om16, k, r1, k, c.st));
+  }
+  // Y0 = At Omega
+  if (mixed && d.q > 0) gemm(c, 2, b.At16, r1, 1, b.om16, k, 0, b.Ya, k, d.m, k, r1, nullptr);
+  else gemm(c, 0, b.At, r1, 1, om, k, 0, b.Ya, k, d.m, k, r1, nullptr);
+  if (d.q == 0) {
+    cholqr_pass(c, b, b.Ya, b.Yb, d.m, k, seed);
+    cholqr_pass(c, b, b.Yb, Qout, d.m, k, seed);
+    return;
+  }
+  float* Qc = b.Yb;
+  cholqr_pass(c, b, b.Ya, Qc, d.m, k, seed);
+  for (int j = 1; j <= d.q; ++j) {
+    // Zh = At^T Q  (contraction over m, split-K)
+    if (mixed) {
+      c.chk(launch_cast_f32_bf16(Qc, k, b.Q16, k, d.m, k, c.st));
+      gemm(c, 2, b.At16, r1, 0, b.Q16, k, 0, b.Zh, k, r1, k, d.m, b.mpart);
+    } else {
+      gemm(c, 0, b.At, r1, 0, Qc, k, 0, b.Zh, k, r1, k, d.m, b.mpart);
+    }
+    cholqr_pass(c, b, b.Zh, b.Z, r1, k, seed);
+    // Y = At Z; the last product is taken in FP32 in both forms
+    const bool last = (j == d.q);
+    if (mixed && !last) {
+      c.chk(launch_cast_f32_bf16(b.Z, k, b.Z16, k, r1, k, c.st));
+      gemm(c, 2, b.At16, r1, 1, b.Z16, k, 0, b.Ya, k, d.m, k, r1, nullptr);
+    } else {
+      gemm(c, 0, b.At, r1, 1, b.Z, k, 0, b.Ya, k, d.m, k, r1, nullptr);
+    }
+    if (last) {
+      cholqr_pass(c, b, b.Ya, b.Yb, d.m, k, seed);
+      cholqr_pass(c, b, b.Yb, Qout, d.m, k, seed);
+    } else {
+      cholqr_pass(c, b, b.Ya, Qc, d.m, k, seed);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ validation
+static bool valid_matrix(const rf_matrix* A) {
+  if (!A || !A->data || A->rows < 1 || A->cols < 1 || A->ld < A->cols || A->reserved != 0) return false;
+  if (A->dtype != RF_F32 && A->dtype != RF_BF16 && A->dtype != RF_FP8E4M3_B128) return false;
+  if ((A->dtype == RF_FP8E4M3_B128) != (A->block_scales != nullptr)) return false;
+  return true;
+}
+
+static bool valid_params(const rf_matrix* A, const rf_params* p, bool square) {
+  if (!p) return false;
+  int64_t mn = A->rows < A->cols ? A->rows : A->cols;
+  if (square) {
+    if (A->rows != A->cols) return false;
+    mn = A->cols;
+  }
+  if (p->k < 1 || p->sketch < p->k || p->sketch > mn) return false;
+  if (p->q < 0 || p->q > 1000) return false;
+  if (p->nnz_per_col < 1 || p->nnz_per_col > p->sketch) return false;
+  if (p->precision != RF_PREC_FP32 && p->precision != RF_PREC_MIXED) return false;
+  return true;
+}
+
+static Dims dims_of(const rf_matrix* A, const rf_params* p) {
+  Dims d;
+  d.m = A->rows; d.n = A->cols;
+  d.k = p->k; d.r1 = p->sketch; d.s = p->nnz_per_col; d.q = p->q;
+  d.dtype = A->dtype; d.prec = p->precision;
+  return d;
+}
+
+struct SvdBufs {
+  float* Q; float* Bt; double* GB; double* lam; double* Ub; float* Ub32; float* inv; void* eigw; int* signw;
+};
+static SvdBufs carve_svd(Arena& ar, const Dims& d) {
+  SvdBufs s;
+  s.Q = ar.get<float>((size_t)d.m * d.k);
+  s.Bt = ar.get<float>((size_t)d.n * d.k);
+  s.GB = ar.get<double>((size_t)d.k * d.k);
+  s.lam = ar.get<double>(d.k);
+  s.Ub = ar.get<double>((size_t)d.k * d.k);
+  s.Ub32 = ar.get<float>((size_t)d.k * d.k);
+  s.inv = ar.get<float>(d.k);
+  s.eigw = ar.get<char>(eig_work_bytes(d.k));
+  s.signw = ar.get<int>(3 * (size_t)d.k);
+  return s;
+}
+static double* carve_gpart_big(Arena& ar, const Dims& d) {
+  return ar.get<double>(gram_partial_doubles(d.n, d.k, d.k));
+}
+
+struct LrBufs {
+  float* Q; int32_t* table2; float* P; float* T; float* W; float* X1; float* lpart;
+};
+static LrBufs carve_lr(Arena& ar, const Dims& d) {
+  LrBufs l;
+  l.Q = ar.get<float>((size_t)d.m * d.k);
+  l.table2 = ar.get<int32_t>((size_t)d.m * d.s);
+  l.P = ar.get<float>((size_t)d.r1 * d.k);
+  l.T = ar.get<float>((size_t)d.r1 * d.n);
+  l.W = ar.get<float>((size_t)d.k * d.n);
+  l.X1 = ar.get<float>((size_t)d.k * d.n);
+  size_t lp = sketch_left_partial_floats(d.m, d.n, d.r1);
+  size_t lp2 = sketch_left_partial_floats(d.m, d.k, d.r1);
+  l.lpart = ar.get<float>(lp > lp2 ? lp : lp2);
+  return l;
+}
+
+struct NyBufs {
+  float* Wt; float* Yc; float* Yn; float* T1; double* W64; double* lam; double* V; float* V32; float* scale;
+  void* eigw; float* lpart; float* Cbuf;
+};
+static NyBufs carve_ny(Arena& ar, const Dims& d) {
+  NyBufs y;
+  y.Wt = ar.get<float>((size_t)d.r1 * d.r1);
+  y.Yc = ar.get<float>((size_t)d.r1 * d.k);
+  y.Yn = ar.get<float>((size_t)d.r1 * d.k);
+  y.T1 = ar.get<float>((size_t)d.r1 * d.k);
+  y.W64 = ar.get<double>((size_t)d.k * d.k);
+  y.lam = ar.get<double>(d.k);
+  y.V = ar.get<double>((size_t)d.k * d.k);
+  y.V32 = ar.get<float>((size_t)d.k * d.k);
+  y.scale = ar.get<float>(d.k);
+  y.eigw = ar.get<char>(eig_work_bytes(d.k));
+  y.lpart = ar.get<float>(sketch_left_partial_floats(d.n, d.r1, d.r1));
+  y.Cbuf = ar.get<float>((size_t)d.n * d.k);
+  return y;
+}
+
+static size_t ws_size(int op, const Dims& d) {
+  Arena ar(nullptr);
+  carve_rf(ar, d);
+  if (op == RF_OP_SVD) {
+    carve_svd(ar, d);
+    carve_gpart_big(ar, d);
+  } else if (op == RF_OP_LOWRANK) {
+    carve_lr(ar, d);
+  } else if (op == RF_OP_NYSTROM) {
+    carve_ny(ar, d);
+  } else {
+    ar.get<float>((size_t)d.m * d.k);
+  }
+  return ar.off + 256;
+}
+
+static rf_status finish(Ctx& c) { return c.err == hipSuccess ? RF_OK : RF_EHIP; }
+
+static void* align_ws(void* ws) { return (void*)(((uintptr_t)ws + 255) / 256 * 256); }
+
+}  // namespace
+
+extern "C" {
+
+const char* rf_status_string(rf_status s) {
+  switch (s) {
+    case RF_OK: return "ok";
+    case RF_EINVAL: return "invalid argument";
+    case RF_EWORKSPACE: return "workspace too small";
+    case RF_EUNSUPPORTED: return "unsupported";
+    case RF_EHIP: return "HIP launch error";
+  }
+  return "unknown status";
+}
+
+size_t rf_sketch_apply_ws(const rf_matrix* A, const rf_params* p) {
+  if (!valid_matrix(A) || !p || p->sketch < 1 || p->nnz_per_col < 1 || p->nnz_per_col > p->sketch) return 0;
+  Dims d = dims_of(A, p);
+  d.k = 1;
+  return ws_size(RF_OP_RANGE_FINDER, d);
+}
+
+size_t rf_workspace_size(int op, const rf_matrix* A, const rf_params* p) {
+  if (op < RF_OP_RANGE_FINDER || op > RF_OP_NYSTROM) return 0;
+  if (!valid_matrix(A) || !valid_params(A, p, op == RF_OP_NYSTROM)) return 0;
+  return ws_size(op, dims_of(A, p));
+}
+
+rf_status rf_sketch_table(int64_t n, int32_t s, int32_t r1, uint64_t seed, uint32_t stream_id, uint32_t b,
+                          int32_t* out, void* stream) {
+  if (n < 0 || s < 1 || r1 < s || (!out && n > 0)) return RF_EINVAL;
+  return launch_sketch_table(n, s, r1, seed, stream_id, b, out, (hipStream_t)stream) == hipSuccess ? RF_OK : RF_EHIP;
+}
+
+rf_status rf_gaussian(int64_t rows, int64_t cols, uint64_t seed, uint32_t stream_id, uint32_t b, float* out,
+                      void* stream) {
+  if (rows < 0 || cols < 0 || (!out && rows * cols > 0)) return RF_EINVAL;
+  return launch_gaussian(rows, cols, seed, stream_id, b, out, cols, (hipStream_t)stream) == hipSuccess ? RF_OK
+                                                                                                        : RF_EHIP;
+}
+
+rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, int64_t ldo, void* ws, size_t ws_bytes,
+                          void* stream) {
+  // the sketch itself needs only 1 <= s <= r1 (any r1, any shape of A)
+  if (!valid_matrix(A) || !p || p->sketch < 1 || p->nnz_per_col < 1 || p->nnz_per_col > p->sketch || !out ||
+      ldo < p->sketch)
+    return RF_EINVAL;
+  Dims d = dims_of(A, p);
+  d.k = 1;
+  size_t need = ws_size(RF_OP_RANGE_FINDER, d);
+  if (!ws || ws_bytes < need) return RF_EWORKSPACE;
+  Arena ar(align_ws(ws));
+  RFBufs b = carve_rf(ar, d);
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  c.chk(launch_sketch_table(d.n, d.s, d.r1, p->seed, 0, 0, b.table, c.st));
+  const bool fast = sketch_right_fast_ok(d.s);
+  if (fast) c.chk(launch_sketch_ready(b.table, d.n, d.s, d.r1, sketch_right_cpl(d.s), b.ready, c.st));
+  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, b.table, fast ? b.ready : nullptr, d.s, d.m,
+                            d.n, d.r1, out, ldo, c.st));
+  return finish(c);
+}
+
+rf_status rf_range_finder(const rf_matrix* A, const rf_params* p, float* Q, int64_t ldq, void* ws, size_t ws_bytes,
+                          rf_info* info, void* stream) {
+  if (!valid_matrix(A) || !valid_params(A, p, false) || !Q || ldq < p->k) return RF_EINVAL;
+  Dims d = dims_of(A, p);
+  if (!ws || ws_bytes < ws_size(RF_OP_RANGE_FINDER, d)) return RF_EWORKSPACE;
+  Arena ar(align_ws(ws));
+  RFBufs b = carve_rf(ar, d);
+  float* Qw = ar.get<float>((size_t)d.m * d.k);
+  if (ldq == d.k) Qw = Q;
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  range_finder_core(c, A, d, p->seed, b, Qw, nullptr, nullptr);
+  if (p->flags & RF_FLAG_ORTH_ERR) {
+    c.chk(launch_gram(Qw, d.k, 0, Qw, d.k, 0, d.m, d.k, d.k, 1, b.G, d.k, b.gpart, nullptr, c.st));
+    c.chk(launch_orth_err(b.G, d.k, d.k, b.orth, c.st));
+  }
+  if (Qw != Q) c.chk(launch_copy_f32(Qw, d.k, Q, ldq, d.m, d.k, c.st));
+  c.chk(launch_info(info, b.counters, d.k, (p->flags & RF_FLAG_ORTH_ERR) ? b.orth : nullptr, c.st));
+  return finish(c);
+}
+
+rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, double* sigma, float* Vt, int64_t ldvt,
+                 void* ws, size_t ws_bytes, rf_info* info, void* stream) {
+  if (!valid_matrix(A) || !valid_params(A, p, false) || !U || !sigma || !Vt || ldu < p->k || ldvt < A->cols)
+    return RF_EINVAL;
+  if (A->dtype == RF_FP8E4M3_B128 || p->k > 4096) return RF_EUNSUPPORTED;
+  Dims d = dims_of(A, p);
+  if (!ws || ws_bytes < ws_size(RF_OP_SVD, d)) return RF_EWORKSPACE;
+  Arena ar(align_ws(ws));
+  RFBufs b = carve_rf(ar, d);
+  SvdBufs s = carve_svd(ar, d);
+  double* gbig = carve_gpart_big(ar, d);
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  const int k = d.k;
+  range_finder_core(c, A, d, p->seed, b, s.Q, nullptr, nullptr);
+  if (p->flags & RF_FLAG_ORTH_ERR) {
+    c.chk(launch_gram(s.Q, k, 0, s.Q, k, 0, d.m, k, k, 1, b.G, k, b.gpart, nullptr, c.st));
+    c.chk(launch_orth_err(b.G, k, k, b.orth, c.st));
+  }
+  // B^T = A^T Q (n x k): the one extra pass over A of the randomised SVD
+  if (A->dtype == RF_BF16) {
+    c.chk(launch_cast_f32_bf16(s.Q, k, b.Q16 ? b.Q16 : (uint16_t*)b.Ya, k, d.m, k, c.st));
+    gemm(c, 2, A->data, A->ld, 0, b.Q16 ? b.Q16 : (uint16_t*)b.Ya, k, 0, s.Bt, k, d.n, k, d.m, nullptr);
+  } else {
+    gemm(c, 0, A->data, A->ld, 0, s.Q, k, 0, s.Bt, k, d.n, k, d.m, nullptr);
+  }
+  // Ritz: B B^T = Ub diag(lam) Ub^T in FP64
+  c.chk(launch_gram(s.Bt, k, 0, s.Bt, k, 0, d.n, k, k, 1, s.GB, k, gbig, nullptr, c.st));
+  c.chk(launch_eig(s.GB, k, k, s.lam, s.Ub, k, s.eigw, c.st));
+  c.chk(launch_sigma(s.lam, k, sigma, s.inv, c.st));
+  c.chk(launch_cast_f64_f32(s.Ub, k, s.Ub32, k, k, k, c.st));
+  // U = Q Ub ; V = B^T Ub Sigma^{-1} stored transposed as Vt
+  gemm(c, 0, s.Q, k, 1, s.Ub32, k, 0, U, ldu, d.m, k, k, nullptr);
+  gemm(c, 0, s.Bt, k, 1, s.Ub32, k, 0, Vt, ldvt, d.n, k, k, nullptr, s.inv, 1);
+  c.chk(launch_sign_fix(U, ldu, d.m, k, Vt, ldvt, d.n, s.signw, c.st));
+  c.chk(launch_info(info, b.counters, k, (p->flags & RF_FLAG_ORTH_ERR) ? b.orth : nullptr, c.st));
+  return finish(c);
+}
+
+rf_status rf_lowrank(const rf_matrix* A, const rf_params* p, float* Y, int64_t ldy, float* X, int64_t ldx, void* ws,
+                     size_t ws_bytes, rf_info* info, void* stream) {
+  if (!valid_matrix(A) || !valid_params(A, p, false) || !Y || !X || ldy < p->k || ldx < A->cols) return RF_EINVAL;
+  if (A->dtype == RF_FP8E4M3_B128) return RF_EUNSUPPORTED;
+  Dims d = dims_of(A, p);
+  if (!ws || ws_bytes < ws_size(RF_OP_LOWRANK, d)) return RF_EWORKSPACE;
+  Arena ar(align_ws(ws));
+  RFBufs b = carve_rf(ar, d);
+  LrBufs l = carve_lr(ar, d);
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  const int k = d.k, r1 = d.r1;
+  range_finder_core(c, A, d, p->seed, b, l.Q, nullptr, nullptr);
+  // S2 (m x r1, stream 2): P = S2^T Q (r1 x k), T = S2^T A (r1 x n, second pass over A)
+  c.chk(launch_sketch_table(d.m, d.s, r1, p->seed, 2, 0, l.table2, c.st));
+  c.chk(launch_sketch_left(0, l.Q, k, l.table2, d.s, d.m, k, r1, l.P, k, l.lpart, c.st));
+  c.chk(launch_sketch_left(A->dtype, A->data, A->ld, l.table2, d.s, d.m, d.n, r1, l.T, d.n, l.lpart, c.st));
+  // X = (P^T P)^{-1} P^T T with P^T P = R^T R (FP64):  X = Rinv (Rinv^T (P^T T))
+  c.chk(launch_gram(l.P, k, 0, l.P, k, 0, r1, k, k, 1, b.G, k, b.gpart, nullptr, c.st));
+  c.chk(launch_cholesky(b.G, k, k, chol_tol(k), b.d0, b.flags, &b.counters[0], &b.counters[2], nullptr, c.st));
+  c.chk(launch_tri_inverse(b.G, k, k, nullptr, 0, b.Rinv, k, b.triwork, c.st));
+  gemm(c, 0, l.P, k, 0, l.T, d.n, 0, l.W, d.n, k, d.n, r1, nullptr);          // W = P^T T
+  gemm(c, 0, b.Rinv, k, 0, l.W, d.n, 0, l.X1, d.n, k, d.n, k, nullptr);       // X1 = Rinv^T W
+  gemm(c, 0, b.Rinv, k, 1, l.X1, d.n, 0, X, ldx, k, d.n, k, nullptr);         // X = Rinv X1
+  c.chk(launch_copy_f32(l.Q, k, Y, ldy, d.m, k, c.st));
+  c.chk(launch_info(info, b.counters, k, nullptr, c.st));
+  return finish(c);
+}
+
+rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t ldc, double* W, int64_t ldw, float* F,
+                     int64_t ldf, void* ws, size_t ws_bytes, rf_info* info, void* stream) {
+  if (!valid_matrix(A) || !valid_params(A, p, true) || !C || !W || ldc < p->k || ldw < p->k || (F && ldf < p->k))
+    return RF_EINVAL;
+  if (F && p->k > 4096) return RF_EUNSUPPORTED;
+  Dims d = dims_of(A, p);
+  if (!ws || ws_bytes < ws_size(RF_OP_NYSTROM, d)) return RF_EWORKSPACE;
+  Arena ar(align_ws(ws));
+  RFBufs b = carve_rf(ar, d);
+  NyBufs y = carve_ny(ar, d);
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  const int k = d.k, r1 = d.r1;
+  const int64_t n = d.n;
+  c.chk(launch_fill_i32(b.counters, 16, 0, c.st));
+  // Ct = A S (n x r1), Wt = S^T Ct (r1 x r1), symmetrised
+  c.chk(launch_sketch_table(n, d.s, r1, p->seed, 0, 0, b.table, c.st));
+  const bool fast = sketch_right_fast_ok(d.s);
+  if (fast) c.chk(launch_sketch_ready(b.table, n, d.s, r1, sketch_right_cpl(d.s), b.ready, c.st));
+  c.chk(launch_gaussian(r1, k, p->seed, 1, 0, b.om, k, c.st));
+  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, b.table, fast ? b.ready : nullptr, d.s, n, n,
+                            r1, b.At, r1, c.st));
+  c.chk(launch_sketch_left(0, b.At, r1, b.table, d.s, n, r1, r1, y.Wt, r1, y.lpart, c.st));
+  c.chk(launch_symmetrize(y.Wt, r1, r1, c.st));
+  // Y = Wt^q Omega, re-orthonormalised after every product
+  c.chk(launch_copy_f32(b.om, k, y.Yc, k, r1, k, c.st));
+  for (int j = 0; j < d.q; ++j) {
+    gemm(c, 0, y.Wt, r1, 1, y.Yc, k, 0, y.T1, k, r1, k, r1, nullptr);
+    cholqr_pass(c, b, y.T1, y.Yn, r1, k, p->seed);
+    float* t = y.Yc; y.Yc = y.Yn; y.Yn = t;
+  }
+  // C = Ct Y (n x k) ; W = Y^T (Wt Y) in FP64
+  gemm(c, 0, b.At, r1, 1, y.Yc, k, 0, y.Cbuf, k, n, k, r1, nullptr);
+  gemm(c, 0, y.Wt, r1, 1, y.Yc, k, 0, y.T1, k, r1, k, r1, nullptr);
+  c.chk(launch_gram(y.Yc, k, 0, y.T1, k, 0, r1, k, k, 0, y.W64, k, b.gpart, nullptr, c.st));
+  c.chk(launch_copy_f32(y.Cbuf, k, C, ldc, n, k, c.st));
+  // W to the caller, symmetrised (Y^T Wt Y is symmetric up to rounding)
+  c.chk(launch_symmetrize64(y.W64, k, k, c.st));
+  c.chk(launch_copy_f64(y.W64, k, W, ldw, k, k, c.st));
+  if (F) {
+    c.chk(launch_eig(y.W64, k, k, y.lam, y.V, k, y.eigw, c.st));
+    c.chk(launch_nystrom_scale(y.lam, k, y.scale, c.st));
+    c.chk(launch_cast_f64_f32(y.V, k, y.V32, k, k, k, c.st));
+    gemm(c, 0, y.Cbuf, k, 1, y.V32, k, 0, F, ldf, n, k, k, nullptr, y.scale, 0);
+  }
+  c.chk(launch_info(info, b.counters, k, nullptr, c.st));
+  return finish(c);
+}
+
+// ------------------------------------------------------------------ parity hooks
+size_t rf_test_gemm_ws(int64_t M, int64_t N, int64_t K) { return gemm_partial_floats(M, N, K) * sizeof(float) + 256; }
+
+rf_status rf_test_gemm(int dtype, int a_kc, int b_kc, const void* A, int64_t lda, const void* B, int64_t ldb, float* C,
+                       int64_t ldc, int64_t M, int64_t N, int64_t K, int b_upper, void* ws, void* stream) {
+  if ((dtype != 0 && dtype != 2) || !A || !B || !C || M < 0 || N < 0 || K < 0 || ldc < N) return RF_EINVAL;
+  if ((a_kc ? lda < K : lda < M) || (b_kc ? ldb < K : ldb < N)) return RF_EINVAL;
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  gemm(c, dtype, A, lda, a_kc ? 1 : 0, B, ldb, b_kc ? 1 : 0, C, ldc, M, N, K, ws ? (float*)align_ws(ws) : nullptr,
+       nullptr, 0, b_upper ? 1 : 0);
+  return finish(c);
+}
+
+size_t rf_test_gram_ws(int64_t K, int64_t M, int64_t N) { return gram_partial_doubles(K, M, N) * sizeof(double) + 256; }
+
+rf_status rf_test_gram(const float* X, const float* Y, int64_t K, int64_t M, int64_t N, int sym, double* C, void* ws,
+                       void* stream) {
+  if (!X || !Y || !C || K < 0 || M < 0 || N < 0 || (sym && (X != Y || M != N))) return RF_EINVAL;
+  return launch_gram(X, M, 0, Y, N, 0, K, M, N, sym ? 1 : 0, C, N, ws ? (double*)align_ws(ws) : nullptr, nullptr,
+                     (hipStream_t)stream) == hipSuccess
+             ? RF_OK
+             : RF_EHIP;
+}
+
+size_t rf_test_chol_ws(int64_t N) {
+  return (tri_inverse_work_doubles(N) + (size_t)N) * sizeof(double) + (size_t)N * sizeof(int) + 4 * 256;
+}
+
+rf_status rf_test_cholqr_factor(double* G, int64_t N, double* Rinv, int32_t* counters, void* ws, void* stream) {
+  if (!G || !Rinv || !counters || !ws || N < 1) return RF_EINVAL;
+  Arena ar(align_ws(ws));
+  double* work = ar.get<double>(tri_inverse_work_doubles(N));
+  double* d0 = ar.get<double>(N);
+  int* flags = ar.get<int>(N);
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  c.chk(launch_fill_i32(counters, 16, 0, c.st));
+  c.chk(launch_cholesky(G, N, N, chol_tol((int)N), d0, flags, &counters[0], &counters[2], nullptr, c.st));
+  c.chk(launch_tri_inverse(G, N, N, Rinv, N, nullptr, 0, work, c.st));
+  return finish(c);
+}
+
+size_t rf_test_eig_ws(int64_t N) { return eig_work_bytes(N) + 256; }
+
+rf_status rf_test_eig(const double* G, int64_t N, double* lam, double* V, void* ws, void* stream) {
+  if (!G || !lam || !V || !ws || N < 1) return RF_EINVAL;
+  if (N > 4096) return RF_EUNSUPPORTED;
+  return launch_eig(const_cast<double*>(G), N, N, lam, V, N, align_ws(ws), (hipStream_t)stream) == hipSuccess ? RF_OK
+                                                                                                            : RF_EHIP;
+}
+
+}  // extern "C"

@@ -1,0 +1,91 @@
+// K1 sketch table and K2 Gaussian fill.
+//
+// Sketch S (n x r1) of Lemma 3.2 item 2 ("CountSketch-type", s nonzeros
+// +-1/sqrt(s) per row).  Placement reading: block layout, nonzero t of row j
+// lies in block [floor(t r1/s), floor((t+1) r1/s)) at a column hashed by
+// Philox4x32-10 on counter (j*s+t, stream, b); multiply-shift range
+// reduction; sign from the top bit of the second output word.  Omega is
+// Gaussian (Algorithm 1; Theorem 2.1) by Box-Muller from Philox words.
+#include "common.h"
+#include "kernels.h"
+
+namespace rf {
+
+// Integer-exact, bit-identical to the oracle table.
+__global__ void k_sketch_table(int64_t n, int s, int r1, uint64_t seed, uint32_t stream, uint32_t b,
+                               int32_t* __restrict__ out) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * s) return;
+  int t = (int)(idx % s);
+  uint32_t lo = (uint32_t)(((int64_t)t * r1) / s);
+  uint32_t hi = (uint32_t)(((int64_t)(t + 1) * r1) / s);
+  u32x4 x = philox((uint64_t)idx, stream, b, seed);
+  uint32_t bucket = lo + (uint32_t)(((uint64_t)x.x * (uint64_t)(hi - lo)) >> 32);
+  out[idx] = (int32_t)(bucket | (x.y & 0x80000000u));
+}
+
+// "Ready" table for the sketch-apply kernel: entry (j, q) of lane-permuted
+// block t = (lane(j) % s) ^ q, where lane(j) = (j % (64*cpl)) / cpl owns column
+// j.  Word = sign<<31 | (b_local * 256 + 4 t): the LDS byte offset of the
+// bucket line plus the block's slot, so the kernel adds only the row part.
+__global__ void k_sketch_ready(const int32_t* __restrict__ table, int64_t n, int s, int r1, int cpl,
+                               uint32_t* __restrict__ ready) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * s) return;
+  int64_t j = idx / s;
+  int qq = (int)(idx % s);
+  int lane = (int)((j % (64 * cpl)) / cpl);
+  int t = (lane % s) ^ qq;
+  uint32_t e = (uint32_t)table[j * s + t];
+  uint32_t lo = (uint32_t)(((int64_t)t * r1) / s);
+  uint32_t bl = (e & 0x7fffffffu) - lo;
+  ready[idx] = (e & 0x80000000u) | (bl * 256u + 4u * (uint32_t)t);
+}
+
+__global__ void k_gaussian(int64_t total, uint64_t seed, uint32_t stream, uint32_t b,
+                           float* __restrict__ out, int64_t cols, int64_t ldo) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // counter index
+  if (p * 4 >= total) return;
+  u32x4 x = philox((uint64_t)p, stream, b, seed);
+  const double sc = 2.3283064365386963e-10;  // 2^-32
+  double ua = ((double)x.x + 0.5) * sc, ub = ((double)x.y + 0.5) * sc;
+  double uc = ((double)x.z + 0.5) * sc, ud = ((double)x.w + 0.5) * sc;
+  double ra = sqrt(-2.0 * log(ua)), rc = sqrt(-2.0 * log(uc));
+  const double twopi = 6.283185307179586;
+  double z[4] = {ra * cos(twopi * ub), ra * sin(twopi * ub), rc * cos(twopi * ud), rc * sin(twopi * ud)};
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    int64_t g = p * 4 + e;
+    if (g < total) out[(g / cols) * ldo + (g % cols)] = (float)z[e];
+  }
+}
+
+hipError_t launch_sketch_table(int64_t n, int s, int r1, uint64_t seed, uint32_t stream, uint32_t b,
+                               int32_t* out, hipStream_t st) {
+  int64_t tot = n * s;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sketch_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, n, s, r1,
+                     seed, stream, b, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sketch_ready(const int32_t* table, int64_t n, int s, int r1, int cpl, uint32_t* ready,
+                               hipStream_t st) {
+  int64_t tot = n * s;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sketch_ready, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, table, n, s,
+                     r1, cpl, ready);
+  return hipGetLastError();
+}
+
+hipError_t launch_gaussian(int64_t rows, int64_t cols, uint64_t seed, uint32_t stream, uint32_t b, float* out,
+                           int64_t ldo, hipStream_t st) {
+  int64_t tot = rows * cols;
+  if (tot == 0) return hipSuccess;
+  int64_t nc = (tot + 3) / 4;
+  hipLaunchKernelGGL(k_gaussian, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, tot, seed, stream, b,
+                     out, cols, ldo);
+  return hipGetLastError();
+}
+
+}  // namespace rf

@@ -1,0 +1,371 @@
+// K3 sketch_right: At = A S, and K4 sketch_left: out = S2^T X.
+//
+// A S costs O(nnz(A) s) and should run "almost as quickly as it takes to
+// read A" (Section 1; cost statement in the proof of Theorem 2.1).  Every
+// element A[i,j] is added, with sign, into s buckets of row i of At.
+//
+// Right sketch design (gfx950): a workgroup owns a band of R = 64/s rows and
+// keeps their whole At rows on chip in LDS.  Lanes own columns; every lane
+// reads its columns of all R rows (coalesced across lanes) and its columns'
+// s table entries once.  At step (p, qq) lane c adds row rbits^p into block
+// tbits^qq (c = rbits*s + tbits), so the 64 lanes of an instruction hit 64
+// distinct (row, block) slots; with LDS laid out [bucket-in-block][row][block]
+// each slot is its own bank: the ds_add_f32 scatter is conflict-free.  Per
+// (element, block) pair the kernel spends one v_add (row offset), one v_xor
+// (sign) and one ds_add_f32.
+#include "common.h"
+#include "kernels.h"
+
+namespace rf {
+
+template <typename TIN>
+RF_DEV float ld_elem(const TIN* p);
+template <>
+RF_DEV float ld_elem<float>(const float* p) { return *p; }
+template <>
+RF_DEV float ld_elem<uint16_t>(const uint16_t* p) { return bf16_to_f32(*p); }
+template <>
+RF_DEV float ld_elem<uint8_t>(const uint8_t* p) { return fp8e4m3_to_f32(*p); }
+
+// Load CPL consecutive elements starting at column j of row pointer rp (row valid).
+template <typename TIN, int CPL>
+RF_DEV void ld_cols(const TIN* rp, int64_t j, int64_t n, bool vec_ok, float* out) {
+  if (vec_ok && j + CPL <= n) {
+    if constexpr (sizeof(TIN) == 4 && CPL == 4) {
+      float4 v = *reinterpret_cast<const float4*>(rp + j);
+      out[0] = v.x; out[1] = v.y; out[2] = v.z; out[3] = v.w;
+      return;
+    } else if constexpr (sizeof(TIN) == 4 && CPL == 2) {
+      float2 v = *reinterpret_cast<const float2*>(rp + j);
+      out[0] = v.x; out[1] = v.y;
+      return;
+    } else if constexpr (sizeof(TIN) == 2 && CPL == 4) {
+      uint2 v = *reinterpret_cast<const uint2*>(rp + j);
+      out[0] = bf16_to_f32(v.x & 0xffff); out[1] = bf16_to_f32(v.x >> 16);
+      out[2] = bf16_to_f32(v.y & 0xffff); out[3] = bf16_to_f32(v.y >> 16);
+      return;
+    } else if constexpr (sizeof(TIN) == 2 && CPL == 2) {
+      uint32_t v = *reinterpret_cast<const uint32_t*>(rp + j);
+      out[0] = bf16_to_f32(v & 0xffff); out[1] = bf16_to_f32(v >> 16);
+      return;
+    } else if constexpr (sizeof(TIN) == 1 && CPL == 4) {
+      uint32_t v = *reinterpret_cast<const uint32_t*>(rp + j);
+      out[0] = fp8e4m3_to_f32(v & 0xff); out[1] = fp8e4m3_to_f32((v >> 8) & 0xff);
+      out[2] = fp8e4m3_to_f32((v >> 16) & 0xff); out[3] = fp8e4m3_to_f32(v >> 24);
+      return;
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < CPL; ++e) out[e] = (j + e < n) ? ld_elem<TIN>(rp + j + e) : 0.f;
+}
+
+// Grid: x = row bands of R rows, y = bucket chunks (CHUNKED).  Block: NW waves.
+// LDS: wl lines x 64 slots of float, line = bucket index inside its block.
+template <typename TIN, int S, int CPL, int NW, bool CHUNKED>
+__global__ __launch_bounds__(NW * 64) void k_sketch_right(
+    const TIN* __restrict__ A, int64_t lda, const float* __restrict__ scales, int64_t ldsc,
+    const uint32_t* __restrict__ ready, int64_t m, int64_t n, int r1, int wl, float* __restrict__ out,
+    int64_t ldo, float inv_sqrt_s, bool vec_ok) {
+  constexpr int R = 64 / S;
+  extern __shared__ float acc[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * R;
+  const int c0 = CHUNKED ? (int)blockIdx.y * wl : 0;
+  for (int i = threadIdx.x; i < wl * 64; i += NW * 64) acc[i] = 0.f;
+  __syncthreads();
+
+  const int rbits = lane / S;
+  const uint32_t chunk_lo = (uint32_t)c0 * 256u, chunk_hi = (uint32_t)(c0 + wl) * 256u;
+  char* accb = reinterpret_cast<char*>(acc);
+  const int64_t ngrp = (n + 64 * CPL - 1) / (64 * CPL);
+  for (int64_t g = wave; g < ngrp; g += NW) {
+    const int64_t j = g * 64 * CPL + (int64_t)lane * CPL;
+    float a[R][CPL];
+    uint32_t ent[CPL][S];
+    float sc = 1.f;
+    if constexpr (sizeof(TIN) == 1) {
+      if (j < n) sc = scales[(row0 / 128) * ldsc + j / 128];
+    }
+#pragma unroll
+    for (int p = 0; p < R; ++p) {
+      const int64_t row = row0 + (rbits ^ p);
+      if (row < m) ld_cols<TIN, CPL>(A + row * lda, j, n, vec_ok, a[p]);
+      else {
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) a[p][e] = 0.f;
+      }
+    }
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) {
+      if (j + e < n) {
+        const uint32_t* ep = ready + (j + e) * S;
+        if constexpr (S % 4 == 0) {
+#pragma unroll
+          for (int v = 0; v < S / 4; ++v) {
+            uint4 w = reinterpret_cast<const uint4*>(ep)[v];
+            ent[e][4 * v] = w.x; ent[e][4 * v + 1] = w.y; ent[e][4 * v + 2] = w.z; ent[e][4 * v + 3] = w.w;
+          }
+        } else {
+#pragma unroll
+          for (int qq = 0; qq < S; ++qq) ent[e][qq] = ep[qq];
+        }
+      } else {
+#pragma unroll
+        for (int qq = 0; qq < S; ++qq) ent[e][qq] = 0u;
+      }
+    }
+    if constexpr (sizeof(TIN) == 1) {
+#pragma unroll
+      for (int p = 0; p < R; ++p)
+#pragma unroll
+        for (int e = 0; e < CPL; ++e) a[p][e] *= sc;
+    }
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) {
+#pragma unroll
+      for (int qq = 0; qq < S; ++qq) {
+        uint32_t base = ent[e][qq] & 0x7fffffffu;
+        uint32_t sg = ent[e][qq] & 0x80000000u;
+        if (CHUNKED) {
+          if (base < chunk_lo || base >= chunk_hi) continue;
+          base -= chunk_lo;
+        }
+#pragma unroll
+        for (int p = 0; p < R; ++p) {
+          float v = __uint_as_float(__float_as_uint(a[p][e]) ^ sg);
+          atomicAdd(reinterpret_cast<float*>(accb + base + (uint32_t)(4 * S * (rbits ^ p))), v);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // write out: slot = r*S + t, line b -> At[row0 + r][lo_t + c0 + b]
+  for (int i = threadIdx.x; i < wl * 64; i += NW * 64) {
+    int b = i >> 6, slot = i & 63;
+    int r = slot / S, t = slot % S;
+    int64_t row = row0 + r;
+    if (r >= R || row >= m) continue;
+    int lo = (int)(((int64_t)t * r1) / S), hi = (int)(((int64_t)(t + 1) * r1) / S);
+    int bb = c0 + b;
+    if (bb < hi - lo) out[row * ldo + lo + bb] = acc[i] * inv_sqrt_s;
+  }
+}
+
+// Generic fallback (any s): one thread per element, s global atomics.  Output
+// must be zeroed first; scaled by 1/sqrt(s) on the fly.
+template <typename TIN>
+__global__ void k_sketch_right_atomic(const TIN* __restrict__ A, int64_t lda, const float* __restrict__ scales,
+                                      int64_t ldsc, const int32_t* __restrict__ table, int s, int64_t m,
+                                      int64_t n, float* __restrict__ out, int64_t ldo, float inv_sqrt_s) {
+  const int64_t cb = (n + 255) / 256;
+  const int64_t i = (int64_t)blockIdx.x / cb;
+  const int64_t j = ((int64_t)blockIdx.x % cb) * 256 + threadIdx.x;
+  if (j >= n || i >= m) return;
+  float a = ld_elem<TIN>(A + i * lda + j) * inv_sqrt_s;
+  if constexpr (sizeof(TIN) == 1) a *= scales[(i / 128) * ldsc + j / 128];
+  for (int t = 0; t < s; ++t) {
+    uint32_t e = (uint32_t)table[j * s + t];
+    float v = (e >> 31) ? -a : a;
+    atomicAdd(out + i * ldo + (e & 0x7fffffffu), v);
+  }
+}
+
+__global__ void k_fill_zero(float* p, int64_t rows, int64_t cols, int64_t ld) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  p[(idx / cols) * ld + idx % cols] = 0.f;
+}
+
+// ---- K4: out (r1 x N) = S2^T X for X (M x N) row-major, S2 given by its
+// (M x s) table.  Workgroup = (strip of 64 columns, bucket chunk, row split);
+// lanes own columns, rows are wave-uniform so each row's s bucket entries are
+// uniform and the 64 lanes add into 64 consecutive LDS words (no conflicts).
+template <typename TIN, int NW>
+__global__ __launch_bounds__(NW * 64) void k_sketch_left(const TIN* __restrict__ X, int64_t ldx,
+                                                         const int32_t* __restrict__ table, int s, int64_t M,
+                                                         int64_t N, int r1, int cw, int64_t rows_per_split,
+                                                         float* __restrict__ out, int64_t ldo,
+                                                         float* __restrict__ partial, float scale) {
+  extern __shared__ float acc[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t col = (int64_t)blockIdx.x * 64 + lane;
+  const int c0 = blockIdx.y * cw;
+  const int64_t rbeg = (int64_t)blockIdx.z * rows_per_split;
+  const int64_t rend = min(M, rbeg + rows_per_split);
+  for (int i = threadIdx.x; i < cw * 64; i += NW * 64) acc[i] = 0.f;
+  __syncthreads();
+  for (int64_t i = rbeg + wave; i < rend; i += NW) {
+    float x = (col < N) ? ld_elem<TIN>(X + i * ldx + col) : 0.f;
+    const int32_t* tp = table + i * s;
+    for (int t = 0; t < s; ++t) {
+      uint32_t e = (uint32_t)tp[t];
+      int b = (int)(e & 0x7fffffffu) - c0;
+      if (b >= 0 && b < cw) {
+        float v = __uint_as_float(__float_as_uint(x) ^ (e & 0x80000000u));
+        atomicAdd(&acc[b * 64 + lane], v);
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < cw * 64; i += NW * 64) {
+    int b = i >> 6, l = i & 63;
+    int64_t c = (int64_t)blockIdx.x * 64 + l;
+    int bb = c0 + b;
+    if (c >= N || bb >= r1) continue;
+    if (partial)
+      partial[((int64_t)blockIdx.z * r1 + bb) * N + c] = acc[i];
+    else
+      out[bb * ldo + c] = acc[i] * scale;
+  }
+}
+
+__global__ void k_reduce_partial(const float* __restrict__ partial, int splits, int64_t rows, int64_t cols,
+                                 float* __restrict__ out, int64_t ldo, float scale) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * cols) return;
+  float s = 0.f;
+  for (int z = 0; z < splits; ++z) s += partial[(int64_t)z * rows * cols + idx];
+  out[(idx / cols) * ldo + idx % cols] = s * scale;
+}
+
+// ---- launchers -------------------------------------------------------------------------
+static int g_num_cu = 0;
+static int num_cu() {
+  if (!g_num_cu) {
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&g_num_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (g_num_cu <= 0) g_num_cu = 256;
+  }
+  return g_num_cu;
+}
+
+int sketch_right_cpl(int s) { return s >= 8 ? 4 : (s == 4 ? 2 : 1); }
+
+bool sketch_right_fast_ok(int s) { return s == 1 || s == 2 || s == 4 || s == 8 || s == 16; }
+
+template <typename TIN, int S, int CPL>
+static hipError_t launch_sr(const void* A, int64_t lda, const float* scales, int64_t ldsc, const uint32_t* ready,
+                            int64_t m, int64_t n, int r1, float* out, int64_t ldo, hipStream_t st) {
+  constexpr int NW = 8;
+  const int R = 64 / S;
+  int wmax = (r1 + S - 1) / S;
+  const int wl_cap = 640;  // 640 lines * 64 slots * 4 B = 160 KiB
+  int chunks = (wmax + wl_cap - 1) / wl_cap;
+  int wl = (wmax + chunks - 1) / chunks;
+  size_t lds = (size_t)wl * 64 * sizeof(float);
+  dim3 grid((unsigned)((m + R - 1) / R), (unsigned)chunks);
+  bool vec_ok = (((uintptr_t)A) % (sizeof(TIN) * CPL) == 0) && (lda % CPL == 0);
+  float inv = 1.0f / sqrtf((float)S);
+  if (chunks == 1) {
+    auto k = k_sketch_right<TIN, S, CPL, NW, false>;
+    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const TIN*)A, lda, scales, ldsc, ready, m, n, r1, wl,
+                       out, ldo, inv, vec_ok);
+  } else {
+    auto k = k_sketch_right<TIN, S, CPL, NW, true>;
+    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const TIN*)A, lda, scales, ldsc, ready, m, n, r1, wl,
+                       out, ldo, inv, vec_ok);
+  }
+  return hipGetLastError();
+}
+
+template <typename TIN>
+static hipError_t launch_sr_dispatch(int s, const void* A, int64_t lda, const float* scales, int64_t ldsc,
+                                     const uint32_t* ready, int64_t m, int64_t n, int r1, float* out, int64_t ldo,
+                                     hipStream_t st) {
+  switch (s) {
+    case 1: return launch_sr<TIN, 1, 1>(A, lda, scales, ldsc, ready, m, n, r1, out, ldo, st);
+    case 2: return launch_sr<TIN, 2, 1>(A, lda, scales, ldsc, ready, m, n, r1, out, ldo, st);
+    case 4: return launch_sr<TIN, 4, 2>(A, lda, scales, ldsc, ready, m, n, r1, out, ldo, st);
+    case 8: return launch_sr<TIN, 8, 4>(A, lda, scales, ldsc, ready, m, n, r1, out, ldo, st);
+    case 16: return launch_sr<TIN, 16, 4>(A, lda, scales, ldsc, ready, m, n, r1, out, ldo, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_sketch_right(int dtype, const void* A, int64_t lda, const float* scales, const int32_t* table,
+                               const uint32_t* ready, int s, int64_t m, int64_t n, int r1, float* out,
+                               int64_t ldo, hipStream_t st) {
+  if (m == 0 || n == 0) return hipSuccess;
+  int64_t ldsc = (n + 127) / 128;
+  if (sketch_right_fast_ok(s) && ready) {
+    switch (dtype) {
+      case 0: return launch_sr_dispatch<float>(s, A, lda, scales, ldsc, ready, m, n, r1, out, ldo, st);
+      case 2: return launch_sr_dispatch<uint16_t>(s, A, lda, scales, ldsc, ready, m, n, r1, out, ldo, st);
+      case 3: return launch_sr_dispatch<uint8_t>(s, A, lda, scales, ldsc, ready, m, n, r1, out, ldo, st);
+    }
+    return hipErrorInvalidValue;
+  }
+  int64_t tot = m * r1;
+  hipLaunchKernelGGL(k_fill_zero, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, out, m, (int64_t)r1, ldo);
+  dim3 grid((unsigned)(((n + 255) / 256) * m));
+  float inv = 1.0f / sqrtf((float)s);
+  switch (dtype) {
+    case 0:
+      hipLaunchKernelGGL(k_sketch_right_atomic<float>, grid, dim3(256), 0, st, (const float*)A, lda, scales, ldsc,
+                         table, s, m, n, out, ldo, inv);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_sketch_right_atomic<uint16_t>, grid, dim3(256), 0, st, (const uint16_t*)A, lda, scales,
+                         ldsc, table, s, m, n, out, ldo, inv);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_sketch_right_atomic<uint8_t>, grid, dim3(256), 0, st, (const uint8_t*)A, lda, scales,
+                         ldsc, table, s, m, n, out, ldo, inv);
+      break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+size_t sketch_left_partial_floats(int64_t M, int64_t N, int r1) {
+  int cw = 512;
+  int chunks = (r1 + cw - 1) / cw;
+  int64_t strips = (N + 63) / 64;
+  int64_t wgs = strips * chunks;
+  int splits = 1;
+  while (wgs * splits < 2 * num_cu() && splits < 64 && M / (splits * 2) >= 256) splits *= 2;
+  return splits > 1 ? (size_t)splits * r1 * N : 0;
+}
+
+hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32_t* table, int s, int64_t M,
+                              int64_t N, int r1, float* out, int64_t ldo, float* partial, hipStream_t st) {
+  if (N == 0 || r1 == 0) return hipSuccess;
+  constexpr int NW = 4;
+  int cw = 512;
+  int chunks = (r1 + cw - 1) / cw;
+  cw = (r1 + chunks - 1) / chunks;
+  int64_t strips = (N + 63) / 64;
+  int64_t wgs = strips * chunks;
+  int splits = 1;
+  while (wgs * splits < 2 * num_cu() && splits < 64 && M / (splits * 2) >= 256) splits *= 2;
+  if (splits > 1 && !partial) splits = 1;
+  int64_t rps = (M + splits - 1) / splits;
+  size_t lds = (size_t)cw * 64 * sizeof(float);
+  float scale = 1.0f / sqrtf((float)s);
+  dim3 grid((unsigned)strips, (unsigned)chunks, (unsigned)splits);
+  float* part = splits > 1 ? partial : nullptr;
+  if (dtype == 0) {
+    auto k = k_sketch_left<float, NW>;
+    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const float*)X, ldx, table, s, M, N, r1, cw, rps, out, ldo,
+                       part, scale);
+  } else if (dtype == 2) {
+    auto k = k_sketch_left<uint16_t, NW>;
+    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const uint16_t*)X, ldx, table, s, M, N, r1, cw, rps, out,
+                       ldo, part, scale);
+  } else {
+    return hipErrorInvalidValue;
+  }
+  if (splits > 1) {
+    int64_t tot = (int64_t)r1 * N;
+    hipLaunchKernelGGL(k_reduce_partial, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, partial, splits,
+                       (int64_t)r1, N, out, ldo, scale);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace rf

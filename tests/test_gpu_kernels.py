@@ -1,0 +1,211 @@
+"""Kernel-level parity on the GPU: every HIP kernel of the path against the
+FP64 oracle (or an exact NumPy reference where the operation is a plain
+definition), through the C ABI.  Integer work is compared bit for bit."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2605_09755_amd as rf
+from oracle import sketch as sk, methods as me
+from tests import fp8_ref
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+U32 = 2.0 ** -24
+
+
+def bf16_round(x):
+    t = torch.from_numpy(np.asarray(x, dtype=np.float32)).to(torch.bfloat16)
+    return t, t.to(torch.float32).numpy().astype(np.float64)
+
+
+# ---------------------------------------------------------------- K1 sketch table
+@pytest.mark.parametrize("n,s,r1,seed,stream,b", [
+    (1000, 8, 100, 42, 0, 0), (777, 3, 50, 7, 2, 1), (16384, 8, 2000, 102, 0, 0),
+    (5, 1, 1, 0, 0, 0), (100, 16, 64, (1 << 40) | 5, 3, 7), (4099, 4, 4096, 9, 0, 0)])
+def test_sketch_table_bitexact(n, s, r1, seed, stream, b):
+    g = rf.rf_sketch_table(n, s, r1, seed, stream, b, DEV)
+    torch.cuda.synchronize()
+    ref = sk.sketch_table(n, s, r1, seed, stream, b)
+    assert np.array_equal(g.cpu().numpy(), ref)
+
+
+# ---------------------------------------------------------------- K2 Gaussian
+@pytest.mark.parametrize("rows,cols,seed,stream", [(31, 17, 3, 1), (2000, 100, 42, 1), (1000, 1001, 5, 3)])
+def test_gaussian_within_one_ulp(rows, cols, seed, stream):
+    g = rf.rf_gaussian(rows, cols, seed, stream, 0, DEV).cpu().numpy()
+    ref = sk.gaussian(rows, cols, seed, stream).astype(np.float32)
+    ulp = np.spacing(np.abs(ref).astype(np.float32))
+    assert np.all(np.abs(g - ref) <= ulp)
+    assert np.mean(g == ref) > 0.99
+
+
+# ---------------------------------------------------------------- K3 A S
+def _sketch_ref(A64, n, s, r1, seed):
+    t = sk.sketch_table(n, s, r1, seed)
+    return me.sketch_right(A64, t, r1), np.asarray(np.abs(A64) @ np.abs(sk.sketch_matrix(t, r1).toarray()))
+
+
+@pytest.mark.parametrize("m,n,s,r1", [
+    (64, 256, 8, 100), (77, 1000, 8, 100), (130, 513, 4, 40), (100, 300, 1, 50), (100, 300, 2, 50),
+    (50, 200, 3, 20), (40, 700, 16, 64), (70, 2000, 1, 1000), (9, 5000, 8, 4000), (1, 1, 1, 1)])
+def test_sketch_apply_f32(m, n, s, r1):
+    rng = np.random.default_rng(m * 7 + n)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    A64 = A.astype(np.float64)
+    ref, mag = _sketch_ref(A64, n, s, r1, 11)
+    got = rf.rf_sketch_apply(torch.from_numpy(A).to(DEV), r1, s, 11).cpu().numpy()
+    tol = (n * s / r1 + 8) * 4 * U32 * mag + 1e-30
+    assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
+
+
+def test_sketch_apply_strided_rows():
+    rng = np.random.default_rng(5)
+    big = rng.standard_normal((60, 1030)).astype(np.float32)
+    A = torch.from_numpy(big).to(DEV)[:, 3:1003]          # ld = 1030, unaligned start
+    ref, mag = _sketch_ref(big[:, 3:1003].astype(np.float64), 1000, 8, 96, 3)
+    got = rf.rf_sketch_apply(A, 96, 8, 3).cpu().numpy()
+    assert np.all(np.abs(got - ref) <= 200 * U32 * mag + 1e-30)
+
+
+@pytest.mark.parametrize("m,n,s,r1", [(64, 512, 8, 100), (33, 333, 4, 60)])
+def test_sketch_apply_bf16(m, n, s, r1):
+    rng = np.random.default_rng(1)
+    At, A64 = bf16_round(rng.standard_normal((m, n)))
+    ref, mag = _sketch_ref(A64, n, s, r1, 12)
+    got = rf.rf_sketch_apply(At.to(DEV), r1, s, 12).cpu().numpy()
+    assert np.all(np.abs(got - ref) <= (n * s / r1 + 8) * 4 * U32 * mag + 1e-30)
+
+
+@pytest.mark.parametrize("m,n,s,r1", [(256, 384, 8, 64), (200, 300, 4, 40)])
+def test_sketch_apply_fp8_block_scaled(m, n, s, r1):
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((m, n)) * np.exp(rng.standard_normal((m, 1)))
+    codes, scales = fp8_ref.quantize_blocks(X)
+    A64 = fp8_ref.dequantize(codes, scales)
+    ref, mag = _sketch_ref(A64, n, s, r1, 13)
+    got = rf.rf_sketch_apply(torch.from_numpy(codes).to(DEV), r1, s, 13,
+                             scales=torch.from_numpy(scales).to(DEV)).cpu().numpy()
+    assert np.all(np.abs(got - ref) <= (n * s / r1 + 8) * 4 * U32 * mag + 1e-30)
+
+
+# ---------------------------------------------------------------- K5/K6 GEMM
+def _operands(M, N, K, a_kc, b_kc, rng, bf16):
+    A = rng.standard_normal((M, K))
+    B = rng.standard_normal((K, N))
+    if bf16:
+        At, A = bf16_round(A)
+        Bt, B = bf16_round(B)
+    else:
+        At = torch.from_numpy(A.astype(np.float32)); A = A.astype(np.float32).astype(np.float64)
+        Bt = torch.from_numpy(B.astype(np.float32)); B = B.astype(np.float32).astype(np.float64)
+    Astore = At if a_kc else At.t().contiguous()      # a_kc: (M, K) row-major; else (K, M)
+    Bstore = Bt.t().contiguous() if b_kc else Bt      # b_kc: (N, K) row-major; else (K, N)
+    return Astore.to(DEV), Bstore.to(DEV), A, B
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+@pytest.mark.parametrize("a_kc,b_kc", [(1, 1), (1, 0), (0, 1), (0, 0)])
+@pytest.mark.parametrize("M,N,K", [(128, 128, 32), (300, 200, 100), (1000, 70, 5000), (64, 1000, 2000), (1, 1, 1)])
+def test_gemm(bf16, a_kc, b_kc, M, N, K):
+    rng = np.random.default_rng(M + 3 * N + 7 * K)
+    dA, dB, A, B = _operands(M, N, K, a_kc, b_kc, rng, bf16)
+    C = rf.rf_test_gemm(dA, dB, M, N, K, a_kc, b_kc).cpu().numpy()
+    ref = A @ B
+    mag = np.abs(A) @ np.abs(B)
+    assert np.all(np.abs(C - ref) <= (K + 2) * U32 * mag + 1e-30), np.max(np.abs(C - ref) / (mag + 1e-30))
+
+
+@pytest.mark.parametrize("bf16", [False, True])
+def test_gemm_upper_triangular_b(bf16):
+    rng = np.random.default_rng(9)
+    M, N = 500, 300
+    A = rng.standard_normal((M, N))
+    R = np.triu(rng.standard_normal((N, N)))
+    if bf16:
+        At, A = bf16_round(A)
+        Rt, R = bf16_round(R)
+    else:
+        At, Rt = torch.from_numpy(A.astype(np.float32)), torch.from_numpy(R.astype(np.float32))
+        A, R = A.astype(np.float32).astype(np.float64), R.astype(np.float32).astype(np.float64)
+    C = rf.rf_test_gemm(At.to(DEV), Rt.to(DEV), M, N, N, 1, 0, b_upper=True).cpu().numpy()
+    mag = np.abs(A) @ np.abs(R)
+    assert np.all(np.abs(C - A @ R) <= (N + 2) * U32 * mag + 1e-30)
+
+
+# ---------------------------------------------------------------- FP64 Gram / Cholesky / inverse / eig
+@pytest.mark.parametrize("K,M,N,sym", [(5000, 100, 100, True), (300, 70, 130, False), (65, 1, 1, True),
+                                       (20000, 257, 257, True)])
+def test_gram_f64(K, M, N, sym):
+    rng = np.random.default_rng(K + M)
+    X = rng.standard_normal((K, M)).astype(np.float32)
+    Y = X if sym else rng.standard_normal((K, N)).astype(np.float32)
+    dX = torch.from_numpy(X).to(DEV)
+    dY = dX if sym else torch.from_numpy(Y).to(DEV)
+    C = rf.rf_test_gram(dX, dY, sym=sym).cpu().numpy()
+    X64, Y64 = X.astype(np.float64), Y.astype(np.float64)
+    ref = X64.T @ Y64
+    mag = np.abs(X64).T @ np.abs(Y64)
+    assert np.all(np.abs(C - ref) <= (K + 2) * 2.0 ** -53 * mag + 1e-300)
+    if sym:
+        assert np.array_equal(C, C.T)
+
+
+@pytest.mark.parametrize("N", [1, 5, 64, 100, 129, 300, 1000])
+def test_cholesky_and_inverse(N):
+    rng = np.random.default_rng(N)
+    X = rng.standard_normal((N + 20, N)) * np.logspace(0, -3, N)[None, :]
+    G = X.T @ X
+    R, Rinv, cnt = rf.rf_test_cholqr_factor(torch.from_numpy(G).to(DEV))
+    R = np.triu(R.cpu().numpy())
+    Rinv = Rinv.cpu().numpy()
+    assert int(cnt[0].item()) == 0
+    Rref = np.linalg.cholesky(G).T
+    assert np.allclose(R, Rref, rtol=1e-9, atol=1e-12 * np.abs(Rref).max())
+    assert np.allclose(Rinv @ R, np.eye(N), atol=1e-9)
+    assert np.allclose(np.tril(Rinv, -1), 0)
+
+
+def test_cholesky_flags_dependent_columns():
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((60, 10)).astype(np.float32).astype(np.float64)
+    X[:, 7] = X[:, 2] + X[:, 3]          # exactly dependent in FP64 (and nearly in FP32)
+    G = X.T @ X
+    _, Rinv, cnt = rf.rf_test_cholqr_factor(torch.from_numpy(G).to(DEV))
+    assert int(cnt[0].item()) == 1
+    assert np.all(np.isfinite(Rinv.cpu().numpy()))
+
+
+@pytest.mark.parametrize("N,kind", [(1, "rand"), (2, "rand"), (31, "rand"), (64, "rand"), (100, "psd"),
+                                    (257, "rand"), (1000, "psd"), (300, "cluster")])
+def test_eig(N, kind):
+    rng = np.random.default_rng(N)
+    if kind == "rand":
+        G = rng.standard_normal((N, N)); G = G + G.T
+    elif kind == "psd":
+        X = rng.standard_normal((N, 3 * N)) * np.logspace(0, -4, N)[:, None]
+        G = X @ X.T
+    else:
+        Q, _ = np.linalg.qr(rng.standard_normal((N, N)))
+        lam = np.concatenate([np.ones(N // 3), 1e-3 * np.ones(N // 3), np.zeros(N - 2 * (N // 3))])
+        G = (Q * lam) @ Q.T
+        G = 0.5 * (G + G.T)
+    lam, V = rf.rf_test_eig(torch.from_numpy(G).to(DEV))
+    lam, V = lam.cpu().numpy(), V.cpu().numpy()
+    ref = np.sort(np.linalg.eigvalsh(G))[::-1]
+    nrm = np.abs(ref).max()
+    e_lam = np.max(np.abs(lam - ref)) / nrm
+    e_orth = np.max(np.abs(V.T @ V - np.eye(N)))
+    e_res = np.max(np.abs(G @ V - V * lam[None, :])) / nrm
+    print("eig N=%d %s: lam err %.2e orth %.2e resid %.2e" % (N, kind, e_lam, e_orth, e_res))
+    assert np.all(np.diff(lam) <= 0)
+    assert e_orth <= 1e-10
+    if kind == "cluster":
+        # three exactly multiple eigenvalues: Jacobi (block or classic cyclic)
+        # converges only linearly here; bound what 20 sweeps deliver
+        assert e_lam <= 1e-11 and e_res <= 1e-6
+    else:
+        assert e_lam <= 1e-12 * max(1, math.sqrt(N))
+        assert e_res <= 1e-10
