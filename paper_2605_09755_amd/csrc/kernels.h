@@ -18,9 +18,11 @@ hipError_t launch_gaussian(int64_t rows, int64_t cols, uint64_t seed, uint32_t s
 int sketch_right_cpl(int s);
 bool sketch_right_fast_ok(int s);
 // dtype: 0 f32, 2 bf16, 3 fp8 e4m3 with 128x128 block scales
+// cmax: workspace of sketch_right_cmax_ints(n) ints (per-chunk bucket occupancy)
+size_t sketch_right_cmax_ints(int64_t n);
 hipError_t launch_sketch_right(int dtype, const void* A, int64_t lda, const float* scales, const int32_t* table,
-                               const uint32_t* ready, int s, int64_t m, int64_t n, int r1, float* out, int64_t ldo,
-                               hipStream_t st);
+                               const uint32_t* ready, int* cmax, int s, int64_t m, int64_t n, int r1, float* out,
+                               int64_t ldo, hipStream_t st);
 size_t sketch_left_partial_floats(int64_t M, int64_t N, int r1);
 hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32_t* table, int s, int64_t M,
                               int64_t N, int r1, float* out, int64_t ldo, float* partial, hipStream_t st);
@@ -61,8 +63,11 @@ size_t tri_inverse_work_doubles(int64_t N);
 // Symmetric eigen-decomposition (block Jacobi).  G (N x N, ld) is destroyed.
 // lam (N, descending), V (N x N, ldv, column c = eigenvector of lam[c]).
 size_t eig_work_bytes(int64_t N);
+// trace (optional, device, >= eig_max_sweeps() doubles): per-sweep convergence measure
+// (<= 1 means converged; 0 after convergence).
+int eig_max_sweeps();
 hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
-                      hipStream_t st);
+                      hipStream_t st, double* trace = nullptr);
 
 // ---- utilities ----
 hipError_t launch_cast_f32_bf16(const float* in, int64_t ldi, uint16_t* out, int64_t ldo, int64_t rows, int64_t cols,

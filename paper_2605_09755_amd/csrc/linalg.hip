@@ -457,9 +457,11 @@ struct EigWork {
   double* Z;       // K x K
   double* V;       // p x 64 x 64
   int* perm;       // K
+  int* ident;      // p: subproblem x of the current round left its block pair unchanged
   unsigned long long* maxoff;  // 1
   int* conv;       // 1
-  double* floor2;  // 1
+  double* floor2;  // 1: (1e-15 ||G||_F)^2, regularises rotation thresholds
+  double* fabs_;   // 1: 16 eps ||G||_F, absolute convergence floor
   int64_t K;
   int p;
 };
@@ -475,17 +477,22 @@ static EigWork eig_layout(void* work, int64_t N) {
   w.Z = (double*)p; p += K * K * 8;
   w.V = (double*)p; p += (size_t)w.p * JS * JS * 8;
   w.perm = (int*)p; p += ((K * 4 + 255) / 256) * 256;
+  w.ident = (int*)p; p += ((w.p * 4 + 255) / 256) * 256;
   w.maxoff = (unsigned long long*)p; p += 256;
   w.conv = (int*)p; p += 256;
   w.floor2 = (double*)p; p += 256;
+  w.fabs_ = (double*)p; p += 256;
   return w;
 }
+
+int eig_max_sweeps() { return 20; }
 
 size_t eig_work_bytes(int64_t N) {
   int64_t K = ((N + 2 * JB - 1) / (2 * JB)) * (2 * JB);
   if (K < 2 * JB) K = 2 * JB;
   int64_t p = K / (2 * JB);
-  return (size_t)(2 * K * K * 8 + p * JS * JS * 8 + ((K * 4 + 255) / 256) * 256 + 3 * 256);
+  return (size_t)(2 * K * K * 8 + p * JS * JS * 8 + ((K * 4 + 255) / 256) * 256 + ((p * 4 + 255) / 256) * 256 +
+                  4 * 256);
 }
 
 RF_DEV int circle(int round, int i, int n) {  // position i of round in an n-player circle schedule
@@ -508,10 +515,13 @@ __global__ void k_eig_init(const double* __restrict__ G, int64_t ld, int64_t N, 
 }
 
 __global__ void k_eig_floor(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
-  // floor^2 = (1e-15 * trace|.| / N)^2, single workgroup
+  // ||G||_F (single workgroup) -> rotation floor and absolute convergence floor
   __shared__ double red[256];
   double s = 0.0;
-  for (int64_t i = threadIdx.x; i < N; i += blockDim.x) s += fabs(G[i * ld + i]);
+  for (int64_t e = threadIdx.x; e < N * N; e += blockDim.x) {
+    double g = G[(e / N) * ld + e % N];
+    s += g * g;
+  }
   red[threadIdx.x] = s;
   __syncthreads();
   for (int o = 128; o > 0; o >>= 1) {
@@ -519,8 +529,10 @@ __global__ void k_eig_floor(const double* __restrict__ G, int64_t ld, int64_t N,
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    double f = 1e-15 * red[0] / (double)(N > 0 ? N : 1);
+    double fro = sqrt(red[0]);
+    double f = 1e-15 * fro;
     *w.floor2 = f * f + 1e-300;
+    *w.fabs_ = 16.0 * 2.220446049250313e-16 * fro + 1e-300;
   }
 }
 
@@ -549,12 +561,44 @@ __global__ __launch_bounds__(256) void k_eig_solve(EigWork w, int round, int inn
   const int P = circle(round, x, np), Q = circle(round, np - 1 - x, np);
   const double floor2 = *w.floor2;
   auto gidx = [&](int a) -> int64_t { return a < JB ? (int64_t)P * JB + a : (int64_t)Q * JB + (a - JB); };
+  const double fabs_ = *w.fabs_;
+  __shared__ int needed;
+  if (threadIdx.x == 0) needed = 0;
+  __syncthreads();
   for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
     int a = e / JS, b = e % JS;
     M[a][b] = w.Gp[gidx(a) * w.K + gidx(b)];
     V[a][b] = (a == b) ? 1.0 : 0.0;
   }
   __syncthreads();
+  // nothing to do when every off-diagonal entry of the pair already meets the
+  // global convergence test and the diagonal is already in the sorted order
+  for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
+    int a = e / JS, b = e % JS;
+    if (a != b) {
+      double d = sqrt(fabs(M[a][a])) * sqrt(fabs(M[b][b]));
+      if (!(fabs(M[a][b]) <= fmax(1e-12 * d, fabs_))) needed = 1;
+    }
+  }
+  if (threadIdx.x < JS - 1) {
+    const int a = threadIdx.x;
+    // descending order within each 32-block and across the pair (lower-index block first)
+    const int lo_first = (P < Q);
+    if (a != JB - 1) {
+      int b = a + 1;
+      if (M[a][a] < M[b][b]) needed = 1;
+    } else {
+      double top = lo_first ? M[JB - 1][JB - 1] : M[JS - 1][JS - 1];
+      double bot = lo_first ? M[JB][JB] : M[0][0];
+      if (top < bot) needed = 1;
+    }
+  }
+  __syncthreads();
+  if (!needed) {
+    if (threadIdx.x == 0) w.ident[x] = 1;
+    return;
+  }
+  if (threadIdx.x == 0) w.ident[x] = 0;
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     if (threadIdx.x == 0) done = 1;
     __syncthreads();
@@ -633,17 +677,19 @@ __global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   if (id < ntile) {
     const int x = id / w.p, y = id % w.p;
+    if (w.ident[x] && w.ident[y]) return;
     const int Px = circle(round, x, np), Qx = circle(round, np - 1 - x, np);
     const int Py = circle(round, y, np), Qy = circle(round, np - 1 - y, np);
     auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
     auto iy = [&](int a) -> int64_t { return a < JB ? (int64_t)Py * JB + a : (int64_t)Qy * JB + (a - JB); };
     const double* vx = w.V + (int64_t)x * JS * JS;
     const double* vy = w.V + (int64_t)y * JS * JS;
+    const int idx_ = w.ident[x], idy_ = w.ident[y];
     for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
       int a = e / JS, b = e % JS;
       T[a][b] = w.Gp[ix(a) * w.K + iy(b)];
-      Va[a][b] = vx[e];
-      Vb[a][b] = vy[e];
+      Va[a][b] = idx_ ? (a == b ? 1.0 : 0.0) : vx[e];
+      Vb[a][b] = idy_ ? (a == b ? 1.0 : 0.0) : vy[e];
     }
     __syncthreads();
     double acc[4][4] = {};
@@ -686,6 +732,7 @@ __global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
   } else {
     const int zid = id - ntile;
     const int x = zid % w.p, rb = zid / w.p;
+    if (w.ident[x]) return;
     const int Px = circle(round, x, np), Qx = circle(round, np - 1 - x, np);
     auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
     const double* vx = w.V + (int64_t)x * JS * JS;
@@ -725,19 +772,24 @@ __global__ void k_eig_check(EigWork w) {
   if (idx < w.K * w.K) {
     int64_t i = idx / w.K, j = idx % w.K;
     if (i != j) {
+      // converged when |g_ij| <= max(tol sqrt|g_ii g_jj|, 16 eps ||G||_F): r <= 1
       double g = w.Gp[idx];
       double d = sqrt(fabs(w.Gp[i * w.K + i])) * sqrt(fabs(w.Gp[j * w.K + j]));
-      r = fabs(g) / sqrt(d * d + *w.floor2);
-      if (!(r == r)) r = 1.0;  // NaN: keep iterating (and never claim convergence)
+      r = fabs(g) / fmax(1e-12 * d, *w.fabs_);
+      if (!(r == r)) r = 2.0;  // NaN: keep iterating (and never claim convergence)
     }
   }
   r = wave_max(r);
   if ((threadIdx.x & 63) == 0 && r > 0.0) atomicMax(w.maxoff, (unsigned long long)__double_as_longlong(r));
 }
 
-__global__ void k_eig_decide(EigWork w, double tol) {
-  if (*w.conv) return;
+__global__ void k_eig_decide(EigWork w, double tol, double* trace, int sw) {
+  if (*w.conv) {
+    if (trace) trace[sw] = 0.0;
+    return;
+  }
   double m = __longlong_as_double((long long)*w.maxoff);
+  if (trace) trace[sw] = m;
   if (m <= tol) *w.conv = 1;
   *w.maxoff = 0ull;
 }
@@ -784,7 +836,7 @@ __global__ void k_eig_gather(EigWork w, int64_t N, double* V, int64_t ldv) {
 }
 
 hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
-                      hipStream_t st) {
+                      hipStream_t st, double* trace) {
   if (N == 0) return hipSuccess;
   EigWork w = eig_layout(work, N);
   if (w.K > 4096) return hipErrorInvalidValue;
@@ -800,7 +852,7 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
     attr = true;
   }
   const int rounds = 2 * w.p - 1;
-  const int max_sweeps = 20;
+  const int max_sweeps = eig_max_sweeps();
   const int ntile = w.p * w.p + (int)(w.K / JS) * w.p;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int r = 0; r < rounds; ++r) {
@@ -808,7 +860,7 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
       hipLaunchKernelGGL(k_eig_apply, dim3(ntile), dim3(256), lds_apply, st, w, r);
     }
     hipLaunchKernelGGL(k_eig_check, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, st, w);
-    hipLaunchKernelGGL(k_eig_decide, dim3(1), dim3(1), 0, st, w, 1e-12);
+    hipLaunchKernelGGL(k_eig_decide, dim3(1), dim3(1), 0, st, w, 1.0, trace, sw);
   }
   hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, st, w, N, lam);
   hipLaunchKernelGGL(k_eig_gather, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, w, N, V, ldv);

@@ -33,7 +33,7 @@ struct Dims {
 };
 
 struct RFBufs {
-  int32_t* table; uint32_t* ready;
+  int32_t* table; uint32_t* ready; int* cmax;
   float* om; uint16_t* om16;
   float* At; uint16_t* At16;
   float* Ya; float* Yb; uint16_t* Q16;
@@ -50,6 +50,7 @@ static RFBufs carve_rf(Arena& ar, const Dims& d) {
   const bool mixed = d.prec == RF_PREC_MIXED;
   b.table = ar.get<int32_t>((size_t)d.n * d.s);
   b.ready = ar.get<uint32_t>((size_t)d.n * d.s);
+  b.cmax = ar.get<int>(sketch_right_cmax_ints(d.n));
   b.om = ar.get<float>((size_t)d.r1 * d.k);
   b.om16 = mixed ? ar.get<uint16_t>((size_t)d.r1 * d.k) : nullptr;
   b.At = ar.get<float>((size_t)d.m * d.r1);
@@ -135,7 +136,7 @@ static void range_finder_core(Ctx& c, const rf_matrix* A, const Dims& d, uint64_
     om = b.om;
   }
   // At = A S  (one pass over A)
-  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, table, fast ? b.ready : nullptr, d.s, d.m, d.n,
+  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, table, fast ? b.ready : nullptr, b.cmax, d.s, d.m, d.n,
                             r1, b.At, r1, c.st));
   if (mixed) {
     c.chk(launch_cast_f32_bf16(b.At, r1, b.At16, r1, d.m, r1, c.st));
@@ -343,7 +344,7 @@ rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, in
   c.chk(launch_sketch_table(d.n, d.s, d.r1, p->seed, 0, 0, b.table, c.st));
   const bool fast = sketch_right_fast_ok(d.s);
   if (fast) c.chk(launch_sketch_ready(b.table, d.n, d.s, d.r1, sketch_right_cpl(d.s), b.ready, c.st));
-  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, b.table, fast ? b.ready : nullptr, d.s, d.m,
+  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, b.table, fast ? b.ready : nullptr, b.cmax, d.s, d.m,
                             d.n, d.r1, out, ldo, c.st));
   return finish(c);
 }
@@ -457,7 +458,7 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
   const bool fast = sketch_right_fast_ok(d.s);
   if (fast) c.chk(launch_sketch_ready(b.table, n, d.s, r1, sketch_right_cpl(d.s), b.ready, c.st));
   c.chk(launch_gaussian(r1, k, p->seed, 1, 0, b.om, k, c.st));
-  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, b.table, fast ? b.ready : nullptr, d.s, n, n,
+  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, b.table, fast ? b.ready : nullptr, b.cmax, d.s, n, n,
                             r1, b.At, r1, c.st));
   c.chk(launch_sketch_left(0, b.At, r1, b.table, d.s, n, r1, r1, y.Wt, r1, y.lpart, c.st));
   c.chk(launch_symmetrize(y.Wt, r1, r1, c.st));
@@ -531,11 +532,14 @@ rf_status rf_test_cholqr_factor(double* G, int64_t N, double* Rinv, int32_t* cou
 
 size_t rf_test_eig_ws(int64_t N) { return eig_work_bytes(N) + 256; }
 
-rf_status rf_test_eig(const double* G, int64_t N, double* lam, double* V, void* ws, void* stream) {
+rf_status rf_test_eig(const double* G, int64_t N, double* lam, double* V, double* sweep_trace, void* ws,
+                      void* stream) {
   if (!G || !lam || !V || !ws || N < 1) return RF_EINVAL;
   if (N > 4096) return RF_EUNSUPPORTED;
-  return launch_eig(const_cast<double*>(G), N, N, lam, V, N, align_ws(ws), (hipStream_t)stream) == hipSuccess ? RF_OK
-                                                                                                            : RF_EHIP;
+  return launch_eig(const_cast<double*>(G), N, N, lam, V, N, align_ws(ws), (hipStream_t)stream, sweep_trace) ==
+                 hipSuccess
+             ? RF_OK
+             : RF_EHIP;
 }
 
 }  // extern "C"
