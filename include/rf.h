@@ -167,10 +167,11 @@ rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, in
      Rinv (N x N FP64, ld N) = R^{-1}; counters: device int32[16] ([0] = number
      of pivots declared dependent).  ws >= rf_test_chol_ws(N) bytes.
    rf_test_eig: eigenpairs of symmetric G (N x N FP64, ld N, preserved): lam
-     (N, descending), V (N x N, ld N); sweep_trace (device double[32] or NULL)
-     receives the per-sweep convergence measure max |g_ij| / max(1e-12
-     sqrt|g_ii g_jj|, 16 eps ||G||_F) (converged when <= 1; 0 once converged).
-     ws >= rf_test_eig_ws(N) bytes; N <= 4096. */
+     (N, descending), V (N x N, ld N), block Jacobi stopped when every
+     |g_ij| <= max(tol sqrt|g_ii g_jj|, 16 eps ||G||_F) (rf_svd and rf_nystrom
+     use tol = 1e-7); sweep_trace (device double[32] or NULL) receives the
+     per-sweep value of max |g_ij| / max(...) (converged when <= 1; 0 once
+     converged).  ws >= rf_test_eig_ws(N) bytes; N <= 4096. */
 size_t rf_test_gemm_ws(int64_t M, int64_t N, int64_t K);
 rf_status rf_test_gemm(int dtype, int a_kc, int b_kc, const void* A, int64_t lda, const void* B, int64_t ldb,
                        float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, int b_upper, void* ws,
@@ -181,8 +182,8 @@ rf_status rf_test_gram(const float* X, const float* Y, int64_t K, int64_t M, int
 size_t rf_test_chol_ws(int64_t N);
 rf_status rf_test_cholqr_factor(double* G, int64_t N, double* Rinv, int32_t* counters, void* ws, void* stream);
 size_t rf_test_eig_ws(int64_t N);
-rf_status rf_test_eig(const double* G, int64_t N, double* lam, double* V, double* sweep_trace, void* ws,
-                      void* stream);
+rf_status rf_test_eig(const double* G, int64_t N, double tol, double* lam, double* V, double* sweep_trace,
+                      void* ws, void* stream);
 
 const char* rf_status_string(rf_status s);
 

@@ -105,7 +105,7 @@ def lib():
         L.rf_test_eig_ws.restype = sz
         L.rf_test_eig_ws.argtypes = [i64]
         L.rf_test_eig.restype = i32
-        L.rf_test_eig.argtypes = [vp, i64, vp, vp, vp, vp, vp]
+        L.rf_test_eig.argtypes = [vp, i64, ctypes.c_double, vp, vp, vp, vp, vp]
         _lib = L
     return _lib
 
@@ -289,14 +289,15 @@ def rf_test_cholqr_factor(G):
     return G, Rinv, counters
 
 
-def rf_test_eig(G, trace=False):
+def rf_test_eig(G, trace=False, tol=1e-12):
     N = G.shape[0]
     G = G.contiguous()
     lam = torch.empty(N, dtype=torch.float64, device=G.device)
     V = torch.empty((N, N), dtype=torch.float64, device=G.device)
     tr = torch.zeros(32, dtype=torch.float64, device=G.device) if trace else None
     ws = torch.empty(int(lib().rf_test_eig_ws(N)), dtype=torch.uint8, device=G.device)
-    _check("rf_test_eig", lib().rf_test_eig(_ptr(G), N, _ptr(lam), _ptr(V), _ptr(tr), _ptr(ws), _stream(G.device)))
+    _check("rf_test_eig", lib().rf_test_eig(_ptr(G), N, float(tol), _ptr(lam), _ptr(V), _ptr(tr), _ptr(ws),
+                                            _stream(G.device)))
     return (lam, V, tr) if trace else (lam, V)
 
 

@@ -65,9 +65,13 @@ size_t tri_inverse_work_doubles(int64_t N);
 size_t eig_work_bytes(int64_t N);
 // trace (optional, device, >= eig_max_sweeps() doubles): per-sweep convergence measure
 // (<= 1 means converged; 0 after convergence).
+// Relative tolerance used for FP32 outputs (U, V, F): eigenvalue errors are second
+// order in it and the computed V = B^T U Sigma^{-1} is orthonormal to about tol.
+constexpr double kEigTolFP32 = 1e-7;
 int eig_max_sweeps();
+// tol: converged when every |g_ij| <= max(tol sqrt|g_ii g_jj|, 16 eps ||G||_F).
 hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
-                      hipStream_t st, double* trace = nullptr);
+                      hipStream_t st, double tol, double* trace = nullptr);
 
 // ---- utilities ----
 hipError_t launch_cast_f32_bf16(const float* in, int64_t ldi, uint16_t* out, int64_t ldo, int64_t rows, int64_t cols,

@@ -450,7 +450,7 @@ hipError_t launch_tri_inverse(const double* R, int64_t ld, int64_t N, double* ou
 // its rotation V (64 x 64) is applied to the rows/columns of G and to Z in a
 // second kernel, tile by tile, in place.  Converged when every off-diagonal
 // entry is <= tol * sqrt(|G_ii G_jj| + floor^2).
-constexpr int JB = 32, JS = 64;
+constexpr int JBMAX = 32, JSMAX = 64;  // largest block width supported by the workspace layout
 
 struct EigWork {
   double* Gp;      // K x K
@@ -462,16 +462,18 @@ struct EigWork {
   int* conv;       // 1
   double* floor2;  // 1: (1e-15 ||G||_F)^2, regularises rotation thresholds
   double* fabs_;   // 1: 16 eps ||G||_F, absolute convergence floor
+  double tol;      // relative off-diagonal tolerance
   int64_t K;
   int p;
 };
 
-static EigWork eig_layout(void* work, int64_t N) {
+static EigWork eig_layout(void* work, int64_t N, int JB) {
   EigWork w;
   int64_t K = ((N + 2 * JB - 1) / (2 * JB)) * (2 * JB);
   if (K < 2 * JB) K = 2 * JB;
   w.K = K;
   w.p = (int)(K / (2 * JB));
+  const int JS = 2 * JB;
   char* p = (char*)work;
   w.Gp = (double*)p; p += K * K * 8;
   w.Z = (double*)p; p += K * K * 8;
@@ -488,11 +490,14 @@ static EigWork eig_layout(void* work, int64_t N) {
 int eig_max_sweeps() { return 20; }
 
 size_t eig_work_bytes(int64_t N) {
-  int64_t K = ((N + 2 * JB - 1) / (2 * JB)) * (2 * JB);
-  if (K < 2 * JB) K = 2 * JB;
+  // sized for the smallest block width (most pairs) and the largest padding
+  const int JB = 16, JS = 32;
+  int64_t K = ((N + 2 * JBMAX - 1) / (2 * JBMAX)) * (2 * JBMAX);
+  if (K < 2 * JBMAX) K = 2 * JBMAX;
   int64_t p = K / (2 * JB);
+  (void)JB;
   return (size_t)(2 * K * K * 8 + p * JS * JS * 8 + ((K * 4 + 255) / 256) * 256 + ((p * 4 + 255) / 256) * 256 +
-                  4 * 256);
+                  4 * 256) + 4096;
 }
 
 RF_DEV int circle(int round, int i, int n) {  // position i of round in an n-player circle schedule
@@ -549,7 +554,9 @@ RF_DEV void jacobi_rot(double app, double aqq, double apq, double floor2, double
   s = t * c;
 }
 
-__global__ __launch_bounds__(256) void k_eig_solve(EigWork w, int round, int inner_sweeps) {
+template <int JB>
+__global__ __launch_bounds__(1024) void k_eig_solve(EigWork w, int round, int inner_sweeps) {
+  constexpr int JS = 2 * JB;
   if (*w.conv) return;
   extern __shared__ double sm[];
   double(*M)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm);
@@ -577,7 +584,7 @@ __global__ __launch_bounds__(256) void k_eig_solve(EigWork w, int round, int inn
     int a = e / JS, b = e % JS;
     if (a != b) {
       double d = sqrt(fabs(M[a][a])) * sqrt(fabs(M[b][b]));
-      if (!(fabs(M[a][b]) <= fmax(1e-12 * d, fabs_))) needed = 1;
+      if (!(fabs(M[a][b]) <= fmax(w.tol * d, fabs_))) needed = 1;
     }
   }
   if (threadIdx.x < JS - 1) {
@@ -665,7 +672,9 @@ __global__ __launch_bounds__(256) void k_eig_solve(EigWork w, int round, int inn
 }
 
 // Tiles (x, y): G[I_x, I_y] <- V_x^T G[I_x, I_y] V_y ; tiles for Z: Z[rows, I_x] <- Z[rows, I_x] V_x.
+template <int JB>
 __global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
+  constexpr int JS = 2 * JB;
   if (*w.conv) return;
   extern __shared__ double sm[];
   double(*T)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm);
@@ -692,40 +701,41 @@ __global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
       Vb[a][b] = idy_ ? (a == b ? 1.0 : 0.0) : vy[e];
     }
     __syncthreads();
-    double acc[4][4] = {};
+    constexpr int RT = JS / 16;
+    double acc[RT][RT] = {};
     for (int k = 0; k < JS; ++k) {  // U = T Vy
-      double t[4], v[4];
+      double t[RT], v[RT];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) t[u] = T[ty + 16 * u][k];
+      for (int u = 0; u < RT; ++u) t[u] = T[ty + 16 * u][k];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = Vb[k][tx + 16 * c];
+      for (int c = 0; c < RT; ++c) v[c] = Vb[k][tx + 16 * c];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < RT; ++u)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[u][c] += t[u] * v[c];
+        for (int c = 0; c < RT; ++c) acc[u][c] += t[u] * v[c];
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < RT; ++u)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) T[ty + 16 * u][tx + 16 * c] = acc[u][c];
+      for (int c = 0; c < RT; ++c) T[ty + 16 * u][tx + 16 * c] = acc[u][c];
     __syncthreads();
-    double o[4][4] = {};
+    double o[RT][RT] = {};
     for (int k = 0; k < JS; ++k) {  // Vx^T U
-      double a[4], t[4];
+      double a[RT], t[RT];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = Va[k][ty + 16 * u];
+      for (int u = 0; u < RT; ++u) a[u] = Va[k][ty + 16 * u];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) t[c] = T[k][tx + 16 * c];
+      for (int c = 0; c < RT; ++c) t[c] = T[k][tx + 16 * c];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < RT; ++u)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) o[u][c] += a[u] * t[c];
+        for (int c = 0; c < RT; ++c) o[u][c] += a[u] * t[c];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < RT; ++u)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < RT; ++c) {
         int a = ty + 16 * u, b = tx + 16 * c;
         w.Gp[ix(a) * w.K + iy(b)] = o[u][c];
       }
@@ -743,22 +753,23 @@ __global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
       Va[a][b] = vx[e];
     }
     __syncthreads();
-    double acc[4][4] = {};
+    constexpr int RT = JS / 16;
+    double acc[RT][RT] = {};
     for (int k = 0; k < JS; ++k) {
-      double t[4], v[4];
+      double t[RT], v[RT];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) t[u] = T[ty + 16 * u][k];
+      for (int u = 0; u < RT; ++u) t[u] = T[ty + 16 * u][k];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) v[c] = Va[k][tx + 16 * c];
+      for (int c = 0; c < RT; ++c) v[c] = Va[k][tx + 16 * c];
 #pragma unroll
-      for (int u = 0; u < 4; ++u)
+      for (int u = 0; u < RT; ++u)
 #pragma unroll
-        for (int c = 0; c < 4; ++c) acc[u][c] += t[u] * v[c];
+        for (int c = 0; c < RT; ++c) acc[u][c] += t[u] * v[c];
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < RT; ++u)
 #pragma unroll
-      for (int c = 0; c < 4; ++c) {
+      for (int c = 0; c < RT; ++c) {
         int64_t r = r0 + ty + 16 * u;
         if (r < w.K) w.Z[r * w.K + ix(tx + 16 * c)] = acc[u][c];
       }
@@ -775,7 +786,7 @@ __global__ void k_eig_check(EigWork w) {
       // converged when |g_ij| <= max(tol sqrt|g_ii g_jj|, 16 eps ||G||_F): r <= 1
       double g = w.Gp[idx];
       double d = sqrt(fabs(w.Gp[i * w.K + i])) * sqrt(fabs(w.Gp[j * w.K + j]));
-      r = fabs(g) / fmax(1e-12 * d, *w.fabs_);
+      r = fabs(g) / fmax(w.tol * d, *w.fabs_);
       if (!(r == r)) r = 2.0;  // NaN: keep iterating (and never claim convergence)
     }
   }
@@ -835,33 +846,41 @@ __global__ void k_eig_gather(EigWork w, int64_t N, double* V, int64_t ldv) {
   V[r * ldv + c] = w.Z[r * w.K + w.perm[c]];
 }
 
-hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
-                      hipStream_t st, double* trace) {
-  if (N == 0) return hipSuccess;
-  EigWork w = eig_layout(work, N);
-  if (w.K > 4096) return hipErrorInvalidValue;
+template <int JB>
+static void eig_rounds(EigWork w, int64_t N, hipStream_t st, double* trace) {
+  constexpr int JS = 2 * JB;
   int64_t KK = w.K * w.K;
-  hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, st, G, ld, N, w);
-  hipLaunchKernelGGL(k_eig_floor, dim3(1), dim3(256), 0, st, G, ld, N, w);
   size_t lds_solve = 2 * JS * (JS + 1) * sizeof(double);
   size_t lds_apply = 3 * JS * (JS + 1) * sizeof(double);
-  static bool attr = false;
-  if (!attr) {
-    hipFuncSetAttribute((const void*)k_eig_solve, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_solve);
-    hipFuncSetAttribute((const void*)k_eig_apply, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_apply);
-    attr = true;
-  }
+  hipFuncSetAttribute((const void*)k_eig_solve<JB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_solve);
+  hipFuncSetAttribute((const void*)k_eig_apply<JB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_apply);
   const int rounds = 2 * w.p - 1;
   const int max_sweeps = eig_max_sweeps();
   const int ntile = w.p * w.p + (int)(w.K / JS) * w.p;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int r = 0; r < rounds; ++r) {
-      hipLaunchKernelGGL(k_eig_solve, dim3(w.p), dim3(256), lds_solve, st, w, r, sw < 2 ? 2 : 1);
-      hipLaunchKernelGGL(k_eig_apply, dim3(ntile), dim3(256), lds_apply, st, w, r);
+      hipLaunchKernelGGL(k_eig_solve<JB>, dim3(w.p), dim3(1024), lds_solve, st, w, r, 1);
+      hipLaunchKernelGGL(k_eig_apply<JB>, dim3(ntile), dim3(256), lds_apply, st, w, r);
     }
     hipLaunchKernelGGL(k_eig_check, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, st, w);
     hipLaunchKernelGGL(k_eig_decide, dim3(1), dim3(1), 0, st, w, 1.0, trace, sw);
   }
+}
+
+int eig_block_width(int64_t N) { (void)N; return 32; }
+
+hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
+                      hipStream_t st, double tol, double* trace) {
+  if (N == 0) return hipSuccess;
+  const int JB = eig_block_width(N);
+  EigWork w = eig_layout(work, N, JB);
+  w.tol = tol;
+  if (w.K > 4096) return hipErrorInvalidValue;
+  int64_t KK = w.K * w.K;
+  hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, st, G, ld, N, w);
+  hipLaunchKernelGGL(k_eig_floor, dim3(1), dim3(256), 0, st, G, ld, N, w);
+  if (JB == 16) eig_rounds<16>(w, N, st, trace);
+  else eig_rounds<32>(w, N, st, trace);
   hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, st, w, N, lam);
   hipLaunchKernelGGL(k_eig_gather, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, w, N, V, ldv);
   return hipGetLastError();

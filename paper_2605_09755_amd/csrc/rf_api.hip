@@ -398,7 +398,7 @@ rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, 
   }
   // Ritz: B B^T = Ub diag(lam) Ub^T in FP64
   c.chk(launch_gram(s.Bt, k, 0, s.Bt, k, 0, d.n, k, k, 1, s.GB, k, gbig, nullptr, c.st));
-  c.chk(launch_eig(s.GB, k, k, s.lam, s.Ub, k, s.eigw, c.st));
+  c.chk(launch_eig(s.GB, k, k, s.lam, s.Ub, k, s.eigw, c.st, kEigTolFP32));
   c.chk(launch_sigma(s.lam, k, sigma, s.inv, c.st));
   c.chk(launch_cast_f64_f32(s.Ub, k, s.Ub32, k, k, k, c.st));
   // U = Q Ub ; V = B^T Ub Sigma^{-1} stored transposed as Vt
@@ -478,7 +478,7 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
   c.chk(launch_symmetrize64(y.W64, k, k, c.st));
   c.chk(launch_copy_f64(y.W64, k, W, ldw, k, k, c.st));
   if (F) {
-    c.chk(launch_eig(y.W64, k, k, y.lam, y.V, k, y.eigw, c.st));
+    c.chk(launch_eig(y.W64, k, k, y.lam, y.V, k, y.eigw, c.st, kEigTolFP32));
     c.chk(launch_nystrom_scale(y.lam, k, y.scale, c.st));
     c.chk(launch_cast_f64_f32(y.V, k, y.V32, k, k, k, c.st));
     gemm(c, 0, y.Cbuf, k, 1, y.V32, k, 0, F, ldf, n, k, k, nullptr, y.scale, 0);
@@ -532,11 +532,11 @@ rf_status rf_test_cholqr_factor(double* G, int64_t N, double* Rinv, int32_t* cou
 
 size_t rf_test_eig_ws(int64_t N) { return eig_work_bytes(N) + 256; }
 
-rf_status rf_test_eig(const double* G, int64_t N, double* lam, double* V, double* sweep_trace, void* ws,
+rf_status rf_test_eig(const double* G, int64_t N, double tol, double* lam, double* V, double* sweep_trace, void* ws,
                       void* stream) {
-  if (!G || !lam || !V || !ws || N < 1) return RF_EINVAL;
+  if (!G || !lam || !V || !ws || N < 1 || !(tol > 0.0)) return RF_EINVAL;
   if (N > 4096) return RF_EUNSUPPORTED;
-  return launch_eig(const_cast<double*>(G), N, N, lam, V, N, align_ws(ws), (hipStream_t)stream, sweep_trace) ==
+  return launch_eig(const_cast<double*>(G), N, N, lam, V, N, align_ws(ws), (hipStream_t)stream, tol, sweep_trace) ==
                  hipSuccess
              ? RF_OK
              : RF_EHIP;

@@ -169,13 +169,15 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_right_fx(
   constexpr int R = 64 / S;
   constexpr int NT = NW * 64;
   constexpr int64_t J = (int64_t)NW * G * 64 * CPL;  // columns per chunk
+  static_assert(R <= 32, "row flags are kept in one 32-bit mask");
   extern __shared__ int iacc[];
-  __shared__ unsigned wgmax;
+  __shared__ unsigned wgmax, wgbad;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * R;
   const int entries = wl * 64;
   for (int i = tid; i < entries; i += NT) iacc[i] = 0;
-  if (tid == 0) wgmax = 0u;
+  if (tid == 0) { wgmax = 0u; wgbad = 0u; }
+  unsigned bad = 0u;  // bit r: row row0 + r holds a non-finite value
   float facc[FACC];
 #pragma unroll
   for (int i = 0; i < FACC; ++i) facc[i] = 0.f;
@@ -204,7 +206,13 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_right_fx(
         }
 #pragma unroll
         for (int e = 0; e < CPL; ++e) {
-          if constexpr (sizeof(TIN) == 1) a[g][p][e] *= sc;
+          float v = a[g][p][e];
+          if constexpr (sizeof(TIN) == 1) v *= sc;
+          // non-finite entries are kept out of the integer sums (they would wreck
+          // the chunk scale); their rows are set to NaN at the end instead
+          const bool fin = isfinite(v);
+          bad |= fin ? 0u : (1u << (rbits ^ p));
+          a[g][p][e] = fin ? v : 0.f;
           mx = fmaxf(mx, fabsf(a[g][p][e]));
         }
       }
@@ -270,6 +278,11 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_right_fx(
     if (tid == 0) wgmax = 0u;
     __syncthreads();
   }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
+  if (lane == 0 && bad) atomicOr(&wgbad, bad);
+  __syncthreads();
+  const unsigned rows_bad = wgbad;
   // write out: entry idx = b*64 + slot, slot = r*S + t -> At[row0 + r][lo_t + b]
 #pragma unroll
   for (int i = 0; i < FACC; ++i) {
@@ -280,7 +293,8 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_right_fx(
     const int64_t row = row0 + r;
     if (r >= R || row >= m) continue;
     const int lo = (int)(((int64_t)t * r1) / S), hi = (int)(((int64_t)(t + 1) * r1) / S);
-    if (b < hi - lo) out[row * ldo + lo + b] = facc[i] * inv_sqrt_s;
+    const float v = ((rows_bad >> r) & 1u) ? __builtin_nanf("") : facc[i] * inv_sqrt_s;
+    if (b < hi - lo) out[row * ldo + lo + b] = v;
   }
 }
 

@@ -114,4 +114,5 @@ def test_hooks_reject_bad_args():
     assert L.rf_sketch_table(10, 6, 5, 1, 0, 0, FAKE, None) == rf.RF_EINVAL
     assert L.rf_gaussian(-1, 5, 1, 1, 0, FAKE, None) == rf.RF_EINVAL
     assert L.rf_test_gemm(1, 1, 1, FAKE, 4, FAKE, 4, FAKE, 4, 4, 4, 4, 0, None, None) == rf.RF_EINVAL
-    assert L.rf_test_eig(FAKE, 5000, FAKE, FAKE, None, FAKE, None) == rf.RF_EUNSUPPORTED
+    assert L.rf_test_eig(FAKE, 5000, 1e-12, FAKE, FAKE, None, FAKE, None) == rf.RF_EUNSUPPORTED
+    assert L.rf_test_eig(FAKE, 50, 0.0, FAKE, FAKE, None, FAKE, None) == rf.RF_EINVAL

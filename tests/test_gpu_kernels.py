@@ -91,6 +91,27 @@ def test_sketch_apply_fp8_block_scaled(m, n, s, r1):
     assert np.all(np.abs(got - ref) <= (n * s / r1 + 8) * 4 * U32 * mag + 1e-30)
 
 
+@pytest.mark.parametrize("s", [1, 3, 8])
+def test_sketch_apply_nonfinite_rows(s):
+    """A row holding NaN or Inf gives a non-finite row of AS (the FP32 sum over
+    it is non-finite in the buckets it touches); every other row is unaffected."""
+    rng = np.random.default_rng(21)
+    m, n, r1 = 70, 900, 64
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    A[3, 17] = np.nan
+    A[40, 800] = np.inf
+    A[41, 0] = -np.inf
+    clean = np.ones(m, dtype=bool)
+    clean[[3, 40, 41]] = False
+    A64 = np.where(np.isfinite(A), A, 0.0).astype(np.float64)
+    ref, mag = _sketch_ref(A64, n, s, r1, 31)
+    got = rf.rf_sketch_apply(torch.from_numpy(A).to(DEV), r1, s, 31).cpu().numpy()
+    tol = (n * s / r1 + 8) * 4 * U32 * mag + 1e-30
+    assert np.all(np.abs(got[clean] - ref[clean]) <= tol[clean])
+    for i in np.flatnonzero(~clean):
+        assert not np.all(np.isfinite(got[i]))
+
+
 # ---------------------------------------------------------------- K5/K6 GEMM
 def _operands(M, N, K, a_kc, b_kc, rng, bf16):
     A = rng.standard_normal((M, K))
@@ -209,3 +230,28 @@ def test_eig(N, kind):
     else:
         assert e_lam <= 1e-12 * max(1, math.sqrt(N))
         assert e_res <= 1e-10
+
+
+@pytest.mark.parametrize("N", [100, 1000])
+def test_eig_fp32_output_tolerance(N):
+    """The tolerance rf_svd / rf_nystrom use (1e-7): Ritz-like spectrum with a
+    clustered tail; sigma = sqrt(lambda) to 1e-7 relative, residual and
+    orthonormality at the FP32 level."""
+    rng = np.random.default_rng(N + 1)
+    sig = np.maximum(np.arange(1, N + 1) ** -1.5, 1e-4 * rng.uniform(0.33, 1.0, N))
+    sig = np.sort(sig)[::-1]
+    Q, _ = np.linalg.qr(rng.standard_normal((N, N)))
+    G = (Q * sig ** 2) @ Q.T
+    G = 0.5 * (G + G.T)
+    lam, V, tr = rf.rf_test_eig(torch.from_numpy(G).to(DEV), trace=True, tol=1e-7)
+    lam, V = lam.cpu().numpy(), V.cpu().numpy()
+    ref = np.sort(np.linalg.eigvalsh(G))[::-1]
+    print("sweep trace", tr.cpu().numpy()[:21])
+    s_g, s_r = np.sqrt(np.maximum(lam, 0)), np.sqrt(np.maximum(ref, 0))
+    assert np.max(np.abs(s_g - s_r) / s_r) < 1e-7
+    assert np.max(np.abs(V.T @ V - np.eye(N))) < 1e-10
+    # off-diagonal of V^T G V relative to sqrt(l_i l_j) is the tolerance
+    D = V.T @ G @ V
+    d = np.sqrt(np.abs(np.diag(D)))
+    off = np.abs(D - np.diag(np.diag(D))) / np.maximum(np.outer(d, d), 16 * 2.2e-16 * np.linalg.norm(G) / 1e-7)
+    assert off.max() < 2e-7
