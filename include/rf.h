@@ -157,7 +157,8 @@ rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, in
 
 /* Kernel-level hooks used by the parity tests (same kernels as above).
    rf_test_gemm: C (M x N FP32, ldc) = op(A) op(B); dtype 0 = FP32 operands,
-     2 = BF16 operands (uint16 bits); a_kc != 0: op(A)(i,k) = A[i*lda+k] else
+     2 = BF16 operands (uint16 bits), 4 = A FP32 rounded to BF16 (RNE) as it is
+     loaded with B BF16 (BF16 MFMA, FP32 accumulation); a_kc != 0: op(A)(i,k) = A[i*lda+k] else
      A[k*lda+i]; b_kc != 0: op(B)(k,j) = B[j*ldb+k] else B[k*ldb+j];
      b_upper != 0 promises op(B)(k,j) = 0 for k > j.  ws: >= rf_test_gemm_ws(M,N,K)
      bytes (split-K partials), may be NULL to disable split-K.

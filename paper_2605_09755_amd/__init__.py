@@ -257,7 +257,12 @@ def rf_nystrom(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scale
 def rf_test_gemm(A, B, M, N, K, a_kc, b_kc, b_upper=False, split=True):
     """C = op(A) op(B) (FP32 out) with the library's MFMA GEMM.  A, B: float32 or
     bfloat16 device tensors in the layouts described in include/rf.h."""
-    dtype = 0 if A.dtype == torch.float32 else 2
+    if A.dtype == torch.float32 and B.dtype == torch.bfloat16:
+        dtype = 4                      # A rounded to BF16 as it is loaded
+    elif A.dtype == torch.float32:
+        dtype = 0
+    else:
+        dtype = 2
     lda = A.stride(0)
     ldb = B.stride(0)
     C = torch.empty((M, N), dtype=torch.float32, device=A.device)

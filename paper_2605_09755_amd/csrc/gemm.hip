@@ -331,6 +331,210 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       }
 }
 
+// ---------------- BF16 operands, 256 x 256 tiles ----------------------------------------
+// For the large products (Q^T A, the power-loop products at full size).  4 waves,
+// each 128 x 128 = 4 x 4 MFMA 32x32x16 blocks (256 accumulators per lane).  LDS
+// keeps every operand tile in the layout it has in memory, so global loads and LDS
+// stores are 16-byte vectors on both layouts:
+//  * k-contiguous operands: rows of 32 k (+8 pad, 80 B: 16 lanes reading 16 B each
+//    hit 16 disjoint bank quads); a lane's 8 k values are one ds_read_b128;
+//  * m/n-contiguous operands: rows of 256 (+32 pad, 576 B = 64 mod 256 B, so the 8
+//    rows touched by one read fall on two disjoint sets of bank columns); a lane's
+//    8 k values come from two ds_read_b64_tr_b16, which hand lane i of a 16-lane
+//    group element i%4 of the 8-byte chunks addressed by lanes i/4, i/4+4, i/4+8,
+//    i/4+12 -- so when lane s of the group addresses row k0+s/4, column c0+4(s%4),
+//    lane i receives column c0+i at rows k0..k0+3.
+// With AF32 the A operand is FP32 in memory and rounded to BF16 (RNE) on its way
+// into LDS.
+typedef __bf16 bf16x4v __attribute__((__vector_size__(4 * sizeof(__bf16))));
+constexpr int HB = 256, HBK = 32;
+constexpr int TRL = HB + 32;   // m/n-contiguous LDS row, bf16 elements
+constexpr int KRL = HBK + 8;   // k-contiguous LDS row, bf16 elements
+
+template <bool KC>
+constexpr int big_stage_elems() { return KC ? HB * KRL : HBK * TRL; }
+
+RF_DEV bf16x8 big_frag_kc(const uint16_t* S, int row, int k) {
+  return *reinterpret_cast<const bf16x8*>(S + row * KRL + k);
+}
+
+RF_DEV bf16x8 big_frag_tc(const uint16_t* S, int col0, int k0, int lane) {
+  const int g = lane >> 4, s = lane & 15;
+  const int col = col0 + 16 * (g & 1) + 4 * (s & 3);
+  const int kr = k0 + 8 * (g >> 1) + (s >> 2);
+  const uint16_t* p0 = S + kr * TRL + col;
+  const uint16_t* p1 = p0 + 4 * TRL;
+  bf16x4v lo = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((__attribute__((address_space(3))) bf16x4v*)p0);
+  bf16x4v hi = __builtin_amdgcn_ds_read_tr16_b64_v4bf16((__attribute__((address_space(3))) bf16x4v*)p1);
+  return __builtin_bit_cast(bf16x8, __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7));
+}
+
+RF_DEV uint4 pack8_bf16(float4 a, float4 b) {
+  return make_uint4((uint32_t)f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(a.y) << 16),
+                    (uint32_t)f32_to_bf16_rne(a.z) | ((uint32_t)f32_to_bf16_rne(a.w) << 16),
+                    (uint32_t)f32_to_bf16_rne(b.x) | ((uint32_t)f32_to_bf16_rne(b.y) << 16),
+                    (uint32_t)f32_to_bf16_rne(b.z) | ((uint32_t)f32_to_bf16_rne(b.w) << 16));
+}
+
+// One operand's share of a stage: 4 chunks of 8 consecutive elements per thread.
+// KC: chunk c -> row c/4 of the tile, k offset 8 (c%4); else k row c/32, column 8 (c%32).
+template <bool KC, bool F32>
+struct BigStage {
+  uint4 v[4];
+  float4 f[4][2];
+  RF_DEV void load(const void* P_, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, int64_t kend, bool vec,
+                   int tid) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tid + 256 * q;
+      const int64_t r = KC ? r0 + (c >> 2) : r0 + 8 * (c & 31);       // first m/n index of the chunk
+      const int64_t k = KC ? k0 + 8 * (c & 3) : k0 + (c >> 5);        // first k index of the chunk
+      const bool full = KC ? (r < rmax && k + 8 <= kend) : (k < kend && r + 8 <= rmax);
+      if constexpr (F32) {
+        const float* P = reinterpret_cast<const float*>(P_);
+        const float* src = KC ? P + r * ld + k : P + k * ld + r;
+        if (vec && full) {
+          f[q][0] = *reinterpret_cast<const float4*>(src);
+          f[q][1] = *reinterpret_cast<const float4*>(src + 4);
+        } else {
+          float t[8];
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const bool ok = KC ? (r < rmax && k + e < kend) : (k < kend && r + e < rmax);
+            t[e] = ok ? src[e] : 0.f;
+          }
+          f[q][0] = make_float4(t[0], t[1], t[2], t[3]);
+          f[q][1] = make_float4(t[4], t[5], t[6], t[7]);
+        }
+      } else {
+        const uint16_t* P = reinterpret_cast<const uint16_t*>(P_);
+        const uint16_t* src = KC ? P + r * ld + k : P + k * ld + r;
+        if (vec && full) {
+          v[q] = *reinterpret_cast<const uint4*>(src);
+        } else {
+          uint32_t w[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const bool ok0 = KC ? (r < rmax && k + 2 * e < kend) : (k < kend && r + 2 * e < rmax);
+            const bool ok1 = KC ? (r < rmax && k + 2 * e + 1 < kend) : (k < kend && r + 2 * e + 1 < rmax);
+            w[e] = (ok0 ? (uint32_t)src[2 * e] : 0u) | ((ok1 ? (uint32_t)src[2 * e + 1] : 0u) << 16);
+          }
+          v[q] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+      }
+    }
+  }
+  RF_DEV void store(uint16_t* S, int tid) const {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = tid + 256 * q;
+      uint16_t* dst = KC ? S + (c >> 2) * KRL + 8 * (c & 3) : S + (c >> 5) * TRL + 8 * (c & 31);
+      uint4 x;
+      if constexpr (F32) x = pack8_bf16(f[q][0], f[q][1]);
+      else x = v[q];
+      *reinterpret_cast<uint4*>(dst) = x;
+    }
+  }
+};
+
+template <bool AKC, bool BKC, bool AF32>
+__global__ __launch_bounds__(256, 1) void k_gemm_bf16_big(GemmArgs g) {
+  extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
+  constexpr int AS = big_stage_elems<AKC>(), BS = big_stage_elems<BKC>();
+  uint16_t* const A0 = smem;
+  uint16_t* const B0 = smem + 2 * AS;
+
+  const int ntm = (int)((g.M + HB - 1) / HB), ntn = (int)((g.N + HB - 1) / HB);
+  int tm, tn;
+  tile_coords(blockIdx.x, ntm, ntn, tm, tn);
+  const int64_t i0 = (int64_t)tm * HB, j0 = (int64_t)tn * HB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  int64_t kbeg = (int64_t)blockIdx.y * g.kps;
+  int64_t kend = min(g.K, kbeg + g.kps);
+  if (g.b_upper) kend = min(kend, j0 + HB);
+
+  const int aes = AF32 ? 4 : 2;
+  const bool avec = ((((uintptr_t)g.A) & 15) == 0) && ((g.lda * aes) % 16 == 0);
+  const bool bvec = ((((uintptr_t)g.B) & 15) == 0) && ((g.ldb * 2) % 16 == 0);
+
+  f32x16 acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  BigStage<AKC, AF32> sa;
+  BigStage<BKC, false> sb;
+  const int nk = kend > kbeg ? (int)((kend - kbeg + HBK - 1) / HBK) : 0;
+  if (nk > 0) {
+    sa.load(g.A, g.lda, i0, g.M, kbeg, kend, avec, tid);
+    sb.load(g.B, g.ldb, j0, g.N, kbeg, kend, bvec, tid);
+    sa.store(A0, tid);
+    sb.store(B0, tid);
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) {
+      const int64_t k1 = kbeg + (int64_t)(kt + 1) * HBK;
+      sa.load(g.A, g.lda, i0, g.M, k1, kend, avec, tid);
+      sb.load(g.B, g.ldb, j0, g.N, k1, kend, bvec, tid);
+    }
+    const uint16_t* A_ = A0 + buf * AS;
+    const uint16_t* B_ = B0 + buf * BS;
+#pragma unroll
+    for (int kk = 0; kk < HBK / 16; ++kk) {
+      bf16x8 af[4], bfr[4];
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+        af[a] = AKC ? big_frag_kc(A_, wm * 128 + 32 * a + (lane & 31), 16 * kk + 8 * (lane >> 5))
+                    : big_frag_tc(A_, wm * 128 + 32 * a, 16 * kk, lane);
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+        bfr[b] = BKC ? big_frag_kc(B_, wn * 128 + 32 * b + (lane & 31), 16 * kk + 8 * (lane >> 5))
+                     : big_frag_tc(B_, wn * 128 + 32 * b, 16 * kk, lane);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+    }
+    if (kt + 1 < nk) {
+      sa.store(A0 + (buf ^ 1) * AS, tid);
+      sb.store(B0 + (buf ^ 1) * BS, tid);
+    }
+    __syncthreads();
+  }
+
+  // Epilogue through LDS, one 64-row slab (rows 32a.. of both wave rows) at a time:
+  // the accumulator copy is fully unrolled (registers only), the global stores
+  // are row-contiguous across the workgroup.
+  constexpr int SLD = HB + 8;  // 264 floats: lanes 32..63 (4 rows down) land on the other 32 banks
+  float* St = reinterpret_cast<float*>(smem);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        St[(wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * SLD + wn * 128 + 32 * b + (lane & 31)] = acc[a][b][r];
+    __syncthreads();
+    for (int e = tid; e < 64 * HB; e += 256) {
+      const int rr = g.c_trans ? (e & 63) : (e / HB), cc = g.c_trans ? (e >> 6) : (e % HB);
+      const int64_t i = i0 + (rr >> 5) * 128 + 32 * a + (rr & 31), j = j0 + cc;
+      const float v = St[rr * SLD + cc];
+      if (g.partial) {
+        if (i < g.M && j < g.N) g.partial[((int64_t)blockIdx.y * g.M + i) * g.N + j] = v;
+      } else {
+        store_out(g, i, j, v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 __global__ void k_gemm_reduce(GemmArgs g, int splits) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= g.M * g.N) return;
@@ -357,14 +561,41 @@ int gemm_splits(int64_t M, int64_t N, int64_t K) {
   return s;
 }
 
+// 256 x 256 tiles: one workgroup per CU, so split K until the CUs are covered.
+static int gemm_splits_big(int64_t M, int64_t N, int64_t K) {
+  int64_t tiles = ((M + HB - 1) / HB) * ((N + HB - 1) / HB);
+  int s = 1;
+  while (tiles * s < cu_count() && K / (s * 2) >= 1024 && s < 64) s *= 2;
+  return s;
+}
+
+bool gemm_use_big(int dtype, int64_t M, int64_t N) {
+  if (dtype == 4) return true;
+  return dtype == 2 && M >= 512 && N >= 512;
+}
+
 size_t gemm_partial_floats(int64_t M, int64_t N, int64_t K) {
-  int s = gemm_splits(M, N, K);
+  int s1 = gemm_splits(M, N, K), s2 = gemm_splits_big(M, N, K);
+  int s = s1 > s2 ? s1 : s2;
   return s > 1 ? (size_t)s * M * N : 0;
+}
+
+template <bool AKC, bool BKC, bool AF32>
+static void go_big(const GemmArgs& g, dim3 grid, hipStream_t st) {
+  constexpr size_t lds = 2 * (size_t)(big_stage_elems<AKC>() + big_stage_elems<BKC>()) * sizeof(uint16_t);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_gemm_bf16_big<AKC, BKC, AF32>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_gemm_bf16_big<AKC, BKC, AF32>), grid, dim3(256), lds, st, g);
 }
 
 hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  int splits = partial ? gemm_splits(g.M, g.N, g.K) : 1;
+  const bool big = gemm_use_big(dtype, g.M, g.N);
+  int splits = partial ? (big ? gemm_splits_big(g.M, g.N, g.K) : gemm_splits(g.M, g.N, g.K)) : 1;
   if (g.b_upper) splits = 1;
   int64_t bk = 32;
   g.kps = ((g.K + splits - 1) / splits + bk - 1) / bk * bk;
@@ -372,7 +603,8 @@ hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
   splits = (int)((g.K + g.kps - 1) / g.kps);
   if (splits < 1) splits = 1;
   g.partial = splits > 1 ? partial : nullptr;
-  int64_t tiles = ((g.M + GBM - 1) / GBM) * ((g.N + GBN - 1) / GBN);
+  const int64_t bm = big ? HB : GBM, bn = big ? HB : GBN;
+  int64_t tiles = ((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
   dim3 grid((unsigned)tiles, (unsigned)splits);
   auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, g); };
   if (dtype == 0) {
@@ -380,11 +612,21 @@ hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
     else if (g.a_kc && !g.b_kc) go(k_gemm_f32<true, false>);
     else if (!g.a_kc && g.b_kc) go(k_gemm_f32<false, true>);
     else go(k_gemm_f32<false, false>);
+  } else if (dtype == 2 && big) {
+    if (g.a_kc && g.b_kc) go_big<true, true, false>(g, grid, st);
+    else if (g.a_kc && !g.b_kc) go_big<true, false, false>(g, grid, st);
+    else if (!g.a_kc && g.b_kc) go_big<false, true, false>(g, grid, st);
+    else go_big<false, false, false>(g, grid, st);
   } else if (dtype == 2) {
     if (g.a_kc && g.b_kc) go(k_gemm_bf16<true, true>);
     else if (g.a_kc && !g.b_kc) go(k_gemm_bf16<true, false>);
     else if (!g.a_kc && g.b_kc) go(k_gemm_bf16<false, true>);
     else go(k_gemm_bf16<false, false>);
+  } else if (dtype == 4) {
+    if (g.a_kc && g.b_kc) go_big<true, true, true>(g, grid, st);
+    else if (g.a_kc && !g.b_kc) go_big<true, false, true>(g, grid, st);
+    else if (!g.a_kc && g.b_kc) go_big<false, true, true>(g, grid, st);
+    else go_big<false, false, true>(g, grid, st);
   } else {
     return hipErrorInvalidValue;
   }

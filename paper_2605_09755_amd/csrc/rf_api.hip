@@ -492,7 +492,7 @@ size_t rf_test_gemm_ws(int64_t M, int64_t N, int64_t K) { return gemm_partial_fl
 
 rf_status rf_test_gemm(int dtype, int a_kc, int b_kc, const void* A, int64_t lda, const void* B, int64_t ldb, float* C,
                        int64_t ldc, int64_t M, int64_t N, int64_t K, int b_upper, void* ws, void* stream) {
-  if ((dtype != 0 && dtype != 2) || !A || !B || !C || M < 0 || N < 0 || K < 0 || ldc < N) return RF_EINVAL;
+  if ((dtype != 0 && dtype != 2 && dtype != 4) || !A || !B || !C || M < 0 || N < 0 || K < 0 || ldc < N) return RF_EINVAL;
   if ((a_kc ? lda < K : lda < M) || (b_kc ? ldb < K : ldb < N)) return RF_EINVAL;
   Ctx c;
   c.st = (hipStream_t)stream;

@@ -139,6 +139,35 @@ def test_gemm(bf16, a_kc, b_kc, M, N, K):
     assert np.all(np.abs(C - ref) <= (K + 2) * U32 * mag + 1e-30), np.max(np.abs(C - ref) / (mag + 1e-30))
 
 
+@pytest.mark.parametrize("a_kc,b_kc", [(1, 1), (1, 0), (0, 1), (0, 0)])
+@pytest.mark.parametrize("M,N,K", [(512, 512, 64), (600, 700, 300), (1030, 1000, 4100), (777, 520, 33)])
+def test_gemm_bf16_large_tiles(a_kc, b_kc, M, N, K):
+    """Shapes routed to the 256 x 256-tile BF16 kernel (several tiles, ragged
+    edges in M, N and K, split-K)."""
+    rng = np.random.default_rng(M + 5 * N + 11 * K)
+    dA, dB, A, B = _operands(M, N, K, a_kc, b_kc, rng, True)
+    for split in (True, False):
+        C = rf.rf_test_gemm(dA, dB, M, N, K, a_kc, b_kc, split=split).cpu().numpy()
+        mag = np.abs(A) @ np.abs(B)
+        assert np.all(np.abs(C - A @ B) <= (K + 2) * U32 * mag + 1e-30), np.max(np.abs(C - A @ B) / (mag + 1e-30))
+
+
+@pytest.mark.parametrize("a_kc,b_kc", [(1, 0), (0, 0), (0, 1)])
+@pytest.mark.parametrize("M,N,K", [(600, 700, 300), (300, 40, 1000)])
+def test_gemm_f32_a_rounded_on_load(a_kc, b_kc, M, N, K):
+    """A stored FP32 and rounded to BF16 (RNE) as it is loaded: the result is the
+    BF16 product of round(A) and B."""
+    rng = np.random.default_rng(M + N + K)
+    A32 = rng.standard_normal((M, K)).astype(np.float32)
+    At16, A = bf16_round(A32)
+    Bt, B = bf16_round(rng.standard_normal((K, N)))
+    Astore = torch.from_numpy(A32) if a_kc else torch.from_numpy(A32.T.copy())
+    Bstore = Bt.t().contiguous() if b_kc else Bt
+    C = rf.rf_test_gemm(Astore.to(DEV), Bstore.to(DEV), M, N, K, a_kc, b_kc).cpu().numpy()
+    mag = np.abs(A) @ np.abs(B)
+    assert np.all(np.abs(C - A @ B) <= (K + 2) * U32 * mag + 1e-30)
+
+
 @pytest.mark.parametrize("bf16", [False, True])
 def test_gemm_upper_triangular_b(bf16):
     rng = np.random.default_rng(9)
