@@ -6,14 +6,20 @@ Workload (synthetic, seeded; stands in for the paper's data matrices): A is
 Gaussians), sigma_i = i^-1.5 and E i.i.d. Gaussian with spectral size
 1e-4 sigma_1 (entry std 1e-4 / (sqrt(m) + sqrt(n))); k = 1000, sketch 2000,
 8 nonzeros per column of the sketch.  A is generated on the GPU with torch
-(input generation only), stored FP32 (plain form) and once in BF16 (mixed form).
+(input generation only) and stored FP32.  Plain form: FP32 MFMA products.
+Mixed form: the same FP32 A, BF16 MFMA products (A rounded to BF16 as Q^T A
+loads it), last power product FP32; `--forms fp32,mixed,mixed_bf16a` adds the
+form with A stored once in BF16.
 
 One step = one rf_svd call through the C ABI: sketch table, Omega, A S, the
 2q+1 power products with CholeskyQR re-orthonormalisation, final CholeskyQR2,
 B = Q^T A and the FP64 Rayleigh-Ritz SVD.  For each form the smallest q with
 error ratio <= 1.05 is found first (error evaluated untimed in FP64 from the
-outputs), then `--steps` steps at that q are timed with HIP events, inputs
-resident in HBM.  value = mixed-form seconds per factorisation.
+outputs); when a form's error plateaus above 1.05 (the sketched iteration
+converges to the top subspace of A S, Section 4) the target is the smallest
+ratio every form reaches, rounded up to 0.01.  Then `--steps` steps at the
+first q reaching the target are timed with HIP events, inputs resident in HBM.
+value = mixed-form seconds per factorisation.
 """
 import argparse
 import json
@@ -121,8 +127,10 @@ def main():
     bufs = {}
     # 1) accuracy sweep per form (untimed evaluation in FP64)
     for form in forms:
-        Ain = A16 if form == "mixed" else A
-        prec = "mixed" if form == "mixed" else "fp32"
+        # mixed: FP32 A in HBM, BF16 MFMA products (A rounded to BF16 as Q^T A loads it);
+        # mixed_bf16a: A stored once in BF16
+        Ain = A16 if form == "mixed_bf16a" else A
+        prec = "fp32" if form == "fp32" else "mixed"
         p = rf.params(k, l, args.qmax, s, 42, prec)
         nws = rf.rf_workspace_size(rf.RF_OP_SVD, Ain, p)
         ws = torch.empty(nws, dtype=torch.uint8, device=dev)

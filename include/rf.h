@@ -66,8 +66,12 @@ typedef enum {
 /* arithmetic form of the big products (A S, At Z, At^T Q, Q^T A) */
 typedef enum {
   RF_PREC_FP32 = 0,     /* plain: FP32 operands on FP32 MFMA */
-  RF_PREC_MIXED = 1     /* BF16 operands on BF16 MFMA (FP8 A: FP8 MFMA for Q^T A),
-                           FP32 accumulate, last power product in FP32 */
+  RF_PREC_MIXED = 1     /* BF16 operands on BF16 MFMA, FP32 accumulate; the last
+                           power product At Z stays FP32.  An FP32 A is rounded to
+                           BF16 as Q^T A loads it, so sigma and V carry BF16
+                           product error (~1e-3 relative) while the range of Q
+                           (and U) does not.  FP8 A is not accepted by rf_svd /
+                           rf_lowrank (RF_EUNSUPPORTED). */
 } rf_precision;
 /* In both forms the Gram matrices of CholeskyQR2, the Cholesky factors, the
    triangular inverses and the Rayleigh-Ritz eigenproblem are FP64. */
@@ -96,7 +100,8 @@ typedef struct {
 } rf_params;
 
 typedef struct {
-  int32_t status;       /* 0 = ok; bit 1 = Cholesky breakdown repaired; bit 2 = non-finite seen */
+  int32_t status;       /* 0 = ok; bit 1 = Cholesky breakdown repaired; bit 2 = non-finite seen;
+                           bit 4 = a device task queue gave up waiting (results invalid) */
   int32_t rank_found;   /* k minus columns refilled during orthonormalisation (last call) */
   int32_t chol_retries; /* number of CholeskyQR passes that needed column refill */
   int32_t nonfinite;    /* 1 if a NaN/Inf was seen in a Gram matrix */

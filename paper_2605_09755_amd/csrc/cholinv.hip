@@ -1,0 +1,325 @@
+// Cholesky factor and its inverse in one launch: G = R^T R (R upper, in place)
+// and X = R^{-1}, for the CholeskyQR passes (Q = Y R^{-1}; Algorithm 1, line 2).
+//
+// Blocked right-looking factorisation on 64 x 64 tiles, run as a persistent
+// kernel over a task list in dependency order.  Step kb has
+//   A(kb)     factor the diagonal tile: R_kk and X_kk = R_kk^{-1} (one workgroup);
+//   B(kb, j)  panel R_kb,j = X_kk^T G_kb,j for j > kb, and
+//   X(kb, i)  inverse column X_i,kb = -(sum_{l=i..kb-1} X_il R_l,kb) X_kk for i < kb;
+//   C(kb,i,j) trailing update G_ij -= R_kb,i^T R_kb,j for kb < i <= j.
+// Workgroups take task tickets from an atomic counter in this order and wait on
+// per-step completion counters: A(kb) on all C(kb-1), B/X(kb) on A(kb), C(kb) on
+// all B/X(kb).  A task only waits on tasks with smaller tickets, which are held
+// by running workgroups, so the queue drains without co-residency guarantees;
+// every wait is bounded and raises the fault word instead of hanging.
+// Completion is published with an agent-scope release (L2 write-back, the
+// workgroups sit on different XCDs) and observed with an acquire.
+#include "common.h"
+#include "kernels.h"
+
+namespace rf {
+
+constexpr int TB = 64;          // tile
+constexpr int TLD = TB + 1;     // LDS row stride (doubles)
+constexpr unsigned kSpinLimit = 1u << 20;  // polls of ~1 us: a stuck dependency ends the launch in ~1 s
+
+struct CholInvArgs {
+  double* G; int64_t ld; int64_t N;
+  double tol; const double* d0; int* flags; int* count; int* nonfinite;
+  const int* run_if;
+  double* X64; int64_t ldx64;   // R^{-1} in FP64 (required: later tasks read it)
+  float* X32; int64_t ldx32;    // optional FP32 copy
+  int* work;                    // [0] ticket, [1] unused, [2..2+nb) doneA, then doneB, doneC
+  int* fault;                   // set to 1 when a bounded wait gives up
+  int nb;
+};
+
+RF_DEV int nC_of(int nb, int kb) { int t = nb - 1 - kb; return t * (t + 1) / 2; }
+
+// Called by a whole wave (uniform branch); every lane polls the same word.  Gives
+// up after kSpinLimit polls, or at once when another wait has already given up.
+RF_DEV void wait_at_least(int* ctr, int target, int* err) {
+  unsigned spins = 0;
+  while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+    if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
+    __builtin_amdgcn_s_sleep(2);
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      break;
+    }
+  }
+  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+}
+
+RF_DEV void load_tile(double (*T)[TLD], const double* P, int64_t ld, int64_t r0, int64_t c0, int64_t N) {
+  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+    const int r = e / TB, c = e % TB;
+    T[r][c] = (r0 + r < N && c0 + c < N) ? P[(r0 + r) * ld + c0 + c] : 0.0;
+  }
+}
+
+// out[r][c] (+)= sum_l op(P)[r][l] Q[l][c] over a 64-deep tile product; P_TRANS: op(P) = P^T.
+template <bool P_TRANS>
+RF_DEV void tile_mac(double (&acc)[4][4], double (*P)[TLD], double (*Q)[TLD]) {
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  for (int l = 0; l < TB; ++l) {
+    double a[4], b[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) a[u] = P_TRANS ? P[l][ty + 16 * u] : P[ty + 16 * u][l];
+#pragma unroll
+    for (int v = 0; v < 4; ++v) b[v] = Q[l][tx + 16 * v];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
+  }
+}
+
+RF_DEV void put_x(const CholInvArgs& a, int64_t r, int64_t c, double v) {
+  if (r >= a.N || c >= a.N) return;
+  a.X64[r * a.ldx64 + c] = v;
+  if (a.X32) a.X32[r * a.ldx32 + c] = (float)v;
+}
+
+// A(kb): R_kk and X_kk in LDS, written to G and X.
+RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R)[TLD], double (*Xs)[TLD]) {
+  const int64_t b0 = (int64_t)kb * TB;
+  const int nbk = (int)min((int64_t)TB, a.N - b0);
+  load_tile(M, a.G, a.ld, b0, b0, a.N);
+  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+    R[e / TB][e % TB] = 0.0;
+    Xs[e / TB][e % TB] = 0.0;
+  }
+  __syncthreads();
+  for (int c = 0; c < nbk; ++c) {
+    const double d = M[c][c];
+    const bool fin = isfinite(d);
+    const bool bad = !(fin && d > a.tol * a.d0[b0 + c] && d > 0.0);
+    if (threadIdx.x == 0) {
+      if (!fin) *a.nonfinite = 1;
+      if (bad) {
+        a.flags[b0 + c] = 1;
+        atomicAdd(a.count, 1);
+      }
+    }
+    const double rs = bad ? 0.0 : 1.0 / sqrt(d);
+    for (int j = c + 1 + threadIdx.x; j < nbk; j += blockDim.x) R[c][j] = M[c][j] * rs;
+    if (threadIdx.x == 0) R[c][c] = bad ? 1.0 : sqrt(d);
+    if (!bad) {
+      const double id = 1.0 / d;
+      const int w = nbk - c - 1;
+      for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
+        const int i = c + 1 + e / w, j = c + 1 + e % w;
+        if (j >= i) M[i][j] -= M[c][i] * M[c][j] * id;
+      }
+    }
+    __syncthreads();
+  }
+  // X = R^{-1}, rows bottom-up: X_cc = 1/R_cc, X_cj = -X_cc sum_{l=c+1..j} R_cl X_lj
+  for (int c = nbk - 1; c >= 0; --c) {
+    const double inv = 1.0 / R[c][c];
+    for (int j = c + 1 + threadIdx.x; j < nbk; j += blockDim.x) {
+      double s = 0.0;
+      for (int l = c + 1; l <= j; ++l) s += R[c][l] * Xs[l][j];
+      Xs[c][j] = -s * inv;
+    }
+    if (threadIdx.x == 0) Xs[c][c] = inv;
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+    const int r = e / TB, c = e % TB;
+    if (r < nbk && c < nbk) {
+      a.G[(b0 + r) * a.ld + b0 + c] = (c >= r) ? R[r][c] : 0.0;
+      put_x(a, b0 + r, b0 + c, (c >= r) ? Xs[r][c] : 0.0);
+    }
+  }
+}
+
+// B(kb, j): G_kb,j <- X_kk^T G_kb,j, rows of dependent columns cleared.
+RF_DEV void task_panel(const CholInvArgs& a, int kb, int jb, double (*P)[TLD], double (*Q)[TLD]) {
+  const int64_t b0 = (int64_t)kb * TB, c0 = (int64_t)jb * TB;
+  load_tile(P, a.X64, a.ldx64, b0, b0, a.N);
+  load_tile(Q, a.G, a.ld, b0, c0, a.N);
+  __syncthreads();
+  double acc[4][4] = {};
+  tile_mac<true>(acc, P, Q);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = b0 + ty + 16 * u, c = c0 + tx + 16 * v;
+      if (r < a.N && c < a.N) a.G[r * a.ld + c] = a.flags[r] ? 0.0 : acc[u][v];
+    }
+}
+
+// X(kb, i): X_i,kb = -(sum_l X_il R_l,kb) X_kk ; the mirrored lower tile is cleared.
+RF_DEV void task_xcol(const CholInvArgs& a, int kb, int ib, double (*P)[TLD], double (*Q)[TLD]) {
+  const int64_t b0 = (int64_t)kb * TB, i0 = (int64_t)ib * TB;
+  double acc[4][4] = {};
+  for (int lb = ib; lb < kb; ++lb) {
+    const int64_t l0 = (int64_t)lb * TB;
+    __syncthreads();
+    load_tile(P, a.X64, a.ldx64, i0, l0, a.N);
+    load_tile(Q, a.G, a.ld, l0, b0, a.N);
+    __syncthreads();
+    tile_mac<false>(acc, P, Q);
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) P[ty + 16 * u][tx + 16 * v] = acc[u][v];
+  load_tile(Q, a.X64, a.ldx64, b0, b0, a.N);
+  __syncthreads();
+  double o[4][4] = {};
+  tile_mac<false>(o, P, Q);
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      put_x(a, i0 + ty + 16 * u, b0 + tx + 16 * v, -o[u][v]);
+      put_x(a, b0 + tx + 16 * v, i0 + ty + 16 * u, 0.0);
+    }
+}
+
+// C(kb, i, j): G_ij -= R_kb,i^T R_kb,j (upper tiles).
+RF_DEV void task_update(const CholInvArgs& a, int kb, int ib, int jb, double (*P)[TLD], double (*Q)[TLD]) {
+  const int64_t b0 = (int64_t)kb * TB, r0 = (int64_t)ib * TB, c0 = (int64_t)jb * TB;
+  load_tile(P, a.G, a.ld, b0, r0, a.N);
+  load_tile(Q, a.G, a.ld, b0, c0, a.N);
+  __syncthreads();
+  double acc[4][4] = {};
+  tile_mac<true>(acc, P, Q);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+#pragma unroll
+  for (int u = 0; u < 4; ++u)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = r0 + ty + 16 * u, c = c0 + tx + 16 * v;
+      if (r < a.N && c < a.N && c >= r) a.G[r * a.ld + c] -= acc[u][v];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_cholinv(CholInvArgs a) {
+  if (a.run_if && *a.run_if == 0) return;
+  extern __shared__ double sm[];
+  double(*T0)[TLD] = reinterpret_cast<double(*)[TLD]>(sm);
+  double(*T1)[TLD] = reinterpret_cast<double(*)[TLD]>(sm + TB * TLD);
+  double(*T2)[TLD] = reinterpret_cast<double(*)[TLD]>(sm + 2 * TB * TLD);
+  __shared__ int ticket;
+  const int nb = a.nb;
+  int* err = a.fault;
+  int* doneA = a.work + 2;
+  int* doneB = doneA + nb;
+  int* doneC = doneB + nb;
+  int total = 0;
+  for (int kb = 0; kb < nb; ++kb) total += 1 + (nb - 1) + nC_of(nb, kb);
+  // Control flow around the barriers must be uniform: the ticket and the waits are
+  // handled by wave 0 as a whole (a branch on the wave index, never on the lane),
+  // and the ticket is read back as a wave-uniform value.
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    if (wave == 0) {
+      const int old = __builtin_amdgcn_readfirstlane(atomicAdd(a.work, lane == 0 ? 1 : 0));
+      ticket = old;  // every lane of wave 0 stores the same value
+    }
+    __syncthreads();
+    int t = __builtin_amdgcn_readfirstlane(ticket);
+    __syncthreads();
+    if (t >= total) return;
+    int kb = 0;
+    for (;; ++kb) {
+      const int sz = 1 + (nb - 1) + nC_of(nb, kb);
+      if (t < sz) break;
+      t -= sz;
+    }
+    int* done;
+    if (t == 0) {  // A(kb)
+      if (wave == 0 && kb > 0) wait_at_least(&doneC[kb - 1], nC_of(nb, kb - 1), err);
+      __syncthreads();
+      task_diag(a, kb, T0, T1, T2);
+      done = &doneA[kb];
+    } else if (t < nb) {  // B(kb, j) or X(kb, i)
+      if (wave == 0) wait_at_least(&doneA[kb], 1, err);
+      __syncthreads();
+      const int u = t - 1;  // 0 .. nb-2
+      if (u < nb - 1 - kb) task_panel(a, kb, kb + 1 + u, T0, T1);
+      else task_xcol(a, kb, u - (nb - 1 - kb), T0, T1);
+      done = &doneB[kb];
+    } else {  // C(kb, i, j)
+      if (wave == 0) wait_at_least(&doneB[kb], nb - 1, err);
+      __syncthreads();
+      int u = t - nb, ib = kb + 1, w = nb - 1 - kb;
+      while (u >= w) { u -= w; ++ib; --w; }
+      task_update(a, kb, ib, ib + u, T0, T1);
+      done = &doneC[kb];
+    }
+    __syncthreads();
+    if (wave == 0) {
+      __atomic_thread_fence(__ATOMIC_RELEASE);
+      __hip_atomic_fetch_add(done, lane == 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+__global__ void k_cholinv_prep(const double* __restrict__ G, int64_t ld, int64_t N, double* __restrict__ d0,
+                               int* __restrict__ flags, int* count, const int* run_if, int* work, int nwork) {
+  if (run_if && *run_if == 0) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i == 0) *count = 0;
+  if (i < N) {
+    d0[i] = G[i * ld + i];
+    flags[i] = 0;
+  }
+  if (i < nwork) work[i] = 0;
+}
+
+size_t cholinv_work_ints(int64_t N) {
+  const int64_t nb = (N + TB - 1) / TB;
+  return (size_t)(2 + 3 * nb);
+}
+
+static int cu_count_ci() {
+  static int n = 0;
+  if (!n) {
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev);
+    if (n <= 0) n = 256;
+  }
+  return n;
+}
+
+hipError_t launch_cholinv(double* G, int64_t ld, int64_t N, double tol_ratio, double* d0, int* flags, int* count,
+                          int* nonfinite, int* fault, const int* run_if, double* X64, int64_t ldx64, float* X32,
+                          int64_t ldx32, int* work, hipStream_t st) {
+  if (N == 0) return hipSuccess;
+  const int nb = (int)((N + TB - 1) / TB);
+  const int nwork = (int)cholinv_work_ints(N);
+  const int64_t nprep = N > nwork ? N : nwork;
+  hipLaunchKernelGGL(k_cholinv_prep, dim3((unsigned)((nprep + 255) / 256)), dim3(256), 0, st, G, ld, N, d0, flags,
+                     count, run_if, work, nwork);
+  CholInvArgs a;
+  a.G = G; a.ld = ld; a.N = N;
+  a.tol = tol_ratio; a.d0 = d0; a.flags = flags; a.count = count; a.nonfinite = nonfinite;
+  a.run_if = run_if;
+  a.X64 = X64; a.ldx64 = ldx64; a.X32 = X32; a.ldx32 = ldx32;
+  a.work = work; a.fault = fault; a.nb = nb;
+  int total = 0;
+  for (int kb = 0; kb < nb; ++kb) total += 1 + (nb - 1) + (nb - 1 - kb) * (nb - kb) / 2;
+  int grid = cu_count_ci();
+  if (grid > total) grid = total;
+  const size_t lds = 3 * (size_t)TB * TLD * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_cholinv, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_cholinv, dim3((unsigned)grid), dim3(256), lds, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace rf

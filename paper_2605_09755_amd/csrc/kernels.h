@@ -51,15 +51,16 @@ size_t gram_partial_doubles(int64_t K, int64_t M, int64_t N);
 hipError_t launch_gram(const void* X, int64_t ldx, int xdt, const void* Y, int64_t ldy, int ydt, int64_t K,
                        int64_t M, int64_t N, int sym, double* C, int64_t ldc, double* partial, const int* run_if,
                        hipStream_t st);
-// In-place upper Cholesky G = R^T R (N x N, ld).  Pivots below tol_ratio * (original
-// diagonal) are declared deficient: flags[c] = 1, row c of R set to e_c, *count += 1.
-// d0 (N doubles) receives the original diagonal.  info: int32[4] {count, retries, nonfinite, -}.
-hipError_t launch_cholesky(double* G, int64_t ld, int64_t N, double tol_ratio, double* d0, int* flags, int* count,
-                           int* nonfinite, const int* run_if, hipStream_t st);
-// Rinv = R^{-1} for upper-triangular R (N x N, ld); out64 (ld64) and/or out32 (ld32).
-hipError_t launch_tri_inverse(const double* R, int64_t ld, int64_t N, double* out64, int64_t ld64, float* out32,
-                              int64_t ld32, double* work, hipStream_t st);
-size_t tri_inverse_work_doubles(int64_t N);
+// In-place upper Cholesky G = R^T R and X = R^{-1} (upper, lower triangle zeroed) in
+// one persistent launch.  Pivots below tol_ratio * (original diagonal) are declared
+// deficient: flags[c] = 1, row c of R set to e_c, *count += 1; d0 (N doubles)
+// receives the original diagonal; *nonfinite = 1 on a non-finite pivot.  X64 (N x N,
+// ldx64) is required, X32 optional.  work: device int[cholinv_work_ints(N)].
+// *fault = 1 if a bounded wait between tasks gave up.
+size_t cholinv_work_ints(int64_t N);
+hipError_t launch_cholinv(double* G, int64_t ld, int64_t N, double tol_ratio, double* d0, int* flags, int* count,
+                          int* nonfinite, int* fault, const int* run_if, double* X64, int64_t ldx64, float* X32,
+                          int64_t ldx32, int* work, hipStream_t st);
 // Symmetric eigen-decomposition (block Jacobi).  G (N x N, ld) is destroyed.
 // lam (N, descending), V (N x N, ldv, column c = eigenvector of lam[c]).
 size_t eig_work_bytes(int64_t N);

@@ -165,283 +165,6 @@ hipError_t launch_gram(const void* X, int64_t ldx, int xdt, const void* Y, int64
   return hipGetLastError();
 }
 
-// ============================== Cholesky (upper, in place) ==============================
-constexpr int CB = 64;
-
-__global__ void k_chol_prep(const double* __restrict__ G, int64_t ld, int64_t N, double* __restrict__ d0,
-                            int* __restrict__ flags, int* count, const int* run_if) {
-  if (run_if && *run_if == 0) return;
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i == 0) *count = 0;
-  if (i < N) {
-    d0[i] = G[i * ld + i];
-    flags[i] = 0;
-  }
-}
-
-__global__ __launch_bounds__(256) void k_chol_diag(double* __restrict__ G, int64_t ld, int64_t N, int kb,
-                                                   double tol, const double* __restrict__ d0, int* __restrict__ flags,
-                                                   int* count, int* nonfinite, const int* run_if) {
-  if (run_if && *run_if == 0) return;
-  __shared__ double A[CB][CB + 1];
-  __shared__ double piv;
-  __shared__ int bad;
-  const int64_t b0 = (int64_t)kb * CB;
-  const int nb = (int)min((int64_t)CB, N - b0);
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    int i = e / CB, j = e % CB;
-    A[i][j] = (i < nb && j < nb) ? G[(b0 + i) * ld + b0 + j] : 0.0;
-  }
-  __syncthreads();
-  for (int c = 0; c < nb; ++c) {
-    if (threadIdx.x == 0) {
-      double d = A[c][c];
-      double ref = d0[b0 + c];
-      bool fin = isfinite(d);
-      if (!fin) *nonfinite = 1;
-      if (fin && d > tol * ref && d > 0.0) {
-        piv = sqrt(d);
-        bad = 0;
-      } else {
-        piv = 1.0;
-        bad = 1;
-        flags[b0 + c] = 1;
-        atomicAdd(count, 1);
-      }
-    }
-    __syncthreads();
-    for (int j = c + 1 + threadIdx.x; j < nb; j += blockDim.x) A[c][j] = bad ? 0.0 : A[c][j] / piv;
-    if (threadIdx.x == 0) A[c][c] = piv;
-    __syncthreads();
-    int w = nb - c - 1;
-    for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-      int i = c + 1 + e / w, j = c + 1 + e % w;
-      if (j >= i) A[i][j] -= A[c][i] * A[c][j];
-    }
-    __syncthreads();
-  }
-  for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-    int i = e / nb, j = e % nb;
-    G[(b0 + i) * ld + b0 + j] = (j >= i) ? A[i][j] : 0.0;
-  }
-}
-
-// R12 = R11^{-T} G12 for every block column right of kb.
-__global__ __launch_bounds__(64) void k_chol_panel(double* __restrict__ G, int64_t ld, int64_t N, int kb,
-                                                   const int* __restrict__ flags, const int* run_if) {
-  if (run_if && *run_if == 0) return;
-  __shared__ double R[CB][CB + 1];
-  const int64_t b0 = (int64_t)kb * CB;
-  const int nb = (int)min((int64_t)CB, N - b0);
-  const int64_t c0 = b0 + CB + (int64_t)blockIdx.x * CB;
-  const int nc = (int)min((int64_t)CB, N - c0);
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    int i = e / CB, j = e % CB;
-    R[i][j] = (i < nb && j < nb) ? G[(b0 + i) * ld + b0 + j] : 0.0;
-  }
-  __syncthreads();
-  const int j = threadIdx.x;
-  if (j >= nc) return;
-  double x[CB];
-#pragma unroll
-  for (int r = 0; r < CB; ++r) x[r] = (r < nb) ? G[(b0 + r) * ld + c0 + j] : 0.0;
-#pragma unroll
-  for (int r = 0; r < CB; ++r) {
-    if (r < nb) {
-      double s = x[r];
-#pragma unroll
-      for (int t = 0; t < r; ++t) s -= R[t][r] * x[t];
-      x[r] = flags[b0 + r] ? 0.0 : s / R[r][r];
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < CB; ++r)
-    if (r < nb) G[(b0 + r) * ld + c0 + j] = x[r];
-}
-
-// Trailing update of upper tiles (ib <= jb) right/below of block kb.
-__global__ __launch_bounds__(256) void k_chol_update(double* __restrict__ G, int64_t ld, int64_t N, int kb,
-                                                     const int* run_if) {
-  if (run_if && *run_if == 0) return;
-  __shared__ double P[CB][CB];
-  __shared__ double Qm[CB][CB];
-  const int64_t b0 = (int64_t)kb * CB;
-  const int nb = (int)min((int64_t)CB, N - b0);
-  const int nt = (int)((N - b0 - CB + CB - 1) / CB);
-  int ti, tj;
-  upper_tile(blockIdx.x, nt, ti, tj);
-  const int64_t r0 = b0 + CB + (int64_t)ti * CB, q0 = b0 + CB + (int64_t)tj * CB;
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    int k = e / CB, c = e % CB;
-    P[k][c] = (k < nb && r0 + c < N) ? G[(b0 + k) * ld + r0 + c] : 0.0;
-    Qm[k][c] = (k < nb && q0 + c < N) ? G[(b0 + k) * ld + q0 + c] : 0.0;
-  }
-  __syncthreads();
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4] = {};
-  for (int k = 0; k < nb; ++k) {
-    double p[4], qv[4];
-#pragma unroll
-    for (int a = 0; a < 4; ++a) p[a] = P[k][ty + 16 * a];
-#pragma unroll
-    for (int b = 0; b < 4; ++b) qv[b] = Qm[k][tx + 16 * b];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += p[a] * qv[b];
-  }
-#pragma unroll
-  for (int a = 0; a < 4; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      int64_t i = r0 + ty + 16 * a, j = q0 + tx + 16 * b;
-      if (i < N && j < N && j >= i) G[i * ld + j] -= acc[a][b];
-    }
-}
-
-hipError_t launch_cholesky(double* G, int64_t ld, int64_t N, double tol_ratio, double* d0, int* flags, int* count,
-                           int* nonfinite, const int* run_if, hipStream_t st) {
-  if (N == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_chol_prep, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, st, G, ld, N, d0, flags, count,
-                     run_if);
-  int nblk = (int)((N + CB - 1) / CB);
-  for (int kb = 0; kb < nblk; ++kb) {
-    hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(256), 0, st, G, ld, N, kb, tol_ratio, d0, flags, count, nonfinite,
-                       run_if);
-    int nt = nblk - kb - 1;
-    if (nt > 0) {
-      hipLaunchKernelGGL(k_chol_panel, dim3(nt), dim3(64), 0, st, G, ld, N, kb, flags, run_if);
-      hipLaunchKernelGGL(k_chol_update, dim3(nt * (nt + 1) / 2), dim3(256), 0, st, G, ld, N, kb, run_if);
-    }
-  }
-  return hipGetLastError();
-}
-
-// ============================== triangular inverse ==============================
-__global__ void k_zero64(double* p, int64_t n) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0.0;
-}
-
-// X_bb = R_bb^{-1} for every diagonal block; X is N x N with ld N.
-__global__ __launch_bounds__(64) void k_trinv_diag(const double* __restrict__ R, int64_t ld, int64_t N,
-                                                   double* __restrict__ X) {
-  __shared__ double Rs[CB][CB + 1];
-  const int64_t b0 = (int64_t)blockIdx.x * CB;
-  const int nb = (int)min((int64_t)CB, N - b0);
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    int i = e / CB, j = e % CB;
-    Rs[i][j] = (i < nb && j < nb) ? R[(b0 + i) * ld + b0 + j] : 0.0;
-  }
-  __syncthreads();
-  const int j = threadIdx.x;  // column of the inverse
-  if (j >= nb) return;
-  double x[CB];
-#pragma unroll
-  for (int r = CB - 1; r >= 0; --r) {
-    if (r < nb) {
-      double s = (r == j) ? 1.0 : 0.0;
-#pragma unroll
-      for (int c = r + 1; c < CB; ++c)
-        if (c < nb) s -= Rs[r][c] * x[c];
-      x[r] = (r > j) ? 0.0 : s / Rs[r][r];
-    } else {
-      x[r] = 0.0;
-    }
-  }
-#pragma unroll
-  for (int r = 0; r < CB; ++r)
-    if (r < nb) X[(b0 + r) * N + b0 + j] = x[r];
-}
-
-// Block diagonal d: X_ij = -X_ii * sum_{l=i+1..j} R_il X_lj, j = i + d.
-__global__ __launch_bounds__(256) void k_trinv_off(const double* __restrict__ R, int64_t ld, int64_t N, int d,
-                                                   double* __restrict__ X) {
-  __shared__ double Ta[CB][CB];
-  __shared__ double Tb[CB][CB];
-  const int ib = blockIdx.x, jb = ib + d;
-  const int64_t i0 = (int64_t)ib * CB, j0 = (int64_t)jb * CB;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double acc[4][4] = {};
-  for (int lb = ib + 1; lb <= jb; ++lb) {
-    const int64_t l0 = (int64_t)lb * CB;
-    __syncthreads();
-    for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-      int r = e / CB, c = e % CB;
-      Ta[r][c] = (i0 + r < N && l0 + c < N) ? R[(i0 + r) * ld + l0 + c] : 0.0;
-      Tb[r][c] = (l0 + r < N && j0 + c < N) ? X[(l0 + r) * N + j0 + c] : 0.0;
-    }
-    __syncthreads();
-    for (int k = 0; k < CB; ++k) {
-      double a[4], b[4];
-#pragma unroll
-      for (int u = 0; u < 4; ++u) a[u] = Ta[ty + 16 * u][k];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) b[v] = Tb[k][tx + 16 * v];
-#pragma unroll
-      for (int u = 0; u < 4; ++u)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-    }
-  }
-  __syncthreads();
-  // T -> Tb, X_ii -> Ta
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) Tb[ty + 16 * u][tx + 16 * v] = acc[u][v];
-  for (int e = threadIdx.x; e < CB * CB; e += blockDim.x) {
-    int r = e / CB, c = e % CB;
-    Ta[r][c] = (i0 + r < N && i0 + c < N) ? X[(i0 + r) * N + i0 + c] : 0.0;
-  }
-  __syncthreads();
-  double o[4][4] = {};
-  for (int k = 0; k < CB; ++k) {
-    double a[4], b[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = Ta[ty + 16 * u][k];
-#pragma unroll
-    for (int v = 0; v < 4; ++v) b[v] = Tb[k][tx + 16 * v];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) o[u][v] += a[u] * b[v];
-  }
-#pragma unroll
-  for (int u = 0; u < 4; ++u)
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      int64_t r = i0 + ty + 16 * u, c = j0 + tx + 16 * v;
-      if (r < N && c < N) X[r * N + c] = -o[u][v];
-    }
-}
-
-__global__ void k_trinv_out(const double* __restrict__ X, int64_t N, double* out64, int64_t ld64, float* out32,
-                            int64_t ld32) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= N * N) return;
-  int64_t i = idx / N, j = idx % N;
-  double v = X[idx];
-  if (out64) out64[i * ld64 + j] = v;
-  if (out32) out32[i * ld32 + j] = (float)v;
-}
-
-size_t tri_inverse_work_doubles(int64_t N) { return (size_t)N * N; }
-
-hipError_t launch_tri_inverse(const double* R, int64_t ld, int64_t N, double* out64, int64_t ld64, float* out32,
-                              int64_t ld32, double* work, hipStream_t st) {
-  if (N == 0) return hipSuccess;
-  int64_t tot = N * N;
-  hipLaunchKernelGGL(k_zero64, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, work, tot);
-  int nblk = (int)((N + CB - 1) / CB);
-  hipLaunchKernelGGL(k_trinv_diag, dim3(nblk), dim3(64), 0, st, R, ld, N, work);
-  for (int d = 1; d < nblk; ++d)
-    hipLaunchKernelGGL(k_trinv_off, dim3(nblk - d), dim3(256), 0, st, R, ld, N, d, work);
-  hipLaunchKernelGGL(k_trinv_out, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, work, N, out64, ld64, out32,
-                     ld32);
-  return hipGetLastError();
-}
-
 // ============================== block-Jacobi eigensolver ==============================
 // G (K x K, K = 2 p JB, padded with decoupled -1e300 diagonal) is driven to
 // diagonal form by rounds of p independent 64 x 64 subproblems (pairs of 32-wide
@@ -1065,8 +788,8 @@ struct InfoOut {
   double orth_err;
 };
 __global__ void k_info(InfoOut* info, const int* counters, int k, const double* orth) {
-  int retries = counters[1], nonf = counters[2], last = counters[3];
-  info->status = (retries > 0 ? 1 : 0) | (nonf ? 2 : 0);
+  int retries = counters[1], nonf = counters[2], last = counters[3], fault = counters[5];
+  info->status = (retries > 0 ? 1 : 0) | (nonf ? 2 : 0) | (fault ? 4 : 0);
   info->rank_found = k - last;
   info->chol_retries = retries;
   info->nonfinite = nonf;

@@ -38,7 +38,7 @@ struct RFBufs {
   float* At; uint16_t* At16;
   float* Ya; float* Yb; uint16_t* Q16;
   float* Zh; float* Z; uint16_t* Z16;
-  double* G; double* d0; int* flags; int* counters; float* Rinv; double* triwork;
+  double* G; double* d0; int* flags; int* counters; float* Rinv; double* triwork; int* cwork;
   double* gpart; float* mpart; double* orth;
 };
 
@@ -66,7 +66,8 @@ static RFBufs carve_rf(Arena& ar, const Dims& d) {
   b.flags = ar.get<int>((size_t)d.k);
   b.counters = ar.get<int>(16);
   b.Rinv = ar.get<float>((size_t)d.k * d.k);
-  b.triwork = ar.get<double>(tri_inverse_work_doubles(d.k));
+  b.triwork = ar.get<double>((size_t)d.k * d.k);
+  b.cwork = ar.get<int>(cholinv_work_ints(d.k));
   b.gpart = ar.get<double>(gram_partial_doubles(d.m > d.r1 ? d.m : d.r1, d.k, d.k));
   b.mpart = ar.get<float>(gemm_partial_floats(d.r1, d.k, d.m));
   b.orth = ar.get<double>(2);
@@ -107,13 +108,14 @@ static double chol_tol(int k) {
 // replaced (stream-3 Gaussians) and the factorisation repeated.
 static void cholqr_pass(Ctx& c, RFBufs& b, float* X, float* out, int64_t rows, int k, uint64_t seed) {
   c.chk(launch_gram(X, k, 0, X, k, 0, rows, k, k, 1, b.G, k, b.gpart, nullptr, c.st));
-  c.chk(launch_cholesky(b.G, k, k, chol_tol(k), b.d0, b.flags, &b.counters[0], &b.counters[2], nullptr, c.st));
+  c.chk(launch_cholinv(b.G, k, k, chol_tol(k), b.d0, b.flags, &b.counters[0], &b.counters[2], &b.counters[5], nullptr,
+                       b.triwork, k, b.Rinv, k, b.cwork, c.st));
   c.chk(launch_note(b.counters, 0, c.st));
   c.chk(launch_refill(X, k, rows, k, b.flags, &b.counters[4], b.d0, seed, c.st));
   c.chk(launch_gram(X, k, 0, X, k, 0, rows, k, k, 1, b.G, k, b.gpart, &b.counters[4], c.st));
-  c.chk(launch_cholesky(b.G, k, k, chol_tol(k), b.d0, b.flags, &b.counters[0], &b.counters[2], &b.counters[4], c.st));
+  c.chk(launch_cholinv(b.G, k, k, chol_tol(k), b.d0, b.flags, &b.counters[0], &b.counters[2], &b.counters[5],
+                       &b.counters[4], b.triwork, k, b.Rinv, k, b.cwork, c.st));
   c.chk(launch_note(b.counters, 1, c.st));
-  c.chk(launch_tri_inverse(b.G, k, k, nullptr, 0, b.Rinv, k, b.triwork, c.st));
   gemm(c, 0, X, k, 1, b.Rinv, k, 0, out, k, rows, k, k, nullptr, nullptr, 0, 1);
 }
 
@@ -389,10 +391,13 @@ rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, 
     c.chk(launch_gram(s.Q, k, 0, s.Q, k, 0, d.m, k, k, 1, b.G, k, b.gpart, nullptr, c.st));
     c.chk(launch_orth_err(b.G, k, k, b.orth, c.st));
   }
-  // B^T = A^T Q (n x k): the one extra pass over A of the randomised SVD
-  if (A->dtype == RF_BF16) {
-    c.chk(launch_cast_f32_bf16(s.Q, k, b.Q16 ? b.Q16 : (uint16_t*)b.Ya, k, d.m, k, c.st));
-    gemm(c, 2, A->data, A->ld, 0, b.Q16 ? b.Q16 : (uint16_t*)b.Ya, k, 0, s.Bt, k, d.n, k, d.m, nullptr);
+  // B^T = A^T Q (n x k): the one extra pass over A of the randomised SVD.  BF16
+  // products when A is stored in BF16, or in the mixed form (FP32 A is then
+  // rounded to BF16 as it is loaded).
+  if (A->dtype == RF_BF16 || d.prec == RF_PREC_MIXED) {
+    uint16_t* q16 = b.Q16 ? b.Q16 : (uint16_t*)b.Ya;
+    c.chk(launch_cast_f32_bf16(s.Q, k, q16, k, d.m, k, c.st));
+    gemm(c, A->dtype == RF_BF16 ? 2 : 4, A->data, A->ld, 0, q16, k, 0, s.Bt, k, d.n, k, d.m, nullptr);
   } else {
     gemm(c, 0, A->data, A->ld, 0, s.Q, k, 0, s.Bt, k, d.n, k, d.m, nullptr);
   }
@@ -428,8 +433,8 @@ rf_status rf_lowrank(const rf_matrix* A, const rf_params* p, float* Y, int64_t l
   c.chk(launch_sketch_left(A->dtype, A->data, A->ld, l.table2, d.s, d.m, d.n, r1, l.T, d.n, l.lpart, c.st));
   // X = (P^T P)^{-1} P^T T with P^T P = R^T R (FP64):  X = Rinv (Rinv^T (P^T T))
   c.chk(launch_gram(l.P, k, 0, l.P, k, 0, r1, k, k, 1, b.G, k, b.gpart, nullptr, c.st));
-  c.chk(launch_cholesky(b.G, k, k, chol_tol(k), b.d0, b.flags, &b.counters[0], &b.counters[2], nullptr, c.st));
-  c.chk(launch_tri_inverse(b.G, k, k, nullptr, 0, b.Rinv, k, b.triwork, c.st));
+  c.chk(launch_cholinv(b.G, k, k, chol_tol(k), b.d0, b.flags, &b.counters[0], &b.counters[2], &b.counters[5], nullptr,
+                       b.triwork, k, b.Rinv, k, b.cwork, c.st));
   gemm(c, 0, l.P, k, 0, l.T, d.n, 0, l.W, d.n, k, d.n, r1, nullptr);          // W = P^T T
   gemm(c, 0, b.Rinv, k, 0, l.W, d.n, 0, l.X1, d.n, k, d.n, k, nullptr);       // X1 = Rinv^T W
   gemm(c, 0, b.Rinv, k, 1, l.X1, d.n, 0, X, ldx, k, d.n, k, nullptr);         // X = Rinv X1
@@ -513,20 +518,20 @@ rf_status rf_test_gram(const float* X, const float* Y, int64_t K, int64_t M, int
 }
 
 size_t rf_test_chol_ws(int64_t N) {
-  return (tri_inverse_work_doubles(N) + (size_t)N) * sizeof(double) + (size_t)N * sizeof(int) + 4 * 256;
+  return (size_t)N * sizeof(double) + ((size_t)N + cholinv_work_ints(N)) * sizeof(int) + 4 * 256;
 }
 
 rf_status rf_test_cholqr_factor(double* G, int64_t N, double* Rinv, int32_t* counters, void* ws, void* stream) {
   if (!G || !Rinv || !counters || !ws || N < 1) return RF_EINVAL;
   Arena ar(align_ws(ws));
-  double* work = ar.get<double>(tri_inverse_work_doubles(N));
   double* d0 = ar.get<double>(N);
   int* flags = ar.get<int>(N);
+  int* work = ar.get<int>(cholinv_work_ints(N));
   Ctx c;
   c.st = (hipStream_t)stream;
   c.chk(launch_fill_i32(counters, 16, 0, c.st));
-  c.chk(launch_cholesky(G, N, N, chol_tol((int)N), d0, flags, &counters[0], &counters[2], nullptr, c.st));
-  c.chk(launch_tri_inverse(G, N, N, Rinv, N, nullptr, 0, work, c.st));
+  c.chk(launch_cholinv(G, N, N, chol_tol((int)N), d0, flags, &counters[0], &counters[2], &counters[5], nullptr, Rinv,
+                       N, nullptr, 0, work, c.st));
   return finish(c);
 }
 

@@ -148,6 +148,19 @@ def test_mixed_svd_bf16_storage():
     assert np.all(np.abs(sig - ref.sigma) <= 2e-2 * ref.sigma + 1e-3 * ref.sigma[0])
 
 
+def test_mixed_svd_fp32_storage():
+    """Mixed form on FP32 A: Q^T A rounds A to BF16 as it loads it, so sigma
+    carries BF16 product error; the subspace keeps the FP32 range."""
+    A32, A = _instance("poly65k", 1500, 1000)
+    U, sig, Vt, info = rf.rf_svd(dev32(A32), 100, 200, 2, 8, seed=42, precision="mixed")
+    ref = me.rand_svd(A, me.Params(k=100, l=200, q=2, s=8, seed=42))
+    sig = sig.cpu().numpy()
+    U = U.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(sig - ref.sigma) <= 2e-2 * ref.sigma + 1e-3 * ref.sigma[0])
+    assert np.max(np.abs(U.T @ U - np.eye(100))) < 2e-5
+    assert ev.frob_error(A, U) <= 1.02 * ev.frob_error(A, ref.U)
+
+
 # ---------------------------------------------------------------- edge cases
 def test_exact_recovery_rank_le_k():
     rng = np.random.default_rng(3)
