@@ -8,8 +8,8 @@
 //   X(kb, i)  inverse column X_i,kb = -(sum_{l=i..kb-1} X_il R_l,kb) X_kk for i < kb;
 //   C(kb,i,j) trailing update G_ij -= R_kb,i^T R_kb,j for kb < i <= j.
 // Workgroups take task tickets from an atomic counter in this order and wait on
-// per-step completion counters: A(kb) on all C(kb-1), B/X(kb) on A(kb), C(kb) on
-// all B/X(kb).  A task only waits on tasks with smaller tickets, which are held
+// per-step completion counters: A(kb) on all C(kb-1), B(kb) on A(kb), X(kb) on A(kb)
+// and all X(kb-1), C(kb) on all B(kb) (the X columns run beside the factorisation).  A task only waits on tasks with smaller tickets, which are held
 // by running workgroups, so the queue drains without co-residency guarantees;
 // every wait is bounded and raises the fault word instead of hanging.
 // Completion is published with an agent-scope release (L2 write-back, the
@@ -29,7 +29,7 @@ struct CholInvArgs {
   const int* run_if;
   double* X64; int64_t ldx64;   // R^{-1} in FP64 (required: later tasks read it)
   float* X32; int64_t ldx32;    // optional FP32 copy
-  int* work;                    // [0] ticket, [1] unused, [2..2+nb) doneA, then doneB, doneC
+  int* work;                    // [0] ticket, [1] unused, [2..2+nb) doneA, then doneP, doneX, doneC
   int* fault;                   // set to 1 when a bounded wait gives up
   int nb;
 };
@@ -40,7 +40,8 @@ RF_DEV int nC_of(int nb, int kb) { int t = nb - 1 - kb; return t * (t + 1) / 2; 
 // up after kSpinLimit polls, or at once when another wait has already given up.
 RF_DEV void wait_at_least(int* ctr, int target, int* err) {
   unsigned spins = 0;
-  while (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+  // relaxed polls (an acquire per poll would invalidate this XCD's L2 every time)
+  while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
     if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) break;
     __builtin_amdgcn_s_sleep(2);
     if (++spins > kSpinLimit) {
@@ -48,7 +49,7 @@ RF_DEV void wait_at_least(int* ctr, int target, int* err) {
       break;
     }
   }
-  __atomic_thread_fence(__ATOMIC_ACQUIRE);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 RF_DEV void load_tile(double (*T)[TLD], const double* P, int64_t ld, int64_t r0, int64_t c0, int64_t N) {
@@ -107,23 +108,32 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
     if (threadIdx.x == 0) R[c][c] = bad ? 1.0 : sqrt(d);
     if (!bad) {
       const double id = 1.0 / d;
-      const int w = nbk - c - 1;
-      for (int e = threadIdx.x; e < w * w; e += blockDim.x) {
-        const int i = c + 1 + e / w, j = c + 1 + e % w;
-        if (j >= i) M[i][j] -= M[c][i] * M[c][j] * id;
+      const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+      for (int i = c + 1 + ty; i < nbk; i += 16) {
+        const double mi = M[c][i] * id;
+        for (int j = c + 1 + tx; j < nbk; j += 16)
+          if (j >= i) M[i][j] -= mi * M[c][j];
       }
     }
     __syncthreads();
   }
-  // X = R^{-1}, rows bottom-up: X_cc = 1/R_cc, X_cj = -X_cc sum_{l=c+1..j} R_cl X_lj
+  // X = R^{-1}, rows bottom-up: X_cc = 1/R_cc, X_cj = -X_cc sum_{l=c+1..j} R_cl X_lj.
+  // Column j of row c is summed by 4 threads (l interleaved), combined through LDS.
+  double* part = &M[0][0];  // M is free now: 4 x 64 partial sums
   for (int c = nbk - 1; c >= 0; --c) {
-    const double inv = 1.0 / R[c][c];
-    for (int j = c + 1 + threadIdx.x; j < nbk; j += blockDim.x) {
+    const int j = c + 1 + (threadIdx.x >> 2), q = threadIdx.x & 3;
+    if (j < nbk) {
       double s = 0.0;
-      for (int l = c + 1; l <= j; ++l) s += R[c][l] * Xs[l][j];
-      Xs[c][j] = -s * inv;
+      for (int l = c + 1 + q; l <= j; l += 4) s += R[c][l] * Xs[l][j];
+      part[q * TB + j] = s;
     }
-    if (threadIdx.x == 0) Xs[c][c] = inv;
+    __syncthreads();
+    const double inv = 1.0 / R[c][c];
+    if (threadIdx.x < TB) {
+      const int jj = threadIdx.x;
+      if (jj > c && jj < nbk) Xs[c][jj] = -(part[jj] + part[TB + jj] + part[2 * TB + jj] + part[3 * TB + jj]) * inv;
+      if (jj == c) Xs[c][c] = inv;
+    }
     __syncthreads();
   }
   for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
@@ -212,8 +222,9 @@ __global__ __launch_bounds__(256) void k_cholinv(CholInvArgs a) {
   const int nb = a.nb;
   int* err = a.fault;
   int* doneA = a.work + 2;
-  int* doneB = doneA + nb;
-  int* doneC = doneB + nb;
+  int* doneP = doneA + nb;
+  int* doneX = doneP + nb;
+  int* doneC = doneX + nb;
   int total = 0;
   for (int kb = 0; kb < nb; ++kb) total += 1 + (nb - 1) + nC_of(nb, kb);
   // Control flow around the barriers must be uniform: the ticket and the waits are
@@ -243,14 +254,19 @@ __global__ __launch_bounds__(256) void k_cholinv(CholInvArgs a) {
       task_diag(a, kb, T0, T1, T2);
       done = &doneA[kb];
     } else if (t < nb) {  // B(kb, j) or X(kb, i)
-      if (wave == 0) wait_at_least(&doneA[kb], 1, err);
-      __syncthreads();
       const int u = t - 1;  // 0 .. nb-2
-      if (u < nb - 1 - kb) task_panel(a, kb, kb + 1 + u, T0, T1);
+      const bool panel = u < nb - 1 - kb;
+      if (wave == 0) {
+        wait_at_least(&doneA[kb], 1, err);
+        // X(kb, .) reads the X columns of earlier steps
+        if (!panel && kb >= 2) wait_at_least(&doneX[kb - 1], kb - 1, err);
+      }
+      __syncthreads();
+      if (panel) task_panel(a, kb, kb + 1 + u, T0, T1);
       else task_xcol(a, kb, u - (nb - 1 - kb), T0, T1);
-      done = &doneB[kb];
-    } else {  // C(kb, i, j)
-      if (wave == 0) wait_at_least(&doneB[kb], nb - 1, err);
+      done = panel ? &doneP[kb] : &doneX[kb];
+    } else {  // C(kb, i, j): needs the panels of step kb only
+      if (wave == 0) wait_at_least(&doneP[kb], nb - 1 - kb, err);
       __syncthreads();
       int u = t - nb, ib = kb + 1, w = nb - 1 - kb;
       while (u >= w) { u -= w; ++ib; --w; }
@@ -279,7 +295,7 @@ __global__ void k_cholinv_prep(const double* __restrict__ G, int64_t ld, int64_t
 
 size_t cholinv_work_ints(int64_t N) {
   const int64_t nb = (N + TB - 1) / TB;
-  return (size_t)(2 + 3 * nb);
+  return (size_t)(2 + 4 * nb);
 }
 
 static int cu_count_ci() {
