@@ -141,6 +141,35 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
                      int64_t ldw, float* F, int64_t ldf, void* ws, size_t ws_bytes,
                      rf_info* info, void* stream);
 
+/* ---- batched randomised SVD (many independent matrices, one stream) -------
+
+   count problems: As[i] (FP32, device), ps[i] with nnz_per_col = 4, the same q
+   and precision for every i, k <= 1024, sketch <= 1280; shapes and ranks may
+   differ.  Problem i uses seed ps[i].seed with matrix index i in the Philox
+   counter (a single rf_svd call uses index 0), so problem 0 of a batch gives the
+   same sketch and Omega as rf_svd on the same matrix and seed.  Outputs as for
+   rf_svd: U[i] (m_i x k_i, ldu[i]), sigma[i] (k_i), Vt[i] (k_i x n_i, ldvt[i]);
+   info: device array of count rf_info (or NULL).  Host arrays As, ps, U, ldu,
+   sigma, Vt, ldvt are read during the plan call only.
+
+   The plan call validates synchronously (RF_EINVAL, RF_EWORKSPACE, and
+   RF_EUNSUPPORTED for what is outside the limits above), lays out the
+   workspace (ws >= rf_svd_batched_ws(count, As, ps) bytes, device, owned by the
+   caller and kept alive and untouched while the plan is used), writes the
+   per-stage work lists into its head and waits for that upload on `stream`.
+   With use_graph != 0 the launch sequence is captured into a hipGraph (no
+   work runs during the plan call).  rf_svd_batched_run enqueues one batched
+   factorisation on `stream` (a graph launch when captured); runs on one plan
+   must not overlap.  Every stage is one grouped launch over all problems. */
+typedef struct rf_batch_plan rf_batch_plan;
+size_t rf_svd_batched_ws(int32_t count, const rf_matrix* As, const rf_params* ps);
+rf_status rf_svd_batched_plan(int32_t count, const rf_matrix* As, const rf_params* ps, float* const* U,
+                              const int64_t* ldu, double* const* sigma, float* const* Vt, const int64_t* ldvt,
+                              rf_info* info, void* ws, size_t ws_bytes, int32_t use_graph, void* stream,
+                              rf_batch_plan** plan);
+rf_status rf_svd_batched_run(rf_batch_plan* plan, void* stream);
+void rf_svd_batched_destroy(rf_batch_plan* plan);
+
 /* ---- parity hooks (same kernels as the entry points above) ---------------- */
 
 /* Sketch table: out[j*s + t] = bucket | (negative << 31) for j < n, t < s, with

@@ -22,6 +22,7 @@ __all__ = [
     "RF_OP_RANGE_FINDER", "RF_OP_SVD", "RF_OP_LOWRANK", "RF_OP_NYSTROM",
     "lib", "library_path", "rf_status_string", "rf_workspace_size", "rf_sketch_table", "rf_gaussian",
     "rf_sketch_apply", "rf_range_finder", "rf_svd", "rf_lowrank", "rf_nystrom", "RFError",
+    "BatchPlan", "rf_svd_batched",
 ]
 
 RF_OK, RF_EINVAL, RF_EWORKSPACE, RF_EUNSUPPORTED, RF_EHIP = 0, 1, 2, 3, 4
@@ -89,6 +90,15 @@ def lib():
         L.rf_lowrank.argtypes = [M, P, vp, i64, vp, i64, vp, sz, vp, vp]
         L.rf_nystrom.restype = i32
         L.rf_nystrom.argtypes = [M, P, vp, i64, vp, i64, vp, i64, vp, sz, vp, vp]
+        L.rf_svd_batched_ws.restype = sz
+        L.rf_svd_batched_ws.argtypes = [i32, vp, vp]
+        L.rf_svd_batched_plan.restype = i32
+        L.rf_svd_batched_plan.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, i32, vp,
+                                          ctypes.POINTER(ctypes.c_void_p)]
+        L.rf_svd_batched_run.restype = i32
+        L.rf_svd_batched_run.argtypes = [vp, vp]
+        L.rf_svd_batched_destroy.restype = None
+        L.rf_svd_batched_destroy.argtypes = [vp]
         L.rf_test_gemm_ws.restype = sz
         L.rf_test_gemm_ws.argtypes = [i64, i64, i64]
         L.rf_test_gemm.restype = i32
@@ -251,6 +261,57 @@ def rf_nystrom(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scale
     _check("rf_nystrom", lib().rf_nystrom(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(C), k, _ptr(W), k,
                                           _ptr(F), k, _ptr(ws), nws, _ptr(info), _stream(A.device)))
     return C, W, F, info
+
+
+class BatchPlan:
+    """A planned batched randomised SVD over a list of FP32 device matrices
+    (rf_svd_batched_plan).  Holds the workspace and the outputs; run() enqueues
+    one batched factorisation on the current stream (a hipGraph launch when
+    use_graph), results in .U, .sigma, .Vt (lists) and .info (count x 24 bytes)."""
+
+    def __init__(self, As, ks, sketches, q=2, nnz_per_col=4, seeds=0, precision="mixed", use_graph=True):
+        count = len(As)
+        if isinstance(seeds, int):
+            seeds = [seeds] * count
+        dev = As[0].device
+        mats = (RfMatrix * count)(*[matrix(A) for A in As])
+        prms = (RfParams * count)(*[params(k, l, q, nnz_per_col, sd, precision) for k, l, sd in zip(ks, sketches, seeds)])
+        self.As = list(As)
+        self.U = [torch.empty((A.shape[0], k), dtype=torch.float32, device=dev) for A, k in zip(As, ks)]
+        self.sigma = [torch.empty(k, dtype=torch.float64, device=dev) for k in ks]
+        self.Vt = [torch.empty((k, A.shape[1]), dtype=torch.float32, device=dev) for A, k in zip(As, ks)]
+        self.info = torch.zeros((count, INFO_BYTES), dtype=torch.uint8, device=dev)
+        nws = int(lib().rf_svd_batched_ws(count, ctypes.cast(mats, ctypes.c_void_p), ctypes.cast(prms, ctypes.c_void_p)))
+        self.ws = torch.empty(max(nws, 1), dtype=torch.uint8, device=dev)
+        Up = (ctypes.c_void_p * count)(*[_ptr(t) for t in self.U])
+        ldu = (ctypes.c_int64 * count)(*[t.stride(0) for t in self.U])
+        Sp = (ctypes.c_void_p * count)(*[_ptr(t) for t in self.sigma])
+        Vp = (ctypes.c_void_p * count)(*[_ptr(t) for t in self.Vt])
+        ldv = (ctypes.c_int64 * count)(*[t.stride(0) for t in self.Vt])
+        h = ctypes.c_void_p()
+        _check("rf_svd_batched_plan", lib().rf_svd_batched_plan(
+            count, ctypes.cast(mats, ctypes.c_void_p), ctypes.cast(prms, ctypes.c_void_p),
+            ctypes.cast(Up, ctypes.c_void_p), ctypes.cast(ldu, ctypes.c_void_p), ctypes.cast(Sp, ctypes.c_void_p),
+            ctypes.cast(Vp, ctypes.c_void_p), ctypes.cast(ldv, ctypes.c_void_p), _ptr(self.info),
+            _ptr(self.ws) if nws else ctypes.c_void_p(0), nws,
+            1 if use_graph else 0, _stream(dev), ctypes.byref(h)))
+        self._h = h
+        self.device = dev
+
+    def run(self):
+        _check("rf_svd_batched_run", lib().rf_svd_batched_run(self._h, _stream(self.device)))
+        return self
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().rf_svd_batched_destroy(h)
+            self._h = None
+
+
+def rf_svd_batched(As, ks, sketches, q=2, nnz_per_col=4, seeds=0, precision="mixed", use_graph=False):
+    """One batched randomised SVD (plan + run); returns the BatchPlan with the outputs."""
+    return BatchPlan(As, ks, sketches, q, nnz_per_col, seeds, precision, use_graph).run()
 
 
 # ---- kernel-level parity hooks -------------------------------------------------------

@@ -23,16 +23,6 @@ constexpr int TB = 64;          // tile
 constexpr int TLD = TB + 1;     // LDS row stride (doubles)
 constexpr unsigned kSpinLimit = 1u << 20;  // polls of ~1 us: a stuck dependency ends the launch in ~1 s
 
-struct CholInvArgs {
-  double* G; int64_t ld; int64_t N;
-  double tol; const double* d0; int* flags; int* count; int* nonfinite;
-  const int* run_if;
-  double* X64; int64_t ldx64;   // R^{-1} in FP64 (required: later tasks read it)
-  float* X32; int64_t ldx32;    // optional FP32 copy
-  int* work;                    // [0] ticket, [1] unused, [2..2+nb) doneA, then doneP, doneX, doneC
-  int* fault;                   // set to 1 when a bounded wait gives up
-  int nb;
-};
 
 RF_DEV int nC_of(int nb, int kb) { int t = nb - 1 - kb; return t * (t + 1) / 2; }
 
@@ -291,6 +281,65 @@ __global__ void k_cholinv_prep(const double* __restrict__ G, int64_t ld, int64_t
     flags[i] = 0;
   }
   if (i < nwork) work[i] = 0;
+}
+
+// Batched: one workgroup per problem runs the same tasks in dependency order
+// (no queue, no waits); for the small k of a batch of independent matrices.
+__global__ __launch_bounds__(256) void k_cholinv_seq_batched(const CholInvArgs* __restrict__ as) {
+  const CholInvArgs a = as[blockIdx.x];
+  if (a.run_if && *a.run_if == 0) return;
+  extern __shared__ double sm[];
+  double(*T0)[TLD] = reinterpret_cast<double(*)[TLD]>(sm);
+  double(*T1)[TLD] = reinterpret_cast<double(*)[TLD]>(sm + TB * TLD);
+  double(*T2)[TLD] = reinterpret_cast<double(*)[TLD]>(sm + 2 * TB * TLD);
+  for (int64_t i = threadIdx.x; i < a.N; i += blockDim.x) {
+    const_cast<double*>(a.d0)[i] = a.G[i * a.ld + i];
+    a.flags[i] = 0;
+  }
+  if (threadIdx.x == 0) *a.count = 0;
+  __syncthreads();
+  const int nb = a.nb;
+  for (int kb = 0; kb < nb; ++kb) {
+    task_diag(a, kb, T0, T1, T2);
+    __syncthreads();
+    for (int jb = kb + 1; jb < nb; ++jb) {
+      task_panel(a, kb, jb, T0, T1);
+      __syncthreads();
+    }
+    for (int ib = 0; ib < kb; ++ib) {
+      task_xcol(a, kb, ib, T0, T1);
+      __syncthreads();
+    }
+    for (int ib = kb + 1; ib < nb; ++ib)
+      for (int jb = ib; jb < nb; ++jb) {
+        task_update(a, kb, ib, jb, T0, T1);
+        __syncthreads();
+      }
+  }
+}
+
+CholInvArgs cholinv_desc(double* G, int64_t ld, int64_t N, double tol_ratio, double* d0, int* flags, int* count,
+                         int* nonfinite, const int* run_if, double* X64, int64_t ldx64, float* X32, int64_t ldx32) {
+  CholInvArgs a;
+  a.G = G; a.ld = ld; a.N = N;
+  a.tol = tol_ratio; a.d0 = d0; a.flags = flags; a.count = count; a.nonfinite = nonfinite;
+  a.run_if = run_if;
+  a.X64 = X64; a.ldx64 = ldx64; a.X32 = X32; a.ldx32 = ldx32;
+  a.work = nullptr; a.fault = nullptr; a.nb = (int)((N + TB - 1) / TB);
+  return a;
+}
+
+hipError_t launch_cholinv_batched(const CholInvArgs* as, int count, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const size_t lds = 3 * (size_t)TB * TLD * sizeof(double);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_cholinv_seq_batched, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    attr = true;
+  }
+  hipLaunchKernelGGL(k_cholinv_seq_batched, dim3((unsigned)count), dim3(256), lds, st, as);
+  return hipGetLastError();
 }
 
 size_t cholinv_work_ints(int64_t N) {

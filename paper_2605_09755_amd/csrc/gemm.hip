@@ -49,7 +49,7 @@ RF_DEV void store_out(const GemmArgs& g, int64_t i, int64_t j, float v) {
 
 // ---------------- FP32 operands -------------------------------------------------------
 template <bool AKC, bool BKC>
-__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
+RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
   constexpr int BK = 16;
   constexpr int AST = AKC ? (BK + 1) : GBM;  // LDS row stride (floats)
   constexpr int BST = BKC ? (BK + 1) : GBN;
@@ -60,11 +60,11 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
 
   const int ntm = (int)((g.M + GBM - 1) / GBM), ntn = (int)((g.N + GBN - 1) / GBN);
   int tm, tn;
-  tile_coords(blockIdx.x, ntm, ntn, tm, tn);
+  tile_coords(bid, ntm, ntn, tm, tn);
   const int64_t i0 = (int64_t)tm * GBM, j0 = (int64_t)tn * GBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  int64_t kbeg = (int64_t)blockIdx.y * g.kps;
+  int64_t kbeg = (int64_t)split * g.kps;
   int64_t kend = min(g.K, kbeg + g.kps);
   if (g.b_upper) kend = min(kend, j0 + GBN);
   const float* A = reinterpret_cast<const float*>(g.A);
@@ -181,7 +181,7 @@ __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
         int64_t i = i0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         int64_t j = j0 + wn * 64 + b * 32 + (lane & 31);
         if (g.partial) {
-          if (i < g.M && j < g.N) g.partial[((int64_t)blockIdx.y * g.M + i) * g.N + j] = acc[a][b][r];
+          if (i < g.M && j < g.N) g.partial[((int64_t)split * g.M + i) * g.N + j] = acc[a][b][r];
         } else {
           store_out(g, i, j, acc[a][b][r]);
         }
@@ -193,7 +193,7 @@ RF_DEV uint32_t pack_lo(uint32_t a, uint32_t b) { return (a & 0xffffu) | (b << 1
 RF_DEV uint32_t pack_hi(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
 
 template <bool AKC, bool BKC>
-__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
   constexpr int BK = 32;
   constexpr int ST = BK + 8;  // bf16 elements per LDS row (80 B)
   __shared__ __attribute__((aligned(16))) uint16_t As[2][GBM * ST];
@@ -201,11 +201,11 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 
   const int ntm = (int)((g.M + GBM - 1) / GBM), ntn = (int)((g.N + GBN - 1) / GBN);
   int tm, tn;
-  tile_coords(blockIdx.x, ntm, ntn, tm, tn);
+  tile_coords(bid, ntm, ntn, tm, tn);
   const int64_t i0 = (int64_t)tm * GBM, j0 = (int64_t)tn * GBN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  int64_t kbeg = (int64_t)blockIdx.y * g.kps;
+  int64_t kbeg = (int64_t)split * g.kps;
   int64_t kend = min(g.K, kbeg + g.kps);
   if (g.b_upper) kend = min(kend, j0 + GBN);
   const uint16_t* A = reinterpret_cast<const uint16_t*>(g.A);
@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         int64_t i = i0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         int64_t j = j0 + wn * 64 + b * 32 + (lane & 31);
         if (g.partial) {
-          if (i < g.M && j < g.N) g.partial[((int64_t)blockIdx.y * g.M + i) * g.N + j] = acc[a][b][r];
+          if (i < g.M && j < g.N) g.partial[((int64_t)split * g.M + i) * g.N + j] = acc[a][b][r];
         } else {
           store_out(g, i, j, acc[a][b][r]);
         }
@@ -438,7 +438,7 @@ struct BigStage {
 };
 
 template <bool AKC, bool BKC, bool AF32>
-__global__ __launch_bounds__(256, 1) void k_gemm_bf16_big(GemmArgs g) {
+RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
   extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
   constexpr int AS = big_stage_elems<AKC>(), BS = big_stage_elems<BKC>();
   uint16_t* const A0 = smem;
@@ -446,11 +446,11 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_big(GemmArgs g) {
 
   const int ntm = (int)((g.M + HB - 1) / HB), ntn = (int)((g.N + HB - 1) / HB);
   int tm, tn;
-  tile_coords(blockIdx.x, ntm, ntn, tm, tn);
+  tile_coords(bid, ntm, ntn, tm, tn);
   const int64_t i0 = (int64_t)tm * HB, j0 = (int64_t)tn * HB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  int64_t kbeg = (int64_t)blockIdx.y * g.kps;
+  int64_t kbeg = (int64_t)split * g.kps;
   int64_t kend = min(g.K, kbeg + g.kps);
   if (g.b_upper) kend = min(kend, j0 + HB);
 
@@ -526,13 +526,63 @@ __global__ __launch_bounds__(256, 1) void k_gemm_bf16_big(GemmArgs g) {
       const int64_t i = i0 + (rr >> 5) * 128 + 32 * a + (rr & 31), j = j0 + cc;
       const float v = St[rr * SLD + cc];
       if (g.partial) {
-        if (i < g.M && j < g.N) g.partial[((int64_t)blockIdx.y * g.M + i) * g.N + j] = v;
+        if (i < g.M && j < g.N) g.partial[((int64_t)split * g.M + i) * g.N + j] = v;
       } else {
         store_out(g, i, j, v);
       }
     }
     __syncthreads();
   }
+}
+
+template <bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
+  gemm_f32_body<AKC, BKC>(g, blockIdx.x, blockIdx.y);
+}
+template <bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  gemm_bf16_body<AKC, BKC>(g, blockIdx.x, blockIdx.y);
+}
+template <bool AKC, bool BKC, bool AF32>
+__global__ __launch_bounds__(256, 1) void k_gemm_bf16_big(GemmArgs g) {
+  gemm_bf16_big_body<AKC, BKC, AF32>(g, blockIdx.x, blockIdx.y);
+}
+
+// ---- grouped launches: many independent products in one grid --------------------
+// Work list: group i owns tiles [tile_start[i], tile_start[i+1]) of the flat grid;
+// a workgroup finds its group by binary search and runs that group's tile.  All
+// groups of one launch share the operand layouts (template) and the tile shape.
+RF_DEV int find_group(const int* __restrict__ start, int count, int bid) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (start[mid] <= bid) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+template <bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void k_gemm_f32_grouped(const GemmArgs* __restrict__ gs, const int* tile_start,
+                                                          int count) {
+  const int i = find_group(tile_start, count, blockIdx.x);
+  const GemmArgs g = gs[i];
+  if (g.M == 0 || g.N == 0) return;
+  gemm_f32_body<AKC, BKC>(g, blockIdx.x - tile_start[i], 0);
+}
+template <bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void k_gemm_bf16_grouped(const GemmArgs* __restrict__ gs, const int* tile_start,
+                                                           int count) {
+  const int i = find_group(tile_start, count, blockIdx.x);
+  const GemmArgs g = gs[i];
+  if (g.M == 0 || g.N == 0) return;
+  gemm_bf16_body<AKC, BKC>(g, blockIdx.x - tile_start[i], 0);
+}
+template <bool AKC, bool BKC, bool AF32>
+__global__ __launch_bounds__(256, 1) void k_gemm_bf16_big_grouped(const GemmArgs* __restrict__ gs,
+                                                                  const int* tile_start, int count) {
+  const int i = find_group(tile_start, count, blockIdx.x);
+  const GemmArgs g = gs[i];
+  if (g.M == 0 || g.N == 0) return;
+  gemm_bf16_big_body<AKC, BKC, AF32>(g, blockIdx.x - tile_start[i], 0);
 }
 
 __global__ void k_gemm_reduce(GemmArgs g, int splits) {
@@ -633,6 +683,61 @@ hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
   if (splits > 1) {
     int64_t tot = g.M * g.N;
     hipLaunchKernelGGL(k_gemm_reduce, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, g, splits);
+  }
+  return hipGetLastError();
+}
+
+// ---- grouped launcher ---------------------------------------------------------------
+int gemm_group_tiles(int kind, int64_t M, int64_t N) {
+  const int64_t b = (kind == 3 || kind == 4) ? HB : GBM;
+  return (int)(((M + b - 1) / b) * ((N + b - 1) / b));
+}
+
+template <bool AKC, bool BKC, bool AF32>
+static void go_big_grouped(const GemmArgs* gs, const int* ts, int count, int tiles, hipStream_t st) {
+  constexpr size_t lds = 2 * (size_t)(big_stage_elems<AKC>() + big_stage_elems<BKC>()) * sizeof(uint16_t);
+  static bool attr = false;
+  if (!attr) {
+    (void)hipFuncSetAttribute((const void*)k_gemm_bf16_big_grouped<AKC, BKC, AF32>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    attr = true;
+  }
+  hipLaunchKernelGGL((k_gemm_bf16_big_grouped<AKC, BKC, AF32>), dim3((unsigned)tiles), dim3(256), lds, st, gs, ts,
+                     count);
+}
+
+hipError_t launch_gemm_grouped(const GemmArgs* gs, const int* tile_start, int count, int total_tiles, int kind,
+                               int a_kc, int b_kc, hipStream_t st) {
+  if (count == 0 || total_tiles == 0) return hipSuccess;
+  const dim3 grid((unsigned)total_tiles), blk(256);
+  const int sel = (a_kc ? 2 : 0) | (b_kc ? 1 : 0);
+  switch (kind) {
+    case 0:
+      if (sel == 3) hipLaunchKernelGGL((k_gemm_f32_grouped<true, true>), grid, blk, 0, st, gs, tile_start, count);
+      else if (sel == 2) hipLaunchKernelGGL((k_gemm_f32_grouped<true, false>), grid, blk, 0, st, gs, tile_start, count);
+      else if (sel == 1) hipLaunchKernelGGL((k_gemm_f32_grouped<false, true>), grid, blk, 0, st, gs, tile_start, count);
+      else hipLaunchKernelGGL((k_gemm_f32_grouped<false, false>), grid, blk, 0, st, gs, tile_start, count);
+      break;
+    case 2:
+      if (sel == 3) hipLaunchKernelGGL((k_gemm_bf16_grouped<true, true>), grid, blk, 0, st, gs, tile_start, count);
+      else if (sel == 2) hipLaunchKernelGGL((k_gemm_bf16_grouped<true, false>), grid, blk, 0, st, gs, tile_start, count);
+      else if (sel == 1) hipLaunchKernelGGL((k_gemm_bf16_grouped<false, true>), grid, blk, 0, st, gs, tile_start, count);
+      else hipLaunchKernelGGL((k_gemm_bf16_grouped<false, false>), grid, blk, 0, st, gs, tile_start, count);
+      break;
+    case 3:
+      if (sel == 3) go_big_grouped<true, true, false>(gs, tile_start, count, total_tiles, st);
+      else if (sel == 2) go_big_grouped<true, false, false>(gs, tile_start, count, total_tiles, st);
+      else if (sel == 1) go_big_grouped<false, true, false>(gs, tile_start, count, total_tiles, st);
+      else go_big_grouped<false, false, false>(gs, tile_start, count, total_tiles, st);
+      break;
+    case 4:
+      if (sel == 3) go_big_grouped<true, true, true>(gs, tile_start, count, total_tiles, st);
+      else if (sel == 2) go_big_grouped<true, false, true>(gs, tile_start, count, total_tiles, st);
+      else if (sel == 1) go_big_grouped<false, true, true>(gs, tile_start, count, total_tiles, st);
+      else go_big_grouped<false, false, true>(gs, tile_start, count, total_tiles, st);
+      break;
+    default:
+      return hipErrorInvalidValue;
   }
   return hipGetLastError();
 }

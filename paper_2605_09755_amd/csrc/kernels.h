@@ -15,11 +15,30 @@ hipError_t launch_gaussian(int64_t rows, int64_t cols, uint64_t seed, uint32_t s
                            int64_t ldo, hipStream_t st);
 
 // ---- K3 / K4 ----
+// Batched sketch tables (stream 0), ready tables and Omega (stream 1, r1 x k, ld k),
+// problem index b in the Philox counter.  max_entries: max over problems of
+// max(n s, r1 k / 4).
+struct RngArgs {
+  int64_t n; int s, r1, k, cpl; uint64_t seed; uint32_t b;
+  int32_t* table; uint32_t* ready; float* om;
+};
+hipError_t launch_rng_batched(const RngArgs* as, int count, int64_t max_entries, hipStream_t st);
 int sketch_right_cpl(int s);
 bool sketch_right_fast_ok(int s);
 // dtype: 0 f32, 2 bf16, 3 fp8 e4m3 with 128x128 block scales
 // cmax: workspace of sketch_right_cmax_ints(n) ints (per-chunk bucket occupancy)
 size_t sketch_right_cmax_ints(int64_t n);
+// Batched A_i S_i for FP32 A_i with s = 4 nonzeros per column and r1 <= 1280
+// (one problem per grid row): table/ready from the single-problem kernels with
+// cpl = 2, cmax: sketch_right_cmax_ints(n_i) ints each.
+struct SketchArgs {
+  const float* A; int64_t lda;
+  const int32_t* table; const uint32_t* ready; int* cmax;
+  int64_t m, n; int r1; int vec_ok;
+  float* out; int64_t ldo;
+};
+hipError_t launch_sketch_right_batched(const SketchArgs* as, int count, int64_t mmax, int64_t nmax, int r1max,
+                                       hipStream_t st);
 hipError_t launch_sketch_right(int dtype, const void* A, int64_t lda, const float* scales, const int32_t* table,
                                const uint32_t* ready, int* cmax, int s, int64_t m, int64_t n, int r1, float* out,
                                int64_t ldo, hipStream_t st);
@@ -43,6 +62,13 @@ int gemm_splits(int64_t M, int64_t N, int64_t K);
 size_t gemm_partial_floats(int64_t M, int64_t N, int64_t K);
 // dtype: 0 FP32 operands, 2 BF16 operands.  partial may be NULL (no split-K).
 hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st);
+// Grouped products: count independent GemmArgs (device array, kps = K, partial = 0)
+// in one grid; tile_start (device, count + 1 entries) is the prefix sum of
+// gemm_group_tiles(kind, M_i, N_i).  kind: 0 FP32 (128 x 128 tiles), 2 BF16
+// (128 x 128), 3 BF16 (256 x 256), 4 BF16 with A FP32 rounded on load (256 x 256).
+int gemm_group_tiles(int kind, int64_t M, int64_t N);
+hipError_t launch_gemm_grouped(const GemmArgs* gs, const int* tile_start, int count, int total_tiles, int kind,
+                               int a_kc, int b_kc, hipStream_t st);
 
 // ---- FP64 small linear algebra ----
 // C (M x N, FP64, ldc) = X^T Y with X (K x M), Y (K x N) row-major (xdt/ydt: 0 f32, 1 f64).
@@ -51,16 +77,87 @@ size_t gram_partial_doubles(int64_t K, int64_t M, int64_t N);
 hipError_t launch_gram(const void* X, int64_t ldx, int xdt, const void* Y, int64_t ldy, int ydt, int64_t K,
                        int64_t M, int64_t N, int sym, double* C, int64_t ldc, double* partial, const int* run_if,
                        hipStream_t st);
+// ---- batched utilities (device descriptor arrays, one entry per problem) ----
+struct CastArgs { const void* in; void* out; int64_t rows, cols, ldi, ldo; };
+hipError_t launch_cast_batched(const CastArgs* as, int count, int64_t max_elems, int f64_to_f32, hipStream_t st);
+// dependent columns of X replaced (stream 3, problem index b) when *count != 0
+struct RefillArgs { float* X; int64_t ldx, rows, k; const int* flags; const int* count; const double* d0;
+                    uint64_t seed; uint32_t b; };
+hipError_t launch_refill_batched(const RefillArgs* as, int count, int64_t max_elems, hipStream_t st);
+hipError_t launch_note_batched(int* const* cs, int count, int final_, hipStream_t st);
+// Ritz tail: the "pre" launch writes sigma = sqrt(lam), inv = 1/sigma, Ub32 = Ub and
+// clears the sign keys (signw: 3 k ints); after the U and V^T products the "sign"
+// launches apply the sign rule (largest |U| entry of each column positive).
+struct SvdTailArgs {
+  const double* lam; const double* Ub; float* Ub32; double* sigma; float* inv; int* signw;
+  float* U; int64_t ldu; float* Vt; int64_t ldvt; int64_t m, n, k;
+};
+hipError_t launch_svd_tail_pre_batched(const SvdTailArgs* as, int count, int64_t kmax, hipStream_t st);
+hipError_t launch_svd_tail_sign_batched(const SvdTailArgs* as, int count, int64_t kmax, int64_t mmax,
+                                        int64_t max_elems, hipStream_t st);
+// rf_info of problem i from counters + i * stride (k_i from ks, device array).
+hipError_t launch_info_batched(void* infos, const int* counters, int stride, const int* ks, int count, hipStream_t st);
+// Grouped symmetric Grams: C_i (M_i x M_i FP64, ldc) = X_i^T X_i, X_i (K_i x M_i) FP32
+// row-major; skipped when run_if is set and *run_if == 0.  tile_start: prefix sum
+// of gram_group_tiles(M_i) (device, count + 1 entries).
+struct GramArgs {
+  const float* X; int64_t ldx; int64_t K, M;
+  double* C; int64_t ldc;
+  const int* run_if;
+};
+int gram_group_tiles(int64_t M);
+hipError_t launch_gram_grouped(const GramArgs* gs, const int* tile_start, int count, int total_tiles,
+                               hipStream_t st);
 // In-place upper Cholesky G = R^T R and X = R^{-1} (upper, lower triangle zeroed) in
 // one persistent launch.  Pivots below tol_ratio * (original diagonal) are declared
 // deficient: flags[c] = 1, row c of R set to e_c, *count += 1; d0 (N doubles)
 // receives the original diagonal; *nonfinite = 1 on a non-finite pivot.  X64 (N x N,
 // ldx64) is required, X32 optional.  work: device int[cholinv_work_ints(N)].
 // *fault = 1 if a bounded wait between tasks gave up.
+// Batched: one problem per workgroup (problems of a few 64-wide tiles); descriptors
+// from cholinv_desc() in a device array.  Same outputs as launch_cholinv.
+struct CholInvArgs {
+  double* G; int64_t ld; int64_t N;
+  double tol; const double* d0; int* flags; int* count; int* nonfinite;
+  const int* run_if;
+  double* X64; int64_t ldx64;   // R^{-1} in FP64 (required: later tasks read it)
+  float* X32; int64_t ldx32;    // optional FP32 copy
+  int* work;                    // [0] ticket, [1] unused, [2..2+nb) doneA, then doneP, doneX, doneC
+  int* fault;                   // set to 1 when a bounded wait gives up
+  int nb;
+};
+CholInvArgs cholinv_desc(double* G, int64_t ld, int64_t N, double tol_ratio, double* d0, int* flags, int* count,
+                         int* nonfinite, const int* run_if, double* X64, int64_t ldx64, float* X32, int64_t ldx32);
+hipError_t launch_cholinv_batched(const CholInvArgs* as, int count, hipStream_t st);
 size_t cholinv_work_ints(int64_t N);
 hipError_t launch_cholinv(double* G, int64_t ld, int64_t N, double tol_ratio, double* d0, int* flags, int* count,
                           int* nonfinite, int* fault, const int* run_if, double* X64, int64_t ldx64, float* X32,
                           int64_t ldx32, int* work, hipStream_t st);
+// Block-Jacobi workspace view (carved from the caller's workspace by the library).
+struct EigWork {
+  double* Gp;      // K x K
+  double* Z;       // K x K
+  double* V;       // p x 64 x 64
+  int* perm;       // K
+  int* ident;      // p: subproblem x of the current round left its block pair unchanged
+  unsigned long long* maxoff;  // 1
+  int* conv;       // 1
+  double* floor2;  // 1: (1e-15 ||G||_F)^2, regularises rotation thresholds
+  double* fabs_;   // 1: 16 eps ||G||_F, absolute convergence floor
+  double tol;      // relative off-diagonal tolerance
+  int64_t K;
+  int p;
+};
+
+// One problem of a batched eigen-decomposition.
+struct EigBatch {
+  EigWork w;
+  const double* G; int64_t ld; int64_t N;
+  double* lam; double* V; int64_t ldv;
+};
+EigBatch eig_batch_desc(const double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
+                        double tol);
+hipError_t launch_eig_batched(const EigBatch* descs, int count, int64_t Nmax, hipStream_t st);
 // Symmetric eigen-decomposition (block Jacobi).  G (N x N, ld) is destroyed.
 // lam (N, descending), V (N x N, ldv, column c = eigenvector of lam[c]).
 size_t eig_work_bytes(int64_t N);

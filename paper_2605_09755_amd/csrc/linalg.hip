@@ -26,20 +26,18 @@ RF_DEV void upper_tile(int id, int nt, int& tm, int& tn) {
 }
 
 template <typename TX, typename TY>
-__global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int64_t ldx, const TY* __restrict__ Y,
-                                              int64_t ldy, int64_t K, int64_t M, int64_t N, int sym,
-                                              double* __restrict__ C, int64_t ldc, double* __restrict__ partial,
-                                              int64_t kps, const int* run_if) {
-  if (run_if && *run_if == 0) return;
+RF_DEV void gram_body(const TX* __restrict__ X, int64_t ldx, const TY* __restrict__ Y, int64_t ldy, int64_t K,
+                      int64_t M, int64_t N, int sym, double* __restrict__ C, int64_t ldc,
+                      double* __restrict__ partial, int64_t kps, int bid, int split) {
   __shared__ double Xs[GK][GT];
   __shared__ double Ys[GK][GT];
   const int ntm = (int)((M + GT - 1) / GT), ntn = (int)((N + GT - 1) / GT);
   int tm, tn;
-  if (sym) upper_tile(blockIdx.x, ntm, tm, tn);
-  else { tm = blockIdx.x / ntn; tn = blockIdx.x % ntn; }
+  if (sym) upper_tile(bid, ntm, tm, tn);
+  else { tm = bid / ntn; tn = bid % ntn; }
   const int64_t i0 = (int64_t)tm * GT, j0 = (int64_t)tn * GT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, wm = wave >> 1, wn = wave & 1;
-  const int64_t kbeg = (int64_t)blockIdx.y * kps, kend = min(K, kbeg + kps);
+  const int64_t kbeg = (int64_t)split * kps, kend = min(K, kbeg + kps);
   f64x4 acc[2][2];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
@@ -85,12 +83,48 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int64_t 
         if (sym && i > j) continue;
         double v = acc[a][b][r];
         if (partial) {
-          partial[((int64_t)blockIdx.y * M + i) * N + j] = v;
+          partial[((int64_t)split * M + i) * N + j] = v;
         } else {
           C[i * ldc + j] = v;
           if (sym && i != j) C[j * ldc + i] = v;
         }
       }
+}
+
+template <typename TX, typename TY>
+__global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int64_t ldx, const TY* __restrict__ Y,
+                                              int64_t ldy, int64_t K, int64_t M, int64_t N, int sym,
+                                              double* __restrict__ C, int64_t ldc, double* __restrict__ partial,
+                                              int64_t kps, const int* run_if) {
+  if (run_if && *run_if == 0) return;
+  gram_body<TX, TY>(X, ldx, Y, ldy, K, M, N, sym, C, ldc, partial, kps, blockIdx.x, blockIdx.y);
+}
+
+// Grouped symmetric Grams C_i = X_i^T X_i (FP32 X_i, K_i x M_i): group i owns the
+// upper tiles [tile_start[i], tile_start[i+1]) of the flat grid.
+__global__ __launch_bounds__(256) void k_gram_grouped(const GramArgs* __restrict__ gs, const int* tile_start,
+                                                      int count) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tile_start[mid] <= (int)blockIdx.x) lo = mid; else hi = mid - 1;
+  }
+  const GramArgs g = gs[lo];
+  if (g.run_if && *g.run_if == 0) return;
+  gram_body<float, float>(g.X, g.ldx, g.X, g.ldx, g.K, g.M, g.M, 1, g.C, g.ldc, nullptr, g.K + GK,
+                          blockIdx.x - tile_start[lo], 0);
+}
+
+int gram_group_tiles(int64_t M) {
+  const int64_t nt = (M + GT - 1) / GT;
+  return (int)(nt * (nt + 1) / 2);
+}
+
+hipError_t launch_gram_grouped(const GramArgs* gs, const int* tile_start, int count, int total_tiles,
+                               hipStream_t st) {
+  if (count == 0 || total_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gram_grouped, dim3((unsigned)total_tiles), dim3(256), 0, st, gs, tile_start, count);
+  return hipGetLastError();
 }
 
 __global__ void k_gram_reduce(const double* __restrict__ partial, int splits, int64_t M, int64_t N, int sym,
@@ -175,20 +209,6 @@ hipError_t launch_gram(const void* X, int64_t ldx, int xdt, const void* Y, int64
 // entry is <= tol * sqrt(|G_ii G_jj| + floor^2).
 constexpr int JBMAX = 32, JSMAX = 64;  // largest block width supported by the workspace layout
 
-struct EigWork {
-  double* Gp;      // K x K
-  double* Z;       // K x K
-  double* V;       // p x 64 x 64
-  int* perm;       // K
-  int* ident;      // p: subproblem x of the current round left its block pair unchanged
-  unsigned long long* maxoff;  // 1
-  int* conv;       // 1
-  double* floor2;  // 1: (1e-15 ||G||_F)^2, regularises rotation thresholds
-  double* fabs_;   // 1: 16 eps ||G||_F, absolute convergence floor
-  double tol;      // relative off-diagonal tolerance
-  int64_t K;
-  int p;
-};
 
 static EigWork eig_layout(void* work, int64_t N, int JB) {
   EigWork w;
@@ -227,8 +247,7 @@ RF_DEV int circle(int round, int i, int n) {  // position i of round in an n-pla
   return i == 0 ? 0 : 1 + (i - 1 + round) % (n - 1);
 }
 
-__global__ void k_eig_init(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+RF_DEV void eig_init_body(const double* __restrict__ G, int64_t ld, int64_t N, const EigWork& w, int64_t idx) {
   if (idx == 0) {
     *w.maxoff = 0ull;
     *w.conv = 0;
@@ -242,7 +261,7 @@ __global__ void k_eig_init(const double* __restrict__ G, int64_t ld, int64_t N, 
   w.Z[idx] = (i == j) ? 1.0 : 0.0;
 }
 
-__global__ void k_eig_floor(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
+RF_DEV void eig_floor_body(const double* __restrict__ G, int64_t ld, int64_t N, const EigWork& w) {
   // ||G||_F (single workgroup) -> rotation floor and absolute convergence floor
   __shared__ double red[256];
   double s = 0.0;
@@ -278,7 +297,7 @@ RF_DEV void jacobi_rot(double app, double aqq, double apq, double floor2, double
 }
 
 template <int JB>
-__global__ __launch_bounds__(1024) void k_eig_solve(EigWork w, int round, int inner_sweeps) {
+RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x) {
   constexpr int JS = 2 * JB;
   if (*w.conv) return;
   extern __shared__ double sm[];
@@ -287,7 +306,7 @@ __global__ __launch_bounds__(1024) void k_eig_solve(EigWork w, int round, int in
   __shared__ double cs[JS / 2], sn[JS / 2];
   __shared__ int pa[JS / 2], pb[JS / 2];
   __shared__ int done;
-  const int x = blockIdx.x, np = 2 * w.p;
+  const int np = 2 * w.p;
   const int P = circle(round, x, np), Q = circle(round, np - 1 - x, np);
   const double floor2 = *w.floor2;
   auto gidx = [&](int a) -> int64_t { return a < JB ? (int64_t)P * JB + a : (int64_t)Q * JB + (a - JB); };
@@ -396,7 +415,7 @@ __global__ __launch_bounds__(1024) void k_eig_solve(EigWork w, int round, int in
 
 // Tiles (x, y): G[I_x, I_y] <- V_x^T G[I_x, I_y] V_y ; tiles for Z: Z[rows, I_x] <- Z[rows, I_x] V_x.
 template <int JB>
-__global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
+RF_DEV void eig_apply_body(const EigWork& w, int round, int id) {
   constexpr int JS = 2 * JB;
   if (*w.conv) return;
   extern __shared__ double sm[];
@@ -405,7 +424,6 @@ __global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
   double(*Vb)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm + 2 * JS * (JS + 1));
   const int np = 2 * w.p;
   const int ntile = w.p * w.p;
-  const int id = blockIdx.x;
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
   if (id < ntile) {
     const int x = id / w.p, y = id % w.p;
@@ -499,9 +517,8 @@ __global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
   }
 }
 
-__global__ void k_eig_check(EigWork w) {
+RF_DEV void eig_check_body(const EigWork& w, int64_t idx) {
   if (*w.conv) return;
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   double r = 0.0;
   if (idx < w.K * w.K) {
     int64_t i = idx / w.K, j = idx % w.K;
@@ -517,7 +534,7 @@ __global__ void k_eig_check(EigWork w) {
   if ((threadIdx.x & 63) == 0 && r > 0.0) atomicMax(w.maxoff, (unsigned long long)__double_as_longlong(r));
 }
 
-__global__ void k_eig_decide(EigWork w, double tol, double* trace, int sw) {
+RF_DEV void eig_decide_body(const EigWork& w, double tol, double* trace, int sw) {
   if (*w.conv) {
     if (trace) trace[sw] = 0.0;
     return;
@@ -529,7 +546,7 @@ __global__ void k_eig_decide(EigWork w, double tol, double* trace, int sw) {
 }
 
 // Sort diag(Gp) descending (bitonic, one workgroup, K <= 4096), gather outputs.
-__global__ __launch_bounds__(1024) void k_eig_sort(EigWork w, int64_t N, double* lam) {
+RF_DEV void eig_sort_body(const EigWork& w, int64_t N, double* lam) {
   __shared__ double key[4096];
   __shared__ int idx[4096];
   int Kp = 1;
@@ -562,11 +579,75 @@ __global__ __launch_bounds__(1024) void k_eig_sort(EigWork w, int64_t N, double*
   }
 }
 
-__global__ void k_eig_gather(EigWork w, int64_t N, double* V, int64_t ldv) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+RF_DEV void eig_gather_body(const EigWork& w, int64_t N, double* V, int64_t ldv, int64_t e) {
   if (e >= N * N) return;
   int64_t r = e / N, c = e % N;
   V[r * ldv + c] = w.Z[r * w.K + w.perm[c]];
+}
+
+__global__ void k_eig_init(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
+  eig_init_body(G, ld, N, w, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+__global__ void k_eig_floor(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
+  eig_floor_body(G, ld, N, w);
+}
+template <int JB>
+__global__ __launch_bounds__(1024) void k_eig_solve(EigWork w, int round, int inner_sweeps) {
+  eig_solve_body<JB>(w, round, inner_sweeps, blockIdx.x);
+}
+template <int JB>
+__global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
+  eig_apply_body<JB>(w, round, blockIdx.x);
+}
+__global__ void k_eig_check(EigWork w) { eig_check_body(w, (int64_t)blockIdx.x * blockDim.x + threadIdx.x); }
+__global__ void k_eig_decide(EigWork w, double tol, double* trace, int sw) { eig_decide_body(w, tol, trace, sw); }
+__global__ __launch_bounds__(1024) void k_eig_sort(EigWork w, int64_t N, double* lam) { eig_sort_body(w, N, lam); }
+__global__ void k_eig_gather(EigWork w, int64_t N, double* V, int64_t ldv) {
+  eig_gather_body(w, N, V, ldv, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+// ---- batched: one problem per blockIdx.y ------------------------------------------
+__global__ void k_eigb_init(const EigBatch* __restrict__ bs) {
+  const EigBatch b = bs[blockIdx.y];
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < b.w.K * b.w.K;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    eig_init_body(b.G, b.ld, b.N, b.w, idx);
+}
+__global__ void k_eigb_floor(const EigBatch* __restrict__ bs) {
+  const EigBatch b = bs[blockIdx.y];
+  eig_floor_body(b.G, b.ld, b.N, b.w);
+}
+template <int JB>
+__global__ __launch_bounds__(1024) void k_eigb_solve(const EigBatch* __restrict__ bs, int round) {
+  const EigBatch b = bs[blockIdx.y];
+  if ((int)blockIdx.x >= b.w.p || round >= 2 * b.w.p - 1) return;
+  eig_solve_body<JB>(b.w, round, 1, blockIdx.x);
+}
+template <int JB>
+__global__ __launch_bounds__(256) void k_eigb_apply(const EigBatch* __restrict__ bs, int round) {
+  const EigBatch b = bs[blockIdx.y];
+  const int ntile = b.w.p * b.w.p + (int)(b.w.K / (2 * JB)) * b.w.p;
+  if ((int)blockIdx.x >= ntile || round >= 2 * b.w.p - 1) return;
+  eig_apply_body<JB>(b.w, round, blockIdx.x);
+}
+__global__ void k_eigb_check(const EigBatch* __restrict__ bs) {
+  const EigBatch b = bs[blockIdx.y];
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  // every block of the grid row must reach the reduction: no early return
+  eig_check_body(b.w, idx < b.w.K * b.w.K ? idx : b.w.K * b.w.K);
+}
+__global__ void k_eigb_decide(const EigBatch* __restrict__ bs, double tol) {
+  const EigBatch b = bs[blockIdx.y];
+  eig_decide_body(b.w, tol, nullptr, 0);
+}
+__global__ __launch_bounds__(1024) void k_eigb_sort(const EigBatch* __restrict__ bs) {
+  const EigBatch b = bs[blockIdx.y];
+  eig_sort_body(b.w, b.N, b.lam);
+}
+__global__ void k_eigb_gather(const EigBatch* __restrict__ bs) {
+  const EigBatch b = bs[blockIdx.y];
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < b.N * b.N; e += (int64_t)gridDim.x * blockDim.x)
+    eig_gather_body(b.w, b.N, b.V, b.ldv, e);
 }
 
 template <int JB>
@@ -606,6 +687,50 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
   else eig_rounds<32>(w, N, st, trace);
   hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, st, w, N, lam);
   hipLaunchKernelGGL(k_eig_gather, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, w, N, V, ldv);
+  return hipGetLastError();
+}
+
+// Batched eigensolver: problem i (G_i N_i x N_i, ld_i, preserved) -> lam_i, V_i.
+// work_i: eig_work_bytes(N_i) bytes each; descs: device array of count EigBatch
+// written by the caller from eig_batch_desc().  All problems take the same number
+// of launches (the largest), smaller ones skip the rounds they do not have and
+// stop sweeping when converged.
+EigBatch eig_batch_desc(const double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
+                        double tol) {
+  EigBatch b;
+  b.w = eig_layout(work, N, 32);
+  b.w.tol = tol;
+  b.G = G; b.ld = ld; b.N = N; b.lam = lam; b.V = V; b.ldv = ldv;
+  return b;
+}
+
+hipError_t launch_eig_batched(const EigBatch* descs, int count, int64_t Nmax, hipStream_t st) {
+  if (count == 0 || Nmax == 0) return hipSuccess;
+  constexpr int JB = 32, JS = 64;
+  EigWork shape = eig_layout(nullptr, Nmax, JB);
+  const int64_t Kmax = shape.K;
+  const int pmax = shape.p;
+  if (Kmax > 4096) return hipErrorInvalidValue;
+  const size_t lds_solve = 2 * JS * (JS + 1) * sizeof(double);
+  const size_t lds_apply = 3 * JS * (JS + 1) * sizeof(double);
+  (void)hipFuncSetAttribute((const void*)k_eigb_solve<JB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_solve);
+  (void)hipFuncSetAttribute((const void*)k_eigb_apply<JB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_apply);
+  const int64_t KK = Kmax * Kmax;
+  const unsigned gx = (unsigned)((KK + 255) / 256);
+  hipLaunchKernelGGL(k_eigb_init, dim3(gx, count), dim3(256), 0, st, descs);
+  hipLaunchKernelGGL(k_eigb_floor, dim3(1, count), dim3(256), 0, st, descs);
+  const int rounds = 2 * pmax - 1;
+  const int ntile = pmax * pmax + (int)(Kmax / JS) * pmax;
+  for (int sw = 0; sw < eig_max_sweeps(); ++sw) {
+    for (int r = 0; r < rounds; ++r) {
+      hipLaunchKernelGGL(k_eigb_solve<JB>, dim3(pmax, count), dim3(1024), lds_solve, st, descs, r);
+      hipLaunchKernelGGL(k_eigb_apply<JB>, dim3(ntile, count), dim3(256), lds_apply, st, descs, r);
+    }
+    hipLaunchKernelGGL(k_eigb_check, dim3(gx, count), dim3(256), 0, st, descs);
+    hipLaunchKernelGGL(k_eigb_decide, dim3(1, count), dim3(1), 0, st, descs, 1.0);
+  }
+  hipLaunchKernelGGL(k_eigb_sort, dim3(1, count), dim3(1024), 0, st, descs);
+  hipLaunchKernelGGL(k_eigb_gather, dim3((unsigned)((Nmax * Nmax + 255) / 256), count), dim3(256), 0, st, descs);
   return hipGetLastError();
 }
 
@@ -662,11 +787,8 @@ hipError_t launch_fill_i32(int* p, int64_t n, int v, hipStream_t st) {
   return hipGetLastError();
 }
 
-__global__ void k_refill(float* __restrict__ X, int64_t ldx, int64_t rows, int64_t k, const int* __restrict__ flags,
-                         const int* count, const double* __restrict__ d0, uint64_t seed) {
-  if (*count == 0) return;
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * k) return;
+RF_DEV void refill_entry(float* __restrict__ X, int64_t ldx, int64_t rows, int64_t k, const int* __restrict__ flags,
+                         const double* __restrict__ d0, uint64_t seed, uint32_t b, int64_t idx) {
   int64_t i = idx / k, j = idx % k;
   if (!flags[j]) return;
   double dm = 0.0;
@@ -675,7 +797,7 @@ __global__ void k_refill(float* __restrict__ X, int64_t ldx, int64_t rows, int64
   if (!(sc > 0.0) || !isfinite(sc)) sc = 1.0 / sqrt((double)rows);
   // entry (i, j) of a rows x k Gaussian on stream 3
   int64_t e = i * k + j;
-  u32x4 x = philox((uint64_t)(e >> 2), 3u, 0u, seed);
+  u32x4 x = philox((uint64_t)(e >> 2), 3u, b, seed);
   uint32_t w[4] = {x.x, x.y, x.z, x.w};
   int q = (int)(e & 3);
   const double s32 = 2.3283064365386963e-10;
@@ -683,6 +805,14 @@ __global__ void k_refill(float* __restrict__ X, int64_t ldx, int64_t rows, int64
   double rad = sqrt(-2.0 * log(ua));
   double z = (q & 1) ? rad * sin(6.283185307179586 * ub) : rad * cos(6.283185307179586 * ub);
   X[i * ldx + j] = (float)(z * sc);
+}
+
+__global__ void k_refill(float* __restrict__ X, int64_t ldx, int64_t rows, int64_t k, const int* __restrict__ flags,
+                         const int* count, const double* __restrict__ d0, uint64_t seed) {
+  if (*count == 0) return;
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * k) return;
+  refill_entry(X, ldx, rows, k, flags, d0, seed, 0u, idx);
 }
 
 hipError_t launch_refill(float* X, int64_t ldx, int64_t rows, int64_t k, const int* flags, const int* count,
@@ -769,6 +899,123 @@ hipError_t launch_note(int* counters, int final_, hipStream_t st) {
   return hipGetLastError();
 }
 
+// ---- batched utilities (one problem per blockIdx.y, grid-stride inside) -----------
+__global__ void k_cast_batched(const CastArgs* __restrict__ as, int f64_to_f32) {
+  const CastArgs a = as[blockIdx.y];
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < a.rows * a.cols;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = idx / a.cols, j = idx % a.cols;
+    if (f64_to_f32)
+      reinterpret_cast<float*>(a.out)[i * a.ldo + j] = (float)reinterpret_cast<const double*>(a.in)[i * a.ldi + j];
+    else
+      reinterpret_cast<uint16_t*>(a.out)[i * a.ldo + j] = f32_to_bf16_rne(reinterpret_cast<const float*>(a.in)[i * a.ldi + j]);
+  }
+}
+__global__ void k_refill_batched(const RefillArgs* __restrict__ as) {
+  const RefillArgs a = as[blockIdx.y];
+  if (*a.count == 0) return;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < a.rows * a.k;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    if (a.flags[idx % a.k]) refill_entry(a.X, a.ldx, a.rows, a.k, a.flags, a.d0, a.seed, a.b, idx);
+}
+__global__ void k_note_batched(int* const* __restrict__ cs, int count, int final_) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  int* c = cs[i];
+  if (final_) {
+    c[3] = c[0];
+  } else {
+    const int n = c[0];
+    c[4] = n > 0 ? 1 : 0;
+    if (n > 0) c[1] += 1;
+  }
+}
+__global__ void k_svd_tail_batched(const SvdTailArgs* __restrict__ as, int stage) {
+  const SvdTailArgs a = as[blockIdx.z];
+  unsigned long long* keys = reinterpret_cast<unsigned long long*>(a.signw);
+  float* sgn = reinterpret_cast<float*>(a.signw + 2 * a.k);
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (stage == 0) {           // sigma, 1/sigma, FP32 copy of the Ritz vectors, clear the keys
+    const int64_t lim = a.k * a.k > 2 * a.k ? a.k * a.k : 2 * a.k;
+    for (int64_t i = t; i < lim; i += (int64_t)gridDim.x * blockDim.x) {
+      if (i < a.k * a.k) a.Ub32[i] = (float)a.Ub[i];
+      if (i < a.k) {
+        const double l = a.lam[i];
+        const double sv = l > 0.0 ? sqrt(l) : 0.0;
+        a.sigma[i] = sv;
+        a.inv[i] = sv > 0.0 ? (float)(1.0 / sv) : 0.f;
+      }
+      if (i < 2 * a.k) a.signw[i] = 0;
+    }
+  } else if (stage == 1) {    // per column: largest |U| (lowest row on ties), rows split over blockIdx.y
+    if (t >= a.k) return;
+    const int64_t rows_per = (a.m + gridDim.y - 1) / gridDim.y;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per, r1 = min(a.m, r0 + rows_per);
+    unsigned long long best = 0ull;
+    for (int64_t r = r0; r < r1; ++r) {
+      const float v = fabsf(a.U[r * a.ldu + t]);
+      const unsigned long long key =
+          ((unsigned long long)__float_as_uint(v) << 32) | (unsigned long long)(0xffffffffu - (uint32_t)r);
+      best = key > best ? key : best;
+    }
+    if (best) atomicMax(keys + t, best);
+  } else if (stage == 2) {    // signs
+    if (t >= a.k) return;
+    const int64_t rr = 0xffffffffll - (int64_t)(keys[t] & 0xffffffffull);
+    sgn[t] = (rr < a.m && a.U[rr * a.ldu + t] < 0.f) ? -1.f : 1.f;
+  } else {                    // apply to U and V^T
+    const int64_t tot = a.m * a.k + a.k * a.n;
+    for (int64_t idx = t + (int64_t)blockIdx.y * gridDim.x * blockDim.x; idx < tot;
+         idx += (int64_t)gridDim.y * gridDim.x * blockDim.x) {
+      if (idx < a.m * a.k) {
+        const int64_t r = idx / a.k, c = idx % a.k;
+        a.U[r * a.ldu + c] *= sgn[c];
+      } else {
+        const int64_t e = idx - a.m * a.k, c = e / a.n, j = e % a.n;
+        a.Vt[c * a.ldvt + j] *= sgn[c];
+      }
+    }
+  }
+}
+
+hipError_t launch_cast_batched(const CastArgs* as, int count, int64_t max_elems, int f64_to_f32, hipStream_t st) {
+  if (count == 0 || max_elems == 0) return hipSuccess;
+  unsigned gx = (unsigned)((max_elems + 255) / 256);
+  if (gx > 2048) gx = 2048;
+  hipLaunchKernelGGL(k_cast_batched, dim3(gx, count), dim3(256), 0, st, as, f64_to_f32);
+  return hipGetLastError();
+}
+hipError_t launch_refill_batched(const RefillArgs* as, int count, int64_t max_elems, hipStream_t st) {
+  if (count == 0 || max_elems == 0) return hipSuccess;
+  unsigned gx = (unsigned)((max_elems + 255) / 256);
+  if (gx > 2048) gx = 2048;
+  hipLaunchKernelGGL(k_refill_batched, dim3(gx, count), dim3(256), 0, st, as);
+  return hipGetLastError();
+}
+hipError_t launch_note_batched(int* const* cs, int count, int final_, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_note_batched, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, cs, count, final_);
+  return hipGetLastError();
+}
+hipError_t launch_svd_tail_pre_batched(const SvdTailArgs* as, int count, int64_t kmax, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const unsigned g0 = (unsigned)((kmax * kmax + 2 * kmax + 255) / 256);
+  hipLaunchKernelGGL(k_svd_tail_batched, dim3(g0, 1, count), dim3(256), 0, st, as, 0);
+  return hipGetLastError();
+}
+hipError_t launch_svd_tail_sign_batched(const SvdTailArgs* as, int count, int64_t kmax, int64_t mmax,
+                                        int64_t max_elems, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  const unsigned gk = (unsigned)((kmax + 255) / 256);
+  const unsigned gr = (unsigned)((mmax + 255) / 256);
+  hipLaunchKernelGGL(k_svd_tail_batched, dim3(gk, gr, count), dim3(256), 0, st, as, 1);
+  hipLaunchKernelGGL(k_svd_tail_batched, dim3(gk, 1, count), dim3(256), 0, st, as, 2);
+  unsigned ga = (unsigned)((max_elems + 255) / 256);
+  if (ga > 1024) ga = 1024;
+  hipLaunchKernelGGL(k_svd_tail_batched, dim3(ga, 1, count), dim3(256), 0, st, as, 3);
+  return hipGetLastError();
+}
+
 __global__ void k_nystrom_scale(const double* lam, int64_t k, float* scale) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= k) return;
@@ -787,13 +1034,27 @@ struct InfoOut {
   int32_t status, rank_found, chol_retries, nonfinite;
   double orth_err;
 };
-__global__ void k_info(InfoOut* info, const int* counters, int k, const double* orth) {
+RF_DEV void k_info_body(InfoOut* info, const int* counters, int k, const double* orth) {
   int retries = counters[1], nonf = counters[2], last = counters[3], fault = counters[5];
   info->status = (retries > 0 ? 1 : 0) | (nonf ? 2 : 0) | (fault ? 4 : 0);
   info->rank_found = k - last;
   info->chol_retries = retries;
   info->nonfinite = nonf;
   info->orth_err = orth ? *orth : -1.0;
+}
+__global__ void k_info(InfoOut* info, const int* counters, int k, const double* orth) {
+  k_info_body(info, counters, k, orth);
+}
+__global__ void k_info_batched(InfoOut* infos, const int* counters, int stride, const int* ks, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  k_info_body(&infos[i], counters + (int64_t)i * stride, ks[i], nullptr);
+}
+hipError_t launch_info_batched(void* infos, const int* counters, int stride, const int* ks, int count, hipStream_t st) {
+  if (!infos || count == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_info_batched, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, (InfoOut*)infos,
+                     counters, stride, ks, count);
+  return hipGetLastError();
 }
 hipError_t launch_info(void* info, const int* counters, int k, const double* orth, hipStream_t st) {
   if (!info) return hipSuccess;

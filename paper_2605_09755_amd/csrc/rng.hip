@@ -12,26 +12,27 @@
 namespace rf {
 
 // Integer-exact, bit-identical to the oracle table.
-__global__ void k_sketch_table(int64_t n, int s, int r1, uint64_t seed, uint32_t stream, uint32_t b,
-                               int32_t* __restrict__ out) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * s) return;
+RF_DEV int32_t sketch_entry(int64_t idx, int s, int r1, uint64_t seed, uint32_t stream, uint32_t b) {
   int t = (int)(idx % s);
   uint32_t lo = (uint32_t)(((int64_t)t * r1) / s);
   uint32_t hi = (uint32_t)(((int64_t)(t + 1) * r1) / s);
   u32x4 x = philox((uint64_t)idx, stream, b, seed);
   uint32_t bucket = lo + (uint32_t)(((uint64_t)x.x * (uint64_t)(hi - lo)) >> 32);
-  out[idx] = (int32_t)(bucket | (x.y & 0x80000000u));
+  return (int32_t)(bucket | (x.y & 0x80000000u));
+}
+
+__global__ void k_sketch_table(int64_t n, int s, int r1, uint64_t seed, uint32_t stream, uint32_t b,
+                               int32_t* __restrict__ out) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * s) return;
+  out[idx] = sketch_entry(idx, s, r1, seed, stream, b);
 }
 
 // "Ready" table for the sketch-apply kernel: entry (j, q) of lane-permuted
 // block t = (lane(j) % s) ^ q, where lane(j) = (j % (64*cpl)) / cpl owns column
 // j.  Word = sign<<31 | (b_local * 256 + 4 t): the LDS byte offset of the
 // bucket line plus the block's slot, so the kernel adds only the row part.
-__global__ void k_sketch_ready(const int32_t* __restrict__ table, int64_t n, int s, int r1, int cpl,
-                               uint32_t* __restrict__ ready) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= n * s) return;
+RF_DEV uint32_t ready_entry(const int32_t* __restrict__ table, int64_t idx, int s, int r1, int cpl) {
   int64_t j = idx / s;
   int qq = (int)(idx % s);
   int lane = (int)((j % (64 * cpl)) / cpl);
@@ -39,13 +40,18 @@ __global__ void k_sketch_ready(const int32_t* __restrict__ table, int64_t n, int
   uint32_t e = (uint32_t)table[j * s + t];
   uint32_t lo = (uint32_t)(((int64_t)t * r1) / s);
   uint32_t bl = (e & 0x7fffffffu) - lo;
-  ready[idx] = (e & 0x80000000u) | (bl * 256u + 4u * (uint32_t)t);
+  return (e & 0x80000000u) | (bl * 256u + 4u * (uint32_t)t);
 }
 
-__global__ void k_gaussian(int64_t total, uint64_t seed, uint32_t stream, uint32_t b,
-                           float* __restrict__ out, int64_t cols, int64_t ldo) {
-  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // counter index
-  if (p * 4 >= total) return;
+__global__ void k_sketch_ready(const int32_t* __restrict__ table, int64_t n, int s, int r1, int cpl,
+                               uint32_t* __restrict__ ready) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * s) return;
+  ready[idx] = ready_entry(table, idx, s, r1, cpl);
+}
+
+RF_DEV void gaussian_quad(int64_t p, int64_t total, uint64_t seed, uint32_t stream, uint32_t b,
+                          float* __restrict__ out, int64_t cols, int64_t ldo) {
   u32x4 x = philox((uint64_t)p, stream, b, seed);
   const double sc = 2.3283064365386963e-10;  // 2^-32
   double ua = ((double)x.x + 0.5) * sc, ub = ((double)x.y + 0.5) * sc;
@@ -58,6 +64,33 @@ __global__ void k_gaussian(int64_t total, uint64_t seed, uint32_t stream, uint32
     int64_t g = p * 4 + e;
     if (g < total) out[(g / cols) * ldo + (g % cols)] = (float)z[e];
   }
+}
+
+__global__ void k_gaussian(int64_t total, uint64_t seed, uint32_t stream, uint32_t b,
+                           float* __restrict__ out, int64_t cols, int64_t ldo) {
+  int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;  // counter index
+  if (p * 4 >= total) return;
+  gaussian_quad(p, total, seed, stream, b, out, cols, ldo);
+}
+
+// ---- batched: one problem per blockIdx.y, grid-stride over its entries -------------
+__global__ void k_sketch_table_batched(const RngArgs* __restrict__ as) {
+  const RngArgs a = as[blockIdx.y];
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < a.n * a.s;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    a.table[idx] = sketch_entry(idx, a.s, a.r1, a.seed, 0, a.b);
+}
+__global__ void k_sketch_ready_batched(const RngArgs* __restrict__ as) {
+  const RngArgs a = as[blockIdx.y];
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < a.n * a.s;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    a.ready[idx] = ready_entry(a.table, idx, a.s, a.r1, a.cpl);
+}
+__global__ void k_gaussian_batched(const RngArgs* __restrict__ as) {
+  const RngArgs a = as[blockIdx.y];
+  const int64_t total = (int64_t)a.r1 * a.k;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p * 4 < total; p += (int64_t)gridDim.x * blockDim.x)
+    gaussian_quad(p, total, a.seed, 1, a.b, a.om, a.k, a.k);
 }
 
 hipError_t launch_sketch_table(int64_t n, int s, int r1, uint64_t seed, uint32_t stream, uint32_t b,
@@ -85,6 +118,17 @@ hipError_t launch_gaussian(int64_t rows, int64_t cols, uint64_t seed, uint32_t s
   int64_t nc = (tot + 3) / 4;
   hipLaunchKernelGGL(k_gaussian, dim3((unsigned)((nc + 255) / 256)), dim3(256), 0, st, tot, seed, stream, b,
                      out, cols, ldo);
+  return hipGetLastError();
+}
+
+hipError_t launch_rng_batched(const RngArgs* as, int count, int64_t max_entries, hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  unsigned gx = (unsigned)((max_entries + 255) / 256);
+  if (gx > 1024) gx = 1024;
+  if (gx == 0) gx = 1;
+  hipLaunchKernelGGL(k_sketch_table_batched, dim3(gx, count), dim3(256), 0, st, as);
+  hipLaunchKernelGGL(k_sketch_ready_batched, dim3(gx, count), dim3(256), 0, st, as);
+  hipLaunchKernelGGL(k_gaussian_batched, dim3(gx, count), dim3(256), 0, st, as);
   return hipGetLastError();
 }
 

@@ -162,10 +162,10 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_right(
 // partials are folded into FP32 accumulators held in registers (each thread owns
 // a fixed set of LDS words) and cleared.
 template <typename TIN, int S, int CPL, int NW, int G, int FACC>
-__global__ __launch_bounds__(NW * 64) void k_sketch_right_fx(
-    const TIN* __restrict__ A, int64_t lda, const float* __restrict__ scales, int64_t ldsc,
-    const uint32_t* __restrict__ ready, const int* __restrict__ cmax, int64_t m, int64_t n, int r1, int wl,
-    float* __restrict__ out, int64_t ldo, float inv_sqrt_s, bool vec_ok) {
+RF_DEV void sketch_right_fx_body(const TIN* __restrict__ A, int64_t lda, const float* __restrict__ scales,
+                                 int64_t ldsc, const uint32_t* __restrict__ ready, const int* __restrict__ cmax,
+                                 int64_t m, int64_t n, int r1, int wl, float* __restrict__ out, int64_t ldo,
+                                 float inv_sqrt_s, bool vec_ok, int band) {
   constexpr int R = 64 / S;
   constexpr int NT = NW * 64;
   constexpr int64_t J = (int64_t)NW * G * 64 * CPL;  // columns per chunk
@@ -173,7 +173,7 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_right_fx(
   extern __shared__ int iacc[];
   __shared__ unsigned wgmax, wgbad;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * R;
+  const int64_t row0 = (int64_t)band * R;
   const int entries = wl * 64;
   for (int i = tid; i < entries; i += NT) iacc[i] = 0;
   if (tid == 0) { wgmax = 0u; wgbad = 0u; }
@@ -298,11 +298,29 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_right_fx(
   }
 }
 
+template <typename TIN, int S, int CPL, int NW, int G, int FACC>
+__global__ __launch_bounds__(NW * 64) void k_sketch_right_fx(
+    const TIN* __restrict__ A, int64_t lda, const float* __restrict__ scales, int64_t ldsc,
+    const uint32_t* __restrict__ ready, const int* __restrict__ cmax, int64_t m, int64_t n, int r1, int wl,
+    float* __restrict__ out, int64_t ldo, float inv_sqrt_s, bool vec_ok) {
+  sketch_right_fx_body<TIN, S, CPL, NW, G, FACC>(A, lda, scales, ldsc, ready, cmax, m, n, r1, wl, out, ldo, inv_sqrt_s,
+                                                 vec_ok, blockIdx.x);
+}
+
+// Batched sketch pass over FP32 matrices with s = 4 (one problem per blockIdx.y).
+__global__ __launch_bounds__(512) void k_sketch_right_fx_batched(const SketchArgs* __restrict__ as) {
+  const SketchArgs a = as[blockIdx.y];
+  constexpr int R = 64 / 4;
+  if ((int64_t)blockIdx.x * R >= a.m) return;
+  sketch_right_fx_body<float, 4, 2, 8, 2, 40>(a.A, a.lda, nullptr, 0, a.ready, a.cmax, a.m, a.n, a.r1,
+                                              (a.r1 + 3) / 4, a.out, a.ldo, 0.5f, a.vec_ok != 0, blockIdx.x);
+}
+
 // Maximum bucket occupancy per column chunk (over the s blocks): one workgroup per chunk.
-__global__ __launch_bounds__(256) void k_chunk_occupancy(const int32_t* __restrict__ table, int64_t n, int s, int r1,
-                                                         int64_t J, int* __restrict__ cmax) {
+RF_DEV void chunk_occupancy_body(const int32_t* __restrict__ table, int64_t n, int s, int r1, int64_t J,
+                                 int* __restrict__ cmax, int chunk) {
   extern __shared__ int hist[];
-  const int64_t j0 = (int64_t)blockIdx.x * J, j1 = min(n, j0 + J);
+  const int64_t j0 = (int64_t)chunk * J, j1 = min(n, j0 + J);
   for (int i = threadIdx.x; i < r1; i += blockDim.x) hist[i] = 0;
   __syncthreads();
   for (int64_t e = j0 * s + threadIdx.x; e < j1 * s; e += blockDim.x)
@@ -319,7 +337,20 @@ __global__ __launch_bounds__(256) void k_chunk_occupancy(const int32_t* __restri
   __shared__ int red[4];
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
   __syncthreads();
-  if (threadIdx.x == 0) cmax[blockIdx.x] = max(max(red[0], red[1]), max(red[2], red[3]));
+  if (threadIdx.x == 0) cmax[chunk] = max(max(red[0], red[1]), max(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void k_chunk_occupancy(const int32_t* __restrict__ table, int64_t n, int s, int r1,
+                                                         int64_t J, int* __restrict__ cmax) {
+  chunk_occupancy_body(table, n, s, r1, J, cmax, blockIdx.x);
+}
+
+// Batched occupancy for the s = 4 batched sketch pass (chunk J = 8 * 2 * 64 * 2).
+__global__ __launch_bounds__(256) void k_chunk_occupancy_batched(const SketchArgs* __restrict__ as) {
+  const SketchArgs a = as[blockIdx.y];
+  constexpr int64_t J = 8 * 2 * 64 * 2;
+  if ((int64_t)blockIdx.x * J >= a.n) return;
+  chunk_occupancy_body(a.table, a.n, 4, a.r1, J, a.cmax, blockIdx.x);
 }
 
 // Generic fallback (any s): one thread per element, s global atomics.  Output
@@ -478,6 +509,22 @@ static hipError_t launch_sr_fx(const void* A, int64_t lda, const float* scales, 
 }
 
 size_t sketch_right_cmax_ints(int64_t n) { return (size_t)(n / 1024 + 16); }
+
+hipError_t launch_sketch_right_batched(const SketchArgs* as, int count, int64_t mmax, int64_t nmax, int r1max,
+                                       hipStream_t st) {
+  if (count == 0) return hipSuccess;
+  constexpr int64_t J = 8 * 2 * 64 * 2;
+  const size_t hl = (size_t)r1max * sizeof(int);
+  (void)hipFuncSetAttribute((const void*)k_chunk_occupancy_batched, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)hl);
+  hipLaunchKernelGGL(k_chunk_occupancy_batched, dim3((unsigned)((nmax + J - 1) / J), count), dim3(256), hl, st, as);
+  const int wl = (r1max + 3) / 4;
+  const size_t lds = (size_t)wl * 64 * sizeof(int);
+  (void)hipFuncSetAttribute((const void*)k_sketch_right_fx_batched, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)lds);
+  hipLaunchKernelGGL(k_sketch_right_fx_batched, dim3((unsigned)((mmax + 15) / 16), count), dim3(512), lds, st, as);
+  return hipGetLastError();
+}
 
 template <typename TIN>
 static hipError_t launch_sr_dispatch(int s, const void* A, int64_t lda, const float* scales, int64_t ldsc,

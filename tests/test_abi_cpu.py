@@ -116,3 +116,34 @@ def test_hooks_reject_bad_args():
     assert L.rf_test_gemm(1, 1, 1, FAKE, 4, FAKE, 4, FAKE, 4, 4, 4, 4, 0, None, None) == rf.RF_EINVAL
     assert L.rf_test_eig(FAKE, 5000, 1e-12, FAKE, FAKE, None, FAKE, None) == rf.RF_EUNSUPPORTED
     assert L.rf_test_eig(FAKE, 50, 0.0, FAKE, FAKE, None, FAKE, None) == rf.RF_EINVAL
+
+
+def test_batched_entry_points_validate_without_gpu():
+    """Argument checks of the batched plan run before any HIP call."""
+    rf, L = _lib()
+    M = rf.RfMatrix(FAKE, None, 100, 50, 50, rf.RF_F32, 0)
+    P = rf.params(10, 20, 1, 4, 0, "mixed")
+    mats = (rf.RfMatrix * 1)(M)
+    prms = (rf.RfParams * 1)(P)
+    assert L.rf_svd_batched_ws(0, ctypes.cast(mats, ctypes.c_void_p), ctypes.cast(prms, ctypes.c_void_p)) == 0
+    assert L.rf_svd_batched_ws(1, ctypes.cast(mats, ctypes.c_void_p), ctypes.cast(prms, ctypes.c_void_p)) > 0
+    h = ctypes.c_void_p()
+    # null output arrays
+    assert L.rf_svd_batched_plan(1, ctypes.cast(mats, ctypes.c_void_p), ctypes.cast(prms, ctypes.c_void_p),
+                                 None, None, None, None, None, None, None, 0, 0, None, ctypes.byref(h)) == rf.RF_EINVAL
+    ptrs = (ctypes.c_void_p * 1)(FAKE)
+    lds = (ctypes.c_int64 * 1)(1000)
+    args = [ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(lds, ctypes.c_void_p), ctypes.cast(ptrs, ctypes.c_void_p),
+            ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(lds, ctypes.c_void_p)]
+    # unsupported: 8 nonzeros per column in a batch
+    P8 = (rf.RfParams * 1)(rf.params(10, 20, 1, 8, 0, "mixed"))
+    assert L.rf_svd_batched_plan(1, ctypes.cast(mats, ctypes.c_void_p), ctypes.cast(P8, ctypes.c_void_p), *args,
+                                 None, None, 0, 0, None, ctypes.byref(h)) == rf.RF_EUNSUPPORTED
+    # invalid: sketch below k
+    Pb = (rf.RfParams * 1)(rf.params(30, 20, 1, 4, 0, "mixed"))
+    assert L.rf_svd_batched_plan(1, ctypes.cast(mats, ctypes.c_void_p), ctypes.cast(Pb, ctypes.c_void_p), *args,
+                                 None, None, 0, 0, None, ctypes.byref(h)) == rf.RF_EINVAL
+    # workspace too small
+    assert L.rf_svd_batched_plan(1, ctypes.cast(mats, ctypes.c_void_p), ctypes.cast(prms, ctypes.c_void_p), *args,
+                                 None, FAKE, 16, 0, None, ctypes.byref(h)) == rf.RF_EWORKSPACE
+    L.rf_svd_batched_destroy(None)
