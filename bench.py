@@ -58,7 +58,8 @@ def gen_matrix(torch, m, n, p, noise_spec, seed, dev):
     A = (U * sig.to(torch.float32).unsqueeze(0)) @ V.t()
     del U, V
     tau = noise_spec * float(sig[0]) / (math.sqrt(m) + math.sqrt(n))
-    A += tau * torch.randn(m, n, generator=g, device=dev, dtype=torch.float32)
+    if tau > 0.0:
+        A += tau * torch.randn(m, n, generator=g, device=dev, dtype=torch.float32)
     torch.cuda.synchronize()
     return A, tau
 
@@ -101,6 +102,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--forms", default="fp32,mixed")
     ap.add_argument("--q", type=int, default=None, help="fixed q (skip the accuracy sweep)")
+    ap.add_argument("--batch", type=int, default=512, help="matrices in the batched workload (0: skip it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
@@ -225,6 +227,12 @@ def main():
         others[name] = {"bound": "mfma", "achieved": ach / 1e12, "peak": pk / 1e12, "unit": "TFLOP/s",
                         "frac": ach / pk}
 
+    del A, A16
+    torch.cuda.empty_cache()
+    batched = None
+    if args.batch > 0:
+        batched = batched_bench(torch, rf, args.batch, max(args.steps, 5), max(args.warmup, 1), 105, dev)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(m, n, k, l, s, args.seed, main_form["q"])
@@ -254,9 +262,92 @@ def main():
         },
         "roofline": roofline,
         "roofline_other": others,
+        "batched": batched,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def batched_bench(torch, rf, count, steps, warmup, seed, dev, seq_sample=16):
+    """Uneven batch: m ~ U[512, 8192], n ~ U[256, 4096], k ~ U[16, 256], sketch
+    min(2k, n), sigma_i = i^-p with p ~ U[0.5, 2] (no noise), q = 2, s = 4, BF16
+    products (mixed form), one stream, the whole batch replayed as one hipGraph."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        m = int(rng.integers(512, 8193))
+        n = int(rng.integers(256, 4097))
+        k = int(rng.integers(16, 257))
+        p = float(rng.uniform(0.5, 2.0))
+        l = min(2 * k, n)
+        specs.append((m, n, min(k, l), l, p))
+    t0 = time.time()
+    As = [gen_matrix(torch, m, n, p, 0.0, seed * 100003 + i, dev)[0] for i, (m, n, k, l, p) in enumerate(specs)]
+    log("batched: generated %d matrices (%.1f GB FP32) in %.1fs" % (
+        count, sum(m * n for m, n, _, _, _ in specs) * 4 / 1e9, time.time() - t0))
+    ks = [k for _, _, k, _, _ in specs]
+    ls = [l for _, _, _, l, _ in specs]
+    t0 = time.time()
+    plan = rf.BatchPlan(As, ks, ls, q=2, nnz_per_col=4, seeds=105, precision="mixed", use_graph=True)
+    log("batched: plan + graph capture in %.1fs" % (time.time() - t0))
+    for _ in range(warmup):
+        plan.run()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream(dev)
+    times = []
+    for _ in range(steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        plan.run()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    times = np.array(times)
+    infos = plan.info.cpu().numpy()
+    bad = int(sum(int.from_bytes(infos[i, 0:4].tobytes(), "little") & 6 != 0 for i in range(count)))
+    # accuracy on a sample: ||A - U U^T A||_F / opt_F, opt from the known spectrum
+    ratios = []
+    for i in range(0, count, max(1, count // 16)):
+        m, n, k, l, p = specs[i]
+        r = min(m, n)
+        sig = np.arange(1, r + 1, dtype=np.float64) ** -p
+        opt = math.sqrt(float(np.sum(sig[k:] ** 2)))
+        ratios.append(frob_err(torch, As[i], plan.U[i]) / opt)
+    # context: the same problems one rf_svd call each (sample, extrapolated)
+    seq_ms = None
+    if seq_sample:
+        idx = list(range(0, count, max(1, count // seq_sample)))[:seq_sample]
+        for i in idx[:2]:
+            rf.rf_svd(As[i], ks[i], ls[i], 2, 4, 105, "mixed")
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for i in idx:
+            rf.rf_svd(As[i], ks[i], ls[i], 2, 4, 105, "mixed")
+        e1.record(stream)
+        torch.cuda.synchronize()
+        seq_ms = e0.elapsed_time(e1) / len(idx)
+    bytes_two_passes = 2.0 * 4.0 * sum(m * n for m, n, _, _, _ in specs)
+    mean_ms = float(times.mean())
+    out = {
+        "workload": "%d matrices, m~U[512,8192], n~U[256,4096], k~U[16,256], sketch=min(2k,n), sigma_i=i^-p, "
+                    "p~U[0.5,2], no noise; q=2, nnz/col=4, BF16 products; one hipGraph replay per batch" % count,
+        "matrices_per_s": count / (mean_ms / 1e3),
+        "ms_per_batch": mean_ms,
+        "p50_ms": float(np.percentile(times, 50)), "p99_ms": float(np.percentile(times, 99)),
+        "latency_note": "every matrix of a batch completes with the batch: per-matrix latency = batch latency",
+        "steps": steps, "error_ratio_sample_mean": float(np.mean(ratios)), "error_ratio_sample_max": float(np.max(ratios)),
+        "problems_flagged": bad,
+        "a_read_twice_GBps": bytes_two_passes / (mean_ms / 1e3) / 1e9,
+        "sequential_rf_svd_ms_per_matrix": seq_ms,
+        "speedup_vs_sequential": (seq_ms * count / mean_ms) if seq_ms else None,
+    }
+    log("batched: %.2f ms / batch of %d (%.0f matrices/s), p50 %.2f p99 %.2f ms; error ratio sample mean %.4f max %.4f; "
+        "one call per matrix %.2f ms" % (mean_ms, count, out["matrices_per_s"], out["p50_ms"], out["p99_ms"],
+                                          out["error_ratio_sample_mean"], out["error_ratio_sample_max"], seq_ms or -1))
+    del plan, As
+    torch.cuda.empty_cache()
+    return out
 
 
 def cpu_baseline(m, n, k, l, s, seed, q):
