@@ -141,6 +141,25 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
                      int64_t ldw, float* F, int64_t ldf, void* ws, size_t ws_bytes,
                      rf_info* info, void* stream);
 
+/* ---- tuning table for the dense products ---------------------------------
+
+   A product with operands of dtype (0 = FP32, 2 = BF16) and shape M x N x K
+   takes the first rule with matching dtype and M <= max_m, N <= max_n,
+   K <= max_k: tile = 128 or 256 (workgroup tile edge; 256 only for BF16),
+   split = 0 (built-in heuristic) or 1..16 (split-K factor, further capped so
+   each split keeps >= 256 values of K).  Without a matching rule the built-in
+   heuristics apply.  The rules are copied; count = 0 clears them.  The table
+   is process-wide: set it before other calls (it is read on every launch and
+   must not change while a call is enqueuing).  Returns RF_EINVAL (table
+   unchanged) for a malformed rule or count > 256.  Written by the autotuner
+   (paper_2605_09755_amd/autotune.py) as JSON; the Python binding loads the
+   table it finds next to the library. */
+typedef struct {
+  int32_t dtype, tile, split, reserved;
+  int64_t max_m, max_n, max_k;
+} rf_gemm_rule;
+rf_status rf_set_gemm_rules(const rf_gemm_rule* rules, int32_t count);
+
 /* ---- batched randomised SVD (many independent matrices, one stream) -------
 
    count problems: As[i] (FP32, device), ps[i] with nnz_per_col = 4, the same q

@@ -22,7 +22,7 @@ __all__ = [
     "RF_OP_RANGE_FINDER", "RF_OP_SVD", "RF_OP_LOWRANK", "RF_OP_NYSTROM",
     "lib", "library_path", "rf_status_string", "rf_workspace_size", "rf_sketch_table", "rf_gaussian",
     "rf_sketch_apply", "rf_range_finder", "rf_svd", "rf_lowrank", "rf_nystrom", "RFError",
-    "BatchPlan", "rf_svd_batched",
+    "BatchPlan", "rf_svd_batched", "set_gemm_rules", "load_tuning",
 ]
 
 RF_OK, RF_EINVAL, RF_EWORKSPACE, RF_EUNSUPPORTED, RF_EHIP = 0, 1, 2, 3, 4
@@ -90,6 +90,8 @@ def lib():
         L.rf_lowrank.argtypes = [M, P, vp, i64, vp, i64, vp, sz, vp, vp]
         L.rf_nystrom.restype = i32
         L.rf_nystrom.argtypes = [M, P, vp, i64, vp, i64, vp, i64, vp, sz, vp, vp]
+        L.rf_set_gemm_rules.restype = i32
+        L.rf_set_gemm_rules.argtypes = [vp, i32]
         L.rf_svd_batched_ws.restype = sz
         L.rf_svd_batched_ws.argtypes = [i32, vp, vp]
         L.rf_svd_batched_plan.restype = i32
@@ -117,7 +119,35 @@ def lib():
         L.rf_test_eig.restype = i32
         L.rf_test_eig.argtypes = [vp, i64, ctypes.c_double, vp, vp, vp, vp, vp]
         _lib = L
+        if os.path.exists(tuning_path):
+            load_tuning(tuning_path)
     return _lib
+
+
+class RfGemmRule(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("tile", ctypes.c_int32), ("split", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("max_m", ctypes.c_int64), ("max_n", ctypes.c_int64),
+                ("max_k", ctypes.c_int64)]
+
+
+tuning_path = os.path.join(_HERE, "tuning.json")
+
+
+def set_gemm_rules(rules):
+    """Install a GEMM tuning table: rules = [(dtype, tile, split, max_m, max_n, max_k), ...]
+    (dtype 0 FP32 / 2 BF16); [] restores the built-in heuristics."""
+    arr = (RfGemmRule * max(len(rules), 1))(*[RfGemmRule(int(d), int(t), int(sp), 0, int(a), int(b), int(c))
+                                              for d, t, sp, a, b, c in rules])
+    _check("rf_set_gemm_rules", lib().rf_set_gemm_rules(ctypes.cast(arr, ctypes.c_void_p), len(rules)))
+
+
+def load_tuning(path):
+    """Install the rule table written by paper_2605_09755_amd.autotune."""
+    import json
+    with open(path) as f:
+        doc = json.load(f)
+    set_gemm_rules([(r["dtype"], r["tile"], r["split"], r["max_m"], r["max_n"], r["max_k"]) for r in doc["rules"]])
+    return doc
 
 
 def _status_name(s):

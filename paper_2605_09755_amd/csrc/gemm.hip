@@ -13,6 +13,8 @@
 // in registers (2 x 8 blocks) on their way into LDS, which always stores BF16
 // k-contiguous.  Split-K writes FP32 partials that a second kernel sums in
 // fixed order (deterministic).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -619,14 +621,50 @@ static int gemm_splits_big(int64_t M, int64_t N, int64_t K) {
   return s;
 }
 
+// ---- tuning table (written by the autotuner, read on every launch) -------------------
+// First rule whose dtype matches and whose bounds hold picks the tile and the split
+// count; no match: the heuristics above.  Split counts are capped at kMaxTunedSplit
+// (and at K / 256) so the partial buffer sized by gemm_partial_floats always fits.
+constexpr int kMaxRules = 256, kMaxTunedSplit = 16;
+static GemmRule g_rules[kMaxRules];
+static int g_nrules = 0;
+
+int set_gemm_rules(const GemmRule* rules, int count) {
+  if (count < 0 || count > kMaxRules || (count > 0 && !rules)) return -1;
+  for (int i = 0; i < count; ++i) {
+    const GemmRule& r = rules[i];
+    if ((r.dtype != 0 && r.dtype != 2) || (r.tile != 128 && r.tile != 256) || (r.tile == 256 && r.dtype != 2) ||
+        r.split < 0 || r.split > kMaxTunedSplit)
+      return -1;
+  }
+  for (int i = 0; i < count; ++i) g_rules[i] = rules[i];
+  g_nrules = count;
+  return 0;
+}
+
+static int tuned_cap(int64_t K) {
+  int s = 1;
+  while (s < kMaxTunedSplit && K / (2 * s) >= 256) s *= 2;
+  return s;
+}
+
+static const GemmRule* find_rule(int dtype, int64_t M, int64_t N, int64_t K) {
+  for (int i = 0; i < g_nrules; ++i) {
+    const GemmRule& r = g_rules[i];
+    if (r.dtype == dtype && M <= r.max_m && N <= r.max_n && K <= r.max_k) return &r;
+  }
+  return nullptr;
+}
+
 bool gemm_use_big(int dtype, int64_t M, int64_t N) {
   if (dtype == 4) return true;
   return dtype == 2 && M >= 512 && N >= 512;
 }
 
 size_t gemm_partial_floats(int64_t M, int64_t N, int64_t K) {
-  int s1 = gemm_splits(M, N, K), s2 = gemm_splits_big(M, N, K);
-  int s = s1 > s2 ? s1 : s2;
+  int s = gemm_splits(M, N, K);
+  s = std::max(s, gemm_splits_big(M, N, K));
+  s = std::max(s, tuned_cap(K));
   return s > 1 ? (size_t)s * M * N : 0;
 }
 
@@ -644,8 +682,13 @@ static void go_big(const GemmArgs& g, dim3 grid, hipStream_t st) {
 
 hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
   if (g.M == 0 || g.N == 0) return hipSuccess;
-  const bool big = gemm_use_big(dtype, g.M, g.N);
-  int splits = partial ? (big ? gemm_splits_big(g.M, g.N, g.K) : gemm_splits(g.M, g.N, g.K)) : 1;
+  const GemmRule* rule = (dtype == 0 || dtype == 2) ? find_rule(dtype, g.M, g.N, g.K) : nullptr;
+  const bool big = rule ? (rule->tile == 256) : gemm_use_big(dtype, g.M, g.N);
+  int splits = 1;
+  if (partial) {
+    if (rule && rule->split > 0) splits = std::min(rule->split, tuned_cap(g.K));
+    else splits = big ? gemm_splits_big(g.M, g.N, g.K) : gemm_splits(g.M, g.N, g.K);
+  }
   if (g.b_upper) splits = 1;
   int64_t bk = 32;
   g.kps = ((g.K + splits - 1) / splits + bk - 1) / bk * bk;

@@ -58,6 +58,10 @@ struct GemmArgs {
   int64_t kps;            // set by launcher
   float* partial;         // set by launcher
 };
+// Tuning rule: dtype 0 (FP32) or 2 (BF16); applies when M <= max_m, N <= max_n,
+// K <= max_k; tile 128 or 256 (BF16 only); split 0 (heuristic) or 1..16.
+struct GemmRule { int32_t dtype, tile, split, reserved; int64_t max_m, max_n, max_k; };
+int set_gemm_rules(const GemmRule* rules, int count);  // 0 ok, -1 invalid (table unchanged)
 int gemm_splits(int64_t M, int64_t N, int64_t K);
 size_t gemm_partial_floats(int64_t M, int64_t N, int64_t K);
 // dtype: 0 FP32 operands, 2 BF16 operands.  partial may be NULL (no split-K).

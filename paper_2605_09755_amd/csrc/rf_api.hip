@@ -493,6 +493,11 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
 }
 
 // ------------------------------------------------------------------ parity hooks
+rf_status rf_set_gemm_rules(const rf_gemm_rule* rules, int32_t count) {
+  static_assert(sizeof(rf_gemm_rule) == sizeof(GemmRule), "rule layouts differ");
+  return set_gemm_rules(reinterpret_cast<const GemmRule*>(rules), count) == 0 ? RF_OK : RF_EINVAL;
+}
+
 size_t rf_test_gemm_ws(int64_t M, int64_t N, int64_t K) { return gemm_partial_floats(M, N, K) * sizeof(float) + 256; }
 
 rf_status rf_test_gemm(int dtype, int a_kc, int b_kc, const void* A, int64_t lda, const void* B, int64_t ldb, float* C,

@@ -147,3 +147,20 @@ def test_batched_entry_points_validate_without_gpu():
     assert L.rf_svd_batched_plan(1, ctypes.cast(mats, ctypes.c_void_p), ctypes.cast(prms, ctypes.c_void_p), *args,
                                  None, FAKE, 16, 0, None, ctypes.byref(h)) == rf.RF_EWORKSPACE
     L.rf_svd_batched_destroy(None)
+
+
+def test_gemm_rules_validate():
+    rf, L = _lib()
+    big = 1 << 62
+    ok = [(0, 128, 4, big, big, big), (2, 256, 0, 4096, 4096, big)]
+    rf.set_gemm_rules(ok)
+    for bad in [(0, 256, 1, big, big, big),      # 256 tiles are BF16 only
+                (2, 64, 1, big, big, big),       # no such tile
+                (2, 128, 17, big, big, big),     # split above 16
+                (1, 128, 1, big, big, big)]:     # dtype
+        with pytest.raises(rf.RFError) as e:
+            rf.set_gemm_rules([bad])
+        assert e.value.status == rf.RF_EINVAL
+    with pytest.raises(rf.RFError):
+        rf.set_gemm_rules([ok[0]] * 257)
+    rf.set_gemm_rules([])

@@ -284,3 +284,35 @@ def test_eig_fp32_output_tolerance(N):
     d = np.sqrt(np.abs(np.diag(D)))
     off = np.abs(D - np.diag(np.diag(D))) / np.maximum(np.outer(d, d), 16 * 2.2e-16 * np.linalg.norm(G) / 1e-7)
     assert off.max() < 2e-7
+
+
+# ---------------------------------------------------------------- tuning table
+@pytest.mark.parametrize("bf16", [False, True])
+def test_gemm_every_tuned_config_is_correct(bf16):
+    """Each tile / split-K choice the autotuner may install gives the product."""
+    from paper_2605_09755_amd import autotune
+    rng = np.random.default_rng(77)
+    M, N, K = 700, 600, 5000
+    dA, dB, A, B = _operands(M, N, K, 0, 0, rng, bf16)
+    ref = A @ B
+    mag = np.abs(A) @ np.abs(B)
+    big = 1 << 62
+    try:
+        for tile, split in autotune.candidates(2 if bf16 else 0):
+            rf.set_gemm_rules([(2 if bf16 else 0, tile, split, big, big, big)])
+            C = rf.rf_test_gemm(dA, dB, M, N, K, 0, 0).cpu().numpy()
+            assert np.all(np.abs(C - ref) <= (K + 2) * U32 * mag + 1e-30), (tile, split)
+    finally:
+        rf.set_gemm_rules([])
+
+
+def test_autotune_writes_rules():
+    from paper_2605_09755_amd import autotune
+    try:
+        rules = autotune.tune(autotune.QUICK, reps=1, log=lambda *a: None)
+    finally:
+        rf.set_gemm_rules([])
+    assert len(rules) == 2 * len(autotune.QUICK)
+    for r in rules:
+        assert (r["tile"], r["split"]) in autotune.candidates(r["dtype"])
+        assert r["max_m"] >= r["shape"][0] and r["max_n"] >= r["shape"][1] and r["max_k"] >= r["shape"][2]
