@@ -275,7 +275,8 @@ struct Sched {
     // B^T = A^T Q (n x k)
     if (mixed) {
       cast(0, [&](int i) { const Prob& p = P[i]; return CastArgs{p.Q, p.Q16, p.m, p.k, p.k, p.k}; });
-      gemm(4, 0, 0, [&](int i, GemmArgs& g) {
+      // k <= 1024 and mostly small: 128 x 128 tiles waste less of N than 256 x 256
+      gemm(pl.kmax > 512 ? 4 : 5, 0, 0, [&](int i, GemmArgs& g) {
         const Prob& p = P[i];
         g.A = p.A; g.lda = p.lda; g.B = p.Q16; g.ldb = p.k; g.C = p.Bt; g.ldc = p.k; g.M = p.n; g.N = p.k; g.K = p.m;
       });

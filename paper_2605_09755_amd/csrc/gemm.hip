@@ -194,7 +194,12 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
 RF_DEV uint32_t pack_lo(uint32_t a, uint32_t b) { return (a & 0xffffu) | (b << 16); }
 RF_DEV uint32_t pack_hi(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
 
-template <bool AKC, bool BKC>
+RF_DEV uint32_t pack2_bf16(float a, float b) {
+  return (uint32_t)f32_to_bf16_rne(a) | ((uint32_t)f32_to_bf16_rne(b) << 16);
+}
+
+// AF32: the A operand is FP32 in memory and rounded to BF16 (RNE) as it is loaded.
+template <bool AKC, bool BKC, bool AF32 = false>
 RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
   constexpr int BK = 32;
   constexpr int ST = BK + 8;  // bf16 elements per LDS row (80 B)
@@ -274,10 +279,56 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
     *reinterpret_cast<uint4*>(S + (2 * lane) * ST + 8 * wave) = src[0];
     *reinterpret_cast<uint4*>(S + (2 * lane + 1) * ST + 8 * wave) = src[1];
   };
-  const bool avec = AKC ? ((((uintptr_t)A) & 15) == 0 && (g.lda & 7) == 0) : ((((uintptr_t)A) & 3) == 0 && (g.lda & 1) == 0);
+  // FP32 A, same element positions as load_kc / load_tc, rounded to BF16
+  const float* Af = reinterpret_cast<const float*>(g.A);
+  auto load_kc_f32 = [&](int64_t r0, int64_t rmax, int64_t k0, uint4* dst, bool vec) {
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+      int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 8;
+      int64_t r = r0 + row, k = k0 + kc;
+      float t[8];
+      if (vec && r < rmax && k + 8 <= kend) {
+        const float4 x0 = *reinterpret_cast<const float4*>(Af + r * g.lda + k);
+        const float4 x1 = *reinterpret_cast<const float4*>(Af + r * g.lda + k + 4);
+        t[0] = x0.x; t[1] = x0.y; t[2] = x0.z; t[3] = x0.w; t[4] = x1.x; t[5] = x1.y; t[6] = x1.z; t[7] = x1.w;
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = (r < rmax && k + e < kend) ? Af[r * g.lda + k + e] : 0.f;
+      }
+      dst[ps] = make_uint4(pack2_bf16(t[0], t[1]), pack2_bf16(t[2], t[3]), pack2_bf16(t[4], t[5]),
+                           pack2_bf16(t[6], t[7]));
+    }
+  };
+  auto load_tc_f32 = [&](int64_t r0, int64_t rmax, int64_t k0, uint4* dst, bool vec) {
+    uint32_t w[8];
+    int64_t r = r0 + 2 * lane;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      int64_t k = k0 + 8 * wave + e;
+      float lo, hi;
+      if (vec && k < kend && r + 1 < rmax) {
+        const float2 x = *reinterpret_cast<const float2*>(Af + k * g.lda + r);
+        lo = x.x; hi = x.y;
+      } else {
+        lo = (k < kend && r < rmax) ? Af[k * g.lda + r] : 0.f;
+        hi = (k < kend && r + 1 < rmax) ? Af[k * g.lda + r + 1] : 0.f;
+      }
+      w[e] = pack2_bf16(lo, hi);
+    }
+    dst[0] = make_uint4(pack_lo(w[0], w[1]), pack_lo(w[2], w[3]), pack_lo(w[4], w[5]), pack_lo(w[6], w[7]));
+    dst[1] = make_uint4(pack_hi(w[0], w[1]), pack_hi(w[2], w[3]), pack_hi(w[4], w[5]), pack_hi(w[6], w[7]));
+  };
+  const bool avec = AF32 ? (AKC ? ((((uintptr_t)Af) & 15) == 0 && (g.lda & 3) == 0)
+                                : ((((uintptr_t)Af) & 7) == 0 && (g.lda & 1) == 0))
+                         : (AKC ? ((((uintptr_t)A) & 15) == 0 && (g.lda & 7) == 0)
+                                : ((((uintptr_t)A) & 3) == 0 && (g.lda & 1) == 0));
   const bool bvec = BKC ? ((((uintptr_t)B) & 15) == 0 && (g.ldb & 7) == 0) : ((((uintptr_t)B) & 3) == 0 && (g.ldb & 1) == 0);
   auto gload = [&](int64_t k0) {
-    if (AKC) load_kc(A, g.lda, i0, g.M, k0, sa, avec); else load_tc(A, g.lda, i0, g.M, k0, sa, avec);
+    if constexpr (AF32) {
+      if (AKC) load_kc_f32(i0, g.M, k0, sa, avec); else load_tc_f32(i0, g.M, k0, sa, avec);
+    } else {
+      if (AKC) load_kc(A, g.lda, i0, g.M, k0, sa, avec); else load_tc(A, g.lda, i0, g.M, k0, sa, avec);
+    }
     if (BKC) load_kc(B, g.ldb, j0, g.N, k0, sb, bvec); else load_tc(B, g.ldb, j0, g.N, k0, sb, bvec);
   };
   auto sstore = [&](int buf) {
@@ -578,6 +629,14 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_grouped(const GemmArgs* __res
   if (g.M == 0 || g.N == 0) return;
   gemm_bf16_body<AKC, BKC>(g, blockIdx.x - tile_start[i], 0);
 }
+template <bool AKC, bool BKC>
+__global__ __launch_bounds__(256) void k_gemm_bf16a32_grouped(const GemmArgs* __restrict__ gs, const int* tile_start,
+                                                              int count) {
+  const int i = find_group(tile_start, count, blockIdx.x);
+  const GemmArgs g = gs[i];
+  if (g.M == 0 || g.N == 0) return;
+  gemm_bf16_body<AKC, BKC, true>(g, blockIdx.x - tile_start[i], 0);
+}
 template <bool AKC, bool BKC, bool AF32>
 __global__ __launch_bounds__(256, 1) void k_gemm_bf16_big_grouped(const GemmArgs* __restrict__ gs,
                                                                   const int* tile_start, int count) {
@@ -766,6 +825,12 @@ hipError_t launch_gemm_grouped(const GemmArgs* gs, const int* tile_start, int co
       else if (sel == 2) hipLaunchKernelGGL((k_gemm_bf16_grouped<true, false>), grid, blk, 0, st, gs, tile_start, count);
       else if (sel == 1) hipLaunchKernelGGL((k_gemm_bf16_grouped<false, true>), grid, blk, 0, st, gs, tile_start, count);
       else hipLaunchKernelGGL((k_gemm_bf16_grouped<false, false>), grid, blk, 0, st, gs, tile_start, count);
+      break;
+    case 5:
+      if (sel == 3) hipLaunchKernelGGL((k_gemm_bf16a32_grouped<true, true>), grid, blk, 0, st, gs, tile_start, count);
+      else if (sel == 2) hipLaunchKernelGGL((k_gemm_bf16a32_grouped<true, false>), grid, blk, 0, st, gs, tile_start, count);
+      else if (sel == 1) hipLaunchKernelGGL((k_gemm_bf16a32_grouped<false, true>), grid, blk, 0, st, gs, tile_start, count);
+      else hipLaunchKernelGGL((k_gemm_bf16a32_grouped<false, false>), grid, blk, 0, st, gs, tile_start, count);
       break;
     case 3:
       if (sel == 3) go_big_grouped<true, true, false>(gs, tile_start, count, total_tiles, st);

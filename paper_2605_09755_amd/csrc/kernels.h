@@ -69,7 +69,8 @@ hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st);
 // Grouped products: count independent GemmArgs (device array, kps = K, partial = 0)
 // in one grid; tile_start (device, count + 1 entries) is the prefix sum of
 // gemm_group_tiles(kind, M_i, N_i).  kind: 0 FP32 (128 x 128 tiles), 2 BF16
-// (128 x 128), 3 BF16 (256 x 256), 4 BF16 with A FP32 rounded on load (256 x 256).
+// (128 x 128), 3 BF16 (256 x 256), 4 BF16 with A FP32 rounded on load (256 x 256),
+// 5 BF16 with A FP32 rounded on load (128 x 128).
 int gemm_group_tiles(int kind, int64_t M, int64_t N);
 hipError_t launch_gemm_grouped(const GemmArgs* gs, const int* tile_start, int count, int total_tiles, int kind,
                                int a_kc, int b_kc, hipStream_t st);
