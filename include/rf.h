@@ -70,8 +70,9 @@ typedef enum {
                            power product At Z stays FP32.  An FP32 A is rounded to
                            BF16 as Q^T A loads it, so sigma and V carry BF16
                            product error (~1e-3 relative) while the range of Q
-                           (and U) does not.  FP8 A is not accepted by rf_svd /
-                           rf_lowrank (RF_EUNSUPPORTED). */
+                           (and U) does not.  FP8 A (either form): Q^T A
+                           dequantises A and rounds it to BF16 as it loads it
+                           (BF16 MFMA); the sketch passes dequantise in FP32. */
 } rf_precision;
 /* In both forms the Gram matrices of CholeskyQR2, the Cholesky factors, the
    triangular inverses and the Rayleigh-Ritz eigenproblem are FP64. */
@@ -230,6 +231,12 @@ size_t rf_test_gemm_ws(int64_t M, int64_t N, int64_t K);
 rf_status rf_test_gemm(int dtype, int a_kc, int b_kc, const void* A, int64_t lda, const void* B, int64_t ldb,
                        float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, int b_upper, void* ws,
                        void* stream);
+/* rf_test_gemm_fp8a: C (M x N FP32, ldc) = op(A) op(B) with A OCP e4m3 bytes stored
+   K x M row-major (lda >= M; op(A)(i,k) = A[k*lda+i] * scales[(k/128)*ceil(M/128) + i/128],
+   the block-scaled form of rf_dtype RF_FP8E4M3_B128), rounded to BF16 as it is
+   loaded, and B BF16 (b_kc as in rf_test_gemm); BF16 MFMA, FP32 accumulation. */
+rf_status rf_test_gemm_fp8a(const uint8_t* A, int64_t lda, const float* scales, const uint16_t* B, int64_t ldb,
+                            int b_kc, float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, void* stream);
 size_t rf_test_gram_ws(int64_t K, int64_t M, int64_t N);
 rf_status rf_test_gram(const float* X, const float* Y, int64_t K, int64_t M, int64_t N, int sym, double* C,
                        void* ws, void* stream);

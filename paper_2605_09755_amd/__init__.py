@@ -106,6 +106,8 @@ def lib():
         L.rf_test_gemm.restype = i32
         L.rf_test_gemm.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, vp, i64, vp, i64, vp, i64, i64, i64,
                                    i64, ctypes.c_int, vp, vp]
+        L.rf_test_gemm_fp8a.restype = i32
+        L.rf_test_gemm_fp8a.argtypes = [vp, i64, vp, vp, i64, ctypes.c_int, vp, i64, i64, i64, i64, vp]
         L.rf_test_gram_ws.restype = sz
         L.rf_test_gram_ws.argtypes = [i64, i64, i64]
         L.rf_test_gram.restype = i32
@@ -360,6 +362,14 @@ def rf_test_gemm(A, B, M, N, K, a_kc, b_kc, b_upper=False, split=True):
     ws = torch.empty(int(lib().rf_test_gemm_ws(M, N, K)), dtype=torch.uint8, device=A.device) if split else None
     _check("rf_test_gemm", lib().rf_test_gemm(dtype, int(a_kc), int(b_kc), _ptr(A), lda, _ptr(B), ldb, _ptr(C), N, M,
                                               N, K, int(b_upper), _ptr(ws), _stream(A.device)))
+    return C
+
+
+def rf_test_gemm_fp8a(A8, scales, B, M, N, K, b_kc):
+    """C = op(A) op(B): A8 (K x M uint8 e4m3 codes, 128 x 128 block scales), B bfloat16."""
+    C = torch.empty((M, N), dtype=torch.float32, device=A8.device)
+    _check("rf_test_gemm_fp8a", lib().rf_test_gemm_fp8a(_ptr(A8), A8.stride(0), _ptr(scales), _ptr(B), B.stride(0),
+                                                        int(b_kc), _ptr(C), N, M, N, K, _stream(A8.device)))
     return C
 
 

@@ -431,19 +431,37 @@ RF_DEV uint4 pack8_bf16(float4 a, float4 b) {
 
 // One operand's share of a stage: 4 chunks of 8 consecutive elements per thread.
 // KC: chunk c -> row c/4 of the tile, k offset 8 (c%4); else k row c/32, column 8 (c%32).
-template <bool KC, bool F32>
+template <bool KC, int MODE>  // MODE 0: BF16, 1: FP32, 2: FP8 e4m3 x block scale (m/n-contiguous only)
 struct BigStage {
+  static constexpr bool F32 = (MODE == 1);
+  static constexpr bool F8 = (MODE == 2);
+  static_assert(!(F8 && KC), "FP8 operands are read m/n-contiguous");
   uint4 v[4];
   float4 f[4][2];
+  uint2 b8[4];
+  float sc[4];
   RF_DEV void load(const void* P_, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, int64_t kend, bool vec,
-                   int tid) {
+                   int tid, const float* scales = nullptr, int64_t ldsc = 0) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int c = tid + 256 * q;
       const int64_t r = KC ? r0 + (c >> 2) : r0 + 8 * (c & 31);       // first m/n index of the chunk
       const int64_t k = KC ? k0 + 8 * (c & 3) : k0 + (c >> 5);        // first k index of the chunk
       const bool full = KC ? (r < rmax && k + 8 <= kend) : (k < kend && r + 8 <= rmax);
-      if constexpr (F32) {
+      if constexpr (F8) {
+        const uint8_t* P = reinterpret_cast<const uint8_t*>(P_);
+        const uint8_t* src = P + k * ld + r;
+        sc[q] = (k < kend && r < rmax) ? scales[(k >> 7) * ldsc + (r >> 7)] : 0.f;
+        if (vec && full) {
+          b8[q] = *reinterpret_cast<const uint2*>(src);
+        } else {
+          uint32_t w[2] = {0u, 0u};
+#pragma unroll
+          for (int e = 0; e < 8; ++e)
+            if (k < kend && r + e < rmax) w[e >> 2] |= (uint32_t)src[e] << (8 * (e & 3));
+          b8[q] = make_uint2(w[0], w[1]);
+        }
+      } else if constexpr (F32) {
         const float* P = reinterpret_cast<const float*>(P_);
         const float* src = KC ? P + r * ld + k : P + k * ld + r;
         if (vec && full) {
@@ -483,14 +501,22 @@ struct BigStage {
       const int c = tid + 256 * q;
       uint16_t* dst = KC ? S + (c >> 2) * KRL + 8 * (c & 3) : S + (c >> 5) * TRL + 8 * (c & 31);
       uint4 x;
-      if constexpr (F32) x = pack8_bf16(f[q][0], f[q][1]);
-      else x = v[q];
+      if constexpr (F8) {
+        float t[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = fp8e4m3_to_f32(((e < 4 ? b8[q].x : b8[q].y) >> (8 * (e & 3))) & 0xffu) * sc[q];
+        x = pack8_bf16(make_float4(t[0], t[1], t[2], t[3]), make_float4(t[4], t[5], t[6], t[7]));
+      } else if constexpr (F32) {
+        x = pack8_bf16(f[q][0], f[q][1]);
+      } else {
+        x = v[q];
+      }
       *reinterpret_cast<uint4*>(dst) = x;
     }
   }
 };
 
-template <bool AKC, bool BKC, bool AF32>
+template <bool AKC, bool BKC, int AMODE>
 RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
   extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
   constexpr int AS = big_stage_elems<AKC>(), BS = big_stage_elems<BKC>();
@@ -507,8 +533,9 @@ RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
   int64_t kend = min(g.K, kbeg + g.kps);
   if (g.b_upper) kend = min(kend, j0 + HB);
 
-  const int aes = AF32 ? 4 : 2;
-  const bool avec = ((((uintptr_t)g.A) & 15) == 0) && ((g.lda * aes) % 16 == 0);
+  const int aes = AMODE == 1 ? 4 : (AMODE == 2 ? 1 : 2);
+  const int aal = AMODE == 2 ? 8 : 16;  // FP8 chunks are 8 bytes
+  const bool avec = ((((uintptr_t)g.A) & (aal - 1)) == 0) && ((g.lda * aes) % aal == 0);
   const bool bvec = ((((uintptr_t)g.B) & 15) == 0) && ((g.ldb * 2) % 16 == 0);
 
   f32x16 acc[4][4];
@@ -519,11 +546,11 @@ RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  BigStage<AKC, AF32> sa;
-  BigStage<BKC, false> sb;
+  BigStage<AKC, AMODE> sa;
+  BigStage<BKC, 0> sb;
   const int nk = kend > kbeg ? (int)((kend - kbeg + HBK - 1) / HBK) : 0;
   if (nk > 0) {
-    sa.load(g.A, g.lda, i0, g.M, kbeg, kend, avec, tid);
+    sa.load(g.A, g.lda, i0, g.M, kbeg, kend, avec, tid, g.a_scales, g.a_ldsc);
     sb.load(g.B, g.ldb, j0, g.N, kbeg, kend, bvec, tid);
     sa.store(A0, tid);
     sb.store(B0, tid);
@@ -533,7 +560,7 @@ RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
     const int buf = kt & 1;
     if (kt + 1 < nk) {
       const int64_t k1 = kbeg + (int64_t)(kt + 1) * HBK;
-      sa.load(g.A, g.lda, i0, g.M, k1, kend, avec, tid);
+      sa.load(g.A, g.lda, i0, g.M, k1, kend, avec, tid, g.a_scales, g.a_ldsc);
       sb.load(g.B, g.ldb, j0, g.N, k1, kend, bvec, tid);
     }
     const uint16_t* A_ = A0 + buf * AS;
@@ -596,9 +623,9 @@ template <bool AKC, bool BKC>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   gemm_bf16_body<AKC, BKC>(g, blockIdx.x, blockIdx.y);
 }
-template <bool AKC, bool BKC, bool AF32>
+template <bool AKC, bool BKC, int AMODE>
 __global__ __launch_bounds__(256, 1) void k_gemm_bf16_big(GemmArgs g) {
-  gemm_bf16_big_body<AKC, BKC, AF32>(g, blockIdx.x, blockIdx.y);
+  gemm_bf16_big_body<AKC, BKC, AMODE>(g, blockIdx.x, blockIdx.y);
 }
 
 // ---- grouped launches: many independent products in one grid --------------------
@@ -637,13 +664,13 @@ __global__ __launch_bounds__(256) void k_gemm_bf16a32_grouped(const GemmArgs* __
   if (g.M == 0 || g.N == 0) return;
   gemm_bf16_body<AKC, BKC, true>(g, blockIdx.x - tile_start[i], 0);
 }
-template <bool AKC, bool BKC, bool AF32>
+template <bool AKC, bool BKC, int AMODE>
 __global__ __launch_bounds__(256, 1) void k_gemm_bf16_big_grouped(const GemmArgs* __restrict__ gs,
                                                                   const int* tile_start, int count) {
   const int i = find_group(tile_start, count, blockIdx.x);
   const GemmArgs g = gs[i];
   if (g.M == 0 || g.N == 0) return;
-  gemm_bf16_big_body<AKC, BKC, AF32>(g, blockIdx.x - tile_start[i], 0);
+  gemm_bf16_big_body<AKC, BKC, AMODE>(g, blockIdx.x - tile_start[i], 0);
 }
 
 __global__ void k_gemm_reduce(GemmArgs g, int splits) {
@@ -716,7 +743,7 @@ static const GemmRule* find_rule(int dtype, int64_t M, int64_t N, int64_t K) {
 }
 
 bool gemm_use_big(int dtype, int64_t M, int64_t N) {
-  if (dtype == 4) return true;
+  if (dtype == 4 || dtype == 6) return true;
   return dtype == 2 && M >= 512 && N >= 512;
 }
 
@@ -727,7 +754,7 @@ size_t gemm_partial_floats(int64_t M, int64_t N, int64_t K) {
   return s > 1 ? (size_t)s * M * N : 0;
 }
 
-template <bool AKC, bool BKC, bool AF32>
+template <bool AKC, bool BKC, int AF32>
 static void go_big(const GemmArgs& g, dim3 grid, hipStream_t st) {
   constexpr size_t lds = 2 * (size_t)(big_stage_elems<AKC>() + big_stage_elems<BKC>()) * sizeof(uint16_t);
   static bool attr = false;
@@ -765,20 +792,24 @@ hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
     else if (!g.a_kc && g.b_kc) go(k_gemm_f32<false, true>);
     else go(k_gemm_f32<false, false>);
   } else if (dtype == 2 && big) {
-    if (g.a_kc && g.b_kc) go_big<true, true, false>(g, grid, st);
-    else if (g.a_kc && !g.b_kc) go_big<true, false, false>(g, grid, st);
-    else if (!g.a_kc && g.b_kc) go_big<false, true, false>(g, grid, st);
-    else go_big<false, false, false>(g, grid, st);
+    if (g.a_kc && g.b_kc) go_big<true, true, 0>(g, grid, st);
+    else if (g.a_kc && !g.b_kc) go_big<true, false, 0>(g, grid, st);
+    else if (!g.a_kc && g.b_kc) go_big<false, true, 0>(g, grid, st);
+    else go_big<false, false, 0>(g, grid, st);
   } else if (dtype == 2) {
     if (g.a_kc && g.b_kc) go(k_gemm_bf16<true, true>);
     else if (g.a_kc && !g.b_kc) go(k_gemm_bf16<true, false>);
     else if (!g.a_kc && g.b_kc) go(k_gemm_bf16<false, true>);
     else go(k_gemm_bf16<false, false>);
+  } else if (dtype == 6) {
+    if (g.a_kc || !g.a_scales) return hipErrorInvalidValue;
+    if (g.b_kc) go_big<false, true, 2>(g, grid, st);
+    else go_big<false, false, 2>(g, grid, st);
   } else if (dtype == 4) {
-    if (g.a_kc && g.b_kc) go_big<true, true, true>(g, grid, st);
-    else if (g.a_kc && !g.b_kc) go_big<true, false, true>(g, grid, st);
-    else if (!g.a_kc && g.b_kc) go_big<false, true, true>(g, grid, st);
-    else go_big<false, false, true>(g, grid, st);
+    if (g.a_kc && g.b_kc) go_big<true, true, 1>(g, grid, st);
+    else if (g.a_kc && !g.b_kc) go_big<true, false, 1>(g, grid, st);
+    else if (!g.a_kc && g.b_kc) go_big<false, true, 1>(g, grid, st);
+    else go_big<false, false, 1>(g, grid, st);
   } else {
     return hipErrorInvalidValue;
   }
@@ -795,7 +826,7 @@ int gemm_group_tiles(int kind, int64_t M, int64_t N) {
   return (int)(((M + b - 1) / b) * ((N + b - 1) / b));
 }
 
-template <bool AKC, bool BKC, bool AF32>
+template <bool AKC, bool BKC, int AF32>
 static void go_big_grouped(const GemmArgs* gs, const int* ts, int count, int tiles, hipStream_t st) {
   constexpr size_t lds = 2 * (size_t)(big_stage_elems<AKC>() + big_stage_elems<BKC>()) * sizeof(uint16_t);
   static bool attr = false;
@@ -833,16 +864,16 @@ hipError_t launch_gemm_grouped(const GemmArgs* gs, const int* tile_start, int co
       else hipLaunchKernelGGL((k_gemm_bf16a32_grouped<false, false>), grid, blk, 0, st, gs, tile_start, count);
       break;
     case 3:
-      if (sel == 3) go_big_grouped<true, true, false>(gs, tile_start, count, total_tiles, st);
-      else if (sel == 2) go_big_grouped<true, false, false>(gs, tile_start, count, total_tiles, st);
-      else if (sel == 1) go_big_grouped<false, true, false>(gs, tile_start, count, total_tiles, st);
-      else go_big_grouped<false, false, false>(gs, tile_start, count, total_tiles, st);
+      if (sel == 3) go_big_grouped<true, true, 0>(gs, tile_start, count, total_tiles, st);
+      else if (sel == 2) go_big_grouped<true, false, 0>(gs, tile_start, count, total_tiles, st);
+      else if (sel == 1) go_big_grouped<false, true, 0>(gs, tile_start, count, total_tiles, st);
+      else go_big_grouped<false, false, 0>(gs, tile_start, count, total_tiles, st);
       break;
     case 4:
-      if (sel == 3) go_big_grouped<true, true, true>(gs, tile_start, count, total_tiles, st);
-      else if (sel == 2) go_big_grouped<true, false, true>(gs, tile_start, count, total_tiles, st);
-      else if (sel == 1) go_big_grouped<false, true, true>(gs, tile_start, count, total_tiles, st);
-      else go_big_grouped<false, false, true>(gs, tile_start, count, total_tiles, st);
+      if (sel == 3) go_big_grouped<true, true, 1>(gs, tile_start, count, total_tiles, st);
+      else if (sel == 2) go_big_grouped<true, false, 1>(gs, tile_start, count, total_tiles, st);
+      else if (sel == 1) go_big_grouped<false, true, 1>(gs, tile_start, count, total_tiles, st);
+      else go_big_grouped<false, false, 1>(gs, tile_start, count, total_tiles, st);
       break;
     default:
       return hipErrorInvalidValue;

@@ -44,7 +44,8 @@ hipError_t launch_sketch_right(int dtype, const void* A, int64_t lda, const floa
                                int64_t ldo, hipStream_t st);
 size_t sketch_left_partial_floats(int64_t M, int64_t N, int r1);
 hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32_t* table, int s, int64_t M,
-                              int64_t N, int r1, float* out, int64_t ldo, float* partial, hipStream_t st);
+                              int64_t N, int r1, float* out, int64_t ldo, float* partial, hipStream_t st,
+                              const float* scales = nullptr);
 
 // ---- K5 / K6 ----
 struct GemmArgs {
@@ -57,6 +58,8 @@ struct GemmArgs {
   int b_upper;            // op(B)(k,j) == 0 for k > j (skip those k)
   int64_t kps;            // set by launcher
   float* partial;         // set by launcher
+  const float* a_scales;  // FP8 A only: 128 x 128 block scales of the stored A (k-block rows)
+  int64_t a_ldsc;         //   scale of element (k, i) = a_scales[(k/128) * a_ldsc + i/128]
 };
 // Tuning rule: dtype 0 (FP32) or 2 (BF16); applies when M <= max_m, N <= max_n,
 // K <= max_k; tile 128 or 256 (BF16 only); split 0 (heuristic) or 1..16.

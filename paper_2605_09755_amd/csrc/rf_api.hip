@@ -84,9 +84,12 @@ struct Ctx {
 
 static void gemm(Ctx& c, int dtype, const void* A, int64_t lda, int a_kc, const void* B, int64_t ldb, int b_kc, void* C,
                  int64_t ldc, int64_t M, int64_t N, int64_t K, float* partial, const float* colscale = nullptr,
-                 int c_trans = 0, int b_upper = 0, int c_bf16 = 0) {
+                 int c_trans = 0, int b_upper = 0, int c_bf16 = 0, const float* a_scales = nullptr,
+                 int64_t a_ldsc = 0) {
   GemmArgs g;
   memset(&g, 0, sizeof(g));
+  g.a_scales = a_scales;
+  g.a_ldsc = a_ldsc;
   g.A = A; g.lda = lda; g.a_kc = a_kc;
   g.B = B; g.ldb = ldb; g.b_kc = b_kc;
   g.C = C; g.ldc = ldc; g.c_trans = c_trans; g.c_bf16 = c_bf16;
@@ -376,7 +379,7 @@ rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, 
                  void* ws, size_t ws_bytes, rf_info* info, void* stream) {
   if (!valid_matrix(A) || !valid_params(A, p, false) || !U || !sigma || !Vt || ldu < p->k || ldvt < A->cols)
     return RF_EINVAL;
-  if (A->dtype == RF_FP8E4M3_B128 || p->k > 4096) return RF_EUNSUPPORTED;
+  if (p->k > 4096) return RF_EUNSUPPORTED;
   Dims d = dims_of(A, p);
   if (!ws || ws_bytes < ws_size(RF_OP_SVD, d)) return RF_EWORKSPACE;
   Arena ar(align_ws(ws));
@@ -394,7 +397,13 @@ rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, 
   // B^T = A^T Q (n x k): the one extra pass over A of the randomised SVD.  BF16
   // products when A is stored in BF16, or in the mixed form (FP32 A is then
   // rounded to BF16 as it is loaded).
-  if (A->dtype == RF_BF16 || d.prec == RF_PREC_MIXED) {
+  if (A->dtype == RF_FP8E4M3_B128) {
+    // block-scaled FP8 A is dequantised and rounded to BF16 as it is loaded
+    uint16_t* q16 = b.Q16 ? b.Q16 : (uint16_t*)b.Ya;
+    c.chk(launch_cast_f32_bf16(s.Q, k, q16, k, d.m, k, c.st));
+    gemm(c, 6, A->data, A->ld, 0, q16, k, 0, s.Bt, k, d.n, k, d.m, nullptr, nullptr, 0, 0, 0, A->block_scales,
+         (d.n + 127) / 128);
+  } else if (A->dtype == RF_BF16 || d.prec == RF_PREC_MIXED) {
     uint16_t* q16 = b.Q16 ? b.Q16 : (uint16_t*)b.Ya;
     c.chk(launch_cast_f32_bf16(s.Q, k, q16, k, d.m, k, c.st));
     gemm(c, A->dtype == RF_BF16 ? 2 : 4, A->data, A->ld, 0, q16, k, 0, s.Bt, k, d.n, k, d.m, nullptr);
@@ -417,7 +426,6 @@ rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, 
 rf_status rf_lowrank(const rf_matrix* A, const rf_params* p, float* Y, int64_t ldy, float* X, int64_t ldx, void* ws,
                      size_t ws_bytes, rf_info* info, void* stream) {
   if (!valid_matrix(A) || !valid_params(A, p, false) || !Y || !X || ldy < p->k || ldx < A->cols) return RF_EINVAL;
-  if (A->dtype == RF_FP8E4M3_B128) return RF_EUNSUPPORTED;
   Dims d = dims_of(A, p);
   if (!ws || ws_bytes < ws_size(RF_OP_LOWRANK, d)) return RF_EWORKSPACE;
   Arena ar(align_ws(ws));
@@ -430,7 +438,8 @@ rf_status rf_lowrank(const rf_matrix* A, const rf_params* p, float* Y, int64_t l
   // S2 (m x r1, stream 2): P = S2^T Q (r1 x k), T = S2^T A (r1 x n, second pass over A)
   c.chk(launch_sketch_table(d.m, d.s, r1, p->seed, 2, 0, l.table2, c.st));
   c.chk(launch_sketch_left(0, l.Q, k, l.table2, d.s, d.m, k, r1, l.P, k, l.lpart, c.st));
-  c.chk(launch_sketch_left(A->dtype, A->data, A->ld, l.table2, d.s, d.m, d.n, r1, l.T, d.n, l.lpart, c.st));
+  c.chk(launch_sketch_left(A->dtype, A->data, A->ld, l.table2, d.s, d.m, d.n, r1, l.T, d.n, l.lpart, c.st,
+                           A->block_scales));
   // X = (P^T P)^{-1} P^T T with P^T P = R^T R (FP64):  X = Rinv (Rinv^T (P^T T))
   c.chk(launch_gram(l.P, k, 0, l.P, k, 0, r1, k, k, 1, b.G, k, b.gpart, nullptr, c.st));
   c.chk(launch_cholinv(b.G, k, k, chol_tol(k), b.d0, b.flags, &b.counters[0], &b.counters[2], &b.counters[5], nullptr,
@@ -508,6 +517,16 @@ rf_status rf_test_gemm(int dtype, int a_kc, int b_kc, const void* A, int64_t lda
   c.st = (hipStream_t)stream;
   gemm(c, dtype, A, lda, a_kc ? 1 : 0, B, ldb, b_kc ? 1 : 0, C, ldc, M, N, K, ws ? (float*)align_ws(ws) : nullptr,
        nullptr, 0, b_upper ? 1 : 0);
+  return finish(c);
+}
+
+rf_status rf_test_gemm_fp8a(const uint8_t* A, int64_t lda, const float* scales, const uint16_t* B, int64_t ldb, int b_kc,
+                            float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, void* stream) {
+  if (!A || !scales || !B || !C || M < 0 || N < 0 || K < 0 || ldc < N || lda < M || (b_kc ? ldb < K : ldb < N))
+    return RF_EINVAL;
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  gemm(c, 6, A, lda, 0, B, ldb, b_kc ? 1 : 0, C, ldc, M, N, K, nullptr, nullptr, 0, 0, 0, scales, (M + 127) / 128);
   return finish(c);
 }
 

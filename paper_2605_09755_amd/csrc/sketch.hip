@@ -384,6 +384,7 @@ __global__ void k_fill_zero(float* p, int64_t rows, int64_t cols, int64_t ld) {
 // uniform and the 64 lanes add into 64 consecutive LDS words (no conflicts).
 template <typename TIN, int NW>
 __global__ __launch_bounds__(NW * 64) void k_sketch_left(const TIN* __restrict__ X, int64_t ldx,
+                                                         const float* __restrict__ bscale, int64_t ldsc,
                                                          const int32_t* __restrict__ table, int s, int64_t M,
                                                          int64_t N, int r1, int cw, int64_t rows_per_split,
                                                          float* __restrict__ out, int64_t ldo,
@@ -398,6 +399,7 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_left(const TIN* __restrict__
   __syncthreads();
   for (int64_t i = rbeg + wave; i < rend; i += NW) {
     float x = (col < N) ? ld_elem<TIN>(X + i * ldx + col) : 0.f;
+    if constexpr (sizeof(TIN) == 1) x *= (col < N) ? bscale[(i >> 7) * ldsc + (col >> 7)] : 0.f;
     const int32_t* tp = table + i * s;
     for (int t = 0; t < s; ++t) {
       uint32_t e = (uint32_t)tp[t];
@@ -595,7 +597,8 @@ size_t sketch_left_partial_floats(int64_t M, int64_t N, int r1) {
 }
 
 hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32_t* table, int s, int64_t M,
-                              int64_t N, int r1, float* out, int64_t ldo, float* partial, hipStream_t st) {
+                              int64_t N, int r1, float* out, int64_t ldo, float* partial, hipStream_t st,
+                              const float* scales) {
   if (N == 0 || r1 == 0) return hipSuccess;
   constexpr int NW = 4;
   int cw = 512;
@@ -611,16 +614,22 @@ hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32
   float scale = 1.0f / sqrtf((float)s);
   dim3 grid((unsigned)strips, (unsigned)chunks, (unsigned)splits);
   float* part = splits > 1 ? partial : nullptr;
+  const int64_t ldsc = (N + 127) / 128;
   if (dtype == 0) {
     auto k = k_sketch_left<float, NW>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const float*)X, ldx, table, s, M, N, r1, cw, rps, out, ldo,
-                       part, scale);
+    hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const float*)X, ldx, nullptr, 0, table, s, M, N, r1, cw, rps,
+                       out, ldo, part, scale);
   } else if (dtype == 2) {
     auto k = k_sketch_left<uint16_t, NW>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const uint16_t*)X, ldx, table, s, M, N, r1, cw, rps, out,
-                       ldo, part, scale);
+    hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const uint16_t*)X, ldx, nullptr, 0, table, s, M, N, r1, cw,
+                       rps, out, ldo, part, scale);
+  } else if (dtype == 3 && scales) {
+    auto k = k_sketch_left<uint8_t, NW>;
+    hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const uint8_t*)X, ldx, scales, ldsc, table, s, M, N, r1, cw,
+                       rps, out, ldo, part, scale);
   } else {
     return hipErrorInvalidValue;
   }

@@ -168,6 +168,24 @@ def test_gemm_f32_a_rounded_on_load(a_kc, b_kc, M, N, K):
     assert np.all(np.abs(C - A @ B) <= (K + 2) * U32 * mag + 1e-30)
 
 
+@pytest.mark.parametrize("b_kc", [0, 1])
+@pytest.mark.parametrize("M,N,K", [(600, 300, 1000), (520, 700, 257), (1030, 64, 4100)])
+def test_gemm_fp8_block_scaled_a(b_kc, M, N, K):
+    """A stored as e4m3 with 128 x 128 block scales (K x M), dequantised and rounded
+    to BF16 as it is loaded: the result is the BF16 product of round(dequant(A)) and B."""
+    rng = np.random.default_rng(M + 3 * N + K)
+    X = rng.standard_normal((K, M)) * np.exp(rng.standard_normal((K, 1)))
+    codes, scales = fp8_ref.quantize_blocks(X)
+    Adeq = fp8_ref.dequantize(codes, scales)
+    _, A = bf16_round(Adeq.T)                           # op(A) = A^T of the stored K x M
+    Bt, B = bf16_round(rng.standard_normal((K, N)))
+    Bstore = Bt.t().contiguous() if b_kc else Bt
+    C = rf.rf_test_gemm_fp8a(torch.from_numpy(codes).to(DEV), torch.from_numpy(scales).to(DEV), Bstore.to(DEV),
+                             M, N, K, b_kc).cpu().numpy()
+    mag = np.abs(A) @ np.abs(B)
+    assert np.all(np.abs(C - A @ B) <= (K + 2) * U32 * mag + 1e-30)
+
+
 @pytest.mark.parametrize("bf16", [False, True])
 def test_gemm_upper_triangular_b(bf16):
     rng = np.random.default_rng(9)

@@ -161,6 +161,32 @@ def test_mixed_svd_fp32_storage():
     assert ev.frob_error(A, U) <= 1.02 * ev.frob_error(A, ref.U)
 
 
+@pytest.mark.parametrize("precision", ["fp32", "mixed"])
+def test_fp8_storage_svd_and_lowrank(precision):
+    """A stored once in e4m3 with 128 x 128 block scales: the oracle runs on the
+    dequantised matrix.  Q^T A uses BF16 products (sigma within BF16 product
+    error); the range and Algorithm 2's Y X keep FP32-level agreement."""
+    from tests import fp8_ref
+    A32, _ = _instance("exp65k", 1300, 900)
+    codes, scales = fp8_ref.quantize_blocks(A32.astype(np.float64))
+    Aq = fp8_ref.dequantize(codes, scales)
+    dA = torch.from_numpy(codes).to(DEV)
+    dS = torch.from_numpy(scales).to(DEV)
+    U, sig, Vt, info = rf.rf_svd(dA, 80, 160, 2, 8, seed=42, precision=precision, scales=dS)
+    ref = me.rand_svd(Aq, me.Params(k=80, l=160, q=2, s=8, seed=42))
+    sig = sig.cpu().numpy()
+    U = U.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(sig - ref.sigma) <= 2e-2 * ref.sigma + 1e-3 * ref.sigma[0])
+    assert ev.frob_error(Aq, U) <= 1.02 * ev.frob_error(Aq, ref.U)
+    Y, X, _ = rf.rf_lowrank(dA, 80, 160, 2, 8, seed=42, precision=precision, scales=dS)
+    Y = Y.cpu().numpy().astype(np.float64)
+    X = X.cpu().numpy().astype(np.float64)
+    lr = me.lowrank(Aq, me.Params(k=80, l=160, q=2, s=8, seed=42))
+    e_gpu = np.linalg.norm(Aq - Y @ X)
+    e_ref = np.linalg.norm(Aq - lr.Q @ lr.X)
+    assert e_gpu <= 1.02 * e_ref + 1e-6 * np.linalg.norm(Aq)
+
+
 # ---------------------------------------------------------------- edge cases
 def test_exact_recovery_rank_le_k():
     rng = np.random.default_rng(3)
