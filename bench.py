@@ -103,10 +103,16 @@ def main():
     ap.add_argument("--forms", default="fp32,mixed")
     ap.add_argument("--q", type=int, default=None, help="fixed q (skip the accuracy sweep)")
     ap.add_argument("--batch", type=int, default=512, help="matrices in the batched workload (0: skip it)")
+    ap.add_argument("--counter-run", choices=["sketch", "copy"], default=None,
+                    help="for rocprofv3 --pmc runs: three sketch passes over the workload matrix, or three copies "
+                         "of 1 GiB (FETCH_SIZE / WRITE_SIZE calibration); prints nothing else")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build runs on one GPU only (no multi-GPU path); use --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.counter_run:
+        counter_run(args)
+        return
 
     import torch
     import paper_2605_09755_amd as rf
@@ -217,7 +223,7 @@ def main():
     sk = roof["sketch_f32"]
     achieved = sk["bytes"] / sk["seconds_per_call"]
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": None, "kernel": "k_sketch_right_fx<float,8,4,8,2,40>",
+                "frac": achieved / HBM_PEAK, "traffic": sketch_traffic(), "kernel": "k_sketch_right_fx<float,8,4,8,2,40>",
                 "per_launch": "read A %d x %d FP32 + write At %d x %d FP32" % (m, n, m, l)}
     others = {}
     for name in ("qta_f32", "qta_bf16"):
@@ -266,6 +272,48 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def counter_run(args):
+    import torch
+    import paper_2605_09755_amd as rf
+    dev = torch.device("cuda:0")
+    if args.counter_run == "copy":
+        x = torch.empty(1 << 28, dtype=torch.float32, device=dev).uniform_()
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+    else:
+        # the sketch's memory traffic does not depend on the values, so a Gaussian
+        # matrix of the workload's shape stands in (no QR, which the counter
+        # collection does not survive)
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed)
+        A = torch.randn((args.m, args.n), generator=g, device=dev)
+        for _ in range(3):
+            rf.rf_sketch_apply(A, args.sketch, args.s, 42)
+    torch.cuda.synchronize()
+
+
+def sketch_traffic():
+    """HBM bytes per launch of the sketch kernel from the committed counter summary,
+    valid only while the kernel source is the one the counters were taken on."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "sketch_right_fx_poly65k_counters.md")
+    src = os.path.join(ROOT, "paper_2605_09755_amd", "csrc", "sketch.hip")
+    try:
+        text = open(path).read()
+        digest = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        key, sep, val = line.partition(":")
+        if sep and key.strip() in ("source_sha256_16", "traffic_bytes"):
+            fields[key.strip()] = val.strip().strip("`")
+    if fields.get("source_sha256_16") != digest or "traffic_bytes" not in fields:
+        return None
+    return float(fields["traffic_bytes"])
 
 
 def batched_bench(torch, rf, count, steps, warmup, seed, dev, seq_sample=16):
