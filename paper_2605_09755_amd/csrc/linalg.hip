@@ -283,17 +283,32 @@ RF_DEV void eig_floor_body(const double* __restrict__ G, int64_t ld, int64_t N, 
   }
 }
 
+// Symmetric 2x2 Jacobi rotation (Golub & Van Loan, sym.schur2): J = [c s; -s c]
+// zeroes apq in J^T [app apq; apq aqq] J for t = s / c = sign(d) 2 apq /
+// (|d| + sqrt(d^2 + 4 apq^2)), d = aqq - app (the smaller root of
+// t^2 + 2 tau t - 1 = 0, tau = d / (2 apq)).  The angle is taken in FP32 from d
+// and 2 apq scaled by a power of two (no overflow or underflow); (c, s) is then
+// normalised in FP64 (c^2 + s^2 = 1 to FP64 rounding, second-order correction of
+// 1/sqrt(c0^2 + s0^2)).  Callers apply the rotation exactly, so the FP32 angle
+// only leaves a residual of relative size ~1e-7 in the pair for later rotations.
+// Pairs with |apq| <= 1e-17 sqrt(|app aqq| + floor2) are left alone.
 RF_DEV void jacobi_rot(double app, double aqq, double apq, double floor2, double& c, double& s) {
-  double scale = sqrt(fabs(app) * fabs(aqq) + floor2);
-  if (!(fabs(apq) > 1e-17 * scale)) {
-    c = 1.0;
-    s = 0.0;
+  if (!(apq * apq > 1e-34 * (fabs(app * aqq) + floor2))) {
+    c = 1.0; s = 0.0;
     return;
   }
-  double tau = (aqq - app) / (2.0 * apq);
-  double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-  c = 1.0 / sqrt(1.0 + t * t);
-  s = t * c;
+  const double d = aqq - app, y2 = 2.0 * apq;
+  int e;
+  (void)frexp(fmax(fabs(d), fabs(y2)), &e);
+  const float x = (float)ldexp(d, -e), y = (float)ldexp(y2, -e);  // max(|x|, |y|) in [1/2, 1)
+  const float den = fabsf(x) + __builtin_amdgcn_sqrtf(x * x + y * y);
+  const float tf = (x >= 0.f ? y : -y) * __builtin_amdgcn_rcpf(den);
+  const float c0 = __builtin_amdgcn_rsqf(1.f + tf * tf), s0 = tf * c0;
+  const double dc = c0, ds = s0;
+  const double del = fma(dc, dc, ds * ds) - 1.0;
+  const double f = fma(del, fma(del, 0.375, -0.5), 1.0);
+  c = dc * f;
+  s = ds * f;
 }
 
 template <int JB>
@@ -365,7 +380,7 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
         pa[u] = a;
         pb[u] = b;
         double c, s;
-        jacobi_rot(M[a][a], M[b][b], M[a][b], floor2, c, s);
+        jacobi_rot(M[a][a], M[b][b], M[a][b], floor2, c, s);  // FP32 angle, exact FP64 rotation
         cs[u] = c;
         sn[u] = s;
       }
@@ -380,7 +395,6 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
         double t10 = su * m00 + cu * m10, t11 = su * m01 + cu * m11;
         double r00 = cv * t00 - sv * t01, r01 = sv * t00 + cv * t01;
         double r10 = cv * t10 - sv * t11, r11 = sv * t10 + cv * t11;
-        if (u == v) { r01 = 0.0; r10 = 0.0; }
         M[a][cc] = r00; M[a][d] = r01; M[b][cc] = r10; M[b][d] = r11;
       }
       for (int e = threadIdx.x; e < JS * (JS / 2); e += blockDim.x) {
@@ -413,109 +427,165 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
   for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) out[(e / JS) * JS + rnk[e % JS]] = V[e / JS][e % JS];
 }
 
-// Tiles (x, y): G[I_x, I_y] <- V_x^T G[I_x, I_y] V_y ; tiles for Z: Z[rows, I_x] <- Z[rows, I_x] V_x.
+// 64 x 64 FP64 products on v_mfma_f64_16x16x4f64, 4 waves, each a 32 x 32
+// quadrant of 2 x 2 blocks of 16 x 16.  Operand A (16 x 4 per MFMA, lane l holds
+// row l%16, k = l/16) and B (4 x 16, lane l holds column l%16, k = l/16).  The
+// result of block (i, j), register r of lane l, is row wm*32 + i*16 + l/16 + 4r,
+// column wn*32 + j*16 + l%16.
+struct Mfma64 {
+  int lane, wm, wn;
+  RF_DEV Mfma64() : lane(threadIdx.x & 63), wm((threadIdx.x >> 6) >> 1), wn((threadIdx.x >> 6) & 1) {}
+  RF_DEV int arow(int i) const { return wm * 32 + i * 16 + (lane & 15); }
+  RF_DEV int bcol(int j) const { return wn * 32 + j * 16 + (lane & 15); }
+  RF_DEV int krow(int kk) const { return 4 * kk + (lane >> 4); }
+  // register operands of a row-major 64 x 64 matrix in global memory:
+  // B operand (X as B: X[k][col]) or A operand of X^T (X^T[row][k] = X[k][row])
+  RF_DEV void load_b(const double* __restrict__ X, double (&r)[16][2]) const {
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) r[kk][j] = X[krow(kk) * 64 + bcol(j)];
+  }
+  RF_DEV void load_at(const double* __restrict__ X, double (&r)[16][2]) const {
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk)
+#pragma unroll
+      for (int i = 0; i < 2; ++i) r[kk][i] = X[krow(kk) * 64 + arow(i)];
+  }
+  // acc = S B with S in LDS (A operand) and B in registers
+  RF_DEV void mul_lds_reg(const double (*S)[65], const double (&bv)[16][2], f64x4 (&acc)[2][2]) const {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double af[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) af[i] = S[arow(i)][krow(kk)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bv[kk][j], acc[i][j], 0, 0, 0);
+    }
+  }
+  // acc = A S with A in registers (A operand) and S in LDS (B operand)
+  RF_DEV void mul_reg_lds(const double (&av)[16][2], const double (*S)[65], f64x4 (&acc)[2][2]) const {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      double bf[2];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) bf[j] = S[krow(kk)][bcol(j)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk][i], bf[j], acc[i][j], 0, 0, 0);
+    }
+  }
+  RF_DEV void store(const f64x4 (&acc)[2][2], double (*S)[65]) const {
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) S[wm * 32 + i * 16 + (lane >> 4) + 4 * r][bcol(j)] = acc[i][j][r];
+  }
+};
+
+// Work item id < p(p+1)/2: tile (x, y), x <= y, G[I_x, I_y] <- V_x^T G[I_x, I_y] V_y,
+// written to both (x, y) and (y, x) so G stays exactly symmetric.  Other ids:
+// Z[rows, I_x] <- Z[rows, I_x] V_x for one 64-row strip.  256 threads; the tile
+// is staged in LDS, the V operands go from global memory straight to registers.
 template <int JB>
 RF_DEV void eig_apply_body(const EigWork& w, int round, int id) {
   constexpr int JS = 2 * JB;
+  static_assert(JS == 64, "the MFMA tile product is written for 64 x 64 subproblems");
   if (*w.conv) return;
   extern __shared__ double sm[];
   double(*T)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm);
-  double(*Va)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm + JS * (JS + 1));
-  double(*Vb)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm + 2 * JS * (JS + 1));
   const int np = 2 * w.p;
-  const int ntile = w.p * w.p;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  if (id < ntile) {
-    const int x = id / w.p, y = id % w.p;
-    if (w.ident[x] && w.ident[y]) return;
+  const int nsym = w.p * (w.p + 1) / 2;
+  const Mfma64 mm;
+  f64x4 acc[2][2];
+  double opa[16][2], opb[16][2];
+  if (id < nsym) {
+    int x, y;
+    upper_tile(id, w.p, x, y);
+    const int idx_ = w.ident[x], idy_ = w.ident[y];
+    if (idx_ && idy_) return;
     const int Px = circle(round, x, np), Qx = circle(round, np - 1 - x, np);
     const int Py = circle(round, y, np), Qy = circle(round, np - 1 - y, np);
     auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
     auto iy = [&](int a) -> int64_t { return a < JB ? (int64_t)Py * JB + a : (int64_t)Qy * JB + (a - JB); };
-    const double* vx = w.V + (int64_t)x * JS * JS;
-    const double* vy = w.V + (int64_t)y * JS * JS;
-    const int idx_ = w.ident[x], idy_ = w.ident[y];
-    for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
-      int a = e / JS, b = e % JS;
-      T[a][b] = w.Gp[ix(a) * w.K + iy(b)];
-      Va[a][b] = idx_ ? (a == b ? 1.0 : 0.0) : vx[e];
-      Vb[a][b] = idy_ ? (a == b ? 1.0 : 0.0) : vy[e];
+    if (!idy_) mm.load_b(w.V + (int64_t)y * JS * JS, opb);
+    if (!idx_) mm.load_at(w.V + (int64_t)x * JS * JS, opa);
+    for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
+      const int a = e >> 5, b = (e & 31) * 2;
+      const double2 g = *reinterpret_cast<const double2*>(w.Gp + ix(a) * w.K + iy(b));
+      T[a][b] = g.x;
+      T[a][b + 1] = g.y;
     }
     __syncthreads();
-    constexpr int RT = JS / 16;
-    double acc[RT][RT] = {};
-    for (int k = 0; k < JS; ++k) {  // U = T Vy
-      double t[RT], v[RT];
-#pragma unroll
-      for (int u = 0; u < RT; ++u) t[u] = T[ty + 16 * u][k];
-#pragma unroll
-      for (int c = 0; c < RT; ++c) v[c] = Vb[k][tx + 16 * c];
-#pragma unroll
-      for (int u = 0; u < RT; ++u)
-#pragma unroll
-        for (int c = 0; c < RT; ++c) acc[u][c] += t[u] * v[c];
+    if (!idy_) {  // T <- T V_y
+      mm.mul_lds_reg(T, opb, acc);
+      __syncthreads();
+      mm.store(acc, T);
+      __syncthreads();
     }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < RT; ++u)
-#pragma unroll
-      for (int c = 0; c < RT; ++c) T[ty + 16 * u][tx + 16 * c] = acc[u][c];
-    __syncthreads();
-    double o[RT][RT] = {};
-    for (int k = 0; k < JS; ++k) {  // Vx^T U
-      double a[RT], t[RT];
-#pragma unroll
-      for (int u = 0; u < RT; ++u) a[u] = Va[k][ty + 16 * u];
-#pragma unroll
-      for (int c = 0; c < RT; ++c) t[c] = T[k][tx + 16 * c];
-#pragma unroll
-      for (int u = 0; u < RT; ++u)
-#pragma unroll
-        for (int c = 0; c < RT; ++c) o[u][c] += a[u] * t[c];
+    if (!idx_) {  // T <- V_x^T T
+      mm.mul_reg_lds(opa, T, acc);
+      __syncthreads();
+      mm.store(acc, T);
+      __syncthreads();
     }
-#pragma unroll
-    for (int u = 0; u < RT; ++u)
-#pragma unroll
-      for (int c = 0; c < RT; ++c) {
-        int a = ty + 16 * u, b = tx + 16 * c;
-        w.Gp[ix(a) * w.K + iy(b)] = o[u][c];
+    for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
+      const int a = e >> 5, b = (e & 31) * 2;
+      double2 g;
+      // a diagonal tile is symmetrised from its upper half
+      g.x = (x == y && a > b) ? T[b][a] : T[a][b];
+      g.y = (x == y && a > b + 1) ? T[b + 1][a] : T[a][b + 1];
+      *reinterpret_cast<double2*>(w.Gp + ix(a) * w.K + iy(b)) = g;
+    }
+    if (x != y) {
+      for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
+        const int b = e >> 5, a = (e & 31) * 2;
+        *reinterpret_cast<double2*>(w.Gp + iy(b) * w.K + ix(a)) = double2{T[a][b], T[a + 1][b]};
       }
+    }
   } else {
-    const int zid = id - ntile;
+    const int zid = id - nsym;
     const int x = zid % w.p, rb = zid / w.p;
     if (w.ident[x]) return;
     const int Px = circle(round, x, np), Qx = circle(round, np - 1 - x, np);
     auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
-    const double* vx = w.V + (int64_t)x * JS * JS;
-    const int64_t r0 = (int64_t)rb * JS;
-    for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
-      int a = e / JS, b = e % JS;
-      T[a][b] = (r0 + a < w.K) ? w.Z[(r0 + a) * w.K + ix(b)] : 0.0;
-      Va[a][b] = vx[e];
+    const int64_t r0 = (int64_t)rb * JS;  // K is a multiple of JS: the strip is whole
+    mm.load_b(w.V + (int64_t)x * JS * JS, opb);
+    for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
+      const int a = e >> 5, b = (e & 31) * 2;
+      const double2 z = *reinterpret_cast<const double2*>(w.Z + (r0 + a) * w.K + ix(b));
+      T[a][b] = z.x;
+      T[a][b + 1] = z.y;
     }
     __syncthreads();
-    constexpr int RT = JS / 16;
-    double acc[RT][RT] = {};
-    for (int k = 0; k < JS; ++k) {
-      double t[RT], v[RT];
-#pragma unroll
-      for (int u = 0; u < RT; ++u) t[u] = T[ty + 16 * u][k];
-#pragma unroll
-      for (int c = 0; c < RT; ++c) v[c] = Va[k][tx + 16 * c];
-#pragma unroll
-      for (int u = 0; u < RT; ++u)
-#pragma unroll
-        for (int c = 0; c < RT; ++c) acc[u][c] += t[u] * v[c];
+    mm.mul_lds_reg(T, opb, acc);
+    __syncthreads();
+    mm.store(acc, T);
+    __syncthreads();
+    for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
+      const int a = e >> 5, b = (e & 31) * 2;
+      *reinterpret_cast<double2*>(w.Z + (r0 + a) * w.K + ix(b)) = double2{T[a][b], T[a][b + 1]};
     }
-#pragma unroll
-    for (int u = 0; u < RT; ++u)
-#pragma unroll
-      for (int c = 0; c < RT; ++c) {
-        int64_t r = r0 + ty + 16 * u;
-        if (r < w.K) w.Z[r * w.K + ix(tx + 16 * c)] = acc[u][c];
-      }
   }
 }
+
+// Work items of one apply launch: upper G tiles, then Z strips.
+__host__ __device__ inline int eig_apply_items(int p, int64_t K, int JS) { return p * (p + 1) / 2 + (int)(K / JS) * p; }
 
 RF_DEV void eig_check_body(const EigWork& w, int64_t idx) {
   if (*w.conv) return;
@@ -626,8 +696,7 @@ __global__ __launch_bounds__(1024) void k_eigb_solve(const EigBatch* __restrict_
 template <int JB>
 __global__ __launch_bounds__(256) void k_eigb_apply(const EigBatch* __restrict__ bs, int round) {
   const EigBatch b = bs[blockIdx.y];
-  const int ntile = b.w.p * b.w.p + (int)(b.w.K / (2 * JB)) * b.w.p;
-  if ((int)blockIdx.x >= ntile || round >= 2 * b.w.p - 1) return;
+  if ((int)blockIdx.x >= eig_apply_items(b.w.p, b.w.K, 2 * JB) || round >= 2 * b.w.p - 1) return;
   eig_apply_body<JB>(b.w, round, blockIdx.x);
 }
 __global__ void k_eigb_check(const EigBatch* __restrict__ bs) {
@@ -655,12 +724,12 @@ static void eig_rounds(EigWork w, int64_t N, hipStream_t st, double* trace) {
   constexpr int JS = 2 * JB;
   int64_t KK = w.K * w.K;
   size_t lds_solve = 2 * JS * (JS + 1) * sizeof(double);
-  size_t lds_apply = 3 * JS * (JS + 1) * sizeof(double);
+  size_t lds_apply = JS * (JS + 1) * sizeof(double);
   hipFuncSetAttribute((const void*)k_eig_solve<JB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_solve);
   hipFuncSetAttribute((const void*)k_eig_apply<JB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_apply);
   const int rounds = 2 * w.p - 1;
   const int max_sweeps = eig_max_sweeps();
-  const int ntile = w.p * w.p + (int)(w.K / JS) * w.p;
+  const int ntile = eig_apply_items(w.p, w.K, JS);
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int r = 0; r < rounds; ++r) {
       hipLaunchKernelGGL(k_eig_solve<JB>, dim3(w.p), dim3(1024), lds_solve, st, w, r, 1);
@@ -683,8 +752,7 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
   int64_t KK = w.K * w.K;
   hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, st, G, ld, N, w);
   hipLaunchKernelGGL(k_eig_floor, dim3(1), dim3(256), 0, st, G, ld, N, w);
-  if (JB == 16) eig_rounds<16>(w, N, st, trace);
-  else eig_rounds<32>(w, N, st, trace);
+  eig_rounds<32>(w, N, st, trace);
   hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, st, w, N, lam);
   hipLaunchKernelGGL(k_eig_gather, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, w, N, V, ldv);
   return hipGetLastError();
@@ -712,7 +780,7 @@ hipError_t launch_eig_batched(const EigBatch* descs, int count, int64_t Nmax, hi
   const int pmax = shape.p;
   if (Kmax > 4096) return hipErrorInvalidValue;
   const size_t lds_solve = 2 * JS * (JS + 1) * sizeof(double);
-  const size_t lds_apply = 3 * JS * (JS + 1) * sizeof(double);
+  const size_t lds_apply = JS * (JS + 1) * sizeof(double);
   (void)hipFuncSetAttribute((const void*)k_eigb_solve<JB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_solve);
   (void)hipFuncSetAttribute((const void*)k_eigb_apply<JB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_apply);
   const int64_t KK = Kmax * Kmax;
@@ -720,7 +788,7 @@ hipError_t launch_eig_batched(const EigBatch* descs, int count, int64_t Nmax, hi
   hipLaunchKernelGGL(k_eigb_init, dim3(gx, count), dim3(256), 0, st, descs);
   hipLaunchKernelGGL(k_eigb_floor, dim3(1, count), dim3(256), 0, st, descs);
   const int rounds = 2 * pmax - 1;
-  const int ntile = pmax * pmax + (int)(Kmax / JS) * pmax;
+  const int ntile = eig_apply_items(pmax, Kmax, JS);
   for (int sw = 0; sw < eig_max_sweeps(); ++sw) {
     for (int r = 0; r < rounds; ++r) {
       hipLaunchKernelGGL(k_eigb_solve<JB>, dim3(pmax, count), dim3(1024), lds_solve, st, descs, r);
