@@ -42,28 +42,68 @@ RF_DEV void wait_at_least(int* ctr, int target, int* err) {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
+// 256 threads; all 16 loads of a thread are issued before the LDS stores.
 RF_DEV void load_tile(double (*T)[TLD], const double* P, int64_t ld, int64_t r0, int64_t c0, int64_t N) {
-  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
-    const int r = e / TB, c = e % TB;
-    T[r][c] = (r0 + r < N && c0 + c < N) ? P[(r0 + r) * ld + c0 + c] : 0.0;
+  constexpr int NT = 256, IT = TB * TB / NT;
+  const int c = threadIdx.x % TB, rr = threadIdx.x / TB;
+  double v[IT];
+#pragma unroll
+  for (int it = 0; it < IT; ++it) {
+    const int r = rr + it * (NT / TB);
+    v[it] = (r0 + r < N && c0 + c < N) ? P[(r0 + r) * ld + c0 + c] : 0.0;
+  }
+#pragma unroll
+  for (int it = 0; it < IT; ++it) T[rr + it * (NT / TB)][c] = v[it];
+}
+
+// acc (+)= op(P) Q over a 64-deep product of 64 x 64 LDS tiles (op(P) = P^T when
+// P_TRANS) on v_mfma_f64_16x16x4f64.  Wave w owns the 32 x 32 quadrant
+// (w / 2, w % 2) as 2 x 2 blocks of 16 x 16; register r of lane l of block (i, j)
+// holds row tile_row(i, r), column tile_col(j).
+RF_DEV int tile_row(int i, int r) {
+  return ((threadIdx.x >> 6) >> 1) * 32 + i * 16 + ((threadIdx.x & 63) >> 4) + 4 * r;
+}
+RF_DEV int tile_col(int j) { return ((threadIdx.x >> 6) & 1) * 32 + j * 16 + (threadIdx.x & 15); }
+
+template <bool P_TRANS>
+RF_DEV void tile_mac(f64x4 (&acc)[2][2], double (*P)[TLD], double (*Q)[TLD]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1;
+#pragma unroll 4
+  for (int kk = 0; kk < TB / 4; ++kk) {
+    const int kr = 4 * kk + (lane >> 4);
+    double af[2], bf[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int row = wm * 32 + i * 16 + (lane & 15);
+      af[i] = P_TRANS ? P[kr][row] : P[row][kr];
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j) bf[j] = Q[kr][wn * 32 + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[i], bf[j], acc[i][j], 0, 0, 0);
   }
 }
 
-// out[r][c] (+)= sum_l op(P)[r][l] Q[l][c] over a 64-deep tile product; P_TRANS: op(P) = P^T.
-template <bool P_TRANS>
-RF_DEV void tile_mac(double (&acc)[4][4], double (*P)[TLD], double (*Q)[TLD]) {
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  for (int l = 0; l < TB; ++l) {
-    double a[4], b[4];
+RF_DEV void acc_zero(f64x4 (&acc)[2][2]) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) a[u] = P_TRANS ? P[l][ty + 16 * u] : P[ty + 16 * u][l];
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) b[v] = Q[l][tx + 16 * v];
-#pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) acc[u][v] += a[u] * b[v];
-  }
+    for (int j = 0; j < 2; ++j) acc[i][j] = f64x4{0, 0, 0, 0};
+}
+
+// 1/sqrt(d) for d > 0 to FP64 accuracy: FP32 estimate of the scaled argument, two
+// Newton steps r <- r (3 - m r^2) / 2 (each squares the relative error).
+RF_DEV double rsqrt_f64(double d) {
+  int e;
+  (void)frexp(d, &e);
+  const int e2 = e & ~1;                  // even exponent: d = m 2^e2, m in [1/4, 1)
+  const double m = ldexp(d, -e2);
+  double r = (double)__builtin_amdgcn_rsqf((float)m);
+  r = r * fma(-0.5 * m, r * r, 1.5);
+  r = r * fma(-0.5 * m, r * r, 1.5);
+  return ldexp(r, -e2 / 2);
 }
 
 RF_DEV void put_x(const CholInvArgs& a, int64_t r, int64_t c, double v) {
@@ -72,20 +112,54 @@ RF_DEV void put_x(const CholInvArgs& a, int64_t r, int64_t c, double v) {
   if (a.X32) a.X32[r * a.ldx32 + c] = (float)v;
 }
 
-// A(kb): R_kk and X_kk in LDS, written to G and X.
+// Element (a, b) of a thread's 4 x 4 register block with a runtime row a.
+// (value selects, so that the block stays in registers)
+RF_DEV double pick_row(const double (&m)[4][4], int a, int b) {
+  const double v0 = m[0][b], v1 = m[1][b], v2 = m[2][b], v3 = m[3][b];
+  double r = v0;
+  r = (a == 1) ? v1 : r;
+  r = (a == 2) ? v2 : r;
+  r = (a == 3) ? v3 : r;
+  return r;
+}
+
+// A(kb): R_kk and X_kk = R_kk^{-1}, written to G and X.  The tile lives in
+// registers: thread (ty, tx) of 16 x 16 holds entries (ty + 16a, tx + 16b).
+// Cholesky, right-looking, one barrier per column: the threads holding row c + 1
+// publish it (double-buffered) right after their step-c update, and at step c + 1
+// every thread forms R_c+1,. = G_c+1,. / sqrt(g) from it and updates its entries.
+// Inverse by backward elimination on T = I (X_c. = T_c. / R_cc, then
+// T_i. -= R_ic X_c. for i < c), again publishing the next row as soon as it is final.
 RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R)[TLD], double (*Xs)[TLD]) {
   const int64_t b0 = (int64_t)kb * TB;
   const int nbk = (int)min((int64_t)TB, a.N - b0);
-  load_tile(M, a.G, a.ld, b0, b0, a.N);
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  double* rowb = &M[0][0];  // M's LDS is scratch here: 2 row buffers, 1 / R_cc, pivot floors
+  double* rsv = rowb + 2 * TB;
+  double* floor_ = rsv + TB;
+  if (threadIdx.x < nbk) floor_[threadIdx.x] = a.tol * a.d0[b0 + threadIdx.x];
+  double m[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ty + 16 * p, j = tx + 16 * q;
+      m[p][q] = (i < nbk && j < nbk) ? a.G[(b0 + i) * a.ld + b0 + j] : 0.0;
+    }
   for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
     R[e / TB][e % TB] = 0.0;
     Xs[e / TB][e % TB] = 0.0;
   }
+  if (ty == 0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rowb[tx + 16 * q] = m[0][q];
+  }
   __syncthreads();
   for (int c = 0; c < nbk; ++c) {
-    const double d = M[c][c];
+    const double* row = rowb + (c & 1) * TB;
+    const double d = row[c];
     const bool fin = isfinite(d);
-    const bool bad = !(fin && d > a.tol * a.d0[b0 + c] && d > 0.0);
+    const bool bad = !(fin && d > floor_[c] && d > 0.0);
     if (threadIdx.x == 0) {
       if (!fin) *a.nonfinite = 1;
       if (bad) {
@@ -93,39 +167,87 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
         atomicAdd(a.count, 1);
       }
     }
-    const double rs = bad ? 0.0 : 1.0 / sqrt(d);
-    for (int j = c + 1 + threadIdx.x; j < nbk; j += blockDim.x) R[c][j] = M[c][j] * rs;
-    if (threadIdx.x == 0) R[c][c] = bad ? 1.0 : sqrt(d);
-    if (!bad) {
-      const double id = 1.0 / d;
-      const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-      for (int i = c + 1 + ty; i < nbk; i += 16) {
-        const double mi = M[c][i] * id;
-        for (int j = c + 1 + tx; j < nbk; j += 16)
-          if (j >= i) M[i][j] -= mi * M[c][j];
+    const double rs = bad ? 0.0 : rsqrt_f64(d);
+    double ri[4], rj[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const int i = ty + 16 * p;
+      ri[p] = (i > c && i < nbk) ? row[i] * rs : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = tx + 16 * q;
+      rj[q] = (j > c && j < nbk) ? row[j] * rs : 0.0;
+    }
+    if (ty == (c & 15)) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        if (tx + 16 * q > c) R[c][tx + 16 * q] = rj[q];
+      if (tx == (c & 15)) {
+        R[c][c] = bad ? 1.0 : d * rs;
+        rsv[c] = bad ? 1.0 : rs;
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) m[p][q] = fma(-ri[p], rj[q], m[p][q]);
+    const int c1 = c + 1;
+    if (c1 < nbk && ty == (c1 & 15)) {
+      double* nrow = rowb + (c1 & 1) * TB;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) nrow[tx + 16 * q] = pick_row(m, c1 >> 4, q);
+    }
+    __syncthreads();
+  }
+  double* xrb = rowb;  // the row buffers are free again
+  double tt[4][4];
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) tt[p][q] = (ty + 16 * p == tx + 16 * q && ty + 16 * p < nbk) ? 1.0 : 0.0;
+  if (nbk > 0 && ty == ((nbk - 1) & 15)) {
+    const double inv = rsv[nbk - 1];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = tx + 16 * q;
+      xrb[((nbk - 1) & 1) * TB + j] = (j == nbk - 1) ? inv : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int c = nbk - 1; c >= 0; --c) {
+    const double* xr = xrb + (c & 1) * TB;
+    double rc[4], xj[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) rc[p] = (ty + 16 * p < c) ? R[ty + 16 * p][c] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) xj[q] = xr[tx + 16 * q];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) {
+      const bool own = (ty + 16 * p == c);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) tt[p][q] = own ? xj[q] : fma(-rc[p], xj[q], tt[p][q]);
+    }
+    const int c1 = c - 1;
+    if (c1 >= 0 && ty == (c1 & 15)) {
+      const double inv = rsv[c1];
+      double* nx = xrb + (c1 & 1) * TB;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = tx + 16 * q;
+        nx[j] = (j >= c1 && j < nbk) ? pick_row(tt, c1 >> 4, q) * inv : 0.0;
       }
     }
     __syncthreads();
   }
-  // X = R^{-1}, rows bottom-up: X_cc = 1/R_cc, X_cj = -X_cc sum_{l=c+1..j} R_cl X_lj.
-  // Column j of row c is summed by 4 threads (l interleaved), combined through LDS.
-  double* part = &M[0][0];  // M is free now: 4 x 64 partial sums
-  for (int c = nbk - 1; c >= 0; --c) {
-    const int j = c + 1 + (threadIdx.x >> 2), q = threadIdx.x & 3;
-    if (j < nbk) {
-      double s = 0.0;
-      for (int l = c + 1 + q; l <= j; l += 4) s += R[c][l] * Xs[l][j];
-      part[q * TB + j] = s;
+#pragma unroll
+  for (int p = 0; p < 4; ++p)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int i = ty + 16 * p, j = tx + 16 * q;
+      if (j >= i) Xs[i][j] = tt[p][q];
     }
-    __syncthreads();
-    const double inv = 1.0 / R[c][c];
-    if (threadIdx.x < TB) {
-      const int jj = threadIdx.x;
-      if (jj > c && jj < nbk) Xs[c][jj] = -(part[jj] + part[TB + jj] + part[2 * TB + jj] + part[3 * TB + jj]) * inv;
-      if (jj == c) Xs[c][c] = inv;
-    }
-    __syncthreads();
-  }
+  __syncthreads();
   for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
     const int r = e / TB, c = e % TB;
     if (r < nbk && c < nbk) {
@@ -141,22 +263,25 @@ RF_DEV void task_panel(const CholInvArgs& a, int kb, int jb, double (*P)[TLD], d
   load_tile(P, a.X64, a.ldx64, b0, b0, a.N);
   load_tile(Q, a.G, a.ld, b0, c0, a.N);
   __syncthreads();
-  double acc[4][4] = {};
+  f64x4 acc[2][2];
+  acc_zero(acc);
   tile_mac<true>(acc, P, Q);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = b0 + ty + 16 * u, c = c0 + tx + 16 * v;
-      if (r < a.N && c < a.N) a.G[r * a.ld + c] = a.flags[r] ? 0.0 : acc[u][v];
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = b0 + tile_row(i, q), c = c0 + tile_col(j);
+        if (r < a.N && c < a.N) a.G[r * a.ld + c] = a.flags[r] ? 0.0 : acc[i][j][q];
+      }
 }
 
 // X(kb, i): X_i,kb = -(sum_l X_il R_l,kb) X_kk ; the mirrored lower tile is cleared.
 RF_DEV void task_xcol(const CholInvArgs& a, int kb, int ib, double (*P)[TLD], double (*Q)[TLD]) {
   const int64_t b0 = (int64_t)kb * TB, i0 = (int64_t)ib * TB;
-  double acc[4][4] = {};
+  f64x4 acc[2][2];
+  acc_zero(acc);
   for (int lb = ib; lb < kb; ++lb) {
     const int64_t l0 = (int64_t)lb * TB;
     __syncthreads();
@@ -166,22 +291,27 @@ RF_DEV void task_xcol(const CholInvArgs& a, int kb, int ib, double (*P)[TLD], do
     tile_mac<false>(acc, P, Q);
   }
   __syncthreads();
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) P[ty + 16 * u][tx + 16 * v] = acc[u][v];
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) P[tile_row(i, q)][tile_col(j)] = acc[i][j][q];
   load_tile(Q, a.X64, a.ldx64, b0, b0, a.N);
   __syncthreads();
-  double o[4][4] = {};
+  f64x4 o[2][2];
+  acc_zero(o);
   tile_mac<false>(o, P, Q);
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      put_x(a, i0 + ty + 16 * u, b0 + tx + 16 * v, -o[u][v]);
-      put_x(a, b0 + tx + 16 * v, i0 + ty + 16 * u, 0.0);
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = tile_row(i, q), c = tile_col(j);
+        put_x(a, i0 + r, b0 + c, -o[i][j][q]);
+        put_x(a, b0 + c, i0 + r, 0.0);
+      }
 }
 
 // C(kb, i, j): G_ij -= R_kb,i^T R_kb,j (upper tiles).
@@ -190,16 +320,18 @@ RF_DEV void task_update(const CholInvArgs& a, int kb, int ib, int jb, double (*P
   load_tile(P, a.G, a.ld, b0, r0, a.N);
   load_tile(Q, a.G, a.ld, b0, c0, a.N);
   __syncthreads();
-  double acc[4][4] = {};
+  f64x4 acc[2][2];
+  acc_zero(acc);
   tile_mac<true>(acc, P, Q);
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
 #pragma unroll
-  for (int u = 0; u < 4; ++u)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = r0 + ty + 16 * u, c = c0 + tx + 16 * v;
-      if (r < a.N && c < a.N && c >= r) a.G[r * a.ld + c] -= acc[u][v];
-    }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = r0 + tile_row(i, q), c = c0 + tile_col(j);
+        if (r < a.N && c < a.N && c >= r) a.G[r * a.ld + c] -= acc[i][j][q];
+      }
 }
 
 __global__ __launch_bounds__(256) void k_cholinv(CholInvArgs a) {
