@@ -401,6 +401,8 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
 // into LDS.
 typedef __bf16 bf16x4v __attribute__((__vector_size__(4 * sizeof(__bf16))));
 constexpr int HB = 256, HBK = 32;
+constexpr int BT = 512;        // threads of a 256 x 256 workgroup: 8 waves, two per SIMD
+constexpr int NCH = HB * HBK / 8 / BT;  // 8-element chunks per thread and operand per stage
 constexpr int TRL = HB + 32;   // m/n-contiguous LDS row, bf16 elements
 constexpr int KRL = HBK + 8;   // k-contiguous LDS row, bf16 elements
 
@@ -429,22 +431,22 @@ RF_DEV uint4 pack8_bf16(float4 a, float4 b) {
                     (uint32_t)f32_to_bf16_rne(b.z) | ((uint32_t)f32_to_bf16_rne(b.w) << 16));
 }
 
-// One operand's share of a stage: 4 chunks of 8 consecutive elements per thread.
+// One operand's share of a stage: NCH chunks of 8 consecutive elements per thread.
 // KC: chunk c -> row c/4 of the tile, k offset 8 (c%4); else k row c/32, column 8 (c%32).
 template <bool KC, int MODE>  // MODE 0: BF16, 1: FP32, 2: FP8 e4m3 x block scale (m/n-contiguous only)
 struct BigStage {
   static constexpr bool F32 = (MODE == 1);
   static constexpr bool F8 = (MODE == 2);
   static_assert(!(F8 && KC), "FP8 operands are read m/n-contiguous");
-  uint4 v[4];
-  float4 f[4][2];
-  uint2 b8[4];
-  float sc[4];
+  uint4 v[NCH];
+  float4 f[NCH][2];
+  uint2 b8[NCH];
+  float sc[NCH];
   RF_DEV void load(const void* P_, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, int64_t kend, bool vec,
                    int tid, const float* scales = nullptr, int64_t ldsc = 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = tid + 256 * q;
+    for (int q = 0; q < NCH; ++q) {
+      const int c = tid + BT * q;
       const int64_t r = KC ? r0 + (c >> 2) : r0 + 8 * (c & 31);       // first m/n index of the chunk
       const int64_t k = KC ? k0 + 8 * (c & 3) : k0 + (c >> 5);        // first k index of the chunk
       const bool full = KC ? (r < rmax && k + 8 <= kend) : (k < kend && r + 8 <= rmax);
@@ -497,8 +499,8 @@ struct BigStage {
   }
   RF_DEV void store(uint16_t* S, int tid) const {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = tid + 256 * q;
+    for (int q = 0; q < NCH; ++q) {
+      const int c = tid + BT * q;
       uint16_t* dst = KC ? S + (c >> 2) * KRL + 8 * (c & 3) : S + (c >> 5) * TRL + 8 * (c & 31);
       uint4 x;
       if constexpr (F8) {
@@ -528,7 +530,7 @@ RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
   tile_coords(bid, ntm, ntn, tm, tn);
   const int64_t i0 = (int64_t)tm * HB, j0 = (int64_t)tn * HB;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = wave >> 1, wn = wave & 1;
+  const int wm = wave >> 2, wn = wave & 3;  // wave tile: rows wm*128 + [0, 128), columns wn*64 + [0, 64)
   int64_t kbeg = (int64_t)split * g.kps;
   int64_t kend = min(g.K, kbeg + g.kps);
   if (g.b_upper) kend = min(kend, j0 + HB);
@@ -538,11 +540,11 @@ RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
   const bool avec = ((((uintptr_t)g.A) & (aal - 1)) == 0) && ((g.lda * aes) % aal == 0);
   const bool bvec = ((((uintptr_t)g.B) & 15) == 0) && ((g.ldb * 2) % 16 == 0);
 
-  f32x16 acc[4][4];
+  f32x16 acc[4][2];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
@@ -567,19 +569,19 @@ RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
     const uint16_t* B_ = B0 + buf * BS;
 #pragma unroll
     for (int kk = 0; kk < HBK / 16; ++kk) {
-      bf16x8 af[4], bfr[4];
+      bf16x8 af[4], bfr[2];
 #pragma unroll
       for (int a = 0; a < 4; ++a)
         af[a] = AKC ? big_frag_kc(A_, wm * 128 + 32 * a + (lane & 31), 16 * kk + 8 * (lane >> 5))
                     : big_frag_tc(A_, wm * 128 + 32 * a, 16 * kk, lane);
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
-        bfr[b] = BKC ? big_frag_kc(B_, wn * 128 + 32 * b + (lane & 31), 16 * kk + 8 * (lane >> 5))
-                     : big_frag_tc(B_, wn * 128 + 32 * b, 16 * kk, lane);
+      for (int b = 0; b < 2; ++b)
+        bfr[b] = BKC ? big_frag_kc(B_, wn * 64 + 32 * b + (lane & 31), 16 * kk + 8 * (lane >> 5))
+                     : big_frag_tc(B_, wn * 64 + 32 * b, 16 * kk, lane);
 #pragma unroll
       for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[a], bfr[b], acc[a][b], 0, 0, 0);
     }
     if (kt + 1 < nk) {
       sa.store(A0 + (buf ^ 1) * AS, tid);
@@ -596,12 +598,12 @@ RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
 #pragma unroll
   for (int a = 0; a < 4; ++a) {
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r)
-        St[(wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * SLD + wn * 128 + 32 * b + (lane & 31)] = acc[a][b][r];
+        St[(wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * SLD + wn * 64 + 32 * b + (lane & 31)] = acc[a][b][r];
     __syncthreads();
-    for (int e = tid; e < 64 * HB; e += 256) {
+    for (int e = tid; e < 64 * HB; e += BT) {
       const int rr = g.c_trans ? (e & 63) : (e / HB), cc = g.c_trans ? (e >> 6) : (e % HB);
       const int64_t i = i0 + (rr >> 5) * 128 + 32 * a + (rr & 31), j = j0 + cc;
       const float v = St[rr * SLD + cc];
@@ -624,7 +626,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   gemm_bf16_body<AKC, BKC>(g, blockIdx.x, blockIdx.y);
 }
 template <bool AKC, bool BKC, int AMODE>
-__global__ __launch_bounds__(256, 1) void k_gemm_bf16_big(GemmArgs g) {
+__global__ __launch_bounds__(BT, 1) void k_gemm_bf16_big(GemmArgs g) {
   gemm_bf16_big_body<AKC, BKC, AMODE>(g, blockIdx.x, blockIdx.y);
 }
 
@@ -665,7 +667,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16a32_grouped(const GemmArgs* __
   gemm_bf16_body<AKC, BKC, true>(g, blockIdx.x - tile_start[i], 0);
 }
 template <bool AKC, bool BKC, int AMODE>
-__global__ __launch_bounds__(256, 1) void k_gemm_bf16_big_grouped(const GemmArgs* __restrict__ gs,
+__global__ __launch_bounds__(BT, 1) void k_gemm_bf16_big_grouped(const GemmArgs* __restrict__ gs,
                                                                   const int* tile_start, int count) {
   const int i = find_group(tile_start, count, blockIdx.x);
   const GemmArgs g = gs[i];
@@ -763,7 +765,7 @@ static void go_big(const GemmArgs& g, dim3 grid, hipStream_t st) {
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     attr = true;
   }
-  hipLaunchKernelGGL((k_gemm_bf16_big<AKC, BKC, AF32>), grid, dim3(256), lds, st, g);
+  hipLaunchKernelGGL((k_gemm_bf16_big<AKC, BKC, AF32>), grid, dim3(BT), lds, st, g);
 }
 
 hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
@@ -835,7 +837,7 @@ static void go_big_grouped(const GemmArgs* gs, const int* ts, int count, int til
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     attr = true;
   }
-  hipLaunchKernelGGL((k_gemm_bf16_big_grouped<AKC, BKC, AF32>), dim3((unsigned)tiles), dim3(256), lds, st, gs, ts,
+  hipLaunchKernelGGL((k_gemm_bf16_big_grouped<AKC, BKC, AF32>), dim3((unsigned)tiles), dim3(BT), lds, st, gs, ts,
                      count);
 }
 

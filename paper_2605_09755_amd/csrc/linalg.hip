@@ -11,9 +11,6 @@
 namespace rf {
 
 // ============================== Gram: C = X^T Y (FP64) ==============================
-template <typename T>
-RF_DEV double ldd(const T* p) { return (double)*p; }
-
 constexpr int GT = 64;  // output tile
 constexpr int GK = 16;  // k rows per step
 
@@ -25,12 +22,53 @@ RF_DEV void upper_tile(int id, int nt, int& tm, int& tn) {
   tn = r + rem;
 }
 
+// One k-step of a Gram operand: GKS rows of a 64-column panel, EPT consecutive
+// elements per thread (256 threads), held in registers until stored to LDS.
+template <typename T, int GKS>
+struct GramStage {
+  static constexpr int EPT = GKS * GT / 256;
+  T v[EPT];
+  RF_DEV void load(const T* __restrict__ P, int64_t ld, int64_t k0, int64_t kend, int64_t c0, int64_t cmax) {
+    const int r = threadIdx.x / (GT / EPT), c = (threadIdx.x % (GT / EPT)) * EPT;
+    const int64_t k = k0 + r, i = c0 + c;
+    const T* src = P + k * ld + i;
+    if (k < kend && i + EPT <= cmax && (((uintptr_t)src) & 15) == 0) {
+      if constexpr (sizeof(T) == 4) {
+#pragma unroll
+        for (int e = 0; e < EPT; e += 4) {
+          const float4 x = *reinterpret_cast<const float4*>(src + e);
+          v[e] = x.x; v[e + 1] = x.y; v[e + 2] = x.z; v[e + 3] = x.w;
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < EPT; e += 2) {
+          const double2 x = *reinterpret_cast<const double2*>(src + e);
+          v[e] = x.x; v[e + 1] = x.y;
+        }
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < EPT; ++e) v[e] = (k < kend && i + e < cmax) ? src[e] : T(0);
+    }
+  }
+  RF_DEV void store(T (*S)[GT]) const {
+    const int r = threadIdx.x / (GT / EPT), c = (threadIdx.x % (GT / EPT)) * EPT;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) S[r][c + e] = v[e];
+  }
+};
+
+// C tile (64 x 64) = X[:, i0..]^T Y[:, j0..] over rows [split*kps, +kps) on
+// v_mfma_f64_16x16x4f64 (operands widened to FP64 as they leave LDS).  Operand
+// panels are staged in LDS in their own type, double-buffered with a register
+// prefetch of the next k-step, one barrier per step.
 template <typename TX, typename TY>
 RF_DEV void gram_body(const TX* __restrict__ X, int64_t ldx, const TY* __restrict__ Y, int64_t ldy, int64_t K,
                       int64_t M, int64_t N, int sym, double* __restrict__ C, int64_t ldc,
                       double* __restrict__ partial, int64_t kps, int bid, int split) {
-  __shared__ double Xs[GK][GT];
-  __shared__ double Ys[GK][GT];
+  constexpr int GKS = (sizeof(TX) == 4 && sizeof(TY) == 4) ? 32 : 16;  // k rows per step: 32 KB of LDS
+  __shared__ TX Xs[2][GKS][GT];
+  __shared__ TY Ys[2][GKS][GT];
   const int ntm = (int)((M + GT - 1) / GT), ntn = (int)((N + GT - 1) / GT);
   int tm, tn;
   if (sym) upper_tile(bid, ntm, tm, tn);
@@ -43,30 +81,39 @@ RF_DEV void gram_body(const TX* __restrict__ X, int64_t ldx, const TY* __restric
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0, 0, 0, 0};
-  for (int64_t k0 = kbeg; k0 < kend; k0 += GK) {
-    {
-      int r = tid >> 4, c = (tid & 15) * 4;
-      int64_t k = k0 + r;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        int64_t i = i0 + c + e, j = j0 + c + e;
-        Xs[r][c + e] = (k < kend && i < M) ? ldd(X + k * ldx + i) : 0.0;
-        Ys[r][c + e] = (k < kend && j < N) ? ldd(Y + k * ldy + j) : 0.0;
-      }
-    }
+  GramStage<TX, GKS> sx;
+  GramStage<TY, GKS> sy;
+  const int nst = kend > kbeg ? (int)((kend - kbeg + GKS - 1) / GKS) : 0;
+  if (nst > 0) {
+    sx.load(X, ldx, kbeg, kend, i0, M);
+    sy.load(Y, ldy, kbeg, kend, j0, N);
+    sx.store(Xs[0]);
+    sy.store(Ys[0]);
     __syncthreads();
+  }
+  for (int st = 0; st < nst; ++st) {
+    const int buf = st & 1;
+    if (st + 1 < nst) {
+      const int64_t k1 = kbeg + (int64_t)(st + 1) * GKS;
+      sx.load(X, ldx, k1, kend, i0, M);
+      sy.load(Y, ldy, k1, kend, j0, N);
+    }
 #pragma unroll
-    for (int kk = 0; kk < GK / 4; ++kk) {
-      int kr = 4 * kk + (lane >> 4);
+    for (int kk = 0; kk < GKS / 4; ++kk) {
+      const int kr = 4 * kk + (lane >> 4);
       double af[2], bf[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) af[a] = Xs[kr][wm * 32 + a * 16 + (lane & 15)];
+      for (int a = 0; a < 2; ++a) af[a] = (double)Xs[buf][kr][wm * 32 + a * 16 + (lane & 15)];
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bf[b] = Ys[kr][wn * 32 + b * 16 + (lane & 15)];
+      for (int b = 0; b < 2; ++b) bf[b] = (double)Ys[buf][kr][wn * 32 + b * 16 + (lane & 15)];
 #pragma unroll
       for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[a], bf[b], acc[a][b], 0, 0, 0);
+    }
+    if (st + 1 < nst) {
+      sx.store(Xs[buf ^ 1]);
+      sy.store(Ys[buf ^ 1]);
     }
     __syncthreads();
   }
@@ -262,16 +309,18 @@ RF_DEV void eig_init_body(const double* __restrict__ G, int64_t ld, int64_t N, c
 }
 
 RF_DEV void eig_floor_body(const double* __restrict__ G, int64_t ld, int64_t N, const EigWork& w) {
-  // ||G||_F (single workgroup) -> rotation floor and absolute convergence floor
-  __shared__ double red[256];
+  // ||G||_F (single workgroup, fixed summation order) -> rotation floor and
+  // absolute convergence floor
+  __shared__ double red[1024];
+  const int nt = blockDim.x, tc = threadIdx.x % 64, tr = threadIdx.x / 64, rstep = nt / 64;
   double s = 0.0;
-  for (int64_t e = threadIdx.x; e < N * N; e += blockDim.x) {
-    double g = G[(e / N) * ld + e % N];
-    s += g * g;
+  for (int64_t r = tr; r < N; r += rstep) {
+    const double* row = G + r * ld;
+    for (int64_t c = tc; c < N; c += 64) s = fma(row[c], row[c], s);
   }
   red[threadIdx.x] = s;
   __syncthreads();
-  for (int o = 128; o > 0; o >>= 1) {
+  for (int o = nt / 2; o > 0; o >>= 1) {
     if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
     __syncthreads();
   }
@@ -587,21 +636,43 @@ RF_DEV void eig_apply_body(const EigWork& w, int round, int id) {
 // Work items of one apply launch: upper G tiles, then Z strips.
 __host__ __device__ inline int eig_apply_items(int p, int64_t K, int JS) { return p * (p + 1) / 2 + (int)(K / JS) * p; }
 
-RF_DEV void eig_check_body(const EigWork& w, int64_t idx) {
+// Converged when every |g_ij| <= max(tol sqrt|g_ii g_jj|, 16 eps ||G||_F), i.e. the
+// largest r_ij = |g_ij| / max(...) is <= 1.  The check keeps the maximum of r_ij^2
+// (no square roots per entry; the bits of non-negative doubles order like the
+// values) and the decision takes one square root.
+constexpr int kCheckPerThread = 8;  // entries per thread in the convergence check (256-thread blocks)
+
+RF_DEV void eig_check_body(const EigWork& w, int block) {
   if (*w.conv) return;
-  double r = 0.0;
-  if (idx < w.K * w.K) {
-    int64_t i = idx / w.K, j = idx % w.K;
-    if (i != j) {
-      // converged when |g_ij| <= max(tol sqrt|g_ii g_jj|, 16 eps ||G||_F): r <= 1
-      double g = w.Gp[idx];
-      double d = sqrt(fabs(w.Gp[i * w.K + i])) * sqrt(fabs(w.Gp[j * w.K + j]));
-      r = fabs(g) / fmax(w.tol * d, *w.fabs_);
-      if (!(r == r)) r = 2.0;  // NaN: keep iterating (and never claim convergence)
+  __shared__ double red[4];
+  double r2 = 0.0;
+  const int K = (int)w.K;  // K <= 4096
+  const double fl = *w.fabs_, tol2 = w.tol * w.tol;
+#pragma unroll
+  for (int e = 0; e < kCheckPerThread; ++e) {
+    const int64_t idx = ((int64_t)block * kCheckPerThread + e) * 256 + threadIdx.x;
+    if (idx < (int64_t)K * K) {
+      const int i = (int)(idx / K), j = (int)(idx - (int64_t)i * K);
+      if (i != j) {
+        const double g = w.Gp[idx];
+        const double den = fmax(tol2 * fabs(w.Gp[(int64_t)i * K + i] * w.Gp[(int64_t)j * K + j]), fl * fl);
+        double q = (g * g) / den;
+        if (!(q == q)) q = 4.0;  // NaN: keep iterating (and never claim convergence)
+        r2 = fmax(r2, q);
+      }
     }
   }
-  r = wave_max(r);
-  if ((threadIdx.x & 63) == 0 && r > 0.0) atomicMax(w.maxoff, (unsigned long long)__double_as_longlong(r));
+  r2 = wave_max(r2);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = r2;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    if (m > 0.0) atomicMax(w.maxoff, (unsigned long long)__double_as_longlong(m));
+  }
+}
+
+__host__ __device__ inline unsigned eig_check_blocks(int64_t K) {
+  return (unsigned)((K * K + 256 * kCheckPerThread - 1) / (256 * kCheckPerThread));
 }
 
 RF_DEV void eig_decide_body(const EigWork& w, double tol, double* trace, int sw) {
@@ -609,7 +680,7 @@ RF_DEV void eig_decide_body(const EigWork& w, double tol, double* trace, int sw)
     if (trace) trace[sw] = 0.0;
     return;
   }
-  double m = __longlong_as_double((long long)*w.maxoff);
+  const double m = sqrt(__longlong_as_double((long long)*w.maxoff));
   if (trace) trace[sw] = m;
   if (m <= tol) *w.conv = 1;
   *w.maxoff = 0ull;
@@ -658,7 +729,7 @@ RF_DEV void eig_gather_body(const EigWork& w, int64_t N, double* V, int64_t ldv,
 __global__ void k_eig_init(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
   eig_init_body(G, ld, N, w, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
-__global__ void k_eig_floor(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
+__global__ __launch_bounds__(1024) void k_eig_floor(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
   eig_floor_body(G, ld, N, w);
 }
 template <int JB>
@@ -669,7 +740,7 @@ template <int JB>
 __global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
   eig_apply_body<JB>(w, round, blockIdx.x);
 }
-__global__ void k_eig_check(EigWork w) { eig_check_body(w, (int64_t)blockIdx.x * blockDim.x + threadIdx.x); }
+__global__ __launch_bounds__(256) void k_eig_check(EigWork w) { eig_check_body(w, blockIdx.x); }
 __global__ void k_eig_decide(EigWork w, double tol, double* trace, int sw) { eig_decide_body(w, tol, trace, sw); }
 __global__ __launch_bounds__(1024) void k_eig_sort(EigWork w, int64_t N, double* lam) { eig_sort_body(w, N, lam); }
 __global__ void k_eig_gather(EigWork w, int64_t N, double* V, int64_t ldv) {
@@ -683,7 +754,7 @@ __global__ void k_eigb_init(const EigBatch* __restrict__ bs) {
        idx += (int64_t)gridDim.x * blockDim.x)
     eig_init_body(b.G, b.ld, b.N, b.w, idx);
 }
-__global__ void k_eigb_floor(const EigBatch* __restrict__ bs) {
+__global__ __launch_bounds__(1024) void k_eigb_floor(const EigBatch* __restrict__ bs) {
   const EigBatch b = bs[blockIdx.y];
   eig_floor_body(b.G, b.ld, b.N, b.w);
 }
@@ -699,11 +770,10 @@ __global__ __launch_bounds__(256) void k_eigb_apply(const EigBatch* __restrict__
   if ((int)blockIdx.x >= eig_apply_items(b.w.p, b.w.K, 2 * JB) || round >= 2 * b.w.p - 1) return;
   eig_apply_body<JB>(b.w, round, blockIdx.x);
 }
-__global__ void k_eigb_check(const EigBatch* __restrict__ bs) {
+__global__ __launch_bounds__(256) void k_eigb_check(const EigBatch* __restrict__ bs) {
   const EigBatch b = bs[blockIdx.y];
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  // every block of the grid row must reach the reduction: no early return
-  eig_check_body(b.w, idx < b.w.K * b.w.K ? idx : b.w.K * b.w.K);
+  if (blockIdx.x >= eig_check_blocks(b.w.K)) return;  // uniform per block
+  eig_check_body(b.w, blockIdx.x);
 }
 __global__ void k_eigb_decide(const EigBatch* __restrict__ bs, double tol) {
   const EigBatch b = bs[blockIdx.y];
@@ -735,7 +805,7 @@ static void eig_rounds(EigWork w, int64_t N, hipStream_t st, double* trace) {
       hipLaunchKernelGGL(k_eig_solve<JB>, dim3(w.p), dim3(1024), lds_solve, st, w, r, 1);
       hipLaunchKernelGGL(k_eig_apply<JB>, dim3(ntile), dim3(256), lds_apply, st, w, r);
     }
-    hipLaunchKernelGGL(k_eig_check, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, st, w);
+    hipLaunchKernelGGL(k_eig_check, dim3(eig_check_blocks(w.K)), dim3(256), 0, st, w);
     hipLaunchKernelGGL(k_eig_decide, dim3(1), dim3(1), 0, st, w, 1.0, trace, sw);
   }
 }
@@ -751,7 +821,7 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
   if (w.K > 4096) return hipErrorInvalidValue;
   int64_t KK = w.K * w.K;
   hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, st, G, ld, N, w);
-  hipLaunchKernelGGL(k_eig_floor, dim3(1), dim3(256), 0, st, G, ld, N, w);
+  hipLaunchKernelGGL(k_eig_floor, dim3(1), dim3(1024), 0, st, G, ld, N, w);
   eig_rounds<32>(w, N, st, trace);
   hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, st, w, N, lam);
   hipLaunchKernelGGL(k_eig_gather, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, w, N, V, ldv);
@@ -786,7 +856,7 @@ hipError_t launch_eig_batched(const EigBatch* descs, int count, int64_t Nmax, hi
   const int64_t KK = Kmax * Kmax;
   const unsigned gx = (unsigned)((KK + 255) / 256);
   hipLaunchKernelGGL(k_eigb_init, dim3(gx, count), dim3(256), 0, st, descs);
-  hipLaunchKernelGGL(k_eigb_floor, dim3(1, count), dim3(256), 0, st, descs);
+  hipLaunchKernelGGL(k_eigb_floor, dim3(1, count), dim3(1024), 0, st, descs);
   const int rounds = 2 * pmax - 1;
   const int ntile = eig_apply_items(pmax, Kmax, JS);
   for (int sw = 0; sw < eig_max_sweeps(); ++sw) {
@@ -794,7 +864,7 @@ hipError_t launch_eig_batched(const EigBatch* descs, int count, int64_t Nmax, hi
       hipLaunchKernelGGL(k_eigb_solve<JB>, dim3(pmax, count), dim3(1024), lds_solve, st, descs, r);
       hipLaunchKernelGGL(k_eigb_apply<JB>, dim3(ntile, count), dim3(256), lds_apply, st, descs, r);
     }
-    hipLaunchKernelGGL(k_eigb_check, dim3(gx, count), dim3(256), 0, st, descs);
+    hipLaunchKernelGGL(k_eigb_check, dim3(eig_check_blocks(Kmax), count), dim3(256), 0, st, descs);
     hipLaunchKernelGGL(k_eigb_decide, dim3(1, count), dim3(1), 0, st, descs, 1.0);
   }
   hipLaunchKernelGGL(k_eigb_sort, dim3(1, count), dim3(1024), 0, st, descs);
