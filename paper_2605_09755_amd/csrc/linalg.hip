@@ -5,6 +5,9 @@
 // (SVD of B = Q^T A through the eigenpairs of B B^T, Section 2) and of the
 // Nystrom core W (Algorithm 3).  Everything stays on the stream: no host
 // round-trips, conditions are written to device counters.
+#include <mutex>
+#include <vector>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -812,13 +815,12 @@ static void eig_rounds(EigWork w, int64_t N, hipStream_t st, double* trace) {
 
 int eig_block_width(int64_t N) { (void)N; return 32; }
 
-hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
-                      hipStream_t st, double tol, double* trace) {
-  if (N == 0) return hipSuccess;
+// The launch sequence of one eigen-decomposition (about 1300 launches at N = 1000).
+static hipError_t eig_sequence(double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
+                               hipStream_t st, double tol, double* trace) {
   const int JB = eig_block_width(N);
   EigWork w = eig_layout(work, N, JB);
   w.tol = tol;
-  if (w.K > 4096) return hipErrorInvalidValue;
   int64_t KK = w.K * w.K;
   hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, st, G, ld, N, w);
   hipLaunchKernelGGL(k_eig_floor, dim3(1), dim3(1024), 0, st, G, ld, N, w);
@@ -826,6 +828,91 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
   hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, st, w, N, lam);
   hipLaunchKernelGGL(k_eig_gather, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, w, N, V, ldv);
   return hipGetLastError();
+}
+
+// Instantiated graphs of the sequence, keyed by every kernel argument (device
+// pointers, sizes, tolerance): a repeated call with the same buffers replays the
+// graph instead of issuing the launches one by one, which removes the gaps
+// between the short Jacobi kernels.  Least recently used entries are dropped
+// (after a device synchronisation, as a dropped graph may still be running).
+namespace {
+struct EigGraph {
+  int dev;
+  const void *G, *lam, *V, *work, *trace;
+  int64_t ld, N, ldv;
+  double tol;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  uint64_t used;
+  bool same(const EigGraph& o) const {
+    return dev == o.dev && G == o.G && lam == o.lam && V == o.V && work == o.work && trace == o.trace && ld == o.ld &&
+           N == o.N && ldv == o.ldv && tol == o.tol;
+  }
+};
+std::mutex g_eig_mu;
+std::vector<EigGraph> g_eig_graphs;
+uint64_t g_eig_clock = 0;
+constexpr size_t kEigGraphs = 8;
+constexpr int64_t kEigGraphMinN = 128;  // below this the sequence is short
+}  // namespace
+
+hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
+                      hipStream_t st, double tol, double* trace) {
+  if (N == 0) return hipSuccess;
+  if (eig_layout(nullptr, N, eig_block_width(N)).K > 4096) return hipErrorInvalidValue;
+  if (N < kEigGraphMinN) return eig_sequence(G, ld, N, lam, V, ldv, work, st, tol, trace);
+  {
+    // kernel attributes are set outside any capture
+    constexpr int JS = 64;
+    static std::once_flag attr;
+    std::call_once(attr, [] {
+      (void)hipFuncSetAttribute((const void*)k_eig_solve<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(2 * JS * (JS + 1) * sizeof(double)));
+      (void)hipFuncSetAttribute((const void*)k_eig_apply<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)(JS * (JS + 1) * sizeof(double)));
+    });
+  }
+  EigGraph key{};
+  (void)hipGetDevice(&key.dev);
+  key.G = G; key.lam = lam; key.V = V; key.work = work; key.trace = trace;
+  key.ld = ld; key.N = N; key.ldv = ldv; key.tol = tol;
+  std::lock_guard<std::mutex> lock(g_eig_mu);
+  for (auto& e : g_eig_graphs)
+    if (e.same(key)) {
+      e.used = ++g_eig_clock;
+      return hipGraphLaunch(e.exec, st);
+    }
+  hipStream_t cs = nullptr;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+    return eig_sequence(G, ld, N, lam, V, ldv, work, st, tol, trace);
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) == hipSuccess;
+  if (ok) {
+    const hipError_t le = eig_sequence(G, ld, N, lam, V, ldv, work, cs, tol, trace);
+    ok = (hipStreamEndCapture(cs, &g) == hipSuccess) && le == hipSuccess && g != nullptr;
+  }
+  (void)hipStreamDestroy(cs);
+  if (ok) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+  if (!ok) {
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    return eig_sequence(G, ld, N, lam, V, ldv, work, st, tol, trace);
+  }
+  if (g_eig_graphs.size() >= kEigGraphs) {
+    size_t lru = 0;
+    for (size_t i = 1; i < g_eig_graphs.size(); ++i)
+      if (g_eig_graphs[i].used < g_eig_graphs[lru].used) lru = i;
+    (void)hipDeviceSynchronize();
+    (void)hipGraphExecDestroy(g_eig_graphs[lru].exec);
+    (void)hipGraphDestroy(g_eig_graphs[lru].graph);
+    g_eig_graphs.erase(g_eig_graphs.begin() + (ptrdiff_t)lru);
+  }
+  key.graph = g;
+  key.exec = ex;
+  key.used = ++g_eig_clock;
+  g_eig_graphs.push_back(key);
+  return hipGraphLaunch(ex, st);
 }
 
 // Batched eigensolver: problem i (G_i N_i x N_i, ld_i, preserved) -> lam_i, V_i.

@@ -334,3 +334,39 @@ def test_autotune_writes_rules():
     for r in rules:
         assert (r["tile"], r["split"]) in autotune.candidates(r["dtype"])
         assert r["max_m"] >= r["shape"][0] and r["max_n"] >= r["shape"][1] and r["max_k"] >= r["shape"][2]
+
+
+def test_eig_graph_replays_follow_buffer_contents():
+    """Repeated rf_test_eig calls on the same buffers replay one captured graph:
+    each replay must read the buffers' current contents (another matrix, then the
+    first again, bit-identical), with eager work and synchronisation in between."""
+    N = 300
+    rng = np.random.default_rng(77)
+    mats = []
+    for _ in range(2):
+        X = rng.standard_normal((N, 2 * N)) * np.logspace(0, -3, N)[:, None]
+        mats.append(X @ X.T)
+    L = rf.lib()
+    G = torch.empty((N, N), dtype=torch.float64, device=DEV)
+    lam = torch.empty(N, dtype=torch.float64, device=DEV)
+    V = torch.empty((N, N), dtype=torch.float64, device=DEV)
+    ws = torch.empty(int(L.rf_test_eig_ws(N)), dtype=torch.uint8, device=DEV)
+    st = rf._stream(G.device)
+    results = []
+    for rep, which in enumerate([0, 1, 0, 1, 0]):
+        G.copy_(torch.from_numpy(mats[which]))
+        rf._check("rf_test_eig", L.rf_test_eig(rf._ptr(G), N, 1e-12, rf._ptr(lam), rf._ptr(V), rf._ptr(None),
+                                               rf._ptr(ws), st))
+        torch.cuda.synchronize()
+        results.append((which, lam.cpu().numpy().copy(), V.cpu().numpy().copy()))
+        junk = torch.randn(512, 512, device=DEV) @ torch.randn(512, 512, device=DEV)  # eager work between replays
+        torch.cuda.synchronize()
+        del junk
+    for which, l, v in results:
+        ref = np.sort(np.linalg.eigvalsh(mats[which]))[::-1]
+        assert np.max(np.abs(l - ref)) <= 1e-12 * np.abs(ref).max() * math.sqrt(N)
+        assert np.max(np.abs(mats[which] @ v - v * l[None, :])) <= 1e-10 * np.abs(ref).max()
+    for a in range(len(results)):
+        for b in range(a + 1, len(results)):
+            if results[a][0] == results[b][0]:
+                assert np.array_equal(results[a][1], results[b][1]) and np.array_equal(results[a][2], results[b][2])
