@@ -370,8 +370,7 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
   extern __shared__ double sm[];
   double(*M)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm);
   double(*V)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm + JS * (JS + 1));
-  __shared__ double cs[JS / 2], sn[JS / 2];
-  __shared__ int pa[JS / 2], pb[JS / 2];
+  __shared__ double2 csn[JS / 2];
   __shared__ int done;
   const int np = 2 * w.p;
   const int P = circle(round, x, np), Q = circle(round, np - 1 - x, np);
@@ -425,37 +424,47 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
     __syncthreads();
     if (done) break;
     for (int rr = 0; rr < JS - 1; ++rr) {
+      // pair u of inner round rr: (lo, hi) of circle positions u and JS-1-u,
+      // recomputed by every thread; the rotations go through LDS as (c, s) pairs
+      auto pair_of = [&](int u, int& a, int& b) {
+        a = circle(rr, u, JS);
+        b = circle(rr, JS - 1 - u, JS);
+        if (a > b) { const int t = a; a = b; b = t; }
+      };
       if (threadIdx.x < JS / 2) {
-        int u = threadIdx.x;
-        int a = circle(rr, u, JS), b = circle(rr, JS - 1 - u, JS);
-        if (a > b) { int t = a; a = b; b = t; }
-        pa[u] = a;
-        pb[u] = b;
+        const int u = threadIdx.x;
+        int a, b;
+        pair_of(u, a, b);
         double c, s;
         jacobi_rot(M[a][a], M[b][b], M[a][b], floor2, c, s);  // FP32 angle, exact FP64 rotation
-        cs[u] = c;
-        sn[u] = s;
+        csn[u] = double2{c, s};
       }
       __syncthreads();
-      // two-sided update of 2x2 blocks (u, v): M' = J_u^T M J_v
+      // thread t: 2x2 block (u, v) = (t / (JS/2), t % (JS/2)), M' = J_u^T M J_v, and
+      // rows t / (JS/2) + 32 h of V <- V J_v (the same pair v)
       for (int e = threadIdx.x; e < (JS / 2) * (JS / 2); e += blockDim.x) {
-        int u = e / (JS / 2), v = e % (JS / 2);
-        int a = pa[u], b = pb[u], cc = pa[v], d = pb[v];
-        double cu = cs[u], su = sn[u], cv = cs[v], sv = sn[v];
-        double m00 = M[a][cc], m01 = M[a][d], m10 = M[b][cc], m11 = M[b][d];
-        double t00 = cu * m00 - su * m10, t01 = cu * m01 - su * m11;
-        double t10 = su * m00 + cu * m10, t11 = su * m01 + cu * m11;
-        double r00 = cv * t00 - sv * t01, r01 = sv * t00 + cv * t01;
-        double r10 = cv * t10 - sv * t11, r11 = sv * t10 + cv * t11;
-        M[a][cc] = r00; M[a][d] = r01; M[b][cc] = r10; M[b][d] = r11;
-      }
-      for (int e = threadIdx.x; e < JS * (JS / 2); e += blockDim.x) {
-        int row = e / (JS / 2), u = e % (JS / 2);
-        int a = pa[u], b = pb[u];
-        double c = cs[u], s = sn[u];
-        double va = V[row][a], vb = V[row][b];
-        V[row][a] = c * va - s * vb;
-        V[row][b] = s * va + c * vb;
+        const int u = e / (JS / 2), v = e % (JS / 2);
+        int a, b, cc, d;
+        pair_of(u, a, b);
+        pair_of(v, cc, d);
+        const double2 ju = csn[u], jv = csn[v];
+        const double cu = ju.x, su = ju.y, cv = jv.x, sv = jv.y;
+        const double m00 = M[a][cc], m01 = M[a][d], m10 = M[b][cc], m11 = M[b][d];
+        double v0[JS / 32], v1[JS / 32];
+#pragma unroll
+        for (int h = 0; h < JS / 32; ++h) {
+          v0[h] = V[u + (JS / 2) * h][cc];
+          v1[h] = V[u + (JS / 2) * h][d];
+        }
+        const double t00 = cu * m00 - su * m10, t01 = cu * m01 - su * m11;
+        const double t10 = su * m00 + cu * m10, t11 = su * m01 + cu * m11;
+        M[a][cc] = cv * t00 - sv * t01; M[a][d] = sv * t00 + cv * t01;
+        M[b][cc] = cv * t10 - sv * t11; M[b][d] = sv * t10 + cv * t11;
+#pragma unroll
+        for (int h = 0; h < JS / 32; ++h) {
+          V[u + (JS / 2) * h][cc] = cv * v0[h] - sv * v1[h];
+          V[u + (JS / 2) * h][d] = sv * v0[h] + cv * v1[h];
+        }
       }
       __syncthreads();
     }
