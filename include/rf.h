@@ -149,7 +149,9 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
    K <= max_k: tile = 128 or 256 (workgroup tile edge; 256 only for BF16),
    split = 0 (built-in heuristic) or 1..16 (split-K factor, further capped so
    each split keeps >= 256 values of K).  Without a matching rule the built-in
-   heuristics apply.  The rules are copied; count = 0 clears them.  The table
+   heuristics apply.  Products whose A is FP32 or FP8 rounded to BF16 on load
+   (the mixed-precision Q^T A) take the split of the BF16 rule for their shape
+   when that rule picks the 256 tile.  The rules are copied; count = 0 clears them.  The table
    is process-wide: set it before other calls (it is read on every launch and
    must not change while a call is enqueuing).  Returns RF_EINVAL (table
    unchanged) for a malformed rule or count > 256.  Written by the autotuner

@@ -711,7 +711,7 @@ static int gemm_splits_big(int64_t M, int64_t N, int64_t K) {
 
 // ---- tuning table (written by the autotuner, read on every launch) -------------------
 // First rule whose dtype matches and whose bounds hold picks the tile and the split
-// count; no match: the heuristics above.  Split counts are capped at kMaxTunedSplit
+// count (FP32- or FP8-stored A follow the BF16 rules); no match: the heuristics above.  Split counts are capped at kMaxTunedSplit
 // (and at K / 256) so the partial buffer sized by gemm_partial_floats always fits.
 constexpr int kMaxRules = 256, kMaxTunedSplit = 16;
 static GemmRule g_rules[kMaxRules];
@@ -771,12 +771,19 @@ static void go_big(const GemmArgs& g, dim3 grid, hipStream_t st) {
 hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
   if (g.M == 0 || g.N == 0) return hipSuccess;
   const GemmRule* rule = (dtype == 0 || dtype == 2) ? find_rule(dtype, g.M, g.N, g.K) : nullptr;
+  if (dtype == 4 || dtype == 6) {
+    // FP32- and FP8-stored A run the 256-tile BF16 kernel: they take the split of
+    // its BF16 rule for the shape, when that rule picks the 256 tile
+    const GemmRule* r2 = find_rule(2, g.M, g.N, g.K);
+    if (r2 && r2->tile == 256) rule = r2;
+  }
   const bool big = rule ? (rule->tile == 256) : gemm_use_big(dtype, g.M, g.N);
   int splits = 1;
   if (partial) {
     if (rule && rule->split > 0) splits = std::min(rule->split, tuned_cap(g.K));
     else splits = big ? gemm_splits_big(g.M, g.N, g.K) : gemm_splits(g.M, g.N, g.K);
   }
+  if (g.split_cap > 0) splits = std::min(splits, g.split_cap);
   if (g.b_upper) splits = 1;
   int64_t bk = 32;
   g.kps = ((g.K + splits - 1) / splits + bk - 1) / bk * bk;

@@ -60,6 +60,7 @@ struct GemmArgs {
   float* partial;         // set by launcher
   const float* a_scales;  // FP8 A only: 128 x 128 block scales of the stored A (k-block rows)
   int64_t a_ldsc;         //   scale of element (k, i) = a_scales[(k/128) * a_ldsc + i/128]
+  int split_cap;          // > 0: at most this many split-K parts (the partial buffer's size)
 };
 // Tuning rule: dtype 0 (FP32) or 2 (BF16); applies when M <= max_m, N <= max_n,
 // K <= max_k; tile 128 or 256 (BF16 only); split 0 (heuristic) or 1..16.

@@ -85,7 +85,7 @@ struct Ctx {
 static void gemm(Ctx& c, int dtype, const void* A, int64_t lda, int a_kc, const void* B, int64_t ldb, int b_kc, void* C,
                  int64_t ldc, int64_t M, int64_t N, int64_t K, float* partial, const float* colscale = nullptr,
                  int c_trans = 0, int b_upper = 0, int c_bf16 = 0, const float* a_scales = nullptr,
-                 int64_t a_ldsc = 0) {
+                 int64_t a_ldsc = 0, int split_cap = 0) {
   GemmArgs g;
   memset(&g, 0, sizeof(g));
   g.a_scales = a_scales;
@@ -97,6 +97,7 @@ static void gemm(Ctx& c, int dtype, const void* A, int64_t lda, int a_kc, const 
   g.alpha = 1.f;
   g.colscale = colscale;
   g.b_upper = b_upper;
+  g.split_cap = split_cap;
   c.chk(launch_gemm(g, dtype, partial, c.st));
 }
 
@@ -213,8 +214,13 @@ static Dims dims_of(const rf_matrix* A, const rf_params* p) {
   return d;
 }
 
+// Split-K parts the B^T = A^T Q product may use (its partial buffer holds this many
+// n x k FP32 slices; the tuning table's split is capped to it).
+constexpr int kQtaSplitCap = 4;
+
 struct SvdBufs {
   float* Q; float* Bt; double* GB; double* lam; double* Ub; float* Ub32; float* inv; void* eigw; int* signw;
+  float* qpart;
 };
 static SvdBufs carve_svd(Arena& ar, const Dims& d) {
   SvdBufs s;
@@ -227,6 +233,7 @@ static SvdBufs carve_svd(Arena& ar, const Dims& d) {
   s.inv = ar.get<float>(d.k);
   s.eigw = ar.get<char>(eig_work_bytes(d.k));
   s.signw = ar.get<int>(3 * (size_t)d.k);
+  s.qpart = ar.get<float>((size_t)kQtaSplitCap * d.n * d.k);
   return s;
 }
 static double* carve_gpart_big(Arena& ar, const Dims& d) {
@@ -401,14 +408,16 @@ rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, 
     // block-scaled FP8 A is dequantised and rounded to BF16 as it is loaded
     uint16_t* q16 = b.Q16 ? b.Q16 : (uint16_t*)b.Ya;
     c.chk(launch_cast_f32_bf16(s.Q, k, q16, k, d.m, k, c.st));
-    gemm(c, 6, A->data, A->ld, 0, q16, k, 0, s.Bt, k, d.n, k, d.m, nullptr, nullptr, 0, 0, 0, A->block_scales,
-         (d.n + 127) / 128);
+    gemm(c, 6, A->data, A->ld, 0, q16, k, 0, s.Bt, k, d.n, k, d.m, s.qpart, nullptr, 0, 0, 0, A->block_scales,
+         (d.n + 127) / 128, kQtaSplitCap);
   } else if (A->dtype == RF_BF16 || d.prec == RF_PREC_MIXED) {
     uint16_t* q16 = b.Q16 ? b.Q16 : (uint16_t*)b.Ya;
     c.chk(launch_cast_f32_bf16(s.Q, k, q16, k, d.m, k, c.st));
-    gemm(c, A->dtype == RF_BF16 ? 2 : 4, A->data, A->ld, 0, q16, k, 0, s.Bt, k, d.n, k, d.m, nullptr);
+    gemm(c, A->dtype == RF_BF16 ? 2 : 4, A->data, A->ld, 0, q16, k, 0, s.Bt, k, d.n, k, d.m, s.qpart, nullptr, 0, 0,
+         0, nullptr, 0, kQtaSplitCap);
   } else {
-    gemm(c, 0, A->data, A->ld, 0, s.Q, k, 0, s.Bt, k, d.n, k, d.m, nullptr);
+    gemm(c, 0, A->data, A->ld, 0, s.Q, k, 0, s.Bt, k, d.n, k, d.m, s.qpart, nullptr, 0, 0, 0, nullptr, 0,
+         kQtaSplitCap);
   }
   // Ritz: B B^T = Ub diag(lam) Ub^T in FP64
   c.chk(launch_gram(s.Bt, k, 0, s.Bt, k, 0, d.n, k, k, 1, s.GB, k, gbig, nullptr, c.st));
