@@ -112,6 +112,34 @@ RF_DEV void put_x(const CholInvArgs& a, int64_t r, int64_t c, double v) {
   if (a.X32) a.X32[r * a.ldx32 + c] = (float)v;
 }
 
+// Orders one wave's LDS accesses between the steps of a wave-synchronous loop.
+RF_DEV void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+constexpr int SB = 16;  // diagonal sub-block of the inverse
+
+// Inverse of the upper-triangular sub-block [k0, k0 + kn) of R (1 / R_cc in rsv):
+// lane j < kn of the calling wave solves column j by back substitution.
+RF_DEV void inv_sub(int k0, int kn, double (*R)[TLD], double (*Xs)[TLD], const double* rsv) {
+  const int lane = threadIdx.x & 63;
+  if (lane < kn) {
+    double x[SB];
+#pragma unroll
+    for (int c = SB - 1; c >= 0; --c) {
+      double acc = (c == lane) ? 1.0 : 0.0;
+#pragma unroll
+      for (int l = c + 1; l < SB; ++l) acc = fma(-R[k0 + c][k0 + l], x[l], acc);  // R is zero beyond kn
+      x[c] = (c <= lane) ? acc * rsv[k0 + c] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < SB; ++c)
+      if (c <= lane) Xs[k0 + c][k0 + lane] = x[c];
+  }
+}
+
 // Element (a, b) of a thread's 4 x 4 register block with a runtime row a.
 // (value selects, so that the block stays in registers)
 RF_DEV double pick_row(const double (&m)[4][4], int a, int b) {
@@ -128,8 +156,7 @@ RF_DEV double pick_row(const double (&m)[4][4], int a, int b) {
 // Cholesky, right-looking, one barrier per column: the threads holding row c + 1
 // publish it (double-buffered) right after their step-c update, and at step c + 1
 // every thread forms R_c+1,. = G_c+1,. / sqrt(g) from it and updates its entries.
-// Inverse by backward elimination on T = I (X_c. = T_c. / R_cc, then
-// T_i. -= R_ic X_c. for i < c), again publishing the next row as soon as it is final.
+// Inverse blocked by 16 (see below).
 RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R)[TLD], double (*Xs)[TLD]) {
   const int64_t b0 = (int64_t)kb * TB;
   const int nbk = (int)min((int64_t)TB, a.N - b0);
@@ -200,54 +227,36 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
     }
     __syncthreads();
   }
-  double* xrb = rowb;  // the row buffers are free again
-  double tt[4][4];
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) tt[p][q] = (ty + 16 * p == tx + 16 * q && ty + 16 * p < nbk) ? 1.0 : 0.0;
-  if (nbk > 0 && ty == ((nbk - 1) & 15)) {
-    const double inv = rsv[nbk - 1];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int j = tx + 16 * q;
-      xrb[((nbk - 1) & 1) * TB + j] = (j == nbk - 1) ? inv : 0.0;
-    }
-  }
+  // Inverse, blocked by 16: wave w inverts diagonal sub-block w, then the other
+  // blocks follow by block diagonals, X_IJ = -X_II (sum_{L=I+1..J} R_IL X_LJ)
+  // (the row buffers and M are free now: M holds the partial sums).
+  const int nsb = (nbk + SB - 1) / SB;
+  const int wave = threadIdx.x >> 6;
+  if (wave < nsb) inv_sub(wave * SB, min(SB, nbk - wave * SB), R, Xs, rsv);
   __syncthreads();
-  for (int c = nbk - 1; c >= 0; --c) {
-    const double* xr = xrb + (c & 1) * TB;
-    double rc[4], xj[4];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) rc[p] = (ty + 16 * p < c) ? R[ty + 16 * p][c] : 0.0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) xj[q] = xr[tx + 16 * q];
-#pragma unroll
-    for (int p = 0; p < 4; ++p) {
-      const bool own = (ty + 16 * p == c);
-#pragma unroll
-      for (int q = 0; q < 4; ++q) tt[p][q] = own ? xj[q] : fma(-rc[p], xj[q], tt[p][q]);
+  for (int d = 1; d < nsb; ++d) {
+    const int nblk = nsb - d;
+    for (int e = threadIdx.x; e < nblk * SB * SB; e += blockDim.x) {
+      const int I = e / (SB * SB), r = (e / SB) % SB, cc = e % SB, J = I + d;
+      const int i = I * SB + r, jj = J * SB + cc;
+      if (i >= nbk || jj >= nbk) continue;
+      double acc = 0.0;
+      const int lend = min((J + 1) * SB, nbk);
+      for (int l = (I + 1) * SB; l < lend; ++l) acc = fma(R[i][l], Xs[l][jj], acc);
+      M[i][jj] = acc;
     }
-    const int c1 = c - 1;
-    if (c1 >= 0 && ty == (c1 & 15)) {
-      const double inv = rsv[c1];
-      double* nx = xrb + (c1 & 1) * TB;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j = tx + 16 * q;
-        nx[j] = (j >= c1 && j < nbk) ? pick_row(tt, c1 >> 4, q) * inv : 0.0;
-      }
+    __syncthreads();
+    for (int e = threadIdx.x; e < nblk * SB * SB; e += blockDim.x) {
+      const int I = e / (SB * SB), r = (e / SB) % SB, cc = e % SB, J = I + d;
+      const int i = I * SB + r, jj = J * SB + cc;
+      if (i >= nbk || jj >= nbk) continue;
+      double acc = 0.0;
+      const int lend = min((I + 1) * SB, nbk);
+      for (int l = i; l < lend; ++l) acc = fma(Xs[i][l], M[l][jj], acc);
+      Xs[i][jj] = -acc;
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int p = 0; p < 4; ++p)
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int i = ty + 16 * p, j = tx + 16 * q;
-      if (j >= i) Xs[i][j] = tt[p][q];
-    }
-  __syncthreads();
   for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
     const int r = e / TB, c = e % TB;
     if (r < nbk && c < nbk) {
