@@ -103,6 +103,10 @@ def main():
     ap.add_argument("--forms", default="fp32,mixed")
     ap.add_argument("--q", type=int, default=None, help="fixed q (skip the accuracy sweep)")
     ap.add_argument("--batch", type=int, default=512, help="matrices in the batched workload (0: skip it)")
+    ap.add_argument("--workload", choices=["poly65k", "exp65k", "nystrom32k"], default="poly65k",
+                    help="poly65k: the headline workload (default); exp65k: A 65536 x 32768 stored FP32, BF16 and "
+                         "FP8 with block scales, k=2000, sketch 4000, q=3; nystrom32k: Gaussian kernel matrix of "
+                         "32768 points in 32 dimensions, k=512, sketch 1024, q=2")
     ap.add_argument("--counter-run", choices=["sketch", "copy"], default=None,
                     help="for rocprofv3 --pmc runs: three sketch passes over the workload matrix, or three copies "
                          "of 1 GiB (FETCH_SIZE / WRITE_SIZE calibration); prints nothing else")
@@ -112,6 +116,12 @@ def main():
         sys.exit(2)
     if args.counter_run:
         counter_run(args)
+        return
+    if args.workload == "exp65k":
+        exp65k_bench(args)
+        return
+    if args.workload == "nystrom32k":
+        nystrom_bench(args)
         return
 
     import torch
@@ -223,7 +233,7 @@ def main():
     sk = roof["sketch_f32"]
     achieved = sk["bytes"] / sk["seconds_per_call"]
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": sketch_traffic(), "kernel": "k_sketch_right_fx<float,8,4,8,2,40>",
+                "frac": achieved / HBM_PEAK, "traffic": sketch_traffic(), "kernel": "k_sketch_right_fx2<float,8,4,8,32>",
                 "per_launch": "read A %d x %d FP32 + write At %d x %d FP32" % (m, n, m, l)}
     others = {}
     for name in ("qta_f32", "qta_bf16"):
@@ -271,6 +281,214 @@ def main():
         "batched": batched,
         "cpu_baseline": cpu,
     }
+    print(json.dumps(line), flush=True)
+
+
+def time_calls(torch, fn, warmup, steps, stream):
+    """Mean milliseconds per call of fn() over `steps` calls (HIP events on the launch stream)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps
+
+
+def quantize_fp8_blocks(torch, A, blk=128):
+    """OCP e4m3 codes (round to nearest even) and one FP32 scale amax/448 per 128 x 128
+    block (1 for an all-zero block): the FP8 storage form of A."""
+    m, n = A.shape
+    bm, bn = -(-m // blk), -(-n // blk)
+    amax = torch.zeros((bm, bn), dtype=torch.float32, device=A.device)
+    for i in range(bm):
+        rows = A[i * blk:(i + 1) * blk]
+        pad = bn * blk - n
+        t = torch.nn.functional.pad(rows.abs(), (0, pad)) if pad else rows.abs()
+        amax[i] = t.view(rows.shape[0], bn, blk).amax(dim=(0, 2))
+    scales = torch.where(amax > 0, amax / 448.0, torch.ones_like(amax))
+    codes = torch.empty((m, n), dtype=torch.uint8, device=A.device)
+    for i in range(bm):
+        rows = A[i * blk:(i + 1) * blk]
+        sc = scales[i].repeat_interleave(blk)[:n].unsqueeze(0)
+        codes[i * blk:(i + 1) * blk] = (rows / sc).to(torch.float8_e4m3fn).view(torch.uint8)
+    return codes, scales
+
+
+def exp65k_bench(args):
+    """Precision forms on A 65536 x 32768, sigma_i = max(0.995^i, 1e-3 sigma_1) (no additive
+    noise, so opt_F is exact from the spectrum): A stored FP32 (plain FP32 form and mixed form
+    with BF16 products), BF16 and FP8-e4m3 with 128 x 128 block scales (mixed form).
+    k = 2000, sketch 4000, 8 nonzeros per column, q = 0..3 swept; timed at q = 3."""
+    import torch
+    import paper_2605_09755_amd as rf
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    m, n, k, l, s, qcfg = 65536, 32768, 2000, 4000, 8, 3
+    r = min(m, n)
+    sig = np.maximum(0.995 ** np.arange(1, r + 1, dtype=np.float64), 1e-3 * 0.995)
+    opt = math.sqrt(float(np.sum(sig[k:] ** 2)))
+    t0 = time.time()
+    g = torch.Generator(device=dev)
+    g.manual_seed(103)
+    G = torch.randn(m, r, generator=g, device=dev, dtype=torch.float32)
+    U, R = torch.linalg.qr(G)
+    U *= torch.sign(torch.diagonal(R)).unsqueeze(0)
+    del G, R
+    log("exp65k: U %dx%d in %.1fs" % (m, r, time.time() - t0))
+    G = torch.randn(n, r, generator=g, device=dev, dtype=torch.float32)
+    V, R = torch.linalg.qr(G)
+    V *= torch.sign(torch.diagonal(R)).unsqueeze(0)
+    del G, R
+    A = (U * torch.from_numpy(sig).to(dev, torch.float32).unsqueeze(0)) @ V.t()
+    del U, V
+    torch.cuda.synchronize()
+    log("exp65k: generated A %dx%d in %.1fs, opt_F %.6e" % (m, n, time.time() - t0, opt))
+    A16 = A.to(torch.bfloat16)
+    A8, sc8 = quantize_fp8_blocks(torch, A)
+    torch.cuda.synchronize()
+    log("exp65k: BF16 and FP8 storage forms ready")
+    forms = [("fp32", A, None, "fp32"), ("mixed", A, None, "mixed"), ("bf16a", A16, None, "mixed"),
+             ("fp8a", A8, sc8, "mixed")]
+    res = {}
+    for name, Ain, scales, prec in forms:
+        p = rf.params(k, l, qcfg, s, 42, prec)
+        nws = rf.rf_workspace_size(rf.RF_OP_SVD, Ain, p, scales)
+        ws = torch.empty(nws, dtype=torch.uint8, device=dev)
+        out = (torch.empty((m, k), dtype=torch.float32, device=dev), torch.empty(k, dtype=torch.float64, device=dev),
+               torch.empty((k, n), dtype=torch.float32, device=dev),
+               torch.zeros(rf.INFO_BYTES, dtype=torch.uint8, device=dev))
+        sweep = []
+        for q in range(0, qcfg + 1):
+            rf.rf_svd(Ain, k, l, q, s, 42, prec, scales=scales, workspace=(ws, nws), out=out)
+            torch.cuda.synchronize()
+            ratio = frob_err(torch, A, out[0]) / opt
+            sweep.append({"q": q, "ratio": ratio})
+            log("exp65k %s q=%d ratio %.5f info %s" % (name, q, ratio, rf.info_dict(out[3])))
+        ms = time_calls(torch, lambda: rf.rf_svd(Ain, k, l, qcfg, s, 42, prec, scales=scales, workspace=(ws, nws),
+                                                 out=out), args.warmup, max(1, min(args.steps, 5)), stream)
+        res[name] = {"q": qcfg, "ms_per_step": ms, "ratio": sweep[-1]["ratio"], "sweep": sweep}
+        log("exp65k %s: q=%d %.3f ms / factorisation" % (name, qcfg, ms))
+        del ws, out
+        torch.cuda.empty_cache()
+    # live rooflines: the sketch pass per storage form, Q^T A per storage form
+    roof = {}
+    for name, Ain, scales, nbytes in (("sketch_f32", A, None, 4), ("sketch_bf16", A16, None, 2),
+                                      ("sketch_fp8", A8, sc8, 1)):
+        t = time_calls(torch, lambda: rf.rf_sketch_apply(Ain, l, s, 42, scales=scales), 1, 5, stream) / 1e3
+        byts = m * n * nbytes + m * l * 4 + (sc8.numel() * 4 if scales is not None else 0)
+        roof[name] = {"bound": "hbm", "achieved": byts / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                      "frac": byts / t / HBM_PEAK, "ms": t * 1e3}
+    Q = torch.randn(m, k, device=dev, dtype=torch.float32)
+    Q16 = Q.to(torch.bfloat16)
+    for name, fn in (("qta_f32", lambda: rf.rf_test_gemm(A, Q, n, k, m, 0, 0, split=False)),
+                     ("qta_bf16", lambda: rf.rf_test_gemm(A16, Q16, n, k, m, 0, 0, split=False)),
+                     ("qta_fp8", lambda: rf.rf_test_gemm_fp8a(A8, sc8, Q16, n, k, m, 0))):
+        t = time_calls(torch, fn, 1, 5, stream) / 1e3
+        pk = PEAKS["f32" if name == "qta_f32" else "bf16"]
+        roof[name] = {"bound": "mfma", "achieved": 2.0 * m * n * k / t / 1e12, "peak": pk / 1e12,
+                      "unit": "TFLOP/s", "frac": 2.0 * m * n * k / t / pk, "ms": t * 1e3}
+    for kname, r in roof.items():
+        log("exp65k %s: %.3f ms, %.1f %s (%.1f%% of peak)" % (kname, r["ms"], r["achieved"], r["unit"],
+                                                             100 * r["frac"]))
+    line = {"metric": "s per rf_svd factorisation at q=3 by storage form of A; error ratio ‖A−QQᵀA‖_F/opt_F",
+            "value": res["fp8a"]["ms_per_step"] / 1e3, "unit": "s", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "fp8-e4m3 A, bf16 products", "data": "synthetic",
+            "config": {"workload": "exp65k: A 65536x32768 = U diag(max(0.995^i, 1e-3 sigma_1)) V^T, Haar U,V; "
+                                   "rf_svd k=2000 sketch=2000x2 nnz/col=8 q=3 seed=42", "opt_F": opt,
+                       "forms": res,
+                       "speedup_vs_plain_fp32": {f: res["fp32"]["ms_per_step"] / res[f]["ms_per_step"]
+                                                 for f in res}},
+            "roofline": roof}
+    print(json.dumps(line), flush=True)
+
+
+def top_eig_sum_sq(torch, K64, k, width=1024, iters=12, seed=7):
+    """sum_{i<=k} lambda_i^2 of a PSD FP64 matrix by block subspace iteration of `width`
+    columns and a final Rayleigh-Ritz step (harness: exact opt_F of the Nystrom workload).
+    Ritz values of a subspace are no larger than the eigenvalues, so the returned opt_F
+    is an upper bound; the residual of the top k Ritz pairs is returned with it."""
+    g = torch.Generator(device=K64.device)
+    g.manual_seed(seed)
+    X = torch.randn(K64.shape[0], width, generator=g, device=K64.device, dtype=torch.float64)
+    for _ in range(iters):
+        X, _ = torch.linalg.qr(K64 @ X)
+    KX = K64 @ X
+    H = X.t() @ KX
+    lam, W = torch.linalg.eigh(0.5 * (H + H.t()))
+    lam, order = torch.sort(lam, descending=True)
+    W = W[:, order[:k]]
+    V = X @ W
+    res = torch.linalg.norm(KX @ W - V * lam[:k].unsqueeze(0)) / float(lam[0])
+    return float((lam[:k] ** 2).sum()), float(res)
+
+
+def nystrom_bench(args):
+    """Algorithm 3 on a Gaussian kernel matrix: x_i ~ N(0, I_32), n = 32768, h = median
+    Euclidean distance over the pairs of the first 4096 points (mean of the two middle
+    values), K_ij = exp(-|x_i - x_j|^2 / (2 h^2)) computed in FP64 and stored FP32; k = 512,
+    sketch 1024, 8 nonzeros per column, q = 2.  Plain FP32 against mixed (BF16 products,
+    FP64 small factorisations)."""
+    import torch
+    import paper_2605_09755_amd as rf
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    n, d, k, l, s, q = 32768, 32, 512, 1024, 8, 2
+    t0 = time.time()
+    g = torch.Generator(device=dev)
+    g.manual_seed(104)
+    X = torch.randn(n, d, generator=g, device=dev, dtype=torch.float64)
+    Xs = X[:4096]
+    D = torch.cdist(Xs, Xs)
+    iu = torch.triu_indices(4096, 4096, 1, device=dev)
+    dist = torch.sort(D[iu[0], iu[1]]).values
+    mid = dist.numel() // 2
+    h = float(0.5 * (dist[mid - 1] + dist[mid])) if dist.numel() % 2 == 0 else float(dist[mid])
+    del D, iu, dist
+    sq = (X * X).sum(1)
+    D2 = torch.clamp(sq.unsqueeze(1) + sq.unsqueeze(0) - 2.0 * (X @ X.t()), min=0.0)
+    K64 = torch.exp(-D2 / (2.0 * h * h))
+    del D2
+    K64.fill_diagonal_(1.0)
+    K = K64.to(torch.float32)
+    K64 = K.double()          # the stored FP32 matrix is the problem instance
+    torch.cuda.synchronize()
+    log("nystrom32k: K %dx%d (h = %.6f) in %.1fs" % (n, n, h, time.time() - t0))
+    fro2 = float((K64 * K64).sum())
+    top, res = top_eig_sum_sq(torch, K64, k)
+    opt = math.sqrt(max(fro2 - top, 0.0))
+    log("nystrom32k: opt_F %.6e (Ritz residual %.2e) in %.1fs" % (opt, res, time.time() - t0))
+    out = {}
+    for form in ("fp32", "mixed"):
+        p = rf.params(k, l, q, s, 42, form)
+        nws = rf.rf_workspace_size(rf.RF_OP_NYSTROM, K, p)
+        ws = torch.empty(nws, dtype=torch.uint8, device=dev)
+        C, W, F, info = rf.rf_nystrom(K, k, l, q, s, 42, form, workspace=(ws, nws))
+        torch.cuda.synchronize()
+        F64 = F.double()
+        err2 = fro2 - 2.0 * float((F64 * (K64 @ F64)).sum()) + float(((F64.t() @ F64) ** 2).sum())
+        ratio = math.sqrt(max(err2, 0.0)) / opt
+        ms = time_calls(torch, lambda: rf.rf_nystrom(K, k, l, q, s, 42, form, workspace=(ws, nws)),
+                        args.warmup, max(1, args.steps), stream)
+        out[form] = {"q": q, "ms_per_step": ms, "ratio": ratio, "info": rf.info_dict(info)}
+        log("nystrom32k %s: ratio %.5f  %.3f ms / call  info %s" % (form, ratio, ms, rf.info_dict(info)))
+        del ws, C, W, F, F64
+    t = time_calls(torch, lambda: rf.rf_sketch_apply(K, l, s, 42), 1, 5, stream) / 1e3
+    byts = n * n * 4 + n * l * 4
+    roof = {"bound": "hbm", "achieved": byts / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+            "frac": byts / t / HBM_PEAK, "ms": t * 1e3, "kernel": "K S (sketch pass over K)"}
+    log("nystrom32k sketch K S: %.3f ms, %.1f GB/s (%.1f%%)" % (t * 1e3, roof["achieved"], 100 * roof["frac"]))
+    line = {"metric": "s per rf_nystrom call; error ratio ‖K−FFᵀ‖_F/opt_F", "value": out["mixed"]["ms_per_step"] / 1e3,
+            "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "bf16 products, f64 small factorisations",
+            "data": "synthetic",
+            "config": {"workload": "nystrom32k: Gaussian kernel of 32768 points ~ N(0, I_32), h = median distance "
+                                   "of the first 4096 points; rf_nystrom k=512 sketch=1024 nnz/col=8 q=2 seed=42",
+                       "h": h, "opt_F": opt, "opt_ritz_residual": res, "forms": out,
+                       "speedup_mixed_vs_plain": out["fp32"]["ms_per_step"] / out["mixed"]["ms_per_step"]},
+            "roofline": roof}
     print(json.dumps(line), flush=True)
 
 

@@ -25,6 +25,9 @@ struct RngArgs {
 hipError_t launch_rng_batched(const RngArgs* as, int count, int64_t max_entries, hipStream_t st);
 int sketch_right_cpl(int s);
 bool sketch_right_fast_ok(int s);
+// The single-problem ready table is written in the compact 16-bit form (and read by
+// the two-workgroups-per-CU sketch kernel) when this holds.
+bool sketch_right_ready16(int s, int r1);
 // dtype: 0 f32, 2 bf16, 3 fp8 e4m3 with 128x128 block scales
 // cmax: workspace of sketch_right_cmax_ints(n) ints (per-chunk bucket occupancy)
 size_t sketch_right_cmax_ints(int64_t n);

@@ -50,6 +50,17 @@ __global__ void k_sketch_ready(const int32_t* __restrict__ table, int64_t n, int
   ready[idx] = ready_entry(table, idx, s, r1, cpl);
 }
 
+// Compact form for sketches of at most 256 lines per block: entry (j, q) is the
+// 16-bit word sign<<15 | (b_local * 64 + t) of the same lane-permuted block t, the
+// LDS word index of the bucket line plus the block's slot (< 2^14).
+__global__ void k_sketch_ready16(const int32_t* __restrict__ table, int64_t n, int s, int r1, int cpl,
+                                 uint16_t* __restrict__ ready) {
+  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * s) return;
+  const uint32_t w = ready_entry(table, idx, s, r1, cpl);
+  ready[idx] = (uint16_t)(((w >> 31) << 15) | ((w & 0x7fffffffu) >> 2));
+}
+
 RF_DEV void gaussian_quad(int64_t p, int64_t total, uint64_t seed, uint32_t stream, uint32_t b,
                           float* __restrict__ out, int64_t cols, int64_t ldo) {
   u32x4 x = philox((uint64_t)p, stream, b, seed);
@@ -106,8 +117,12 @@ hipError_t launch_sketch_ready(const int32_t* table, int64_t n, int s, int r1, i
                                hipStream_t st) {
   int64_t tot = n * s;
   if (tot == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_sketch_ready, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, table, n, s,
-                     r1, cpl, ready);
+  if (sketch_right_ready16(s, r1))
+    hipLaunchKernelGGL(k_sketch_ready16, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, table, n, s,
+                       r1, cpl, reinterpret_cast<uint16_t*>(ready));
+  else
+    hipLaunchKernelGGL(k_sketch_ready, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, table, n, s,
+                       r1, cpl, ready);
   return hipGetLastError();
 }
 

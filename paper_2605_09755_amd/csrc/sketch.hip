@@ -307,6 +307,241 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_right_fx(
                                                  vec_ok, blockIdx.x);
 }
 
+// Two-workgroups-per-CU form of the fixed-point pass, for sketches of at most 256
+// lines per block (64 KiB of integer partials per band).  It keeps one column group
+// per wave (J = 512 CPL columns per chunk) and reads the compact 16-bit table, so a
+// thread fits in 128 VGPRs and two workgroups share a CU: one streams its next
+// chunk from HBM while the other runs its atomics.
+//
+// Every row of the band has its own scale 2^E_r, set from that row's chunk maximum,
+// so the rounding of a row is relative to the row itself (rows of very different
+// size may share a band).  The integer partials are not folded after every chunk:
+// a chunk is added at the current scales when, for every row, its values lose at
+// most two bits against their own scale and the running bound on the row's partials
+// (sum over chunks of c_chunk max_chunk 2^E_r plus c_chunk for the rounding) stays
+// below 2^31; otherwise all partials are folded into the FP32 registers first and
+// each E_r is reset from this chunk with two bits of headroom
+// (2^26 <= c max 2^E_r < 2^28: at least seven chunks fit between folds, and a term
+// is rounded to at most c 2^-25 times its chunk's row maximum).  A thread's LDS
+// words all belong to row lane / s,
+// so a fold needs one scale per thread.  One barrier per chunk (three rotating sets
+// of row maxima), a second only on a fold.
+template <typename TIN, int S, int CPL, int NW, int FACC>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sketch_right_fx2(
+    const TIN* __restrict__ A, int64_t lda, const float* __restrict__ scales, int64_t ldsc,
+    const uint16_t* __restrict__ ready, const int* __restrict__ cmax, int64_t m, int64_t n, int r1, int wl,
+    float* __restrict__ out, int64_t ldo, float inv_sqrt_s, bool vec_ok) {
+  constexpr int R = 64 / S;
+  constexpr int NT = NW * 64;
+  constexpr int64_t J = (int64_t)NT * CPL;  // columns per chunk
+  static_assert(R <= 32, "row flags are kept in one 32-bit mask");
+  static_assert(S % 2 == 0, "table entries are read in pairs");
+  extern __shared__ int iacc[];
+  __shared__ unsigned rowmax[3][R], wgbad;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * R;
+  const int entries = wl * 64;
+  for (int i = tid; i < entries; i += NT) iacc[i] = 0;
+  if (tid < 3 * R) (&rowmax[0][0])[tid] = 0u;
+  if (tid == 0) wgbad = 0u;
+  unsigned bad = 0u;  // bit r: row row0 + r holds a non-finite value
+  float facc[FACC];
+#pragma unroll
+  for (int i = 0; i < FACC; ++i) facc[i] = 0.f;
+  __syncthreads();
+  const int rbits = lane / S, tbits = lane % S;
+  char* accb = reinterpret_cast<char*>(iacc);
+  // Per-row fixed-point state, kept by lane r of every wave for row r (lanes >= R
+  // hold copies of nothing in particular); every wave computes the same values.
+  int E = 0;           // partials of row `lane` hold sum(x 2^E), rounded per term
+  float used = 0.f;    // bound on |partial| of the row in integer units since the last fold
+  bool live = false;   // the row holds unfolded terms
+  const int myrow = lane < R ? lane : 0;
+  const int64_t nch = (n + J - 1) / J;
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    // Opaque copy of the lane's row bits: the per-row offsets derived from it are
+    // recomputed per chunk instead of being held live across the loop.
+    int rb = rbits;
+    asm volatile("" : "+v"(rb));
+    float a[R][CPL];
+    uint32_t ent[CPL][S / 2];  // two 16-bit words each
+    float mx[R];               // mx[p]: max |a| of row rb ^ p over the lane's columns
+    float chk[R];              // chk[p]: sum of a * 0, NaN iff row rb ^ p has a non-finite value
+    const int64_t j = ch * J + ((int64_t)wave * 64 + lane) * CPL;
+    float sc = 1.f;
+    if constexpr (sizeof(TIN) == 1) {
+      if (j < n) sc = scales[(row0 / 128) * ldsc + j / 128];
+    }
+    // interior chunk of a full band: unconditional vector loads (uniform branch)
+    const bool interior = vec_ok && row0 + R <= m && (ch + 1) * J <= n;
+    if (interior) {
+#pragma unroll
+      for (int p = 0; p < R; ++p) ld_cols<TIN, CPL>(A + (row0 + (rb ^ p)) * lda, j, n, true, a[p]);
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) {
+        const uint16_t* ep = ready + (j + e) * S;
+        if constexpr (S == 4) {
+          const uint2 w = *reinterpret_cast<const uint2*>(ep);
+          ent[e][0] = w.x; ent[e][1] = w.y;
+        } else {
+#pragma unroll
+          for (int v = 0; v < S / 8; ++v) {
+            const uint4 w = reinterpret_cast<const uint4*>(ep)[v];
+            ent[e][4 * v] = w.x; ent[e][4 * v + 1] = w.y; ent[e][4 * v + 2] = w.z; ent[e][4 * v + 3] = w.w;
+          }
+        }
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < R; ++p) {
+        const int64_t row = row0 + (rb ^ p);
+        if (row < m && j < n) ld_cols<TIN, CPL>(A + row * lda, j, n, vec_ok, a[p]);
+        else {
+#pragma unroll
+          for (int e = 0; e < CPL; ++e) a[p][e] = 0.f;
+        }
+      }
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) {
+        if (j + e < n) {
+          const uint16_t* ep = ready + (j + e) * S;
+          if constexpr (S == 4) {
+            const uint2 w = *reinterpret_cast<const uint2*>(ep);
+            ent[e][0] = w.x; ent[e][1] = w.y;
+          } else {
+#pragma unroll
+            for (int v = 0; v < S / 8; ++v) {
+              const uint4 w = reinterpret_cast<const uint4*>(ep)[v];
+              ent[e][4 * v] = w.x; ent[e][4 * v + 1] = w.y; ent[e][4 * v + 2] = w.z; ent[e][4 * v + 3] = w.w;
+            }
+          }
+        } else {
+#pragma unroll
+          for (int v = 0; v < S / 2; ++v) ent[e][v] = 0u;
+        }
+      }
+    }
+#pragma unroll
+    for (int p = 0; p < R; ++p) {
+      mx[p] = 0.f;
+      chk[p] = 0.f;
+#pragma unroll
+      for (int e = 0; e < CPL; ++e) {
+        if constexpr (sizeof(TIN) == 1) a[p][e] *= sc;
+        // a row holding a non-finite value is set to NaN at the end; its own integer
+        // sums are then meaningless, and its scale is kept out of the fold decisions
+        chk[p] = fmaf(a[p][e], 0.f, chk[p]);
+        mx[p] = fmaxf(mx[p], fabsf(a[p][e]));
+      }
+      bad |= isfinite(chk[p]) ? 0u : (1u << (rb ^ p));
+    }
+    // row maxima: the S lanes of equal rb hold the same rows; reduce over them, then
+    // one LDS max per row from the lanes with tbits == 0 (distinct rows, no conflicts)
+    const int slot = (int)(ch % 3);
+#pragma unroll
+    for (int p = 0; p < R; ++p) {
+#pragma unroll
+      for (int o = 1; o < S; o <<= 1) mx[p] = fmaxf(mx[p], __shfl_xor(mx[p], o, 64));
+      if (tbits == 0 && mx[p] > 0.f) atomicMax(&rowmax[slot][rb ^ p], __float_as_uint(mx[p]));
+    }
+    __syncthreads();
+    // row maxima of slot (ch + 2) % 3 were last read before this barrier and are next
+    // written after the next one
+    if (tid < R) rowmax[(slot + 2) % 3][tid] = 0u;
+    const int c = max(cmax[ch], 1);
+    const int cbits = 32 - __clz(c);  // c < 2^cbits
+    // lane r decides for row r; the workgroup folds if any row must
+    const float gm = __uint_as_float(rowmax[slot][myrow]);
+    const bool nz = lane < R && gm > 0.f && isfinite(gm);
+    int eg = 0;
+    frexpf(gm, &eg);                                 // gm < 2^eg
+    const int enew = min(28 - (eg + cbits), 126);   // 2^26 <= c gm 2^enew < 2^28; 2^enew finite
+    const float need = ldexpf(gm * (float)c, E) + (float)c;
+    // fold when a row would lose more than two bits at its current scale or could
+    // overflow a partial
+    const bool want = nz && live && (enew > E + 2 || used + need >= 2.0e9f);
+    const bool fold = __any(want);
+    if (!__any(nz)) continue;  // all-zero chunk: nothing to add
+    if (fold) {
+      const int ef = __shfl(E, rbits, 64);  // every word of this thread belongs to row rbits
+      const bool lv = __shfl((int)live, rbits, 64) != 0;
+      if (lv) {
+#pragma unroll
+        for (int i = 0; i < FACC; ++i) {
+          const int idx = tid + i * NT;
+          if (idx < entries) {
+            facc[i] += ldexpf((float)iacc[idx], -ef);
+            iacc[idx] = 0;
+          }
+        }
+      }
+      live = false;
+      __syncthreads();
+    }
+    if (nz) {
+      if (live) {
+        used += need;
+      } else {
+        E = enew;
+        used = ldexpf(gm * (float)c, E) + (float)c;
+        live = true;
+      }
+    }
+    // the lane's multiplier for row rb ^ p
+    float mul[R];
+#pragma unroll
+    for (int p = 0; p < R; ++p) mul[p] = ldexpf(1.f, __shfl(E, rb ^ p, 64));
+#pragma unroll
+    for (int e = 0; e < CPL; ++e) {
+      int xi[R], nxi[R];  // the terms and their negations: a sign costs one select
+#pragma unroll
+      for (int p = 0; p < R; ++p) {
+        // round half up, floor(x + 1/2), in one instruction; |x| < 2^28
+        asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(xi[p]) : "v"(a[p][e] * mul[p]));
+        nxi[p] = -xi[p];
+      }
+#pragma unroll
+      for (int qq = 0; qq < S; ++qq) {
+        const uint32_t w = ent[e][qq >> 1];
+        // word index of (line, block) and the sign of the entry's 16-bit half
+        const uint32_t word = (qq & 1) ? ((w >> 16) & 0x3fffu) : (w & 0x3fffu);
+        const bool neg = (qq & 1) ? ((int)w < 0) : ((w & 0x8000u) != 0u);
+#pragma unroll
+        for (int p = 0; p < R; ++p)
+          atomicAdd(reinterpret_cast<int*>(accb + (word << 2) + (uint32_t)(4 * S * (rb ^ p))), neg ? nxi[p] : xi[p]);
+      }
+    }
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
+  if (lane == 0 && bad) atomicOr(&wgbad, bad);
+  __syncthreads();
+  {
+    const int ef = __shfl(E, rbits, 64);
+    if (__shfl((int)live, rbits, 64) != 0) {
+#pragma unroll
+      for (int i = 0; i < FACC; ++i) {
+        const int idx = tid + i * NT;
+        if (idx < entries) facc[i] += ldexpf((float)iacc[idx], -ef);
+      }
+    }
+  }
+  const unsigned rows_bad = wgbad;
+  // write out: entry idx = b*64 + slot, slot = r*S + t -> At[row0 + r][lo_t + b]
+#pragma unroll
+  for (int i = 0; i < FACC; ++i) {
+    const int idx = tid + i * NT;
+    if (idx >= entries) continue;
+    const int b = idx >> 6, sl = idx & 63;
+    const int r = sl / S, t = sl % S;
+    const int64_t row = row0 + r;
+    if (r >= R || row >= m) continue;
+    const int lo = (int)(((int64_t)t * r1) / S), hi = (int)(((int64_t)(t + 1) * r1) / S);
+    const float v = ((rows_bad >> r) & 1u) ? __builtin_nanf("") : facc[i] * inv_sqrt_s;
+    if (b < hi - lo) out[row * ldo + lo + b] = v;
+  }
+}
+
 // Batched sketch pass over FP32 matrices with s = 4 (one problem per blockIdx.y).
 __global__ __launch_bounds__(512) void k_sketch_right_fx_batched(const SketchArgs* __restrict__ as) {
   const SketchArgs a = as[blockIdx.y];
@@ -498,6 +733,31 @@ static hipError_t launch_sr_fx_g(const void* A, int64_t lda, const float* scales
   return hipGetLastError();
 }
 
+bool sketch_right_ready16(int s, int r1) { return (s == 4 || s == 8 || s == 16) && (r1 + s - 1) / s <= 256; }
+
+template <typename TIN, int S, int CPL>
+static hipError_t launch_sr_fx2(const void* A, int64_t lda, const float* scales, int64_t ldsc, const int32_t* table,
+                                const uint16_t* ready, int* cmax, int64_t m, int64_t n, int r1, float* out,
+                                int64_t ldo, hipStream_t st) {
+  constexpr int NW = 8;
+  constexpr int64_t J = (int64_t)NW * 64 * CPL;
+  const int R = 64 / S;
+  const int wl = (r1 + S - 1) / S;  // <= 256: 32 FP32 accumulators per thread
+  const int64_t nch = (n + J - 1) / J;
+  size_t hl = (size_t)r1 * sizeof(int);
+  hipFuncSetAttribute((const void*)k_chunk_occupancy, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hl);
+  hipLaunchKernelGGL(k_chunk_occupancy, dim3((unsigned)nch), dim3(256), hl, st, table, n, S, r1, J, cmax);
+  size_t lds = (size_t)wl * 64 * sizeof(int);
+  dim3 grid((unsigned)((m + R - 1) / R));
+  bool vec_ok = (((uintptr_t)A) % (sizeof(TIN) * CPL) == 0) && (lda % CPL == 0);
+  float inv = 1.0f / sqrtf((float)S);
+  auto k = k_sketch_right_fx2<TIN, S, CPL, NW, 32>;
+  hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const TIN*)A, lda, scales, ldsc, ready, cmax, m, n, r1, wl, out,
+                     ldo, inv, vec_ok);
+  return hipGetLastError();
+}
+
 // FP32 accumulators per thread: ceil(wl*64/512) <= 40 keeps two column groups per
 // wave in flight; larger sketches hold one group to stay within 256 VGPRs.
 template <typename TIN, int S, int CPL>
@@ -533,6 +793,16 @@ static hipError_t launch_sr_dispatch(int s, const void* A, int64_t lda, const fl
                                      const int32_t* table, const uint32_t* ready, int* cmax, int64_t m, int64_t n,
                                      int r1, float* out, int64_t ldo, hipStream_t st) {
   const int wl = (r1 + s - 1) / s;
+  if (sketch_right_ready16(s, r1)) {  // the ready table is in the 16-bit form
+    if (!cmax) return hipErrorInvalidValue;
+    const uint16_t* r16 = reinterpret_cast<const uint16_t*>(ready);
+    switch (s) {
+      case 4: return launch_sr_fx2<TIN, 4, 2>(A, lda, scales, ldsc, table, r16, cmax, m, n, r1, out, ldo, st);
+      case 8: return launch_sr_fx2<TIN, 8, 4>(A, lda, scales, ldsc, table, r16, cmax, m, n, r1, out, ldo, st);
+      case 16: return launch_sr_fx2<TIN, 16, 4>(A, lda, scales, ldsc, table, r16, cmax, m, n, r1, out, ldo, st);
+      default: break;
+    }
+  }
   if (cmax && wl <= 640) {
     switch (s) {
       case 4: return launch_sr_fx<TIN, 4, 2>(A, lda, scales, ldsc, table, ready, cmax, m, n, r1, out, ldo, st);

@@ -91,6 +91,50 @@ def test_sketch_apply_fp8_block_scaled(m, n, s, r1):
     assert np.all(np.abs(got - ref) <= (n * s / r1 + 8) * 4 * U32 * mag + 1e-30)
 
 
+def _fixed_point_bound(A64, table, r1, s, J=2048):
+    """Rounding bound of the fixed-point scatter.  Within a column chunk of the pass
+    (2048 columns, or 1024 for s = 4, inside the 2048-column chunks used here) a row's
+    terms are rounded to half a grid step of at most c 2^-25 times the largest |a| of
+    the chunk over the row's band of 64/s rows (c = the chunk's largest bucket
+    occupancy; two bits of headroom and up to two bits kept from an earlier chunk's
+    scale).  Returns, per output, that bound summed over the output's terms, times
+    1/sqrt(s)."""
+    m, n = A64.shape
+    R = max(64 // s, 1)
+    buckets = (table.astype(np.int64) & 0x7FFFFFFF)
+    out = np.zeros((m, r1))
+    for c0 in range(0, n, J):
+        cols = slice(c0, min(n, c0 + J))
+        cnt = np.zeros((r1,))
+        for t in range(s):
+            cnt += np.bincount(buckets[cols, t], minlength=r1)
+        cmax = max(cnt.max(), 1.0)
+        half_step = np.zeros((m,))
+        for b0 in range(0, m, R):
+            half_step[b0:b0 + R] = np.max(np.abs(A64[b0:b0 + R, cols])) * cmax * 2.0 ** -25
+        out += half_step[:, None] * cnt[None, :]
+    return out / math.sqrt(s)
+
+
+@pytest.mark.parametrize("s,r1", [(8, 200), (4, 96), (16, 400), (8, 4000)])
+def test_sketch_apply_chunk_scales(s, r1):
+    """Column chunks of very different magnitude (and an all-zero chunk) over many
+    chunks: every fixed-point rescale and partial fold of the pass is exercised.
+    A term that is tiny next to the largest entry of its chunk is rounded on that
+    entry's grid, so the bound adds the fixed-point grid to the summation bound."""
+    rng = np.random.default_rng(s * 1000 + r1)
+    m, n = 40, 2048 * 13 + 77
+    A = rng.standard_normal((m, n))
+    f = np.repeat([1.0, 1e3, 1e-3, 1.0, 0.0, 1.0, 1.0, 2.0 ** 20, 1.0, 1.0, 1.0, 1.0, 1e-6, 1.0], 2048)[:n]
+    A = (A * f).astype(np.float32)
+    A64 = A.astype(np.float64)
+    ref, mag = _sketch_ref(A64, n, s, r1, 17)
+    got = rf.rf_sketch_apply(torch.from_numpy(A).to(DEV), r1, s, 17).cpu().numpy()
+    fx = _fixed_point_bound(A64, sk.sketch_table(n, s, r1, 17), r1, s)
+    tol = (n * s / r1 + 8) * 4 * U32 * mag + fx + 1e-30
+    assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
+
+
 @pytest.mark.parametrize("s", [1, 3, 8])
 def test_sketch_apply_nonfinite_rows(s):
     """A row holding NaN or Inf gives a non-finite row of AS (the FP32 sum over
