@@ -233,7 +233,7 @@ def main():
     sk = roof["sketch_f32"]
     achieved = sk["bytes"] / sk["seconds_per_call"]
     roofline = {"bound": "hbm", "achieved": achieved / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK, "traffic": sketch_traffic(), "kernel": "k_sketch_right_fx2<float,8,4,8,32>",
+                "frac": achieved / HBM_PEAK, "traffic": sketch_traffic(), "kernel": "k_sketch_right_fx2<float,8,4,8>",
                 "per_launch": "read A %d x %d FP32 + write At %d x %d FP32" % (m, n, m, l)}
     others = {}
     for name in ("qta_f32", "qta_bf16"):
@@ -517,7 +517,7 @@ def sketch_traffic():
     """HBM bytes per launch of the sketch kernel from the committed counter summary,
     valid only while the kernel source is the one the counters were taken on."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "sketch_right_fx_poly65k_counters.md")
+    path = os.path.join(ROOT, "profiles", "sketch_right_fx2_poly65k_counters.md")
     src = os.path.join(ROOT, "paper_2605_09755_amd", "csrc", "sketch.hip")
     try:
         text = open(path).read()

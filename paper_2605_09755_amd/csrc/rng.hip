@@ -50,9 +50,9 @@ __global__ void k_sketch_ready(const int32_t* __restrict__ table, int64_t n, int
   ready[idx] = ready_entry(table, idx, s, r1, cpl);
 }
 
-// Compact form for sketches of at most 256 lines per block: entry (j, q) is the
+// Compact form for sketches of at most 512 lines per block: entry (j, q) is the
 // 16-bit word sign<<15 | (b_local * 64 + t) of the same lane-permuted block t, the
-// LDS word index of the bucket line plus the block's slot (< 2^14).
+// LDS word index of the bucket line plus the block's slot (< 2^15).
 __global__ void k_sketch_ready16(const int32_t* __restrict__ table, int64_t n, int s, int r1, int cpl,
                                  uint16_t* __restrict__ ready) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

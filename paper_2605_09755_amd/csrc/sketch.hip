@@ -308,7 +308,8 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_right_fx(
 }
 
 // Two-workgroups-per-CU form of the fixed-point pass, for sketches of at most 256
-// lines per block (64 KiB of integer partials per band).  It keeps one column group
+// lines per block (64 KiB of integer partials per band; up to 512 lines run one
+// workgroup per CU).  It keeps one column group
 // per wave (J = 512 CPL columns per chunk) and reads the compact 16-bit table, so a
 // thread fits in 128 VGPRs and two workgroups share a CU: one streams its next
 // chunk from HBM while the other runs its atomics.
@@ -327,7 +328,7 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_right_fx(
 // so a fold needs one scale per thread.  One barrier per chunk (three rotating sets
 // of row maxima), a second only on a fold.
 template <typename TIN, int S, int CPL, int NW, int FACC>
-__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sketch_right_fx2(
+__device__ __forceinline__ void sketch_right_fx2_body(
     const TIN* __restrict__ A, int64_t lda, const float* __restrict__ scales, int64_t ldsc,
     const uint16_t* __restrict__ ready, const int* __restrict__ cmax, int64_t m, int64_t n, int r1, int wl,
     float* __restrict__ out, int64_t ldo, float inv_sqrt_s, bool vec_ok) {
@@ -345,11 +346,15 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   if (tid < 3 * R) (&rowmax[0][0])[tid] = 0u;
   if (tid == 0) wgbad = 0u;
   unsigned bad = 0u;  // bit r: row row0 + r holds a non-finite value
-  float facc[FACC];
-#pragma unroll
-  for (int i = 0; i < FACC; ++i) facc[i] = 0.f;
   __syncthreads();
   const int rbits = lane / S, tbits = lane % S;
+  // The thread's LDS words are (line wave + i NW, row rbits, block tbits): their FP32
+  // sums live in the output itself, which only this thread touches.
+  const int64_t orow = row0 + rbits;
+  const int blo = (int)(((int64_t)tbits * r1) / S), bw = (int)(((int64_t)(tbits + 1) * r1) / S) - blo;
+  float* const optr = out + (orow < m ? orow : 0) * ldo + blo;
+  const bool owrite = orow < m;
+  bool ofirst = true;  // the output holds no folded sums yet
   char* accb = reinterpret_cast<char*>(iacc);
   // Per-row fixed-point state, kept by lane r of every wave for row r (lanes >= R
   // hold copies of nothing in particular); every wave computes the same values.
@@ -466,15 +471,16 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
       const int ef = __shfl(E, rbits, 64);  // every word of this thread belongs to row rbits
       const bool lv = __shfl((int)live, rbits, 64) != 0;
       if (lv) {
-#pragma unroll
         for (int i = 0; i < FACC; ++i) {
           const int idx = tid + i * NT;
-          if (idx < entries) {
-            facc[i] += ldexpf((float)iacc[idx], -ef);
-            iacc[idx] = 0;
-          }
+          if (idx >= entries) break;
+          const int b = (tid >> 6) + i * NW;
+          const float v = ldexpf((float)iacc[idx], -ef);
+          iacc[idx] = 0;
+          if (owrite && b < bw) optr[b] = ofirst ? v : optr[b] + v;
         }
       }
+      ofirst = ofirst && !lv;
       live = false;
       __syncthreads();
     }
@@ -504,7 +510,7 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
       for (int qq = 0; qq < S; ++qq) {
         const uint32_t w = ent[e][qq >> 1];
         // word index of (line, block) and the sign of the entry's 16-bit half
-        const uint32_t word = (qq & 1) ? ((w >> 16) & 0x3fffu) : (w & 0x3fffu);
+        const uint32_t word = (qq & 1) ? ((w >> 16) & 0x7fffu) : (w & 0x7fffu);
         const bool neg = (qq & 1) ? ((int)w < 0) : ((w & 0x8000u) != 0u);
 #pragma unroll
         for (int p = 0; p < R; ++p)
@@ -516,30 +522,40 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4)))
   for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
   if (lane == 0 && bad) atomicOr(&wgbad, bad);
   __syncthreads();
-  {
-    const int ef = __shfl(E, rbits, 64);
-    if (__shfl((int)live, rbits, 64) != 0) {
-#pragma unroll
-      for (int i = 0; i < FACC; ++i) {
-        const int idx = tid + i * NT;
-        if (idx < entries) facc[i] += ldexpf((float)iacc[idx], -ef);
-      }
+  const int ef = __shfl(E, rbits, 64);
+  const bool lv = __shfl((int)live, rbits, 64) != 0;
+  const bool rbad = ((wgbad >> rbits) & 1u) != 0u;
+  if (owrite) {
+    for (int i = 0; i < FACC; ++i) {
+      const int idx = tid + i * NT;
+      if (idx >= entries) break;
+      const int b = (tid >> 6) + i * NW;
+      if (b >= bw) continue;
+      float v = lv ? ldexpf((float)iacc[idx], -ef) : 0.f;
+      if (!ofirst) v += optr[b];
+      optr[b] = rbad ? __builtin_nanf("") : v * inv_sqrt_s;
     }
   }
-  const unsigned rows_bad = wgbad;
-  // write out: entry idx = b*64 + slot, slot = r*S + t -> At[row0 + r][lo_t + b]
-#pragma unroll
-  for (int i = 0; i < FACC; ++i) {
-    const int idx = tid + i * NT;
-    if (idx >= entries) continue;
-    const int b = idx >> 6, sl = idx & 63;
-    const int r = sl / S, t = sl % S;
-    const int64_t row = row0 + r;
-    if (r >= R || row >= m) continue;
-    const int lo = (int)(((int64_t)t * r1) / S), hi = (int)(((int64_t)(t + 1) * r1) / S);
-    const float v = ((rows_bad >> r) & 1u) ? __builtin_nanf("") : facc[i] * inv_sqrt_s;
-    if (b < hi - lo) out[row * ldo + lo + b] = v;
-  }
+}
+
+// Up to 256 lines per block: 64 KiB of partials and 128 VGPRs, two workgroups per CU.
+template <typename TIN, int S, int CPL, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sketch_right_fx2(
+    const TIN* __restrict__ A, int64_t lda, const float* __restrict__ scales, int64_t ldsc,
+    const uint16_t* __restrict__ ready, const int* __restrict__ cmax, int64_t m, int64_t n, int r1, int wl,
+    float* __restrict__ out, int64_t ldo, float inv_sqrt_s, bool vec_ok) {
+  sketch_right_fx2_body<TIN, S, CPL, NW, 32>(A, lda, scales, ldsc, ready, cmax, m, n, r1, wl, out, ldo, inv_sqrt_s,
+                                             vec_ok);
+}
+
+// 257 to 512 lines per block: up to 128 KiB of partials, one workgroup per CU.
+template <typename TIN, int S, int CPL, int NW>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_sketch_right_fx2w(
+    const TIN* __restrict__ A, int64_t lda, const float* __restrict__ scales, int64_t ldsc,
+    const uint16_t* __restrict__ ready, const int* __restrict__ cmax, int64_t m, int64_t n, int r1, int wl,
+    float* __restrict__ out, int64_t ldo, float inv_sqrt_s, bool vec_ok) {
+  sketch_right_fx2_body<TIN, S, CPL, NW, 64>(A, lda, scales, ldsc, ready, cmax, m, n, r1, wl, out, ldo, inv_sqrt_s,
+                                             vec_ok);
 }
 
 // Batched sketch pass over FP32 matrices with s = 4 (one problem per blockIdx.y).
@@ -733,7 +749,7 @@ static hipError_t launch_sr_fx_g(const void* A, int64_t lda, const float* scales
   return hipGetLastError();
 }
 
-bool sketch_right_ready16(int s, int r1) { return (s == 4 || s == 8 || s == 16) && (r1 + s - 1) / s <= 256; }
+bool sketch_right_ready16(int s, int r1) { return (s == 4 || s == 8 || s == 16) && (r1 + s - 1) / s <= 512; }
 
 template <typename TIN, int S, int CPL>
 static hipError_t launch_sr_fx2(const void* A, int64_t lda, const float* scales, int64_t ldsc, const int32_t* table,
@@ -742,7 +758,7 @@ static hipError_t launch_sr_fx2(const void* A, int64_t lda, const float* scales,
   constexpr int NW = 8;
   constexpr int64_t J = (int64_t)NW * 64 * CPL;
   const int R = 64 / S;
-  const int wl = (r1 + S - 1) / S;  // <= 256: 32 FP32 accumulators per thread
+  const int wl = (r1 + S - 1) / S;  // <= 512: 32 (64) FP32 accumulators per thread up to 256 (512) lines
   const int64_t nch = (n + J - 1) / J;
   size_t hl = (size_t)r1 * sizeof(int);
   hipFuncSetAttribute((const void*)k_chunk_occupancy, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hl);
@@ -751,7 +767,7 @@ static hipError_t launch_sr_fx2(const void* A, int64_t lda, const float* scales,
   dim3 grid((unsigned)((m + R - 1) / R));
   bool vec_ok = (((uintptr_t)A) % (sizeof(TIN) * CPL) == 0) && (lda % CPL == 0);
   float inv = 1.0f / sqrtf((float)S);
-  auto k = k_sketch_right_fx2<TIN, S, CPL, NW, 32>;
+  auto k = wl <= 256 ? k_sketch_right_fx2<TIN, S, CPL, NW> : k_sketch_right_fx2w<TIN, S, CPL, NW>;
   hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const TIN*)A, lda, scales, ldsc, ready, cmax, m, n, r1, wl, out,
                      ldo, inv, vec_ok);

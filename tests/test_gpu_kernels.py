@@ -48,49 +48,6 @@ def _sketch_ref(A64, n, s, r1, seed):
     return me.sketch_right(A64, t, r1), np.asarray(np.abs(A64) @ np.abs(sk.sketch_matrix(t, r1).toarray()))
 
 
-@pytest.mark.parametrize("m,n,s,r1", [
-    (64, 256, 8, 100), (77, 1000, 8, 100), (130, 513, 4, 40), (100, 300, 1, 50), (100, 300, 2, 50),
-    (50, 200, 3, 20), (40, 700, 16, 64), (70, 2000, 1, 1000), (9, 5000, 8, 4000), (1, 1, 1, 1)])
-def test_sketch_apply_f32(m, n, s, r1):
-    rng = np.random.default_rng(m * 7 + n)
-    A = rng.standard_normal((m, n)).astype(np.float32)
-    A64 = A.astype(np.float64)
-    ref, mag = _sketch_ref(A64, n, s, r1, 11)
-    got = rf.rf_sketch_apply(torch.from_numpy(A).to(DEV), r1, s, 11).cpu().numpy()
-    tol = (n * s / r1 + 8) * 4 * U32 * mag + 1e-30
-    assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
-
-
-def test_sketch_apply_strided_rows():
-    rng = np.random.default_rng(5)
-    big = rng.standard_normal((60, 1030)).astype(np.float32)
-    A = torch.from_numpy(big).to(DEV)[:, 3:1003]          # ld = 1030, unaligned start
-    ref, mag = _sketch_ref(big[:, 3:1003].astype(np.float64), 1000, 8, 96, 3)
-    got = rf.rf_sketch_apply(A, 96, 8, 3).cpu().numpy()
-    assert np.all(np.abs(got - ref) <= 200 * U32 * mag + 1e-30)
-
-
-@pytest.mark.parametrize("m,n,s,r1", [(64, 512, 8, 100), (33, 333, 4, 60)])
-def test_sketch_apply_bf16(m, n, s, r1):
-    rng = np.random.default_rng(1)
-    At, A64 = bf16_round(rng.standard_normal((m, n)))
-    ref, mag = _sketch_ref(A64, n, s, r1, 12)
-    got = rf.rf_sketch_apply(At.to(DEV), r1, s, 12).cpu().numpy()
-    assert np.all(np.abs(got - ref) <= (n * s / r1 + 8) * 4 * U32 * mag + 1e-30)
-
-
-@pytest.mark.parametrize("m,n,s,r1", [(256, 384, 8, 64), (200, 300, 4, 40)])
-def test_sketch_apply_fp8_block_scaled(m, n, s, r1):
-    rng = np.random.default_rng(2)
-    X = rng.standard_normal((m, n)) * np.exp(rng.standard_normal((m, 1)))
-    codes, scales = fp8_ref.quantize_blocks(X)
-    A64 = fp8_ref.dequantize(codes, scales)
-    ref, mag = _sketch_ref(A64, n, s, r1, 13)
-    got = rf.rf_sketch_apply(torch.from_numpy(codes).to(DEV), r1, s, 13,
-                             scales=torch.from_numpy(scales).to(DEV)).cpu().numpy()
-    assert np.all(np.abs(got - ref) <= (n * s / r1 + 8) * 4 * U32 * mag + 1e-30)
-
-
 def _fixed_point_bound(A64, table, r1, s, J=2048):
     """Rounding bound of the fixed-point scatter.  Within a column chunk of the pass
     (2048 columns, or 1024 for s = 4, inside the 2048-column chunks used here) a row's
@@ -116,6 +73,56 @@ def _fixed_point_bound(A64, table, r1, s, J=2048):
     return out / math.sqrt(s)
 
 
+def _sketch_tol(A64, n, s, r1, seed, mag):
+    """FP32 summation bound plus the fixed-point grid of the scatter."""
+    return ((n * s / r1 + 8) * 4 * U32 * mag + _fixed_point_bound(A64, sk.sketch_table(n, s, r1, seed), r1, s)
+            + 1e-30)
+
+
+@pytest.mark.parametrize("m,n,s,r1", [
+    (64, 256, 8, 100), (77, 1000, 8, 100), (130, 513, 4, 40), (100, 300, 1, 50), (100, 300, 2, 50),
+    (50, 200, 3, 20), (40, 700, 16, 64), (70, 2000, 1, 1000), (9, 5000, 8, 4000), (1, 1, 1, 1),
+    (20, 3000, 4, 1500), (17, 7000, 16, 6000), (33, 6000, 8, 5000)])
+def test_sketch_apply_f32(m, n, s, r1):
+    rng = np.random.default_rng(m * 7 + n)
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    A64 = A.astype(np.float64)
+    ref, mag = _sketch_ref(A64, n, s, r1, 11)
+    got = rf.rf_sketch_apply(torch.from_numpy(A).to(DEV), r1, s, 11).cpu().numpy()
+    tol = _sketch_tol(A64, n, s, r1, 11, mag)
+    assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
+
+
+def test_sketch_apply_strided_rows():
+    rng = np.random.default_rng(5)
+    big = rng.standard_normal((60, 1030)).astype(np.float32)
+    A = torch.from_numpy(big).to(DEV)[:, 3:1003]          # ld = 1030, unaligned start
+    ref, mag = _sketch_ref(big[:, 3:1003].astype(np.float64), 1000, 8, 96, 3)
+    got = rf.rf_sketch_apply(A, 96, 8, 3).cpu().numpy()
+    assert np.all(np.abs(got - ref) <= _sketch_tol(big[:, 3:1003].astype(np.float64), 1000, 8, 96, 3, mag))
+
+
+@pytest.mark.parametrize("m,n,s,r1", [(64, 512, 8, 100), (33, 333, 4, 60), (40, 3000, 8, 3000)])
+def test_sketch_apply_bf16(m, n, s, r1):
+    rng = np.random.default_rng(1)
+    At, A64 = bf16_round(rng.standard_normal((m, n)))
+    ref, mag = _sketch_ref(A64, n, s, r1, 12)
+    got = rf.rf_sketch_apply(At.to(DEV), r1, s, 12).cpu().numpy()
+    assert np.all(np.abs(got - ref) <= _sketch_tol(A64, n, s, r1, 12, mag))
+
+
+@pytest.mark.parametrize("m,n,s,r1", [(256, 384, 8, 64), (200, 300, 4, 40), (130, 3100, 8, 3000)])
+def test_sketch_apply_fp8_block_scaled(m, n, s, r1):
+    rng = np.random.default_rng(2)
+    X = rng.standard_normal((m, n)) * np.exp(rng.standard_normal((m, 1)))
+    codes, scales = fp8_ref.quantize_blocks(X)
+    A64 = fp8_ref.dequantize(codes, scales)
+    ref, mag = _sketch_ref(A64, n, s, r1, 13)
+    got = rf.rf_sketch_apply(torch.from_numpy(codes).to(DEV), r1, s, 13,
+                             scales=torch.from_numpy(scales).to(DEV)).cpu().numpy()
+    assert np.all(np.abs(got - ref) <= _sketch_tol(A64, n, s, r1, 13, mag))
+
+
 @pytest.mark.parametrize("s,r1", [(8, 200), (4, 96), (16, 400), (8, 4000)])
 def test_sketch_apply_chunk_scales(s, r1):
     """Column chunks of very different magnitude (and an all-zero chunk) over many
@@ -130,8 +137,7 @@ def test_sketch_apply_chunk_scales(s, r1):
     A64 = A.astype(np.float64)
     ref, mag = _sketch_ref(A64, n, s, r1, 17)
     got = rf.rf_sketch_apply(torch.from_numpy(A).to(DEV), r1, s, 17).cpu().numpy()
-    fx = _fixed_point_bound(A64, sk.sketch_table(n, s, r1, 17), r1, s)
-    tol = (n * s / r1 + 8) * 4 * U32 * mag + fx + 1e-30
+    tol = _sketch_tol(A64, n, s, r1, 17, mag)
     assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
 
 
@@ -150,7 +156,7 @@ def test_sketch_apply_nonfinite_rows(s):
     A64 = np.where(np.isfinite(A), A, 0.0).astype(np.float64)
     ref, mag = _sketch_ref(A64, n, s, r1, 31)
     got = rf.rf_sketch_apply(torch.from_numpy(A).to(DEV), r1, s, 31).cpu().numpy()
-    tol = (n * s / r1 + 8) * 4 * U32 * mag + 1e-30
+    tol = _sketch_tol(A64, n, s, r1, 31, mag)
     assert np.all(np.abs(got[clean] - ref[clean]) <= tol[clean])
     for i in np.flatnonzero(~clean):
         assert not np.all(np.isfinite(got[i]))
