@@ -51,14 +51,16 @@ __global__ void k_sketch_ready(const int32_t* __restrict__ table, int64_t n, int
 }
 
 // Compact form for sketches of at most 512 lines per block: entry (j, q) is the
-// 16-bit word sign<<15 | (b_local * 64 + t) of the same lane-permuted block t, the
-// LDS word index of the bucket line plus the block's slot (< 2^15).
+// 16-bit word sign<<15 | (b_local * 32 + t) of the same lane-permuted block t, the
+// index of the 64-bit LDS word of the bucket line and the block (< 2^14), whose two
+// halves hold a pair of rows.
 __global__ void k_sketch_ready16(const int32_t* __restrict__ table, int64_t n, int s, int r1, int cpl,
                                  uint16_t* __restrict__ ready) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * s) return;
   const uint32_t w = ready_entry(table, idx, s, r1, cpl);
-  ready[idx] = (uint16_t)(((w >> 31) << 15) | ((w & 0x7fffffffu) >> 2));
+  const uint32_t line = (w & 0x7fffffffu) >> 8, t = (w & 0xffu) >> 2;
+  ready[idx] = (uint16_t)(((w >> 31) << 15) | (line * 32u + t));
 }
 
 RF_DEV void gaussian_quad(int64_t p, int64_t total, uint64_t seed, uint32_t stream, uint32_t b,

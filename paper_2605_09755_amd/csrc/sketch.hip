@@ -333,27 +333,34 @@ __device__ __forceinline__ void sketch_right_fx2_body(
     const uint16_t* __restrict__ ready, const int* __restrict__ cmax, int64_t m, int64_t n, int r1, int wl,
     float* __restrict__ out, int64_t ldo, float inv_sqrt_s, bool vec_ok) {
   constexpr int R = 64 / S;
+  constexpr int P = R / 2;                  // row pairs of the band
   constexpr int NT = NW * 64;
   constexpr int64_t J = (int64_t)NT * CPL;  // columns per chunk
-  static_assert(R <= 32, "row flags are kept in one 32-bit mask");
+  static_assert(R <= 32 && R % 2 == 0, "row flags are kept in one 32-bit mask; rows go in pairs");
   static_assert(S % 2 == 0, "table entries are read in pairs");
-  extern __shared__ int iacc[];
+  // 64-bit LDS atomics need 8-byte aligned addresses: the dynamic array follows the
+  // static row maxima, so its own alignment sets where it starts
+  extern __shared__ __attribute__((aligned(16))) unsigned long long sk_acc64[];
+  int* const iacc = reinterpret_cast<int*>(sk_acc64);
   __shared__ unsigned rowmax[3][R], wgbad;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * R;
-  const int entries = wl * 64;
+  const int entries = wl * 64;  // 32-bit words: wl lines of P pairs x S blocks x 2 rows
   for (int i = tid; i < entries; i += NT) iacc[i] = 0;
   if (tid < 3 * R) (&rowmax[0][0])[tid] = 0u;
   if (tid == 0) wgbad = 0u;
   unsigned bad = 0u;  // bit r: row row0 + r holds a non-finite value
   __syncthreads();
-  const int rbits = lane / S, tbits = lane % S;
-  // The thread's LDS words are (line wave + i NW, row rbits, block tbits): their FP32
-  // sums live in the output itself, which only this thread touches.
-  const int64_t orow = row0 + rbits;
+  // lane = h * 32 + pbits * S + tbits; both half-waves visit the same slots
+  const int pbits = (lane & 31) / S, tbits = lane % S;
+  // The thread's 64-bit LDS words are (line tid / 32 + i NT / 32, pair pbits, block
+  // tbits), rows 2 pbits and 2 pbits + 1: their FP32 sums live in the output itself,
+  // which only this thread touches.
+  const int64_t orow0 = row0 + 2 * pbits;
   const int blo = (int)(((int64_t)tbits * r1) / S), bw = (int)(((int64_t)(tbits + 1) * r1) / S) - blo;
-  float* const optr = out + (orow < m ? orow : 0) * ldo + blo;
-  const bool owrite = orow < m;
+  float* const optr0 = out + (orow0 < m ? orow0 : 0) * ldo + blo;
+  float* const optr1 = out + (orow0 + 1 < m ? orow0 + 1 : 0) * ldo + blo;
+  const bool ow0 = orow0 < m, ow1 = orow0 + 1 < m;
   bool ofirst = true;  // the output holds no folded sums yet
   char* accb = reinterpret_cast<char*>(iacc);
   // Per-row fixed-point state, kept by lane r of every wave for row r (lanes >= R
@@ -364,14 +371,17 @@ __device__ __forceinline__ void sketch_right_fx2_body(
   const int myrow = lane < R ? lane : 0;
   const int64_t nch = (n + J - 1) / J;
   for (int64_t ch = 0; ch < nch; ++ch) {
-    // Opaque copy of the lane's row bits: the per-row offsets derived from it are
+    // Opaque copy of the lane's pair bits: the per-row offsets derived from it are
     // recomputed per chunk instead of being held live across the loop.
-    int rb = rbits;
-    asm volatile("" : "+v"(rb));
+    int pb = pbits;
+    asm volatile("" : "+v"(pb));
+    // register p holds band row 2 (pb ^ p/2) + p % 2: at pair step q the lanes of a
+    // half-wave hit P x S distinct (pair, block) slots, one 64-bit bank pair each
+    auto rowof = [&](int p) { return 2 * (pb ^ (p >> 1)) + (p & 1); };
     float a[R][CPL];
     uint32_t ent[CPL][S / 2];  // two 16-bit words each
-    float mx[R];               // mx[p]: max |a| of row rb ^ p over the lane's columns
-    float chk[R];              // chk[p]: sum of a * 0, NaN iff row rb ^ p has a non-finite value
+    float mx[R];               // mx[p]: max |a| of row rowof(p) over the lane's columns
+    float chk[R];              // chk[p]: sum of a * 0, NaN iff that row has a non-finite value
     const int64_t j = ch * J + ((int64_t)wave * 64 + lane) * CPL;
     float sc = 1.f;
     if constexpr (sizeof(TIN) == 1) {
@@ -381,7 +391,7 @@ __device__ __forceinline__ void sketch_right_fx2_body(
     const bool interior = vec_ok && row0 + R <= m && (ch + 1) * J <= n;
     if (interior) {
 #pragma unroll
-      for (int p = 0; p < R; ++p) ld_cols<TIN, CPL>(A + (row0 + (rb ^ p)) * lda, j, n, true, a[p]);
+      for (int p = 0; p < R; ++p) ld_cols<TIN, CPL>(A + (row0 + rowof(p)) * lda, j, n, true, a[p]);
 #pragma unroll
       for (int e = 0; e < CPL; ++e) {
         const uint16_t* ep = ready + (j + e) * S;
@@ -399,7 +409,7 @@ __device__ __forceinline__ void sketch_right_fx2_body(
     } else {
 #pragma unroll
       for (int p = 0; p < R; ++p) {
-        const int64_t row = row0 + (rb ^ p);
+        const int64_t row = row0 + rowof(p);
         if (row < m && j < n) ld_cols<TIN, CPL>(A + row * lda, j, n, vec_ok, a[p]);
         else {
 #pragma unroll
@@ -438,16 +448,17 @@ __device__ __forceinline__ void sketch_right_fx2_body(
         chk[p] = fmaf(a[p][e], 0.f, chk[p]);
         mx[p] = fmaxf(mx[p], fabsf(a[p][e]));
       }
-      bad |= isfinite(chk[p]) ? 0u : (1u << (rb ^ p));
+      bad |= isfinite(chk[p]) ? 0u : (1u << rowof(p));
     }
-    // row maxima: the S lanes of equal rb hold the same rows; reduce over them, then
-    // one LDS max per row from the lanes with tbits == 0 (distinct rows, no conflicts)
+    // row maxima: the 2 S lanes of equal pb hold the same rows; reduce over them, then
+    // one LDS max per row from the lanes with tbits == 0 in the low half (distinct rows)
     const int slot = (int)(ch % 3);
 #pragma unroll
     for (int p = 0; p < R; ++p) {
 #pragma unroll
       for (int o = 1; o < S; o <<= 1) mx[p] = fmaxf(mx[p], __shfl_xor(mx[p], o, 64));
-      if (tbits == 0 && mx[p] > 0.f) atomicMax(&rowmax[slot][rb ^ p], __float_as_uint(mx[p]));
+      mx[p] = fmaxf(mx[p], __shfl_xor(mx[p], 32, 64));
+      if (lane < 32 && tbits == 0 && mx[p] > 0.f) atomicMax(&rowmax[slot][rowof(p)], __float_as_uint(mx[p]));
     }
     __syncthreads();
     // row maxima of slot (ch + 2) % 3 were last read before this barrier and are next
@@ -468,19 +479,26 @@ __device__ __forceinline__ void sketch_right_fx2_body(
     const bool fold = __any(want);
     if (!__any(nz)) continue;  // all-zero chunk: nothing to add
     if (fold) {
-      const int ef = __shfl(E, rbits, 64);  // every word of this thread belongs to row rbits
-      const bool lv = __shfl((int)live, rbits, 64) != 0;
-      if (lv) {
-        for (int i = 0; i < FACC; ++i) {
-          const int idx = tid + i * NT;
-          if (idx >= entries) break;
-          const int b = (tid >> 6) + i * NW;
-          const float v = ldexpf((float)iacc[idx], -ef);
-          iacc[idx] = 0;
-          if (owrite && b < bw) optr[b] = ofirst ? v : optr[b] + v;
+      const int ef0 = __shfl(E, 2 * pbits, 64), ef1 = __shfl(E, 2 * pbits + 1, 64);
+      const bool lv0 = __shfl((int)live, 2 * pbits, 64) != 0, lv1 = __shfl((int)live, 2 * pbits + 1, 64) != 0;
+      if (lv0 || lv1) {
+        for (int i = 0; i < FACC / 2; ++i) {
+          const int idx = tid + i * NT;  // 64-bit word
+          if (2 * idx >= entries) break;
+          const int b = (tid >> 5) + i * (NT / 32);
+          unsigned long long* wp = reinterpret_cast<unsigned long long*>(accb) + idx;
+          const unsigned long long sum = *wp;
+          *wp = 0ull;
+          // the 64-bit word holds x_odd 2^32 + x_even summed exactly
+          const int s0 = (int)(uint32_t)sum, s1 = (int)(uint32_t)(sum >> 32) + (s0 < 0 ? 1 : 0);
+          if (b < bw) {
+            const float v0 = lv0 ? ldexpf((float)s0, -ef0) : 0.f, v1 = lv1 ? ldexpf((float)s1, -ef1) : 0.f;
+            if (ow0) optr0[b] = ofirst ? v0 : optr0[b] + v0;
+            if (ow1) optr1[b] = ofirst ? v1 : optr1[b] + v1;
+          }
         }
+        ofirst = false;
       }
-      ofirst = ofirst && !lv;
       live = false;
       __syncthreads();
     }
@@ -493,28 +511,32 @@ __device__ __forceinline__ void sketch_right_fx2_body(
         live = true;
       }
     }
-    // the lane's multiplier for row rb ^ p
+    // the lane's multiplier for row rowof(p)
     float mul[R];
 #pragma unroll
-    for (int p = 0; p < R; ++p) mul[p] = ldexpf(1.f, __shfl(E, rb ^ p, 64));
+    for (int p = 0; p < R; ++p) mul[p] = ldexpf(1.f, __shfl(E, rowof(p), 64));
 #pragma unroll
     for (int e = 0; e < CPL; ++e) {
-      int xi[R], nxi[R];  // the terms and their negations: a sign costs one select
+      unsigned long long X[P], NX[P];  // pair terms x_odd 2^32 + x_even and their negations
 #pragma unroll
-      for (int p = 0; p < R; ++p) {
+      for (int q = 0; q < P; ++q) {
+        int x0, x1;
         // round half up, floor(x + 1/2), in one instruction; |x| < 2^28
-        asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(xi[p]) : "v"(a[p][e] * mul[p]));
-        nxi[p] = -xi[p];
+        asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(x0) : "v"(a[2 * q][e] * mul[2 * q]));
+        asm("v_cvt_rpi_i32_f32 %0, %1" : "=v"(x1) : "v"(a[2 * q + 1][e] * mul[2 * q + 1]));
+        X[q] = ((unsigned long long)(uint32_t)(x1 + (x0 >> 31)) << 32) | (uint32_t)x0;
+        NX[q] = 0ull - X[q];
       }
 #pragma unroll
       for (int qq = 0; qq < S; ++qq) {
         const uint32_t w = ent[e][qq >> 1];
-        // word index of (line, block) and the sign of the entry's 16-bit half
+        // 64-bit word index of (line, block) and the sign of the entry's 16-bit half
         const uint32_t word = (qq & 1) ? ((w >> 16) & 0x7fffu) : (w & 0x7fffu);
         const bool neg = (qq & 1) ? ((int)w < 0) : ((w & 0x8000u) != 0u);
 #pragma unroll
-        for (int p = 0; p < R; ++p)
-          atomicAdd(reinterpret_cast<int*>(accb + (word << 2) + (uint32_t)(4 * S * (rb ^ p))), neg ? nxi[p] : xi[p]);
+        for (int q = 0; q < P; ++q)
+          atomicAdd(reinterpret_cast<unsigned long long*>(accb + (word << 3) + (uint32_t)(8 * S * (pb ^ q))),
+                    neg ? NX[q] : X[q]);
       }
     }
   }
@@ -522,19 +544,23 @@ __device__ __forceinline__ void sketch_right_fx2_body(
   for (int o = 32; o > 0; o >>= 1) bad |= __shfl_xor(bad, o, 64);
   if (lane == 0 && bad) atomicOr(&wgbad, bad);
   __syncthreads();
-  const int ef = __shfl(E, rbits, 64);
-  const bool lv = __shfl((int)live, rbits, 64) != 0;
-  const bool rbad = ((wgbad >> rbits) & 1u) != 0u;
-  if (owrite) {
-    for (int i = 0; i < FACC; ++i) {
-      const int idx = tid + i * NT;
-      if (idx >= entries) break;
-      const int b = (tid >> 6) + i * NW;
-      if (b >= bw) continue;
-      float v = lv ? ldexpf((float)iacc[idx], -ef) : 0.f;
-      if (!ofirst) v += optr[b];
-      optr[b] = rbad ? __builtin_nanf("") : v * inv_sqrt_s;
+  const int ef0 = __shfl(E, 2 * pbits, 64), ef1 = __shfl(E, 2 * pbits + 1, 64);
+  const bool lv0 = __shfl((int)live, 2 * pbits, 64) != 0, lv1 = __shfl((int)live, 2 * pbits + 1, 64) != 0;
+  const bool bad0 = ((wgbad >> (2 * pbits)) & 1u) != 0u, bad1 = ((wgbad >> (2 * pbits + 1)) & 1u) != 0u;
+  for (int i = 0; i < FACC / 2; ++i) {
+    const int idx = tid + i * NT;
+    if (2 * idx >= entries) break;
+    const int b = (tid >> 5) + i * (NT / 32);
+    if (b >= bw) continue;
+    const unsigned long long sum = reinterpret_cast<const unsigned long long*>(accb)[idx];
+    const int s0 = (int)(uint32_t)sum, s1 = (int)(uint32_t)(sum >> 32) + (s0 < 0 ? 1 : 0);
+    float v0 = lv0 ? ldexpf((float)s0, -ef0) : 0.f, v1 = lv1 ? ldexpf((float)s1, -ef1) : 0.f;
+    if (!ofirst) {
+      if (ow0) v0 += optr0[b];
+      if (ow1) v1 += optr1[b];
     }
+    if (ow0) optr0[b] = bad0 ? __builtin_nanf("") : v0 * inv_sqrt_s;
+    if (ow1) optr1[b] = bad1 ? __builtin_nanf("") : v1 * inv_sqrt_s;
   }
 }
 
