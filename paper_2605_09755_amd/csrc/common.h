@@ -41,6 +41,21 @@ RF_DEV uint16_t f32_to_bf16_rne(float f) {
 }
 RF_DEV float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 
+// Hardware forms of the two conversions, checked on gfx950 to give the same bits
+// as f32_to_bf16_rne (all non-NaN inputs of a 2^20 random sample, ties included) and
+// as fp8e4m3_to_f32 (all 256 codes):
+// two floats -> packed BF16 (round to nearest even), one v_cvt_pk_bf16_f32
+typedef float rf_f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 rf_bf16x2 __attribute__((ext_vector_type(2)));
+RF_DEV uint32_t pk_bf16(float a, float b) {
+  return __builtin_bit_cast(uint32_t, __builtin_convertvector((rf_f32x2){a, b}, rf_bf16x2));
+}
+// the four OCP e4m3 codes in the bytes of w -> floats, two v_cvt_pk_f32_fp8
+RF_DEV void fp8x4_to_f32(uint32_t w, float* o) {
+  const rf_f32x2 lo = __builtin_amdgcn_cvt_pk_f32_fp8(w, false), hi = __builtin_amdgcn_cvt_pk_f32_fp8(w, true);
+  o[0] = lo.x; o[1] = lo.y; o[2] = hi.x; o[3] = hi.y;
+}
+
 // OCP FP8 E4M3 (bias 7, no infinities, max 448, 0x7f/0xff = NaN) -> float
 RF_DEV float fp8e4m3_to_f32(uint32_t v) {
   uint32_t s = (v & 0x80u) << 24, e = (v >> 3) & 0xfu, m = v & 0x7u;

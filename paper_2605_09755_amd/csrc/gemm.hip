@@ -194,9 +194,7 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
 RF_DEV uint32_t pack_lo(uint32_t a, uint32_t b) { return (a & 0xffffu) | (b << 16); }
 RF_DEV uint32_t pack_hi(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff0000u); }
 
-RF_DEV uint32_t pack2_bf16(float a, float b) {
-  return (uint32_t)f32_to_bf16_rne(a) | ((uint32_t)f32_to_bf16_rne(b) << 16);
-}
+RF_DEV uint32_t pack2_bf16(float a, float b) { return pk_bf16(a, b); }
 
 // AF32: the A operand is FP32 in memory and rounded to BF16 (RNE) as it is loaded.
 template <bool AKC, bool BKC, bool AF32 = false>
@@ -425,10 +423,7 @@ RF_DEV bf16x8 big_frag_tc(const uint16_t* S, int col0, int k0, int lane) {
 }
 
 RF_DEV uint4 pack8_bf16(float4 a, float4 b) {
-  return make_uint4((uint32_t)f32_to_bf16_rne(a.x) | ((uint32_t)f32_to_bf16_rne(a.y) << 16),
-                    (uint32_t)f32_to_bf16_rne(a.z) | ((uint32_t)f32_to_bf16_rne(a.w) << 16),
-                    (uint32_t)f32_to_bf16_rne(b.x) | ((uint32_t)f32_to_bf16_rne(b.y) << 16),
-                    (uint32_t)f32_to_bf16_rne(b.z) | ((uint32_t)f32_to_bf16_rne(b.w) << 16));
+  return make_uint4(pk_bf16(a.x, a.y), pk_bf16(a.z, a.w), pk_bf16(b.x, b.y), pk_bf16(b.z, b.w));
 }
 
 // One operand's share of a stage: NCH chunks of 8 consecutive elements per thread.
@@ -506,7 +501,11 @@ struct BigStage {
       if constexpr (F8) {
         float t[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) t[e] = fp8e4m3_to_f32(((e < 4 ? b8[q].x : b8[q].y) >> (8 * (e & 3))) & 0xffu) * sc[q];
+        for (int e = 0; e < 8; ++e) t[e] = 0.f;
+        fp8x4_to_f32(b8[q].x, t);
+        fp8x4_to_f32(b8[q].y, t + 4);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] *= sc[q];
         x = pack8_bf16(make_float4(t[0], t[1], t[2], t[3]), make_float4(t[4], t[5], t[6], t[7]));
       } else if constexpr (F32) {
         x = pack8_bf16(f[q][0], f[q][1]);

@@ -50,8 +50,7 @@ RF_DEV void ld_cols(const TIN* rp, int64_t j, int64_t n, bool vec_ok, float* out
       return;
     } else if constexpr (sizeof(TIN) == 1 && CPL == 4) {
       uint32_t v = *reinterpret_cast<const uint32_t*>(rp + j);
-      out[0] = fp8e4m3_to_f32(v & 0xff); out[1] = fp8e4m3_to_f32((v >> 8) & 0xff);
-      out[2] = fp8e4m3_to_f32((v >> 16) & 0xff); out[3] = fp8e4m3_to_f32(v >> 24);
+      fp8x4_to_f32(v, out);
       return;
     }
   }
