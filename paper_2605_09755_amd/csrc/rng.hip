@@ -54,13 +54,17 @@ __global__ void k_sketch_ready(const int32_t* __restrict__ table, int64_t n, int
 // 16-bit word sign<<15 | (b_local * 32 + t) of the same lane-permuted block t, the
 // index of the 64-bit LDS word of the bucket line and the block (< 2^14), whose two
 // halves hold a pair of rows.
+RF_DEV uint16_t ready16_entry(const int32_t* __restrict__ table, int64_t idx, int s, int r1, int cpl) {
+  const uint32_t w = ready_entry(table, idx, s, r1, cpl);
+  const uint32_t line = (w & 0x7fffffffu) >> 8, t = (w & 0xffu) >> 2;
+  return (uint16_t)(((w >> 31) << 15) | (line * 32u + t));
+}
+
 __global__ void k_sketch_ready16(const int32_t* __restrict__ table, int64_t n, int s, int r1, int cpl,
                                  uint16_t* __restrict__ ready) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= n * s) return;
-  const uint32_t w = ready_entry(table, idx, s, r1, cpl);
-  const uint32_t line = (w & 0x7fffffffu) >> 8, t = (w & 0xffu) >> 2;
-  ready[idx] = (uint16_t)(((w >> 31) << 15) | (line * 32u + t));
+  ready[idx] = ready16_entry(table, idx, s, r1, cpl);
 }
 
 RF_DEV void gaussian_quad(int64_t p, int64_t total, uint64_t seed, uint32_t stream, uint32_t b,
@@ -93,11 +97,14 @@ __global__ void k_sketch_table_batched(const RngArgs* __restrict__ as) {
        idx += (int64_t)gridDim.x * blockDim.x)
     a.table[idx] = sketch_entry(idx, a.s, a.r1, a.seed, 0, a.b);
 }
+// Batched ready tables in the compact 16-bit form (the batched pass has s = 4 and
+// sketches of at most 1280 columns, 320 lines per block).
 __global__ void k_sketch_ready_batched(const RngArgs* __restrict__ as) {
   const RngArgs a = as[blockIdx.y];
+  uint16_t* const r16 = reinterpret_cast<uint16_t*>(a.ready);
   for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < a.n * a.s;
        idx += (int64_t)gridDim.x * blockDim.x)
-    a.ready[idx] = ready_entry(a.table, idx, a.s, a.r1, a.cpl);
+    r16[idx] = ready16_entry(a.table, idx, a.s, a.r1, a.cpl);
 }
 __global__ void k_gaussian_batched(const RngArgs* __restrict__ as) {
   const RngArgs a = as[blockIdx.y];

@@ -583,13 +583,16 @@ __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(2, 2)))
                                              vec_ok);
 }
 
-// Batched sketch pass over FP32 matrices with s = 4 (one problem per blockIdx.y).
-__global__ __launch_bounds__(512) void k_sketch_right_fx_batched(const SketchArgs* __restrict__ as) {
+// Batched sketch pass over FP32 matrices with s = 4 (one problem per blockIdx.y): the
+// paired-row fixed-point pass, 16-bit tables, chunks of 1024 columns.
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4, 4))) void k_sketch_right_fx_batched(
+    const SketchArgs* __restrict__ as) {
   const SketchArgs a = as[blockIdx.y];
   constexpr int R = 64 / 4;
   if ((int64_t)blockIdx.x * R >= a.m) return;
-  sketch_right_fx_body<float, 4, 2, 8, 2, 40>(a.A, a.lda, nullptr, 0, a.ready, a.cmax, a.m, a.n, a.r1,
-                                              (a.r1 + 3) / 4, a.out, a.ldo, 0.5f, a.vec_ok != 0, blockIdx.x);
+  sketch_right_fx2_body<float, 4, 2, 8, 64>(a.A, a.lda, nullptr, 0, reinterpret_cast<const uint16_t*>(a.ready),
+                                            a.cmax, a.m, a.n, a.r1, (a.r1 + 3) / 4, a.out, a.ldo, 0.5f,
+                                            a.vec_ok != 0);
 }
 
 // Maximum bucket occupancy per column chunk (over the s blocks): one workgroup per chunk.
@@ -621,10 +624,10 @@ __global__ __launch_bounds__(256) void k_chunk_occupancy(const int32_t* __restri
   chunk_occupancy_body(table, n, s, r1, J, cmax, blockIdx.x);
 }
 
-// Batched occupancy for the s = 4 batched sketch pass (chunk J = 8 * 2 * 64 * 2).
+// Batched occupancy for the s = 4 batched sketch pass (chunk J = 512 threads x 2 columns).
 __global__ __launch_bounds__(256) void k_chunk_occupancy_batched(const SketchArgs* __restrict__ as) {
   const SketchArgs a = as[blockIdx.y];
-  constexpr int64_t J = 8 * 2 * 64 * 2;
+  constexpr int64_t J = 512 * 2;
   if ((int64_t)blockIdx.x * J >= a.n) return;
   chunk_occupancy_body(a.table, a.n, 4, a.r1, J, a.cmax, blockIdx.x);
 }
@@ -816,7 +819,7 @@ size_t sketch_right_cmax_ints(int64_t n) { return (size_t)(n / 1024 + 16); }
 hipError_t launch_sketch_right_batched(const SketchArgs* as, int count, int64_t mmax, int64_t nmax, int r1max,
                                        hipStream_t st) {
   if (count == 0) return hipSuccess;
-  constexpr int64_t J = 8 * 2 * 64 * 2;
+  constexpr int64_t J = 512 * 2;
   const size_t hl = (size_t)r1max * sizeof(int);
   (void)hipFuncSetAttribute((const void*)k_chunk_occupancy_batched, hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)hl);
