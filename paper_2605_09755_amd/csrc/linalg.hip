@@ -201,12 +201,15 @@ static int cus() {
   return n;
 }
 
+// Split-K parts: about eight workgroups per CU in all (so that the uneven last share
+// of a CU costs little), each part at least 256 rows of K, at most 128 parts.
 static int gram_splits(int64_t K, int64_t M, int64_t N, int sym) {
   int64_t ntm = (M + GT - 1) / GT, ntn = (N + GT - 1) / GT;
   int64_t tiles = sym ? ntm * (ntm + 1) / 2 : ntm * ntn;
-  int s = 1;
-  while (tiles * s < 2 * cus() && K / (2 * s) >= 256 && s < 128) s *= 2;
-  return s;
+  int64_t s = (8 * (int64_t)cus() + tiles / 2) / tiles;
+  if (s > K / 256) s = K / 256;
+  if (s > 128) s = 128;
+  return s < 1 ? 1 : (int)s;
 }
 
 size_t gram_partial_doubles(int64_t K, int64_t M, int64_t N) {
