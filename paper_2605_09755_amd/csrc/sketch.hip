@@ -7,12 +7,16 @@
 // Right sketch design (gfx950): a workgroup owns a band of R = 64/s rows and
 // keeps their whole At rows on chip in LDS.  Lanes own columns; every lane
 // reads its columns of all R rows (coalesced across lanes) and its columns'
-// s table entries once.  At step (p, qq) lane c adds row rbits^p into block
-// tbits^qq (c = rbits*s + tbits), so the 64 lanes of an instruction hit 64
-// distinct (row, block) slots; with LDS laid out [bucket-in-block][row][block]
-// each slot is its own bank: the ds_add_f32 scatter is conflict-free.  Per
-// (element, block) pair the kernel spends one v_add (row offset), one v_xor
-// (sign) and one ds_add_f32.
+// s table entries once, and the lanes of an instruction visit distinct
+// (row, block) slots, so the LDS scatter is free of bank conflicts.  Three
+// forms, in the order they are chosen:
+//  * k_sketch_right_fx2 / _fx2w (s = 4, 8, 16; at most 256 / 512 lines per
+//    block): fixed point with a scale per row, pairs of rows added by one 64-bit
+//    LDS atomic, partials folded into the output only when needed;
+//  * k_sketch_right_fx (at most 640 lines): fixed point with one scale per band
+//    and chunk, folded into register accumulators after every chunk;
+//  * k_sketch_right (s = 1 or 2, or larger sketches): LDS float atomics;
+//  * k_sketch_right_atomic (any other s): global atomics, the generic fallback.
 #include "common.h"
 #include "kernels.h"
 
@@ -150,7 +154,7 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_right(
   }
 }
 
-// ---- fixed-point variant (the one used) -------------------------------------------------
+// ---- fixed-point variant with one scale per band and chunk ------------------------------
 // LDS float atomics are microcoded on gfx950 (~190 clk per wave instruction against
 // ~4 for integer atomics), so the scatter accumulates in int32.  Per column chunk
 // the workgroup takes the chunk's max |a| (integer ds_max on the float bits) and
@@ -449,16 +453,12 @@ __device__ __forceinline__ void sketch_right_fx2_body(
       }
       bad |= isfinite(chk[p]) ? 0u : (1u << rowof(p));
     }
-    // row maxima: the 2 S lanes of equal pb hold the same rows; reduce over them, then
-    // one LDS max per row from the lanes with tbits == 0 in the low half (distinct rows)
+    // row maxima: one LDS max (on the float bits, all >= 0) per lane and row; the
+    // LDS is otherwise idle in this phase, so this is cheaper than lane shuffles
     const int slot = (int)(ch % 3);
 #pragma unroll
-    for (int p = 0; p < R; ++p) {
-#pragma unroll
-      for (int o = 1; o < S; o <<= 1) mx[p] = fmaxf(mx[p], __shfl_xor(mx[p], o, 64));
-      mx[p] = fmaxf(mx[p], __shfl_xor(mx[p], 32, 64));
-      if (lane < 32 && tbits == 0 && mx[p] > 0.f) atomicMax(&rowmax[slot][rowof(p)], __float_as_uint(mx[p]));
-    }
+    for (int p = 0; p < R; ++p)
+      if (mx[p] > 0.f) atomicMax(&rowmax[slot][rowof(p)], __float_as_uint(mx[p]));
     __syncthreads();
     // row maxima of slot (ch + 2) % 3 were last read before this barrier and are next
     // written after the next one
