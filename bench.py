@@ -194,6 +194,20 @@ def main():
                               "best_ratio": best[form]})
         log("%s: q=%d ratio %.5f  %.3f ms / factorisation" % (form, q_run, ratio_q, ms))
     del bufs
+    # the other entry points on the same matrix and q, mixed form: Algorithm 1 alone
+    # (rf_range_finder) and Algorithm 2 (rf_lowrank, a second sketch pass over A)
+    entry_ms = {}
+    if "mixed" in results:
+        q_run = results["mixed"]["q"]
+        for op, name in ((rf.RF_OP_RANGE_FINDER, "rf_range_finder"), (rf.RF_OP_LOWRANK, "rf_lowrank")):
+            p = rf.params(k, l, q_run, s, 42, "mixed")
+            nws = rf.rf_workspace_size(op, A, p)
+            ws = torch.empty(nws, dtype=torch.uint8, device=dev)
+            fn = rf.rf_range_finder if name == "rf_range_finder" else rf.rf_lowrank
+            entry_ms[name] = time_calls(torch, lambda: fn(A, k, l, q_run, s, 42, "mixed", workspace=(ws, nws)), 1,
+                                        3, stream)
+            log("%s (mixed, q=%d): %.3f ms" % (name, q_run, entry_ms[name]))
+            del ws
 
     # ---- roofline of the dominant kernels, timed live with HIP events on the launch stream
     roof = {}
@@ -275,6 +289,7 @@ def main():
                       "form reaches, rounded up to 0.01)" % target, "opt_F": opt,
             "mixed": results.get("mixed"), "plain_fp32": results.get("fp32"),
             "speedup_mixed_vs_plain": (plain["ms_per_step"] / mixed["ms_per_step"]) if (mixed and plain) else None,
+            "other_entry_points_mixed_ms": entry_ms,
         },
         "roofline": roofline,
         "roofline_other": others,

@@ -241,7 +241,7 @@ static double* carve_gpart_big(Arena& ar, const Dims& d) {
 }
 
 struct LrBufs {
-  float* Q; int32_t* table2; float* P; float* T; float* W; float* X1; float* lpart;
+  float* Q; int32_t* table2; float* P; float* T; float* W; float* X1; float* lpart; int* lwork;
 };
 static LrBufs carve_lr(Arena& ar, const Dims& d) {
   LrBufs l;
@@ -254,12 +254,13 @@ static LrBufs carve_lr(Arena& ar, const Dims& d) {
   size_t lp = sketch_left_partial_floats(d.m, d.n, d.r1);
   size_t lp2 = sketch_left_partial_floats(d.m, d.k, d.r1);
   l.lpart = ar.get<float>(lp > lp2 ? lp : lp2);
+  l.lwork = ar.get<int>(sketch_left_work_ints(d.n > d.k ? d.n : d.k));
   return l;
 }
 
 struct NyBufs {
   float* Wt; float* Yc; float* Yn; float* T1; double* W64; double* lam; double* V; float* V32; float* scale;
-  void* eigw; float* lpart; float* Cbuf;
+  void* eigw; float* lpart; float* Cbuf; int* lwork;
 };
 static NyBufs carve_ny(Arena& ar, const Dims& d) {
   NyBufs y;
@@ -274,6 +275,7 @@ static NyBufs carve_ny(Arena& ar, const Dims& d) {
   y.scale = ar.get<float>(d.k);
   y.eigw = ar.get<char>(eig_work_bytes(d.k));
   y.lpart = ar.get<float>(sketch_left_partial_floats(d.n, d.r1, d.r1));
+  y.lwork = ar.get<int>(sketch_left_work_ints(d.r1));
   y.Cbuf = ar.get<float>((size_t)d.n * d.k);
   return y;
 }
@@ -446,9 +448,9 @@ rf_status rf_lowrank(const rf_matrix* A, const rf_params* p, float* Y, int64_t l
   range_finder_core(c, A, d, p->seed, b, l.Q, nullptr, nullptr);
   // S2 (m x r1, stream 2): P = S2^T Q (r1 x k), T = S2^T A (r1 x n, second pass over A)
   c.chk(launch_sketch_table(d.m, d.s, r1, p->seed, 2, 0, l.table2, c.st));
-  c.chk(launch_sketch_left(0, l.Q, k, l.table2, d.s, d.m, k, r1, l.P, k, l.lpart, c.st));
+  c.chk(launch_sketch_left(0, l.Q, k, l.table2, d.s, d.m, k, r1, l.P, k, l.lpart, c.st, nullptr, l.lwork));
   c.chk(launch_sketch_left(A->dtype, A->data, A->ld, l.table2, d.s, d.m, d.n, r1, l.T, d.n, l.lpart, c.st,
-                           A->block_scales));
+                           A->block_scales, l.lwork));
   // X = (P^T P)^{-1} P^T T with P^T P = R^T R (FP64):  X = Rinv (Rinv^T (P^T T))
   c.chk(launch_gram(l.P, k, 0, l.P, k, 0, r1, k, k, 1, b.G, k, b.gpart, nullptr, c.st));
   c.chk(launch_cholinv(b.G, k, k, chol_tol(k), b.d0, b.flags, &b.counters[0], &b.counters[2], &b.counters[5], nullptr,
@@ -483,7 +485,7 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
   c.chk(launch_gaussian(r1, k, p->seed, 1, 0, b.om, k, c.st));
   c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, b.table, fast ? b.ready : nullptr, b.cmax, d.s, n, n,
                             r1, b.At, r1, c.st));
-  c.chk(launch_sketch_left(0, b.At, r1, b.table, d.s, n, r1, r1, y.Wt, r1, y.lpart, c.st));
+  c.chk(launch_sketch_left(0, b.At, r1, b.table, d.s, n, r1, r1, y.Wt, r1, y.lpart, c.st, nullptr, y.lwork));
   c.chk(launch_symmetrize(y.Wt, r1, r1, c.st));
   // Y = Wt^q Omega, re-orthonormalised after every product
   c.chk(launch_copy_f32(b.om, k, y.Yc, k, r1, k, c.st));

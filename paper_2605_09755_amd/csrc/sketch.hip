@@ -702,6 +702,117 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_left(const TIN* __restrict__
   }
 }
 
+// ---- fixed-point left sketch --------------------------------------------------------
+// The float form above pays for LDS float atomics (~190 clk per wave instruction on
+// gfx950).  Here every output column j (one lane) has one fixed-point scale for the
+// whole pass, set from the column's max |x| over all rows (k_colmax, one extra read
+// of X) and the largest bucket occupancy c over all rows (c = the most terms any
+// output row receives): 2^e > c max_j and terms are rounded to 2^(e-31), so no
+// partial can exceed 2^30 and a term's rounding is at most c 2^-30 of the column
+// maximum.  The scatter is then integer ds_add_u32.  A column holding a non-finite
+// value comes out NaN.
+template <typename TIN>
+__global__ __launch_bounds__(256) void k_colmax(const TIN* __restrict__ X, int64_t ldx, const float* __restrict__ bscale,
+                                                int64_t ldsc, int64_t M, int64_t N, int64_t rows_per_block,
+                                                int* __restrict__ work) {
+  const int64_t col = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (col >= N) return;
+  const int64_t r0 = (int64_t)blockIdx.y * rows_per_block, r1_ = min(M, r0 + rows_per_block);
+  float mx = 0.f;
+  bool bad = false;
+  for (int64_t i = r0; i < r1_; ++i) {
+    float x = ld_elem<TIN>(X + i * ldx + col);
+    if constexpr (sizeof(TIN) == 1) x *= bscale[(i >> 7) * ldsc + (col >> 7)];
+    bad |= !isfinite(x);
+    mx = fmaxf(mx, fabsf(x));
+  }
+  if (mx > 0.f) atomicMax(reinterpret_cast<unsigned*>(work) + col, __float_as_uint(mx));
+  if (bad) atomicOr(work + N + col, 1);
+}
+
+__global__ void k_fill_int(int* __restrict__ p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+template <typename TIN, int NW>
+__global__ __launch_bounds__(NW * 64) void k_sketch_left_fx(const TIN* __restrict__ X, int64_t ldx,
+                                                            const float* __restrict__ bscale, int64_t ldsc,
+                                                            const int32_t* __restrict__ table, int s, int64_t M,
+                                                            int64_t N, int r1, int cw, int64_t rows_per_split,
+                                                            float* __restrict__ out, int64_t ldo,
+                                                            float* __restrict__ partial, float scale,
+                                                            const int* __restrict__ work) {
+  extern __shared__ int iacc[];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t col = (int64_t)blockIdx.x * 64 + lane;
+  const bool colok = col < N;
+  const int c0 = blockIdx.y * cw;
+  const int64_t rbeg = (int64_t)blockIdx.z * rows_per_split;
+  const int64_t rend = min(M, rbeg + rows_per_split);
+  for (int i = threadIdx.x; i < cw * 64; i += NW * 64) iacc[i] = 0;
+  // the lane's column scale
+  const float cm = colok ? __uint_as_float((unsigned)work[col]) : 0.f;
+  const int c = max(work[2 * N], 1);
+  int e = 0;
+  frexpf(cm, &e);                          // cm < 2^e
+  e += 32 - __clz(c);                      // c cm < 2^e
+  const bool live = cm > 0.f && isfinite(cm);
+  const float mul = live ? ldexpf(1.f, 30 - e) : 0.f;
+  const float inv = live ? ldexpf(1.f, e - 30) : 0.f;
+  __syncthreads();
+  auto row_xi = [&](int64_t i) -> int {
+    float x = colok ? ld_elem<TIN>(X + i * ldx + col) : 0.f;
+    if constexpr (sizeof(TIN) == 1) x *= colok ? bscale[(i >> 7) * ldsc + (col >> 7)] : 0.f;
+    return isfinite(x) ? __float2int_rn(x * mul) : 0;
+  };
+  auto row_add = [&](int64_t i, int xi) {
+    const int32_t* tp = table + i * s;
+    if (s == 8) {  // the row's entries as two 16-byte groups (wave-uniform address)
+      const uint4 e0 = reinterpret_cast<const uint4*>(tp)[0], e1 = reinterpret_cast<const uint4*>(tp)[1];
+      const uint32_t en[8] = {e0.x, e0.y, e0.z, e0.w, e1.x, e1.y, e1.z, e1.w};
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const int b = (int)(en[t] & 0x7fffffffu) - c0;
+        if (b >= 0 && b < cw) atomicAdd(&iacc[b * 64 + lane], (en[t] & 0x80000000u) ? -xi : xi);
+      }
+    } else {
+      for (int t = 0; t < s; ++t) {
+        const uint32_t en = (uint32_t)tp[t];
+        const int b = (int)(en & 0x7fffffffu) - c0;
+        if (b >= 0 && b < cw) atomicAdd(&iacc[b * 64 + lane], (en & 0x80000000u) ? -xi : xi);
+      }
+    }
+  };
+  // wave w takes blocks of U consecutive rows, NW blocks apart: U loads in flight per wave
+  constexpr int U = 8;
+  for (int64_t blk = rbeg + (int64_t)wave * U; blk < rend; blk += (int64_t)NW * U) {
+    if (blk + U <= rend) {
+      int xi[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) xi[u] = row_xi(blk + u);
+#pragma unroll
+      for (int u = 0; u < U; ++u) row_add(blk + u, xi[u]);
+    } else {
+      for (int64_t i = blk; i < rend; ++i) row_add(i, row_xi(i));
+    }
+  }
+  __syncthreads();
+  const bool cbad = colok && work[N + col] != 0;
+  for (int i = threadIdx.x; i < cw * 64; i += NW * 64) {
+    int b = i >> 6, l = i & 63;
+    int64_t cc = (int64_t)blockIdx.x * 64 + l;
+    int bb = c0 + b;
+    if (cc >= N || bb >= r1) continue;
+    // every lane reads its own column's words here (i & 63 == lane)
+    const float v = cbad ? __builtin_nanf("") : (float)iacc[i] * inv;
+    if (partial)
+      partial[((int64_t)blockIdx.z * r1 + bb) * N + cc] = v;
+    else
+      out[bb * ldo + cc] = v * scale;
+  }
+}
+
 __global__ void k_reduce_partial(const float* __restrict__ partial, int splits, int64_t rows, int64_t cols,
                                  float* __restrict__ out, int64_t ldo, float scale) {
   int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -910,11 +1021,13 @@ size_t sketch_left_partial_floats(int64_t M, int64_t N, int r1) {
   return splits > 1 ? (size_t)splits * r1 * N : 0;
 }
 
+size_t sketch_left_work_ints(int64_t N) { return (size_t)(2 * N + 16); }
+
 hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32_t* table, int s, int64_t M,
                               int64_t N, int r1, float* out, int64_t ldo, float* partial, hipStream_t st,
-                              const float* scales) {
+                              const float* scales, int* work) {
   if (N == 0 || r1 == 0) return hipSuccess;
-  constexpr int NW = 4;
+  constexpr int NW = 8;
   int cw = 512;
   int chunks = (r1 + cw - 1) / cw;
   cw = (r1 + chunks - 1) / chunks;
@@ -929,6 +1042,47 @@ hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32
   dim3 grid((unsigned)strips, (unsigned)chunks, (unsigned)splits);
   float* part = splits > 1 ? partial : nullptr;
   const int64_t ldsc = (N + 127) / 128;
+  if (work && M > 0 && (dtype == 0 || dtype == 2 || (dtype == 3 && scales))) {
+    const int64_t nw = (int64_t)sketch_left_work_ints(N);
+    hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, work, nw);
+    // column maxima: 256 columns per workgroup, rows in blocks of 512
+    const int64_t rpb = 512;
+    dim3 gcm((unsigned)((N + 255) / 256), (unsigned)((M + rpb - 1) / rpb));
+    if (dtype == 0)
+      hipLaunchKernelGGL(k_colmax<float>, gcm, dim3(256), 0, st, (const float*)X, ldx, scales, ldsc, M, N, rpb, work);
+    else if (dtype == 2)
+      hipLaunchKernelGGL(k_colmax<uint16_t>, gcm, dim3(256), 0, st, (const uint16_t*)X, ldx, scales, ldsc, M, N, rpb,
+                         work);
+    else
+      hipLaunchKernelGGL(k_colmax<uint8_t>, gcm, dim3(256), 0, st, (const uint8_t*)X, ldx, scales, ldsc, M, N, rpb,
+                         work);
+    // largest bucket occupancy over all M rows
+    const size_t hl = (size_t)r1 * sizeof(int);
+    hipFuncSetAttribute((const void*)k_chunk_occupancy, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hl);
+    hipLaunchKernelGGL(k_chunk_occupancy, dim3(1), dim3(256), hl, st, table, M, s, r1, M, work + 2 * N);
+    if (dtype == 0) {
+      auto k = k_sketch_left_fx<float, NW>;
+      hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const float*)X, ldx, nullptr, 0, table, s, M, N, r1, cw,
+                         rps, out, ldo, part, scale, work);
+    } else if (dtype == 2) {
+      auto k = k_sketch_left_fx<uint16_t, NW>;
+      hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const uint16_t*)X, ldx, nullptr, 0, table, s, M, N, r1,
+                         cw, rps, out, ldo, part, scale, work);
+    } else {
+      auto k = k_sketch_left_fx<uint8_t, NW>;
+      hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const uint8_t*)X, ldx, scales, ldsc, table, s, M, N, r1,
+                         cw, rps, out, ldo, part, scale, work);
+    }
+    if (splits > 1) {
+      int64_t tot = (int64_t)r1 * N;
+      hipLaunchKernelGGL(k_reduce_partial, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, partial, splits,
+                         (int64_t)r1, N, out, ldo, scale);
+    }
+    return hipGetLastError();
+  }
   if (dtype == 0) {
     auto k = k_sketch_left<float, NW>;
     hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
