@@ -784,17 +784,55 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_left_fx(const TIN* __restric
       }
     }
   };
-  // wave w takes blocks of U consecutive rows, NW blocks apart: U loads in flight per wave
+  // wave w takes blocks of U consecutive rows, NW blocks apart
   constexpr int U = 8;
-  for (int64_t blk = rbeg + (int64_t)wave * U; blk < rend; blk += (int64_t)NW * U) {
-    if (blk + U <= rend) {
-      int xi[U];
+  const int64_t step = (int64_t)NW * U;
+  int64_t blk = rbeg + (int64_t)wave * U;
+  if (s == 8) {
+    // software pipeline: the next block's U row values and its 64 table entries (one
+    // per lane, read back with readlane) are in flight while this block is scattered
+    float xc[U], xn[U];
+    uint32_t tc = 0u, tn = 0u;
+    auto issue = [&](int64_t b0, float (&x)[U], uint32_t& tv) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) xi[u] = row_xi(blk + u);
+      for (int u = 0; u < U; ++u) {
+        const int64_t i = b0 + u;
+        x[u] = (colok && i < rend) ? ld_elem<TIN>(X + i * ldx + col) : 0.f;
+        if constexpr (sizeof(TIN) == 1) x[u] *= (colok && i < rend) ? bscale[(i >> 7) * ldsc + (col >> 7)] : 0.f;
+      }
+      const int64_t ti = b0 + (lane >> 3);
+      tv = ti < rend ? (uint32_t)table[ti * 8 + (lane & 7)] : 0u;
+    };
+    if (blk < rend) issue(blk, xc, tc);
+    for (; blk < rend; blk += step) {
+      if (blk + step < rend) issue(blk + step, xn, tn);
+      const int nrow = (int)min((int64_t)U, rend - blk);
 #pragma unroll
-      for (int u = 0; u < U; ++u) row_add(blk + u, xi[u]);
-    } else {
-      for (int64_t i = blk; i < rend; ++i) row_add(i, row_xi(i));
+      for (int u = 0; u < U; ++u) {
+        if (u >= nrow) break;
+        const int xi = isfinite(xc[u]) ? __float2int_rn(xc[u] * mul) : 0;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          const uint32_t en = (uint32_t)__builtin_amdgcn_readlane((int)tc, u * 8 + t);
+          const int b = (int)(en & 0x7fffffffu) - c0;
+          if (b >= 0 && b < cw) atomicAdd(&iacc[b * 64 + lane], (en & 0x80000000u) ? -xi : xi);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) xc[u] = xn[u];
+      tc = tn;
+    }
+  } else {
+    for (; blk < rend; blk += step) {
+      if (blk + U <= rend) {
+        int xi[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) xi[u] = row_xi(blk + u);
+#pragma unroll
+        for (int u = 0; u < U; ++u) row_add(blk + u, xi[u]);
+      } else {
+        for (int64_t i = blk; i < rend; ++i) row_add(i, row_xi(i));
+      }
     }
   }
   __syncthreads();
