@@ -46,9 +46,10 @@ hipError_t launch_sketch_right(int dtype, const void* A, int64_t lda, const floa
                                const uint32_t* ready, int* cmax, int s, int64_t m, int64_t n, int r1, float* out,
                                int64_t ldo, hipStream_t st);
 size_t sketch_left_partial_floats(int64_t M, int64_t N, int r1);
-// work: sketch_left_work_ints(N) ints (column maxima, column flags, bucket occupancy)
-// for the fixed-point pass; nullptr selects the LDS float-atomic pass.
-size_t sketch_left_work_ints(int64_t N);
+// work: sketch_left_work_ints(N, r1) ints (column maxima, column flags, bucket
+// occupancy, bucket histogram) for the fixed-point pass; nullptr selects the LDS
+// float-atomic pass.
+size_t sketch_left_work_ints(int64_t N, int r1);
 hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32_t* table, int s, int64_t M,
                               int64_t N, int r1, float* out, int64_t ldo, float* partial, hipStream_t st,
                               const float* scales = nullptr, int* work = nullptr);

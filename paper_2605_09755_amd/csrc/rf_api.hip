@@ -254,7 +254,7 @@ static LrBufs carve_lr(Arena& ar, const Dims& d) {
   size_t lp = sketch_left_partial_floats(d.m, d.n, d.r1);
   size_t lp2 = sketch_left_partial_floats(d.m, d.k, d.r1);
   l.lpart = ar.get<float>(lp > lp2 ? lp : lp2);
-  l.lwork = ar.get<int>(sketch_left_work_ints(d.n > d.k ? d.n : d.k));
+  l.lwork = ar.get<int>(sketch_left_work_ints(d.n > d.k ? d.n : d.k, d.r1));
   return l;
 }
 
@@ -275,7 +275,7 @@ static NyBufs carve_ny(Arena& ar, const Dims& d) {
   y.scale = ar.get<float>(d.k);
   y.eigw = ar.get<char>(eig_work_bytes(d.k));
   y.lpart = ar.get<float>(sketch_left_partial_floats(d.n, d.r1, d.r1));
-  y.lwork = ar.get<int>(sketch_left_work_ints(d.r1));
+  y.lwork = ar.get<int>(sketch_left_work_ints(d.r1, d.r1));
   y.Cbuf = ar.get<float>((size_t)d.n * d.k);
   return y;
 }

@@ -730,6 +730,30 @@ __global__ __launch_bounds__(256) void k_colmax(const TIN* __restrict__ X, int64
   if (bad) atomicOr(work + N + col, 1);
 }
 
+// Bucket counts over all rows of an (M x s) table, many workgroups: a histogram per
+// workgroup in LDS, added into the global one (r1 ints, zeroed beforehand).
+__global__ __launch_bounds__(256) void k_table_hist(const int32_t* __restrict__ table, int64_t M, int s, int r1,
+                                                    int64_t rows_per_block, int* __restrict__ ghist) {
+  extern __shared__ int hist[];
+  for (int i = threadIdx.x; i < r1; i += blockDim.x) hist[i] = 0;
+  __syncthreads();
+  const int64_t e0 = (int64_t)blockIdx.x * rows_per_block * s, e1 = min(M, ((int64_t)blockIdx.x + 1) * rows_per_block) * s;
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += blockDim.x) atomicAdd(&hist[(uint32_t)table[e] & 0x7fffffffu], 1);
+  __syncthreads();
+  for (int i = threadIdx.x; i < r1; i += blockDim.x)
+    if (hist[i]) atomicAdd(ghist + i, hist[i]);
+}
+__global__ __launch_bounds__(256) void k_hist_max(const int* __restrict__ ghist, int r1, int* __restrict__ out) {
+  int mx = 0;
+  for (int i = threadIdx.x; i < r1; i += blockDim.x) mx = max(mx, ghist[i]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) mx = max(mx, __shfl_xor(mx, o, 64));
+  __shared__ int red[4];
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+  __syncthreads();
+  if (threadIdx.x == 0) *out = max(max(red[0], red[1]), max(red[2], red[3]));
+}
+
 __global__ void k_fill_int(int* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -1059,7 +1083,7 @@ size_t sketch_left_partial_floats(int64_t M, int64_t N, int r1) {
   return splits > 1 ? (size_t)splits * r1 * N : 0;
 }
 
-size_t sketch_left_work_ints(int64_t N) { return (size_t)(2 * N + 16); }
+size_t sketch_left_work_ints(int64_t N, int r1) { return (size_t)(2 * N + 16 + r1); }
 
 hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32_t* table, int s, int64_t M,
                               int64_t N, int r1, float* out, int64_t ldo, float* partial, hipStream_t st,
@@ -1081,7 +1105,7 @@ hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32
   float* part = splits > 1 ? partial : nullptr;
   const int64_t ldsc = (N + 127) / 128;
   if (work && M > 0 && (dtype == 0 || dtype == 2 || (dtype == 3 && scales))) {
-    const int64_t nw = (int64_t)sketch_left_work_ints(N);
+    const int64_t nw = (int64_t)sketch_left_work_ints(N, r1);
     hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((nw + 255) / 256)), dim3(256), 0, st, work, nw);
     // column maxima: 256 columns per workgroup, rows in blocks of 512
     const int64_t rpb = 512;
@@ -1094,10 +1118,13 @@ hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32
     else
       hipLaunchKernelGGL(k_colmax<uint8_t>, gcm, dim3(256), 0, st, (const uint8_t*)X, ldx, scales, ldsc, M, N, rpb,
                          work);
-    // largest bucket occupancy over all M rows
+    // largest bucket occupancy over all M rows (global histogram after the column flags)
     const size_t hl = (size_t)r1 * sizeof(int);
-    hipFuncSetAttribute((const void*)k_chunk_occupancy, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hl);
-    hipLaunchKernelGGL(k_chunk_occupancy, dim3(1), dim3(256), hl, st, table, M, s, r1, M, work + 2 * N);
+    const int64_t hrows = 1024;
+    hipFuncSetAttribute((const void*)k_table_hist, hipFuncAttributeMaxDynamicSharedMemorySize, (int)hl);
+    hipLaunchKernelGGL(k_table_hist, dim3((unsigned)((M + hrows - 1) / hrows)), dim3(256), hl, st, table, M, s, r1,
+                       hrows, work + 2 * N + 16);
+    hipLaunchKernelGGL(k_hist_max, dim3(1), dim3(256), 0, st, work + 2 * N + 16, r1, work + 2 * N);
     if (dtype == 0) {
       auto k = k_sketch_left_fx<float, NW>;
       hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
