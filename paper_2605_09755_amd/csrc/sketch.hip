@@ -763,16 +763,25 @@ template <typename TIN, int NW>
 __global__ __launch_bounds__(NW * 64) void k_sketch_left_fx(const TIN* __restrict__ X, int64_t ldx,
                                                             const float* __restrict__ bscale, int64_t ldsc,
                                                             const int32_t* __restrict__ table, int s, int64_t M,
-                                                            int64_t N, int r1, int cw, int64_t rows_per_split,
-                                                            float* __restrict__ out, int64_t ldo,
-                                                            float* __restrict__ partial, float scale,
+                                                            int64_t N, int r1, int cw, int chunks,
+                                                            int64_t rows_per_split, float* __restrict__ out,
+                                                            int64_t ldo, float* __restrict__ partial, float scale,
                                                             const int* __restrict__ work) {
   extern __shared__ int iacc[];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t col = (int64_t)blockIdx.x * 64 + lane;
+  // One-dimensional grid of strips x chunks x splits workgroups.  Workgroup g runs on
+  // XCD g mod 8; the logical index gives each XCD a contiguous range, chunk fastest,
+  // so the chunks of one column strip run at the same time behind one L2 and X is
+  // read from HBM about once instead of once per chunk.
+  const unsigned G = gridDim.x, g = blockIdx.x;
+  const unsigned L = (G & 7u) == 0u ? (g & 7u) * (G >> 3) + (g >> 3) : g;
+  const unsigned strips = (unsigned)((N + 63) / 64);
+  const unsigned bchunk = L % (unsigned)chunks, bstrip = (L / (unsigned)chunks) % strips,
+                 bsplit = L / ((unsigned)chunks * strips);
+  const int64_t col = (int64_t)bstrip * 64 + lane;
   const bool colok = col < N;
-  const int c0 = blockIdx.y * cw;
-  const int64_t rbeg = (int64_t)blockIdx.z * rows_per_split;
+  const int c0 = (int)bchunk * cw;
+  const int64_t rbeg = (int64_t)bsplit * rows_per_split;
   const int64_t rend = min(M, rbeg + rows_per_split);
   for (int i = threadIdx.x; i < cw * 64; i += NW * 64) iacc[i] = 0;
   // the lane's column scale
@@ -831,15 +840,20 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_left_fx(const TIN* __restric
     for (; blk < rend; blk += step) {
       if (blk + step < rend) issue(blk + step, xn, tn);
       const int nrow = (int)min((int64_t)U, rend - blk);
+      // entries of this block that fall in the chunk, one bit per lane (u * 8 + t):
+      // each row visits only its own in-chunk entries (about s cw / r1 of them)
+      const int bl = (int)(tc & 0x7fffffffu) - c0;
+      unsigned long long inm = __ballot(bl >= 0 && bl < cw);
+      if (nrow < U) inm &= (1ull << (nrow * 8)) - 1ull;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        if (u >= nrow) break;
         const int xi = isfinite(xc[u]) ? __float2int_rn(xc[u] * mul) : 0;
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
+        unsigned m = (unsigned)__builtin_amdgcn_readfirstlane((int)((unsigned)(inm >> (u * 8)) & 0xffu));
+        while (m) {
+          const int t = __builtin_ctz(m);
+          m &= m - 1u;
           const uint32_t en = (uint32_t)__builtin_amdgcn_readlane((int)tc, u * 8 + t);
-          const int b = (int)(en & 0x7fffffffu) - c0;
-          if (b >= 0 && b < cw) atomicAdd(&iacc[b * 64 + lane], (en & 0x80000000u) ? -xi : xi);
+          atomicAdd(&iacc[((int)(en & 0x7fffffffu) - c0) * 64 + lane], (en & 0x80000000u) ? -xi : xi);
         }
       }
 #pragma unroll
@@ -863,13 +877,13 @@ __global__ __launch_bounds__(NW * 64) void k_sketch_left_fx(const TIN* __restric
   const bool cbad = colok && work[N + col] != 0;
   for (int i = threadIdx.x; i < cw * 64; i += NW * 64) {
     int b = i >> 6, l = i & 63;
-    int64_t cc = (int64_t)blockIdx.x * 64 + l;
+    int64_t cc = (int64_t)bstrip * 64 + l;
     int bb = c0 + b;
     if (cc >= N || bb >= r1) continue;
     // every lane reads its own column's words here (i & 63 == lane)
     const float v = cbad ? __builtin_nanf("") : (float)iacc[i] * inv;
     if (partial)
-      partial[((int64_t)blockIdx.z * r1 + bb) * N + cc] = v;
+      partial[((int64_t)bsplit * r1 + bb) * N + cc] = v;
     else
       out[bb * ldo + cc] = v * scale;
   }
@@ -1125,21 +1139,24 @@ hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32
     hipLaunchKernelGGL(k_table_hist, dim3((unsigned)((M + hrows - 1) / hrows)), dim3(256), hl, st, table, M, s, r1,
                        hrows, work + 2 * N + 16);
     hipLaunchKernelGGL(k_hist_max, dim3(1), dim3(256), 0, st, work + 2 * N + 16, r1, work + 2 * N);
+    // one workgroup per CU (cw x 64 ints of LDS), 16 waves to keep rows in flight
+    constexpr int NWF = 16;
+    const dim3 g1((unsigned)(strips * chunks * splits));
     if (dtype == 0) {
-      auto k = k_sketch_left_fx<float, NW>;
+      auto k = k_sketch_left_fx<float, NWF>;
       hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const float*)X, ldx, nullptr, 0, table, s, M, N, r1, cw,
-                         rps, out, ldo, part, scale, work);
+      hipLaunchKernelGGL(k, g1, dim3(NWF * 64), lds, st, (const float*)X, ldx, nullptr, 0, table, s, M, N, r1, cw,
+                         chunks, rps, out, ldo, part, scale, work);
     } else if (dtype == 2) {
-      auto k = k_sketch_left_fx<uint16_t, NW>;
+      auto k = k_sketch_left_fx<uint16_t, NWF>;
       hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const uint16_t*)X, ldx, nullptr, 0, table, s, M, N, r1,
-                         cw, rps, out, ldo, part, scale, work);
+      hipLaunchKernelGGL(k, g1, dim3(NWF * 64), lds, st, (const uint16_t*)X, ldx, nullptr, 0, table, s, M, N, r1,
+                         cw, chunks, rps, out, ldo, part, scale, work);
     } else {
-      auto k = k_sketch_left_fx<uint8_t, NW>;
+      auto k = k_sketch_left_fx<uint8_t, NWF>;
       hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      hipLaunchKernelGGL(k, grid, dim3(NW * 64), lds, st, (const uint8_t*)X, ldx, scales, ldsc, table, s, M, N, r1,
-                         cw, rps, out, ldo, part, scale, work);
+      hipLaunchKernelGGL(k, g1, dim3(NWF * 64), lds, st, (const uint8_t*)X, ldx, scales, ldsc, table, s, M, N, r1,
+                         cw, chunks, rps, out, ldo, part, scale, work);
     }
     if (splits > 1) {
       int64_t tot = (int64_t)r1 * N;
