@@ -211,6 +211,17 @@ size_t rf_sketch_apply_ws(const rf_matrix* A, const rf_params* p);
 rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, int64_t ldo,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* T = S2^T A, the left sketch of Algorithm 2 (line 2) as rf_lowrank applies it:
+   S2 is m x r1 (r1 = p->sketch) with s = p->nnz_per_col entries +-1/sqrt(s) per row,
+   drawn from (seed, stream id 2); out r1 x n FP32 row-major (ldo >= n).  Any
+   1 <= s <= r1 (p->k, p->q ignored).  Fixed point per output column: every term is
+   rounded to 2^(e-30) with 2^e > c max_i |a_ij| (c the largest bucket occupancy);
+   a column holding a non-finite value comes out NaN.  ws >= rf_sketch_apply_left_ws
+   bytes; RF_EINVAL / RF_EWORKSPACE as the entry points above. */
+size_t rf_sketch_apply_left_ws(const rf_matrix* A, const rf_params* p);
+rf_status rf_sketch_apply_left(const rf_matrix* A, const rf_params* p, float* out, int64_t ldo,
+                               void* ws, size_t ws_bytes, void* stream);
+
 /* Kernel-level hooks used by the parity tests (same kernels as above).
    rf_test_gemm: C (M x N FP32, ldc) = op(A) op(B); dtype 0 = FP32 operands,
      2 = BF16 operands (uint16 bits), 4 = A FP32 rounded to BF16 (RNE) as it is

@@ -21,7 +21,7 @@ __all__ = [
     "RF_F32", "RF_BF16", "RF_FP8E4M3_B128", "RF_PREC_FP32", "RF_PREC_MIXED",
     "RF_OP_RANGE_FINDER", "RF_OP_SVD", "RF_OP_LOWRANK", "RF_OP_NYSTROM",
     "lib", "library_path", "rf_status_string", "rf_workspace_size", "rf_sketch_table", "rf_gaussian",
-    "rf_sketch_apply", "rf_range_finder", "rf_svd", "rf_lowrank", "rf_nystrom", "RFError",
+    "rf_sketch_apply", "rf_sketch_apply_left", "rf_range_finder", "rf_svd", "rf_lowrank", "rf_nystrom", "RFError",
     "BatchPlan", "rf_svd_batched", "set_gemm_rules", "load_tuning",
 ]
 
@@ -82,6 +82,10 @@ def lib():
         L.rf_sketch_apply_ws.argtypes = [M, P]
         L.rf_sketch_apply.restype = i32
         L.rf_sketch_apply.argtypes = [M, P, vp, i64, vp, sz, vp]
+        L.rf_sketch_apply_left_ws.restype = sz
+        L.rf_sketch_apply_left_ws.argtypes = [M, P]
+        L.rf_sketch_apply_left.restype = i32
+        L.rf_sketch_apply_left.argtypes = [M, P, vp, i64, vp, sz, vp]
         L.rf_range_finder.restype = i32
         L.rf_range_finder.argtypes = [M, P, vp, i64, vp, sz, vp, vp]
         L.rf_svd.restype = i32
@@ -238,6 +242,20 @@ def rf_sketch_apply(A, sketch, nnz_per_col, seed, scales=None):
     out = torch.empty((A.shape[0], sketch), dtype=torch.float32, device=A.device)
     _check("rf_sketch_apply", lib().rf_sketch_apply(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(out),
                                                     sketch, _ptr(ws), nws, _stream(A.device)))
+    return out
+
+
+def rf_sketch_apply_left(A, sketch, nnz_per_col, seed, scales=None):
+    """S2^T A (sketch x n) with the stream-2 sketch of rf_lowrank."""
+    p = params(1, sketch, 0, nnz_per_col, seed)
+    nws = int(lib().rf_sketch_apply_left_ws(ctypes.byref(matrix(A, scales)), ctypes.byref(p)))
+    if nws == 0:
+        raise RFError("rf_sketch_apply_left_ws", RF_EINVAL)
+    ws = torch.empty(nws, dtype=torch.uint8, device=A.device)
+    out = torch.empty((sketch, A.shape[1]), dtype=torch.float32, device=A.device)
+    _check("rf_sketch_apply_left", lib().rf_sketch_apply_left(ctypes.byref(matrix(A, scales)), ctypes.byref(p),
+                                                              _ptr(out), A.shape[1], _ptr(ws), nws,
+                                                              _stream(A.device)))
     return out
 
 

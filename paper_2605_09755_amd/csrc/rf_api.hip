@@ -363,6 +363,40 @@ rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, in
   return finish(c);
 }
 
+// S2^T A as rf_lowrank computes it (Algorithm 2): table of stream 2 over the m rows
+static size_t carve_left(Arena& ar, const rf_matrix* A, const rf_params* p, int32_t** table, float** part, int** work) {
+  const int64_t m = A->rows, n = A->cols;
+  const int r1 = p->sketch, s = p->nnz_per_col;
+  *table = ar.get<int32_t>((size_t)m * s);
+  *part = ar.get<float>(sketch_left_partial_floats(m, n, r1));
+  *work = ar.get<int>(sketch_left_work_ints(n, r1));
+  return ar.off + 256;
+}
+
+size_t rf_sketch_apply_left_ws(const rf_matrix* A, const rf_params* p) {
+  if (!valid_matrix(A) || !p || p->sketch < 1 || p->nnz_per_col < 1 || p->nnz_per_col > p->sketch) return 0;
+  Arena ar(nullptr);
+  int32_t* t; float* pa; int* w;
+  return carve_left(ar, A, p, &t, &pa, &w);
+}
+
+rf_status rf_sketch_apply_left(const rf_matrix* A, const rf_params* p, float* out, int64_t ldo, void* ws,
+                               size_t ws_bytes, void* stream) {
+  if (!valid_matrix(A) || !p || p->sketch < 1 || p->nnz_per_col < 1 || p->nnz_per_col > p->sketch || !out ||
+      ldo < A->cols)
+    return RF_EINVAL;
+  if (!ws || ws_bytes < rf_sketch_apply_left_ws(A, p)) return RF_EWORKSPACE;
+  Arena ar(align_ws(ws));
+  int32_t* table; float* part; int* work;
+  carve_left(ar, A, p, &table, &part, &work);
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  c.chk(launch_sketch_table(A->rows, p->nnz_per_col, p->sketch, p->seed, 2, 0, table, c.st));
+  c.chk(launch_sketch_left(A->dtype, A->data, A->ld, table, p->nnz_per_col, A->rows, A->cols, p->sketch, out, ldo,
+                           part, c.st, A->block_scales, work));
+  return finish(c);
+}
+
 rf_status rf_range_finder(const rf_matrix* A, const rf_params* p, float* Q, int64_t ldq, void* ws, size_t ws_bytes,
                           rf_info* info, void* stream) {
   if (!valid_matrix(A) || !valid_params(A, p, false) || !Q || ldq < p->k) return RF_EINVAL;

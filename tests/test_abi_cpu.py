@@ -27,7 +27,8 @@ def declared_symbols():
 def test_header_declares_entry_points():
     syms = declared_symbols()
     for name in ("rf_range_finder", "rf_svd", "rf_lowrank", "rf_nystrom", "rf_workspace_size",
-                 "rf_sketch_table", "rf_gaussian", "rf_sketch_apply", "rf_status_string"):
+                 "rf_sketch_table", "rf_gaussian", "rf_sketch_apply", "rf_sketch_apply_left",
+                 "rf_sketch_apply_left_ws", "rf_status_string"):
         assert name in syms
 
 

@@ -6,7 +6,7 @@ The instance follows the benchmark's law (sigma_i = i^-1.5, Haar factors, Gaussi
 noise of spectral size 1e-4 sigma_1) with the low-rank part truncated at rank 1200,
 so that it is generated in seconds; the noise keeps A full rank.
 
-Checked: sampled rows of A S element by element; the Ritz singular values (1e-5
+Checked: sampled rows of A S and sampled columns of S2^T A element by element; the Ritz singular values (1e-5
 relative plus the 2e-6 sigma_1 floor of FP32 B = Q^T A); the Frobenius error
 ||A - U U^T A||_F against the oracle's (1e-4 relative in the FP32 form, 2 % in the
 mixed form); orthonormality of U."""
@@ -43,6 +43,28 @@ def instance():
     torch.cuda.synchronize()
     ref = me.rand_svd(A64.cpu().numpy(), me.Params(k=K, l=L, q=Q, s=S, seed=SEED))
     return A32, A64, ref
+
+
+def test_fullsize_sketch_left_columns(instance):
+    """Sampled columns of S2^T A (Algorithm 2's second pass over A) at full size, in
+    the launch configuration rf_lowrank uses; bound as for the small cases: the
+    column's fixed-point grid (cnt_b c max_i |a_ij| 2^-29 / sqrt(s)) plus FP32
+    rounding of the conversion, scale and row-split partials."""
+    A32, A64, _ = instance
+    got = rf.rf_sketch_apply_left(A32, L, S, SEED)
+    cols = np.concatenate([np.random.default_rng(2).choice(N, 30, replace=False), [0, N - 1]])
+    got = got[:, torch.from_numpy(cols).to(DEV)].cpu().numpy()
+    Ac = A64[:, torch.from_numpy(cols).to(DEV)].cpu().numpy()
+    table = sk.sketch_table(M, S, L, SEED, sk.STREAM_S2)
+    S2 = sk.sketch_matrix(table, L)
+    ref = me.sketch_left(Ac, table, L)
+    mag = np.asarray(np.abs(S2.T) @ np.abs(Ac))
+    cnt = np.bincount((table.astype(np.int64) & 0x7FFFFFFF).ravel(), minlength=L).astype(np.float64)
+    tol = (cnt[:, None] * cnt.max() * np.max(np.abs(Ac), axis=0)[None, :] * 2.0 ** -29 / math.sqrt(S)
+           + 72 * U32 * mag + 1e-30)
+    err = np.abs(got - ref)
+    print("left sketch columns: max err/tol %.3f" % np.max(err / tol))
+    assert np.all(err <= tol)
 
 
 def _frob_err(A64, Ud):

@@ -162,6 +162,76 @@ def test_sketch_apply_nonfinite_rows(s):
         assert not np.all(np.isfinite(got[i]))
 
 
+# ---------------------------------------------------------------- S2^T A (Algorithm 2)
+def _left_ref(A64, s, r1, seed):
+    m = A64.shape[0]
+    t = sk.sketch_table(m, s, r1, seed, sk.STREAM_S2)
+    S2 = sk.sketch_matrix(t, r1)
+    ref = me.sketch_left(A64, t, r1)
+    mag = np.asarray(np.abs(S2.T) @ np.abs(A64))
+    return t, ref, mag
+
+
+def _left_tol(A64, t, s, r1, mag):
+    """Bound of the fixed-point left sketch.  Column j has one scale for the whole
+    pass: 2^e > c max_i |a_ij| with 2^e <= 4 c max_i |a_ij| (c = the largest bucket
+    occupancy over all rows), terms rounded to half of 2^(e-30), so output (b, j)
+    with cnt_b terms is off by at most cnt_b c max_i|a_ij| 2^-29 / sqrt(s); plus FP32
+    rounding of the conversion, the 1/sqrt(s) scale and up to 64 row-split partials
+    summed in FP32 (72 units of 2^-24 of the sum of |terms|)."""
+    cnt = np.bincount((t.astype(np.int64) & 0x7FFFFFFF).ravel(), minlength=r1).astype(np.float64)
+    c = max(cnt.max(), 1.0)
+    colmax = np.max(np.abs(A64), axis=0) if A64.shape[0] else np.zeros(A64.shape[1])
+    return cnt[:, None] * c * colmax[None, :] * 2.0 ** -29 / math.sqrt(s) + 72 * U32 * mag + 1e-30
+
+
+@pytest.mark.parametrize("m,n,s,r1", [
+    (3000, 200, 8, 1500), (2001, 130, 8, 700), (4100, 65, 8, 100), (1, 10, 1, 1), (7, 3, 8, 8),
+    (500, 300, 4, 600), (700, 90, 16, 1100), (1000, 64, 3, 50), (300, 1000, 8, 2000)])
+def test_sketch_left_f32(m, n, s, r1):
+    rng = np.random.default_rng(m + 3 * n + s)
+    A = (rng.standard_normal((m, n)) * np.exp(rng.standard_normal((1, n)))).astype(np.float32)
+    A64 = A.astype(np.float64)
+    t, ref, mag = _left_ref(A64, s, r1, 23)
+    got = rf.rf_sketch_apply_left(torch.from_numpy(A).to(DEV), r1, s, 23).cpu().numpy()
+    tol = _left_tol(A64, t, s, r1, mag)
+    assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
+
+
+def test_sketch_left_bf16_and_fp8():
+    rng = np.random.default_rng(8)
+    m, n, s, r1 = 2000, 130, 8, 900
+    At, A64 = bf16_round(rng.standard_normal((m, n)))
+    t, ref, mag = _left_ref(A64, s, r1, 29)
+    got = rf.rf_sketch_apply_left(At.to(DEV), r1, s, 29).cpu().numpy()
+    assert np.all(np.abs(got - ref) <= _left_tol(A64, t, s, r1, mag))
+    X = rng.standard_normal((m, 300)) * np.exp(rng.standard_normal((m, 1)))
+    codes, scales = fp8_ref.quantize_blocks(X)
+    A64 = fp8_ref.dequantize(codes, scales)
+    t, ref, mag = _left_ref(A64, s, r1, 29)
+    got = rf.rf_sketch_apply_left(torch.from_numpy(codes).to(DEV), r1, s, 29,
+                                  scales=torch.from_numpy(scales).to(DEV)).cpu().numpy()
+    assert np.all(np.abs(got - ref) <= _left_tol(A64, t, s, r1, mag))
+
+
+def test_sketch_left_nonfinite_columns():
+    """A column holding NaN or Inf comes out NaN in every bucket; the others are
+    unaffected (their scales never see it)."""
+    rng = np.random.default_rng(9)
+    m, n, s, r1 = 1500, 150, 8, 600
+    A = rng.standard_normal((m, n)).astype(np.float32)
+    A[10, 5] = np.nan
+    A[1400, 77] = np.inf
+    A64 = np.where(np.isfinite(A), A, 0.0).astype(np.float64)
+    t, ref, mag = _left_ref(A64, s, r1, 37)
+    got = rf.rf_sketch_apply_left(torch.from_numpy(A).to(DEV), r1, s, 37).cpu().numpy()
+    clean = np.ones(n, dtype=bool)
+    clean[[5, 77]] = False
+    tol = _left_tol(A64, t, s, r1, mag)
+    assert np.all(np.abs(got[:, clean] - ref[:, clean]) <= tol[:, clean])
+    assert np.all(np.isnan(got[:, ~clean]))
+
+
 # ---------------------------------------------------------------- K5/K6 GEMM
 def _operands(M, N, K, a_kc, b_kc, rng, bf16):
     A = rng.standard_normal((M, K))
