@@ -154,15 +154,16 @@ RF_DEV double pick_row(const double (&m)[4][4], int a, int b) {
 // A(kb): R_kk and X_kk = R_kk^{-1}, written to G and X.  The tile lives in
 // registers: thread (ty, tx) of 16 x 16 holds entries (ty + 16a, tx + 16b).
 // Cholesky, right-looking, one barrier per column: the threads holding row c + 1
-// publish it (double-buffered) right after their step-c update, and at step c + 1
-// every thread forms R_c+1,. = G_c+1,. / sqrt(g) from it and updates its entries.
+// publish it, unscaled, into row c + 1 of R right after their step-c update, and at
+// step c + 1 every thread reads it, forms R_c+1,. = G_c+1,. / sqrt(g) in registers
+// and updates its entries.  R is scaled by its 1 / sqrt(g) once, after the loop.
 // Inverse blocked by 16 (see below).
 RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R)[TLD], double (*Xs)[TLD]) {
   const int64_t b0 = (int64_t)kb * TB;
   const int nbk = (int)min((int64_t)TB, a.N - b0);
   const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double* rowb = &M[0][0];  // M's LDS is scratch here: 2 row buffers, 1 / R_cc, pivot floors
-  double* rsv = rowb + 2 * TB;
+  double* rsc = &M[0][0];   // M's LDS is scratch here: 1 / sqrt(g) per column (0 when dependent),
+  double* rsv = rsc + TB;   // 1 / R_cc for the inverse, pivot floors
   double* floor_ = rsv + TB;
   if (threadIdx.x < nbk) floor_[threadIdx.x] = a.tol * a.d0[b0 + threadIdx.x];
   double m[4][4];
@@ -177,43 +178,41 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
     R[e / TB][e % TB] = 0.0;
     Xs[e / TB][e % TB] = 0.0;
   }
+  __syncthreads();
   if (ty == 0) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) rowb[tx + 16 * q] = m[0][q];
+    for (int q = 0; q < 4; ++q) R[0][tx + 16 * q] = m[0][q];
   }
   __syncthreads();
   for (int c = 0; c < nbk; ++c) {
-    const double* row = rowb + (c & 1) * TB;
-    const double d = row[c];
+    const double* row = R[c];
+    const double d = row[c], fl = floor_[c];
+    double vi[4], vj[4];
+#pragma unroll
+    for (int p = 0; p < 4; ++p) vi[p] = row[ty + 16 * p];   // every index < TB: in the row
+#pragma unroll
+    for (int q = 0; q < 4; ++q) vj[q] = row[tx + 16 * q];
     const bool fin = isfinite(d);
-    const bool bad = !(fin && d > floor_[c] && d > 0.0);
+    const bool bad = !(fin & (d > fl) & (d > 0.0));
+    const double rs = bad ? 0.0 : rsqrt_f64(d);
     if (threadIdx.x == 0) {
       if (!fin) *a.nonfinite = 1;
       if (bad) {
         a.flags[b0 + c] = 1;
         atomicAdd(a.count, 1);
       }
+      rsc[c] = rs;
     }
-    const double rs = bad ? 0.0 : rsqrt_f64(d);
     double ri[4], rj[4];
 #pragma unroll
     for (int p = 0; p < 4; ++p) {
       const int i = ty + 16 * p;
-      ri[p] = (i > c && i < nbk) ? row[i] * rs : 0.0;
+      ri[p] = (i > c && i < nbk) ? vi[p] * rs : 0.0;
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int j = tx + 16 * q;
-      rj[q] = (j > c && j < nbk) ? row[j] * rs : 0.0;
-    }
-    if (ty == (c & 15)) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        if (tx + 16 * q > c) R[c][tx + 16 * q] = rj[q];
-      if (tx == (c & 15)) {
-        R[c][c] = bad ? 1.0 : d * rs;
-        rsv[c] = bad ? 1.0 : rs;
-      }
+      rj[q] = (j > c && j < nbk) ? vj[q] * rs : 0.0;
     }
 #pragma unroll
     for (int p = 0; p < 4; ++p)
@@ -221,12 +220,22 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
       for (int q = 0; q < 4; ++q) m[p][q] = fma(-ri[p], rj[q], m[p][q]);
     const int c1 = c + 1;
     if (c1 < nbk && ty == (c1 & 15)) {
-      double* nrow = rowb + (c1 & 1) * TB;
 #pragma unroll
-      for (int q = 0; q < 4; ++q) nrow[tx + 16 * q] = pick_row(m, c1 >> 4, q);
+      for (int q = 0; q < 4; ++q) R[c1][tx + 16 * q] = pick_row(m, c1 >> 4, q);
     }
     __syncthreads();
   }
+  // R_cj = g_cj / sqrt(g_cc) above the diagonal, sqrt(g_cc) on it, zero below; a
+  // dependent column gets a unit diagonal and a zero row
+  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+    const int r = e / TB, cc = e % TB;
+    if (r >= nbk || cc >= nbk) continue;
+    const double rs = rsc[r];
+    const double v = R[r][cc];
+    R[r][cc] = cc > r ? v * rs : (cc == r ? (rs == 0.0 ? 1.0 : v * rs) : 0.0);
+    if (cc == r) rsv[r] = rs == 0.0 ? 1.0 : rs;
+  }
+  __syncthreads();
   // Inverse, blocked by 16: wave w inverts diagonal sub-block w, then the other
   // blocks follow by block diagonals, X_IJ = -X_II (sum_{L=I+1..J} R_IL X_LJ)
   // (the row buffers and M are free now: M holds the partial sums).
