@@ -251,7 +251,8 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
       if (i >= nbk || jj >= nbk) continue;
       double acc = 0.0;
       const int lend = min((J + 1) * SB, nbk);
-      for (int l = (I + 1) * SB; l < lend; ++l) acc = fma(R[i][l], Xs[l][jj], acc);
+#pragma unroll 8
+      for (int l = (I + 1) * SB; l < lend; ++l) acc = fma(R[i][l], Xs[l][jj], acc);  // reads batched, same order
       M[i][jj] = acc;
     }
     __syncthreads();
@@ -261,6 +262,7 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
       if (i >= nbk || jj >= nbk) continue;
       double acc = 0.0;
       const int lend = min((I + 1) * SB, nbk);
+#pragma unroll 8
       for (int l = i; l < lend; ++l) acc = fma(Xs[i][l], M[l][jj], acc);
       Xs[i][jj] = -acc;
     }
