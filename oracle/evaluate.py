@@ -8,6 +8,11 @@
   operator (the error plotted in Section 4 is ||A - U Sigma V^T|| / sigma_{k+1} - 1,
   and with r2 = k, U Sigma V^T = Q Q^T A).
 
+Pinned by tests/test_oracle_evaluate.py: the explicit residual for any Q
+(orthonormal or not), LAPACK's 2-norm, and the Eckart-Young closed forms
+(the truncated SVD leaves the spectrum tail in the Frobenius norm and
+sigma_{k+1} in the spectral norm) on matrices of known spectrum.
+
 TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
 """
 import numpy as np
