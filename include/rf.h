@@ -81,6 +81,15 @@ enum { RF_OP_RANGE_FINDER = 0, RF_OP_SVD = 1, RF_OP_LOWRANK = 2, RF_OP_NYSTROM =
 
 /* flags */
 #define RF_FLAG_ORTH_ERR 1u   /* compute info->orth_err = max |Q^T Q - I| (one extra FP64 Gram) */
+#define RF_FLAG_CLASSICAL 2u  /* S = I_n: the classical range finder the paper compares against
+                                 (Section 2, "Comparison with Classical Range Finder"; Section 4;
+                                 Algorithm 2 with S1 = I in the additional experiments).  At = A,
+                                 Omega is n x k, the power products read A itself; p->sketch then
+                                 only sizes S2 in rf_lowrank (and must still satisfy k <= sketch
+                                 <= min(m, n)).  FP32 A only (RF_EUNSUPPORTED otherwise); in the
+                                 mixed form A is rounded to BF16 as the products load it and the
+                                 last product At Z stays FP32.  Not accepted by rf_nystrom
+                                 (RF_EUNSUPPORTED). */
 
 typedef struct {
   const void* data;           /* device, row-major rows x cols, leading dim ld (elements) */
@@ -102,7 +111,9 @@ typedef struct {
 
 typedef struct {
   int32_t status;       /* 0 = ok; bit 1 = Cholesky breakdown repaired; bit 2 = non-finite seen;
-                           bit 4 = a device task queue gave up waiting (results invalid) */
+                           bit 4 = a device task queue gave up waiting (results invalid);
+                           bit 8 = a caller-given sketch table had entries outside their
+                           block (rf_range_finder_ex; results are not Algorithm 1's) */
   int32_t rank_found;   /* k minus columns refilled during orthonormalisation (last call) */
   int32_t chol_retries; /* number of CholeskyQR passes that needed column refill */
   int32_t nonfinite;    /* 1 if a NaN/Inf was seen in a Gram matrix */
@@ -119,6 +130,20 @@ size_t rf_workspace_size(int op, const rf_matrix* A, const rf_params* p);
    Algorithm 1) and a final CholeskyQR2. */
 rf_status rf_range_finder(const rf_matrix* A, const rf_params* p, float* Q, int64_t ldq,
                           void* ws, size_t ws_bytes, rf_info* info, void* stream);
+
+/* Algorithm 1 with caller-given random inputs (its inputs S and Omega, Section 2).
+   S_table: device int32[n * s] in the layout rf_sketch_table writes (entry j*s + t =
+   bucket | negative << 31, bucket inside block t = [floor(t r1/s), floor((t+1) r1/s)),
+   value +-1/sqrt(s)), or NULL to draw S from p->seed; must be NULL with
+   RF_FLAG_CLASSICAL (RF_EINVAL otherwise).  Entries outside their block are
+   replaced by the block's first column and reported in info->status bit 8 (the
+   call stays in bounds, the result is then not the requested sketch's).
+   Omega: device FP32 rows x k, row-major with ld = k (rows = r1 = p->sketch, or n
+   with RF_FLAG_CLASSICAL), or NULL to draw it from p->seed.  Both are read only,
+   in stream order, and must stay alive until the call's work has run.  Otherwise
+   as rf_range_finder (same workspace size). */
+rf_status rf_range_finder_ex(const rf_matrix* A, const int32_t* S_table, const float* Omega, const rf_params* p,
+                             float* Q, int64_t ldq, void* ws, size_t ws_bytes, rf_info* info, void* stream);
 
 /* Randomised SVD on top of Algorithm 1 (Section 2; Section 4 uses r2 = k):
    U m x k FP32, sigma k FP64 descending, Vt k x n FP32 with A ~= U diag(sigma) Vt
@@ -137,10 +162,31 @@ rf_status rf_lowrank(const rf_matrix* A, const rf_params* p, float* Y, int64_t l
    F n x k FP32 optional (NULL to skip): F = C V+ Lambda+^{-1/2} from the
    eigenpairs of W with eigenvalues > k * 2^-52 * lambda_max, so that
    C W^+ C^T = F F^T (dropped columns are zero).  For q >= 1 the power iterate
-   Y is re-orthonormalised after every product with Wt. */
+   Y is re-orthonormalised after every product with Wt.  RF_PREC_MIXED: the
+   first q-1 products Wt Y on BF16 MFMA (FP32 accumulation), the last one and
+   C = Ct Y in FP32; Grams, Cholesky, W and its eigenpairs FP64 in both forms. */
 rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t ldc, double* W,
                      int64_t ldw, float* F, int64_t ldf, void* ws, size_t ws_bytes,
                      rf_info* info, void* stream);
+
+/* ---- storage forms of A (the precision workload: A stored once in BF16 and
+   once in FP8-e4m3 with per-128x128-block scales) -------------------------------
+
+   The paper fixes no storage format.  rf_quantize_bf16: out (rows x cols, ldo >=
+   cols, device uint16 BF16 bits) = A rounded to nearest, ties to even (NaN stays
+   NaN).  rf_quantize_fp8_b128: out (rows x cols, ldo >= cols, device uint8 OCP
+   e4m3 codes) and scales (device FP32, ceil(rows/128) x ceil(cols/128) row-major,
+   the block_scales of an RF_FP8E4M3_B128 rf_matrix): scale = amax/448 of the
+   block's finite entries, computed in FP64 and rounded to FP32 (1 for an all-zero
+   block); code = the e4m3 value nearest to a / scale (FP64 division), ties to the
+   even code, saturating at +-448; non-finite entries encode as NaN (0x7f/0xff).
+   A: device FP32, lda >= cols.  One pass over A each.  RF_EINVAL for bad sizes
+   or null pointers; rf_quantize_fp8_b128 returns RF_EUNSUPPORTED for more than
+   65535 row blocks. */
+rf_status rf_quantize_bf16(const float* A, int64_t rows, int64_t cols, int64_t lda, uint16_t* out, int64_t ldo,
+                           void* stream);
+rf_status rf_quantize_fp8_b128(const float* A, int64_t rows, int64_t cols, int64_t lda, uint8_t* out, int64_t ldo,
+                               float* scales, void* stream);
 
 /* ---- tuning table for the dense products ---------------------------------
 

@@ -102,13 +102,21 @@ def power_loop(At, Om, q):
     return Q, rank
 
 
-def range_finder(A, p: Params, table=None, Om=None):
+def range_finder(A, p: Params, table=None, Om=None, classical=False):
     """Algorithm 1.  Pinned by: Eckart-Young lower bound, exact recovery for
     rank(A) <= k, q = 0 span identity, S = I reduction to the classical range
     finder and its convergence to the truncated SVD, convergence to the top-k
     left singular subspace of At for sketched S, Lemma 3.3 / Theorem 3.5
-    on tiny inputs (tests/test_oracle_methods.py, tests/test_oracle_theory.py)."""
+    on tiny inputs (tests/test_oracle_methods.py, tests/test_oracle_theory.py).
+
+    classical=True takes S = I (Section 2, "Comparison with Classical Range
+    Finder"): At = A and Omega is n x k (drawn from the Omega stream with n rows
+    unless given); p.l is then unused here."""
     A = np.asarray(A, dtype=np.float64)
+    if classical:
+        Om = sk.omega(A.shape[1], p.k, p.seed, p.b) if Om is None else Om
+        Q, rank = power_loop(A, Om, p.q)
+        return Result(Q=Q, At=A, rank_found=rank, extras={"table": None, "Omega": Om})
     table, Om = draws(A.shape[1], p, table, Om)
     At = sketch_right(A, table, p.l)
     Q, rank = power_loop(At, Om, p.q)
@@ -124,12 +132,12 @@ def svd_sign_fix(U, Vt):
     return U * sgn[None, :], Vt * sgn[:, None]
 
 
-def rand_svd(A, p: Params, table=None, Om=None):
+def rand_svd(A, p: Params, table=None, Om=None, classical=False):
     """Randomised SVD on top of Algorithm 1 (Section 2; Section 4 protocol).
     Pinned by: U Sigma V^T = Q Q^T A, sigma_i(B) <= sigma_i(A) (interlacing),
     orthonormality of U and V."""
     A = np.asarray(A, dtype=np.float64)
-    res = range_finder(A, p, table, Om)
+    res = range_finder(A, p, table, Om, classical)
     B = res.Q.T @ A
     Ub, sig, Vt = np.linalg.svd(B, full_matrices=False)
     U = res.Q @ Ub
@@ -139,12 +147,13 @@ def rand_svd(A, p: Params, table=None, Om=None):
     return res
 
 
-def lowrank(A, p: Params, table1=None, Om=None, table2=None):
+def lowrank(A, p: Params, table1=None, Om=None, table2=None, classical=False):
     """Algorithm 2.  Pinned by: S2 = I reduces Y X to Q Q^T A; the normal
-    equations (S2^T Q)^T (S2^T Q X - S2^T A) = 0."""
+    equations (S2^T Q)^T (S2^T Q X - S2^T A) = 0.  classical=True runs it with
+    S1 = I (the baseline of the additional experiments); S2 keeps p.l rows."""
     A = np.asarray(A, dtype=np.float64)
     m = A.shape[0]
-    res = range_finder(A, p, table1, Om)
+    res = range_finder(A, p, table1, Om, classical)
     if table2 is None:
         table2 = sk.sketch_table(m, p.s, p.l, p.seed, sk.STREAM_S2, p.b)
     P = sketch_left(res.Q, table2, p.l)

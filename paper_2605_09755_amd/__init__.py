@@ -22,7 +22,8 @@ __all__ = [
     "RF_OP_RANGE_FINDER", "RF_OP_SVD", "RF_OP_LOWRANK", "RF_OP_NYSTROM",
     "lib", "library_path", "rf_status_string", "rf_workspace_size", "rf_sketch_table", "rf_gaussian",
     "rf_sketch_apply", "rf_sketch_apply_left", "rf_range_finder", "rf_svd", "rf_lowrank", "rf_nystrom", "RFError",
-    "BatchPlan", "rf_svd_batched", "set_gemm_rules", "load_tuning",
+    "BatchPlan", "rf_svd_batched", "set_gemm_rules", "load_tuning", "rf_range_finder_ex", "RF_FLAG_CLASSICAL",
+    "rf_quantize_bf16", "rf_quantize_fp8_b128",
 ]
 
 RF_OK, RF_EINVAL, RF_EWORKSPACE, RF_EUNSUPPORTED, RF_EHIP = 0, 1, 2, 3, 4
@@ -30,6 +31,7 @@ RF_F32, RF_F64, RF_BF16, RF_FP8E4M3_B128 = 0, 1, 2, 3
 RF_PREC_FP32, RF_PREC_MIXED = 0, 1
 RF_OP_RANGE_FINDER, RF_OP_SVD, RF_OP_LOWRANK, RF_OP_NYSTROM = 0, 1, 2, 3
 RF_FLAG_ORTH_ERR = 1
+RF_FLAG_CLASSICAL = 2
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "librf.so")
@@ -88,6 +90,8 @@ def lib():
         L.rf_sketch_apply_left.argtypes = [M, P, vp, i64, vp, sz, vp]
         L.rf_range_finder.restype = i32
         L.rf_range_finder.argtypes = [M, P, vp, i64, vp, sz, vp, vp]
+        L.rf_range_finder_ex.restype = i32
+        L.rf_range_finder_ex.argtypes = [M, vp, vp, P, vp, i64, vp, sz, vp, vp]
         L.rf_svd.restype = i32
         L.rf_svd.argtypes = [M, P, vp, i64, vp, vp, i64, vp, sz, vp, vp]
         L.rf_lowrank.restype = i32
@@ -105,6 +109,10 @@ def lib():
         L.rf_svd_batched_run.argtypes = [vp, vp]
         L.rf_svd_batched_destroy.restype = None
         L.rf_svd_batched_destroy.argtypes = [vp]
+        L.rf_quantize_bf16.restype = i32
+        L.rf_quantize_bf16.argtypes = [vp, i64, i64, i64, vp, i64, vp]
+        L.rf_quantize_fp8_b128.restype = i32
+        L.rf_quantize_fp8_b128.argtypes = [vp, i64, i64, i64, vp, i64, vp, vp]
         L.rf_test_gemm_ws.restype = sz
         L.rf_test_gemm_ws.argtypes = [i64, i64, i64]
         L.rf_test_gemm.restype = i32
@@ -180,9 +188,13 @@ def _ptr(t):
 
 def matrix(A, scales=None):
     """rf_matrix descriptor for a 2-D row-major device tensor (float32, bfloat16,
-    or uint8 holding OCP e4m3 bytes together with 128x128 block `scales`)."""
+    or uint8 holding OCP e4m3 bytes together with 128x128 block `scales`).
+    Every shape, dtype and device the kernels index by is checked here, before
+    any launch: the library trusts these pointers."""
     if A.dim() != 2 or A.stride(1) != 1:
         raise ValueError("A must be a 2-D tensor with unit column stride")
+    if A.device.type != "cuda":
+        raise ValueError("A must be a device tensor (got %s)" % A.device)
     if A.dtype == torch.float32:
         dt = RF_F32
     elif A.dtype == torch.bfloat16:
@@ -191,10 +203,30 @@ def matrix(A, scales=None):
         dt = RF_FP8E4M3_B128
         if scales is None:
             raise ValueError("FP8 storage needs block scales")
+        want = ((A.shape[0] + 127) // 128, (A.shape[1] + 127) // 128)
+        if tuple(scales.shape) != want or scales.dtype != torch.float32 or not scales.is_contiguous() \
+                or scales.device != A.device:
+            raise ValueError("block scales must be a contiguous float32 tensor of shape %s on %s (got %s %s on %s)"
+                             % (want, A.device, tuple(scales.shape), scales.dtype, scales.device))
     else:
         raise ValueError("unsupported dtype %s" % A.dtype)
+    if dt != RF_FP8E4M3_B128 and scales is not None:
+        raise ValueError("block scales are only taken with FP8 storage")
     return RfMatrix(A.data_ptr(), scales.data_ptr() if scales is not None else None, A.shape[0], A.shape[1],
                     max(A.stride(0), A.shape[1]), dt, 0)
+
+
+def _check_out(name, t, shape, dtype, device):
+    if (t is None or tuple(t.shape) != tuple(shape) or t.dtype != dtype or t.device != device
+            or not t.is_contiguous()):
+        raise ValueError("%s must be a contiguous %s tensor of shape %s on %s" % (name, dtype, tuple(shape), device))
+
+
+def _check_ws(workspace, need, device):
+    ws, nws = workspace
+    if ws.dtype != torch.uint8 or ws.device != device or not ws.is_contiguous() or ws.numel() < nws or nws < need:
+        raise ValueError("workspace must be a contiguous uint8 device tensor of at least %d bytes on %s" % (need, device))
+    return ws, nws
 
 
 def params(k, sketch, q=0, nnz_per_col=8, seed=0, precision=RF_PREC_FP32, flags=0):
@@ -208,10 +240,12 @@ def rf_workspace_size(op, A, p, scales=None):
     return int(lib().rf_workspace_size(int(op), ctypes.byref(matrix(A, scales)), ctypes.byref(p)))
 
 
-def _workspace(op, A, p, scales):
+def _workspace(op, A, p, scales, given=None):
     n = rf_workspace_size(op, A, p, scales)
     if n == 0:
         raise RFError("rf_workspace_size", RF_EINVAL)
+    if given is not None:
+        return _check_ws(given, n, A.device)
     return torch.empty(n, dtype=torch.uint8, device=A.device), n
 
 
@@ -259,10 +293,15 @@ def rf_sketch_apply_left(A, sketch, nnz_per_col, seed, scales=None):
     return out
 
 
+def _flags(orth_err=False, classical=False):
+    return (RF_FLAG_ORTH_ERR if orth_err else 0) | (RF_FLAG_CLASSICAL if classical else 0)
+
+
 def rf_range_finder(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, orth_err=False,
-                    workspace=None):
-    p = params(k, sketch, q, nnz_per_col, seed, precision, RF_FLAG_ORTH_ERR if orth_err else 0)
-    ws, nws = workspace if workspace is not None else _workspace(RF_OP_RANGE_FINDER, A, p, scales)
+                    workspace=None, classical=False):
+    """Algorithm 1.  classical=True runs S = I (Omega n x k): the baseline of Section 2."""
+    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(orth_err, classical))
+    ws, nws = _workspace(RF_OP_RANGE_FINDER, A, p, scales, workspace)
     Q = torch.empty((A.shape[0], k), dtype=torch.float32, device=A.device)
     info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
     _check("rf_range_finder", lib().rf_range_finder(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(Q), k,
@@ -270,10 +309,30 @@ def rf_range_finder(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", 
     return Q, info
 
 
+def rf_range_finder_ex(A, k, sketch, S_table=None, Omega=None, q=0, nnz_per_col=8, seed=0, precision="fp32",
+                       scales=None, orth_err=False, classical=False, workspace=None):
+    """Algorithm 1 with a caller-given sketch table (int32 n x s, the layout of
+    rf_sketch_table) and/or Omega (float32 rows x k; rows = sketch, or n when
+    classical).  None draws that input from the seed."""
+    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(orth_err, classical))
+    ws, nws = _workspace(RF_OP_RANGE_FINDER, A, p, scales, workspace)
+    n = A.shape[1]
+    if S_table is not None:
+        _check_out("S_table", S_table, (n, nnz_per_col), torch.int32, A.device)
+    if Omega is not None:
+        _check_out("Omega", Omega, (n if classical else sketch, k), torch.float32, A.device)
+    Q = torch.empty((A.shape[0], k), dtype=torch.float32, device=A.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    _check("rf_range_finder_ex", lib().rf_range_finder_ex(ctypes.byref(matrix(A, scales)), _ptr(S_table),
+                                                          _ptr(Omega), ctypes.byref(p), _ptr(Q), k, _ptr(ws), nws,
+                                                          _ptr(info), _stream(A.device)))
+    return Q, info
+
+
 def rf_svd(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, orth_err=False,
-           workspace=None, out=None):
-    p = params(k, sketch, q, nnz_per_col, seed, precision, RF_FLAG_ORTH_ERR if orth_err else 0)
-    ws, nws = workspace if workspace is not None else _workspace(RF_OP_SVD, A, p, scales)
+           workspace=None, out=None, classical=False):
+    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(orth_err, classical))
+    ws, nws = _workspace(RF_OP_SVD, A, p, scales, workspace)
     m, n = A.shape
     if out is None:
         U = torch.empty((m, k), dtype=torch.float32, device=A.device)
@@ -282,14 +341,20 @@ def rf_svd(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=No
         info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
     else:
         U, sig, Vt, info = out
+        _check_out("U", U, (m, k), torch.float32, A.device)
+        _check_out("sigma", sig, (k,), torch.float64, A.device)
+        _check_out("Vt", Vt, (k, n), torch.float32, A.device)
+        _check_out("info", info, (INFO_BYTES,), torch.uint8, A.device)
     _check("rf_svd", lib().rf_svd(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(U), k, _ptr(sig), _ptr(Vt),
                                   n, _ptr(ws), nws, _ptr(info), _stream(A.device)))
     return U, sig, Vt, info
 
 
-def rf_lowrank(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, workspace=None):
-    p = params(k, sketch, q, nnz_per_col, seed, precision)
-    ws, nws = workspace if workspace is not None else _workspace(RF_OP_LOWRANK, A, p, scales)
+def rf_lowrank(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, workspace=None,
+               classical=False):
+    """Algorithm 2; classical=True runs it with S1 = I (S2 still has `sketch` rows)."""
+    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(False, classical))
+    ws, nws = _workspace(RF_OP_LOWRANK, A, p, scales, workspace)
     m, n = A.shape
     Y = torch.empty((m, k), dtype=torch.float32, device=A.device)
     X = torch.empty((k, n), dtype=torch.float32, device=A.device)
@@ -302,7 +367,7 @@ def rf_lowrank(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scale
 def rf_nystrom(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, want_F=True,
                workspace=None):
     p = params(k, sketch, q, nnz_per_col, seed, precision)
-    ws, nws = workspace if workspace is not None else _workspace(RF_OP_NYSTROM, A, p, scales)
+    ws, nws = _workspace(RF_OP_NYSTROM, A, p, scales, workspace)
     n = A.shape[0]
     C = torch.empty((n, k), dtype=torch.float32, device=A.device)
     W = torch.empty((k, k), dtype=torch.float64, device=A.device)
@@ -311,6 +376,31 @@ def rf_nystrom(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scale
     _check("rf_nystrom", lib().rf_nystrom(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(C), k, _ptr(W), k,
                                           _ptr(F), k, _ptr(ws), nws, _ptr(info), _stream(A.device)))
     return C, W, F, info
+
+
+def _check_f32_2d(name, A):
+    if A.dim() != 2 or A.stride(1) != 1 or A.dtype != torch.float32 or A.device.type != "cuda":
+        raise ValueError("%s must be a 2-D float32 device tensor with unit column stride" % name)
+
+
+def rf_quantize_bf16(A):
+    """A (FP32, device) rounded to BF16, nearest-even (the library's kernel)."""
+    _check_f32_2d("A", A)
+    out = torch.empty(A.shape, dtype=torch.bfloat16, device=A.device)
+    _check("rf_quantize_bf16", lib().rf_quantize_bf16(_ptr(A), A.shape[0], A.shape[1], A.stride(0), _ptr(out),
+                                                      A.shape[1], _stream(A.device)))
+    return out
+
+
+def rf_quantize_fp8_b128(A):
+    """A (FP32, device) -> (uint8 OCP e4m3 codes, FP32 128 x 128 block scales)."""
+    _check_f32_2d("A", A)
+    m, n = A.shape
+    codes = torch.empty((m, n), dtype=torch.uint8, device=A.device)
+    scales = torch.empty(((m + 127) // 128, (n + 127) // 128), dtype=torch.float32, device=A.device)
+    _check("rf_quantize_fp8_b128", lib().rf_quantize_fp8_b128(_ptr(A), m, n, A.stride(0), _ptr(codes), n,
+                                                              _ptr(scales), _stream(A.device)))
+    return codes, scales
 
 
 class BatchPlan:

@@ -13,6 +13,9 @@ hipError_t launch_sketch_ready(const int32_t* table, int64_t n, int s, int r1, i
                                hipStream_t st);
 hipError_t launch_gaussian(int64_t rows, int64_t cols, uint64_t seed, uint32_t stream, uint32_t b, float* out,
                            int64_t ldo, hipStream_t st);
+// Copy of a caller-given table with every entry outside its block replaced by the
+// block's first column (sign kept); *bad += number of such entries.
+hipError_t launch_table_sanitize(const int32_t* in, int64_t n, int s, int r1, int32_t* out, int* bad, hipStream_t st);
 
 // ---- K3 / K4 ----
 // Batched sketch tables (stream 0), ready tables and Omega (stream 1, r1 x k, ld k),
@@ -53,6 +56,15 @@ size_t sketch_left_work_ints(int64_t N, int r1);
 hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32_t* table, int s, int64_t M,
                               int64_t N, int r1, float* out, int64_t ldo, float* partial, hipStream_t st,
                               const float* scales = nullptr, int* work = nullptr);
+
+// ---- storage forms of A (quant.hip) ----
+// out (rows x cols, ldo) = BF16 of A (round to nearest even)
+hipError_t launch_quant_bf16(const float* A, int64_t rows, int64_t cols, int64_t lda, uint16_t* out, int64_t ldo,
+                             hipStream_t st);
+// out = OCP e4m3 codes of A / scale(block), scales: ceil(rows/128) x ceil(cols/128)
+// row-major FP32, scale = amax / 448 of the 128 x 128 block (1 if all zero)
+hipError_t launch_quant_fp8_b128(const float* A, int64_t rows, int64_t cols, int64_t lda, uint8_t* out, int64_t ldo,
+                                 float* scales, hipStream_t st);
 
 // ---- K5 / K6 ----
 struct GemmArgs {

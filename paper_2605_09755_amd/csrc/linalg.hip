@@ -810,8 +810,6 @@ static void eig_rounds(EigWork w, int64_t N, hipStream_t st, double* trace) {
   int64_t KK = w.K * w.K;
   size_t lds_solve = 2 * JS * (JS + 1) * sizeof(double);
   size_t lds_apply = JS * (JS + 1) * sizeof(double);
-  hipFuncSetAttribute((const void*)k_eig_solve<JB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_solve);
-  hipFuncSetAttribute((const void*)k_eig_apply<JB>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_apply);
   const int rounds = 2 * w.p - 1;
   const int max_sweeps = eig_max_sweeps();
   const int ntile = eig_apply_items(w.p, w.K, JS);
@@ -845,8 +843,12 @@ static hipError_t eig_sequence(double* G, int64_t ld, int64_t N, double* lam, do
 // Instantiated graphs of the sequence, keyed by every kernel argument (device
 // pointers, sizes, tolerance): a repeated call with the same buffers replays the
 // graph instead of issuing the launches one by one, which removes the gaps
-// between the short Jacobi kernels.  Least recently used entries are dropped
-// (after a device synchronisation, as a dropped graph may still be running).
+// between the short Jacobi kernels.  Each entry records an event after its
+// latest launch; an entry is dropped (least recently used first) only once that
+// event reports completion, so eviction never waits on the device.  When every
+// entry is still in flight the new sequence is launched directly, uncached.
+// While the caller's stream is being captured the sequence is launched straight
+// into that capture (no private stream, no cache).
 namespace {
 struct EigGraph {
   int dev;
@@ -855,6 +857,7 @@ struct EigGraph {
   double tol;
   hipGraph_t graph;
   hipGraphExec_t exec;
+  hipEvent_t done;  // recorded after the entry's latest launch
   uint64_t used;
   bool same(const EigGraph& o) const {
     return dev == o.dev && G == o.G && lam == o.lam && V == o.V && work == o.work && trace == o.trace && ld == o.ld &&
@@ -872,9 +875,8 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
                       hipStream_t st, double tol, double* trace) {
   if (N == 0) return hipSuccess;
   if (eig_layout(nullptr, N, eig_block_width(N)).K > 4096) return hipErrorInvalidValue;
-  if (N < kEigGraphMinN) return eig_sequence(G, ld, N, lam, V, ldv, work, st, tol, trace);
   {
-    // kernel attributes are set outside any capture
+    // kernel attributes are set once, on the first call
     constexpr int JS = 64;
     static std::once_flag attr;
     std::call_once(attr, [] {
@@ -884,6 +886,10 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
                                 (int)(JS * (JS + 1) * sizeof(double)));
     });
   }
+  if (N < kEigGraphMinN) return eig_sequence(G, ld, N, lam, V, ldv, work, st, tol, trace);
+  hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(st, &cap) != hipSuccess) return hipErrorInvalidValue;
+  if (cap != hipStreamCaptureStatusNone) return eig_sequence(G, ld, N, lam, V, ldv, work, st, tol, trace);
   EigGraph key{};
   (void)hipGetDevice(&key.dev);
   key.G = G; key.lam = lam; key.V = V; key.work = work; key.trace = trace;
@@ -892,13 +898,31 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
   for (auto& e : g_eig_graphs)
     if (e.same(key)) {
       e.used = ++g_eig_clock;
-      return hipGraphLaunch(e.exec, st);
+      const hipError_t le = hipGraphLaunch(e.exec, st);
+      if (le != hipSuccess) return le;
+      return hipEventRecord(e.done, st);
     }
+  // room for the new entry: drop the least recently used entry whose last
+  // launch has finished; if none has, run this sequence uncached
+  if (g_eig_graphs.size() >= kEigGraphs) {
+    ptrdiff_t lru = -1;
+    for (size_t i = 0; i < g_eig_graphs.size(); ++i) {
+      if (hipEventQuery(g_eig_graphs[i].done) != hipSuccess) continue;
+      if (lru < 0 || g_eig_graphs[i].used < g_eig_graphs[(size_t)lru].used) lru = (ptrdiff_t)i;
+    }
+    (void)hipGetLastError();  // hipEventQuery reports hipErrorNotReady for busy entries
+    if (lru < 0) return eig_sequence(G, ld, N, lam, V, ldv, work, st, tol, trace);
+    (void)hipGraphExecDestroy(g_eig_graphs[(size_t)lru].exec);
+    (void)hipGraphDestroy(g_eig_graphs[(size_t)lru].graph);
+    (void)hipEventDestroy(g_eig_graphs[(size_t)lru].done);
+    g_eig_graphs.erase(g_eig_graphs.begin() + lru);
+  }
   hipStream_t cs = nullptr;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
     return eig_sequence(G, ld, N, lam, V, ldv, work, st, tol, trace);
   hipGraph_t g = nullptr;
   hipGraphExec_t ex = nullptr;
+  hipEvent_t ev = nullptr;
   bool ok = hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) == hipSuccess;
   if (ok) {
     const hipError_t le = eig_sequence(G, ld, N, lam, V, ldv, work, cs, tol, trace);
@@ -906,25 +930,21 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
   }
   (void)hipStreamDestroy(cs);
   if (ok) ok = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+  if (ok) ok = hipEventCreateWithFlags(&ev, hipEventDisableTiming) == hipSuccess;
   if (!ok) {
+    if (ex) (void)hipGraphExecDestroy(ex);
     if (g) (void)hipGraphDestroy(g);
     (void)hipGetLastError();
     return eig_sequence(G, ld, N, lam, V, ldv, work, st, tol, trace);
   }
-  if (g_eig_graphs.size() >= kEigGraphs) {
-    size_t lru = 0;
-    for (size_t i = 1; i < g_eig_graphs.size(); ++i)
-      if (g_eig_graphs[i].used < g_eig_graphs[lru].used) lru = i;
-    (void)hipDeviceSynchronize();
-    (void)hipGraphExecDestroy(g_eig_graphs[lru].exec);
-    (void)hipGraphDestroy(g_eig_graphs[lru].graph);
-    g_eig_graphs.erase(g_eig_graphs.begin() + (ptrdiff_t)lru);
-  }
   key.graph = g;
   key.exec = ex;
+  key.done = ev;
   key.used = ++g_eig_clock;
   g_eig_graphs.push_back(key);
-  return hipGraphLaunch(ex, st);
+  const hipError_t le = hipGraphLaunch(ex, st);
+  if (le != hipSuccess) return le;
+  return hipEventRecord(ev, st);
 }
 
 // Batched eigensolver: problem i (G_i N_i x N_i, ld_i, preserved) -> lam_i, V_i.
@@ -1272,8 +1292,8 @@ struct InfoOut {
   double orth_err;
 };
 RF_DEV void k_info_body(InfoOut* info, const int* counters, int k, const double* orth) {
-  int retries = counters[1], nonf = counters[2], last = counters[3], fault = counters[5];
-  info->status = (retries > 0 ? 1 : 0) | (nonf ? 2 : 0) | (fault ? 4 : 0);
+  int retries = counters[1], nonf = counters[2], last = counters[3], fault = counters[5], bad = counters[6];
+  info->status = (retries > 0 ? 1 : 0) | (nonf ? 2 : 0) | (fault ? 4 : 0) | (bad ? 8 : 0);
   info->rank_found = k - last;
   info->chol_retries = retries;
   info->nonfinite = nonf;

@@ -30,6 +30,8 @@ struct Dims {
   int64_t m, n;
   int k, r1, s, q;
   int dtype, prec;
+  bool classical;  // S = I_n (RF_FLAG_CLASSICAL): At = A, Omega n x k; r1 then sizes S2 only
+  int64_t rw;      // rows of Omega, Z and At^T Q: n when classical, else r1
 };
 
 struct RFBufs {
@@ -48,19 +50,20 @@ static size_t max3(size_t a, size_t b, size_t c) { return a > b ? (a > c ? a : c
 static RFBufs carve_rf(Arena& ar, const Dims& d) {
   RFBufs b;
   const bool mixed = d.prec == RF_PREC_MIXED;
-  b.table = ar.get<int32_t>((size_t)d.n * d.s);
-  b.ready = ar.get<uint32_t>((size_t)d.n * d.s);
-  b.cmax = ar.get<int>(sketch_right_cmax_ints(d.n));
-  b.om = ar.get<float>((size_t)d.r1 * d.k);
-  b.om16 = mixed ? ar.get<uint16_t>((size_t)d.r1 * d.k) : nullptr;
-  b.At = ar.get<float>((size_t)d.m * d.r1);
-  b.At16 = mixed ? ar.get<uint16_t>((size_t)d.m * d.r1) : nullptr;
+  const bool sk = !d.classical;  // the sketch pass and its tables exist only for S != I
+  b.table = sk ? ar.get<int32_t>((size_t)d.n * d.s) : nullptr;
+  b.ready = sk ? ar.get<uint32_t>((size_t)d.n * d.s) : nullptr;
+  b.cmax = sk ? ar.get<int>(sketch_right_cmax_ints(d.n)) : nullptr;
+  b.om = ar.get<float>((size_t)d.rw * d.k);
+  b.om16 = mixed ? ar.get<uint16_t>((size_t)d.rw * d.k) : nullptr;
+  b.At = sk ? ar.get<float>((size_t)d.m * d.r1) : nullptr;
+  b.At16 = (sk && mixed) ? ar.get<uint16_t>((size_t)d.m * d.r1) : nullptr;
   b.Ya = ar.get<float>((size_t)d.m * d.k);
   b.Yb = ar.get<float>((size_t)d.m * d.k);
   b.Q16 = mixed ? ar.get<uint16_t>((size_t)d.m * d.k) : nullptr;
-  b.Zh = ar.get<float>((size_t)d.r1 * d.k);
-  b.Z = ar.get<float>((size_t)d.r1 * d.k);
-  b.Z16 = mixed ? ar.get<uint16_t>((size_t)d.r1 * d.k) : nullptr;
+  b.Zh = ar.get<float>((size_t)d.rw * d.k);
+  b.Z = ar.get<float>((size_t)d.rw * d.k);
+  b.Z16 = mixed ? ar.get<uint16_t>((size_t)d.rw * d.k) : nullptr;
   b.G = ar.get<double>((size_t)d.k * d.k);
   b.d0 = ar.get<double>((size_t)d.k);
   b.flags = ar.get<int>((size_t)d.k);
@@ -68,8 +71,8 @@ static RFBufs carve_rf(Arena& ar, const Dims& d) {
   b.Rinv = ar.get<float>((size_t)d.k * d.k);
   b.triwork = ar.get<double>((size_t)d.k * d.k);
   b.cwork = ar.get<int>(cholinv_work_ints(d.k));
-  b.gpart = ar.get<double>(gram_partial_doubles(d.m > d.r1 ? d.m : d.r1, d.k, d.k));
-  b.mpart = ar.get<float>(gemm_partial_floats(d.r1, d.k, d.m));
+  b.gpart = ar.get<double>(gram_partial_doubles(d.m > d.rw ? d.m : d.rw, d.k, d.k));
+  b.mpart = ar.get<float>(gemm_partial_floats(d.rw, d.k, d.m));
   b.orth = ar.get<double>(2);
   return b;
 }
@@ -123,34 +126,49 @@ static void cholqr_pass(Ctx& c, RFBufs& b, float* X, float* out, int64_t rows, i
   gemm(c, 0, X, k, 1, b.Rinv, k, 0, out, k, rows, k, k, nullptr, nullptr, 0, 1);
 }
 
+// Operand At of the power products.  Sketched: At = A S (FP32, and its BF16 copy
+// in the mixed form).  Classical (S = I): At = A itself, FP32 operands read as
+// stored, BF16 operands by rounding A to BF16 as it is loaded (GEMM dtype 4).
+struct AtOp {
+  const void* p32; int64_t ld32;           // FP32 operand (GEMM dtype 0)
+  const void* p16; int64_t ld16; int dt16;  // BF16 operand (dtype 2, or 4 for FP32 A)
+};
+
 // Algorithm 1.  Result (m x k FP32, ld k) in `Qout`; b.Ya/b.Yb are used as scratch.
+// table_in / om_in: a caller-given sketch table (already checked for the block
+// layout) and Omega (rw x k, ld k), or null to draw them from the seed.
 static void range_finder_core(Ctx& c, const rf_matrix* A, const Dims& d, uint64_t seed, RFBufs& b, float* Qout,
                               const int32_t* table_in = nullptr, const float* om_in = nullptr) {
   const bool mixed = d.prec == RF_PREC_MIXED;
-  const int k = d.k, r1 = d.r1;
-  c.chk(launch_fill_i32(b.counters, 16, 0, c.st));
-  const int32_t* table = table_in;
-  if (!table) {
-    c.chk(launch_sketch_table(d.n, d.s, r1, seed, 0, 0, b.table, c.st));
-    table = b.table;
-  }
-  const bool fast = sketch_right_fast_ok(d.s);
-  if (fast) c.chk(launch_sketch_ready(table, d.n, d.s, r1, sketch_right_cpl(d.s), b.ready, c.st));
+  const int k = d.k;
+  const int64_t rw = d.rw;
+  if (!table_in) c.chk(launch_fill_i32(b.counters, 16, 0, c.st));
   const float* om = om_in;
   if (!om) {
-    c.chk(launch_gaussian(r1, k, seed, 1, 0, b.om, k, c.st));
+    c.chk(launch_gaussian(rw, k, seed, 1, 0, b.om, k, c.st));
     om = b.om;
   }
-  // At = A S  (one pass over A)
-  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, table, fast ? b.ready : nullptr, b.cmax, d.s, d.m, d.n,
-                            r1, b.At, r1, c.st));
-  if (mixed) {
-    c.chk(launch_cast_f32_bf16(b.At, r1, b.At16, r1, d.m, r1, c.st));
-    c.chk(launch_cast_f32_bf16(om, k, b.om16, k, r1, k, c.st));
+  AtOp at;
+  if (d.classical) {
+    at = AtOp{A->data, A->ld, A->data, A->ld, 4};
+  } else {
+    const int32_t* table = table_in;
+    if (!table) {
+      c.chk(launch_sketch_table(d.n, d.s, d.r1, seed, 0, 0, b.table, c.st));
+      table = b.table;
+    }
+    const bool fast = sketch_right_fast_ok(d.s);
+    if (fast) c.chk(launch_sketch_ready(table, d.n, d.s, d.r1, sketch_right_cpl(d.s), b.ready, c.st));
+    // At = A S  (one pass over A)
+    c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, table, fast ? b.ready : nullptr, b.cmax, d.s,
+                              d.m, d.n, d.r1, b.At, d.r1, c.st));
+    if (mixed) c.chk(launch_cast_f32_bf16(b.At, d.r1, b.At16, d.r1, d.m, d.r1, c.st));
+    at = AtOp{b.At, d.r1, b.At16, d.r1, 2};
   }
+  if (mixed) c.chk(launch_cast_f32_bf16(om, k, b.om16, k, rw, k, c.st));
   // Y0 = At Omega
-  if (mixed && d.q > 0) gemm(c, 2, b.At16, r1, 1, b.om16, k, 0, b.Ya, k, d.m, k, r1, nullptr);
-  else gemm(c, 0, b.At, r1, 1, om, k, 0, b.Ya, k, d.m, k, r1, nullptr);
+  if (mixed && d.q > 0) gemm(c, at.dt16, at.p16, at.ld16, 1, b.om16, k, 0, b.Ya, k, d.m, k, rw, nullptr);
+  else gemm(c, 0, at.p32, at.ld32, 1, om, k, 0, b.Ya, k, d.m, k, rw, nullptr);
   if (d.q == 0) {
     cholqr_pass(c, b, b.Ya, b.Yb, d.m, k, seed);
     cholqr_pass(c, b, b.Yb, Qout, d.m, k, seed);
@@ -162,18 +180,18 @@ static void range_finder_core(Ctx& c, const rf_matrix* A, const Dims& d, uint64_
     // Zh = At^T Q  (contraction over m, split-K)
     if (mixed) {
       c.chk(launch_cast_f32_bf16(Qc, k, b.Q16, k, d.m, k, c.st));
-      gemm(c, 2, b.At16, r1, 0, b.Q16, k, 0, b.Zh, k, r1, k, d.m, b.mpart);
+      gemm(c, at.dt16, at.p16, at.ld16, 0, b.Q16, k, 0, b.Zh, k, rw, k, d.m, b.mpart);
     } else {
-      gemm(c, 0, b.At, r1, 0, Qc, k, 0, b.Zh, k, r1, k, d.m, b.mpart);
+      gemm(c, 0, at.p32, at.ld32, 0, Qc, k, 0, b.Zh, k, rw, k, d.m, b.mpart);
     }
-    cholqr_pass(c, b, b.Zh, b.Z, r1, k, seed);
+    cholqr_pass(c, b, b.Zh, b.Z, rw, k, seed);
     // Y = At Z; the last product is taken in FP32 in both forms
     const bool last = (j == d.q);
     if (mixed && !last) {
-      c.chk(launch_cast_f32_bf16(b.Z, k, b.Z16, k, r1, k, c.st));
-      gemm(c, 2, b.At16, r1, 1, b.Z16, k, 0, b.Ya, k, d.m, k, r1, nullptr);
+      c.chk(launch_cast_f32_bf16(b.Z, k, b.Z16, k, rw, k, c.st));
+      gemm(c, at.dt16, at.p16, at.ld16, 1, b.Z16, k, 0, b.Ya, k, d.m, k, rw, nullptr);
     } else {
-      gemm(c, 0, b.At, r1, 1, b.Z, k, 0, b.Ya, k, d.m, k, r1, nullptr);
+      gemm(c, 0, at.p32, at.ld32, 1, b.Z, k, 0, b.Ya, k, d.m, k, rw, nullptr);
     }
     if (last) {
       cholqr_pass(c, b, b.Ya, b.Yb, d.m, k, seed);
@@ -194,6 +212,7 @@ static bool valid_matrix(const rf_matrix* A) {
 
 static bool valid_params(const rf_matrix* A, const rf_params* p, bool square) {
   if (!p) return false;
+  if (p->flags & ~(RF_FLAG_ORTH_ERR | RF_FLAG_CLASSICAL)) return false;
   int64_t mn = A->rows < A->cols ? A->rows : A->cols;
   if (square) {
     if (A->rows != A->cols) return false;
@@ -211,6 +230,8 @@ static Dims dims_of(const rf_matrix* A, const rf_params* p) {
   d.m = A->rows; d.n = A->cols;
   d.k = p->k; d.r1 = p->sketch; d.s = p->nnz_per_col; d.q = p->q;
   d.dtype = A->dtype; d.prec = p->precision;
+  d.classical = (p->flags & RF_FLAG_CLASSICAL) != 0;
+  d.rw = d.classical ? d.n : d.r1;
   return d;
 }
 
@@ -397,10 +418,15 @@ rf_status rf_sketch_apply_left(const rf_matrix* A, const rf_params* p, float* ou
   return finish(c);
 }
 
-rf_status rf_range_finder(const rf_matrix* A, const rf_params* p, float* Q, int64_t ldq, void* ws, size_t ws_bytes,
-                          rf_info* info, void* stream) {
+// Algorithm 1 as an entry point: rf_range_finder draws S and Omega from the seed,
+// rf_range_finder_ex may take either from the caller.
+static rf_status range_finder_entry(const rf_matrix* A, const rf_params* p, const int32_t* S_table,
+                                    const float* Omega, float* Q, int64_t ldq, void* ws, size_t ws_bytes,
+                                    rf_info* info, void* stream) {
   if (!valid_matrix(A) || !valid_params(A, p, false) || !Q || ldq < p->k) return RF_EINVAL;
   Dims d = dims_of(A, p);
+  if (d.classical && S_table) return RF_EINVAL;  // S = I has no table
+  if (d.classical && A->dtype != RF_F32) return RF_EUNSUPPORTED;
   if (!ws || ws_bytes < ws_size(RF_OP_RANGE_FINDER, d)) return RF_EWORKSPACE;
   Arena ar(align_ws(ws));
   RFBufs b = carve_rf(ar, d);
@@ -408,7 +434,14 @@ rf_status rf_range_finder(const rf_matrix* A, const rf_params* p, float* Q, int6
   if (ldq == d.k) Qw = Q;
   Ctx c;
   c.st = (hipStream_t)stream;
-  range_finder_core(c, A, d, p->seed, b, Qw, nullptr, nullptr);
+  const int32_t* table = nullptr;
+  if (S_table) {
+    // entries outside their block are replaced and reported (info status bit 8)
+    c.chk(launch_fill_i32(b.counters, 16, 0, c.st));
+    c.chk(launch_table_sanitize(S_table, d.n, d.s, d.r1, b.table, &b.counters[6], c.st));
+    table = b.table;
+  }
+  range_finder_core(c, A, d, p->seed, b, Qw, table, Omega);
   if (p->flags & RF_FLAG_ORTH_ERR) {
     c.chk(launch_gram(Qw, d.k, 0, Qw, d.k, 0, d.m, d.k, d.k, 1, b.G, d.k, b.gpart, nullptr, c.st));
     c.chk(launch_orth_err(b.G, d.k, d.k, b.orth, c.st));
@@ -418,12 +451,23 @@ rf_status rf_range_finder(const rf_matrix* A, const rf_params* p, float* Q, int6
   return finish(c);
 }
 
+rf_status rf_range_finder(const rf_matrix* A, const rf_params* p, float* Q, int64_t ldq, void* ws, size_t ws_bytes,
+                          rf_info* info, void* stream) {
+  return range_finder_entry(A, p, nullptr, nullptr, Q, ldq, ws, ws_bytes, info, stream);
+}
+
+rf_status rf_range_finder_ex(const rf_matrix* A, const int32_t* S_table, const float* Omega, const rf_params* p,
+                             float* Q, int64_t ldq, void* ws, size_t ws_bytes, rf_info* info, void* stream) {
+  return range_finder_entry(A, p, S_table, Omega, Q, ldq, ws, ws_bytes, info, stream);
+}
+
 rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, double* sigma, float* Vt, int64_t ldvt,
                  void* ws, size_t ws_bytes, rf_info* info, void* stream) {
   if (!valid_matrix(A) || !valid_params(A, p, false) || !U || !sigma || !Vt || ldu < p->k || ldvt < A->cols)
     return RF_EINVAL;
   if (p->k > 4096) return RF_EUNSUPPORTED;
   Dims d = dims_of(A, p);
+  if (d.classical && A->dtype != RF_F32) return RF_EUNSUPPORTED;
   if (!ws || ws_bytes < ws_size(RF_OP_SVD, d)) return RF_EWORKSPACE;
   Arena ar(align_ws(ws));
   RFBufs b = carve_rf(ar, d);
@@ -472,6 +516,7 @@ rf_status rf_lowrank(const rf_matrix* A, const rf_params* p, float* Y, int64_t l
                      size_t ws_bytes, rf_info* info, void* stream) {
   if (!valid_matrix(A) || !valid_params(A, p, false) || !Y || !X || ldy < p->k || ldx < A->cols) return RF_EINVAL;
   Dims d = dims_of(A, p);
+  if (d.classical && A->dtype != RF_F32) return RF_EUNSUPPORTED;
   if (!ws || ws_bytes < ws_size(RF_OP_LOWRANK, d)) return RF_EWORKSPACE;
   Arena ar(align_ws(ws));
   RFBufs b = carve_rf(ar, d);
@@ -502,6 +547,7 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
   if (!valid_matrix(A) || !valid_params(A, p, true) || !C || !W || ldc < p->k || ldw < p->k || (F && ldf < p->k))
     return RF_EINVAL;
   if (F && p->k > 4096) return RF_EUNSUPPORTED;
+  if (p->flags & RF_FLAG_CLASSICAL) return RF_EUNSUPPORTED;
   Dims d = dims_of(A, p);
   if (!ws || ws_bytes < ws_size(RF_OP_NYSTROM, d)) return RF_EWORKSPACE;
   Arena ar(align_ws(ws));
@@ -521,10 +567,24 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
                             r1, b.At, r1, c.st));
   c.chk(launch_sketch_left(0, b.At, r1, b.table, d.s, n, r1, r1, y.Wt, r1, y.lpart, c.st, nullptr, y.lwork));
   c.chk(launch_symmetrize(y.Wt, r1, r1, c.st));
-  // Y = Wt^q Omega, re-orthonormalised after every product
+  // Y = Wt^q Omega, re-orthonormalised after every product.  Mixed form: every
+  // product but the last on BF16 MFMA (Wt and Y rounded to BF16; the iterate is
+  // re-orthonormalised in FP64 Gram/Cholesky afterwards), the last one in FP32
+  // so that the span of the final Y, which fixes C and W, carries FP32 rounding
+  // only (the same rule as the last power product of Algorithm 1).  C = Ct Y
+  // stays FP32 in both forms: C W^+ C^T is quadratic in C.
+  const bool mixed = d.prec == RF_PREC_MIXED;
+  uint16_t* Wt16 = b.At16;  // n x r1 BF16 buffer of the mixed form, >= r1 x r1
+  uint16_t* Y16 = b.om16;   // r1 x k BF16
+  if (mixed && d.q > 1) c.chk(launch_cast_f32_bf16(y.Wt, r1, Wt16, r1, r1, r1, c.st));
   c.chk(launch_copy_f32(b.om, k, y.Yc, k, r1, k, c.st));
   for (int j = 0; j < d.q; ++j) {
-    gemm(c, 0, y.Wt, r1, 1, y.Yc, k, 0, y.T1, k, r1, k, r1, nullptr);
+    if (mixed && j + 1 < d.q) {
+      c.chk(launch_cast_f32_bf16(y.Yc, k, Y16, k, r1, k, c.st));
+      gemm(c, 2, Wt16, r1, 1, Y16, k, 0, y.T1, k, r1, k, r1, nullptr);
+    } else {
+      gemm(c, 0, y.Wt, r1, 1, y.Yc, k, 0, y.T1, k, r1, k, r1, nullptr);
+    }
     cholqr_pass(c, b, y.T1, y.Yn, r1, k, p->seed);
     float* t = y.Yc; y.Yc = y.Yn; y.Yn = t;
   }
@@ -544,6 +604,22 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
   }
   c.chk(launch_info(info, b.counters, k, nullptr, c.st));
   return finish(c);
+}
+
+// ------------------------------------------------------------------ storage forms
+rf_status rf_quantize_bf16(const float* A, int64_t rows, int64_t cols, int64_t lda, uint16_t* out, int64_t ldo,
+                           void* stream) {
+  if (rows < 0 || cols < 0 || lda < cols || ldo < cols || ((!A || !out) && rows * cols > 0)) return RF_EINVAL;
+  return launch_quant_bf16(A, rows, cols, lda, out, ldo, (hipStream_t)stream) == hipSuccess ? RF_OK : RF_EHIP;
+}
+
+rf_status rf_quantize_fp8_b128(const float* A, int64_t rows, int64_t cols, int64_t lda, uint8_t* out, int64_t ldo,
+                               float* scales, void* stream) {
+  if (rows < 0 || cols < 0 || lda < cols || ldo < cols || ((!A || !out || !scales) && rows * cols > 0))
+    return RF_EINVAL;
+  if ((rows + 127) / 128 > 65535) return RF_EUNSUPPORTED;
+  return launch_quant_fp8_b128(A, rows, cols, lda, out, ldo, scales, (hipStream_t)stream) == hipSuccess ? RF_OK
+                                                                                                       : RF_EHIP;
 }
 
 // ------------------------------------------------------------------ parity hooks

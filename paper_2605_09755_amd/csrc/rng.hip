@@ -145,6 +145,33 @@ hipError_t launch_gaussian(int64_t rows, int64_t cols, uint64_t seed, uint32_t s
   return hipGetLastError();
 }
 
+// Caller-given sketch table (rf_range_finder_ex): entry t of row j must lie in
+// block t = [floor(t r1/s), floor((t+1) r1/s)), the layout every sketch kernel
+// indexes by.  Valid entries are copied; an entry outside its block is replaced
+// by the block's first column (keeping its sign) and counted in *bad, so no
+// kernel reads or writes outside its buffers whatever the table holds.
+__global__ void k_table_sanitize(const int32_t* __restrict__ in, int64_t n, int s, int r1, int32_t* __restrict__ out,
+                                 int* bad) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * s) return;
+  const int t = (int)(idx % s);
+  const uint32_t lo = (uint32_t)(((int64_t)t * r1) / s), hi = (uint32_t)(((int64_t)(t + 1) * r1) / s);
+  const uint32_t e = (uint32_t)in[idx], bucket = e & 0x7fffffffu;
+  if (bucket >= lo && bucket < hi) {
+    out[idx] = (int32_t)e;
+  } else {
+    out[idx] = (int32_t)((e & 0x80000000u) | lo);
+    atomicAdd(bad, 1);
+  }
+}
+
+hipError_t launch_table_sanitize(const int32_t* in, int64_t n, int s, int r1, int32_t* out, int* bad, hipStream_t st) {
+  const int64_t tot = n * s;
+  if (tot == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_table_sanitize, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, in, n, s, r1, out, bad);
+  return hipGetLastError();
+}
+
 hipError_t launch_rng_batched(const RngArgs* as, int count, int64_t max_entries, hipStream_t st) {
   if (count == 0) return hipSuccess;
   unsigned gx = (unsigned)((max_entries + 255) / 256);

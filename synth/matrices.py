@@ -65,6 +65,9 @@ WORKLOADS = {
     "poly65k": dict(m=65536, n=16384, law="poly", p=1.5, noise_spec=1e-4, k=1000, l=2000, s=8, q=2, seed=102),
     # 65536 x 32768, sigma_i = max(0.995^i, 1e-3 sigma_1)
     "exp65k": dict(m=65536, n=32768, law="expfloor", base=0.995, floor=1e-3, k=2000, l=4000, s=8, q=3, seed=103),
+    # the paper's synthetic "polydecay" (Section 4): 30000 x 15000, sigma_i = 30000 / i,
+    # random orthogonal factors, no noise; k = 40, l in {800, 1200, 1600}, CountSketch
+    "polydecay": dict(m=30000, n=15000, law="inv", scale=30000.0, k=40, l=800, s=1, q=2, seed=106),
 }
 
 
@@ -87,7 +90,7 @@ def workload(name, m=None, n=None, seed=None):
     n = w["n"] if n is None else n
     seed = w["seed"] if seed is None else seed
     r = min(m, n)
-    sig = sigma_law(w["law"], r, w.get("p", 1.0), w.get("base", 0.995), w.get("floor", 1e-3))
+    sig = w.get("scale", 1.0) * sigma_law(w["law"], r, w.get("p", 1.0), w.get("base", 0.995), w.get("floor", 1e-3))
     std = 0.0
     if "noise_var" in w:
         std = float(np.sqrt(w["noise_var"]))

@@ -55,6 +55,49 @@ def test_batched_fp32_matches_oracle(use_graph):
         assert int.from_bytes(info[i, 0:4].tobytes(), "little") & 2 == 0
 
 
+def _truncated_problem(m, n, k, p, seed, r=None):
+    """U diag(sigma) V^T with sigma_i = i^-p and Haar factors of rank r (the
+    spectrum law of the batched workload, truncated so that a 8192 x 4096
+    instance is generated in seconds)."""
+    r = min(m, n) if r is None else r
+    sigma = np.arange(1, r + 1, dtype=np.float64) ** -p
+    return synth.spectrum_matrix(m, n, sigma, seed).astype(np.float32)
+
+
+def test_batched_fp32_matches_oracle_at_workload_ranks():
+    """Ranks of the batched workload (k up to 256, so the Cholesky/inverse runs
+    2 to 4 tiles of 64 and the batched Jacobi several rounds), m up to 8192,
+    n up to 4096, sketch = min(2k, n), s = 4, q = 2: each problem against the
+    oracle (problem index i in the Philox counter)."""
+    shapes = [(3000, 1500, 64, 1.2), (2500, 1200, 65, 0.7), (4000, 2000, 128, 1.5), (3000, 2500, 200, 0.5),
+              (8192, 4096, 256, 1.0)]
+    probs = []
+    for i, (m, n, k, pw) in enumerate(shapes):
+        A = _truncated_problem(m, n, k, pw, 300 + i, r=min(m, n, 1024))
+        probs.append((A, k, min(2 * k, n)))
+    As = [torch.from_numpy(A).to(DEV) for A, _, _ in probs]
+    for precision in ("fp32", "mixed"):
+        plan = rf.BatchPlan(As, [k for _, k, _ in probs], [l for _, _, l in probs], q=2, seeds=21,
+                            precision=precision, use_graph=True).run()
+        torch.cuda.synchronize()
+        for i, (A, k, l) in enumerate(probs):
+            ref = _oracle(A, k, l, 2, i, 21)
+            A64 = A.astype(np.float64)
+            U = plan.U[i].cpu().numpy().astype(np.float64)
+            sig = plan.sigma[i].cpu().numpy()
+            eg, eo = ev.frob_error(A64, U), ev.frob_error(A64, ref.U)
+            print("%s problem %d (m %d n %d k %d): err gpu %.8e oracle %.8e rel %.2e" %
+                  (precision, i, A.shape[0], A.shape[1], k, eg, eo, abs(eg - eo) / eo))
+            assert np.max(np.abs(U.T @ U - np.eye(k))) < 2e-5
+            if precision == "fp32":
+                tol = 1e-5 * ref.sigma + 2e-6 * ref.sigma[0]
+                assert np.all(np.abs(sig - ref.sigma) <= tol), (i, np.max(np.abs(sig - ref.sigma) / tol))
+                assert abs(eg - eo) <= 1e-4 * eo, i
+            else:
+                assert eg <= 1.02 * eo, i
+        del plan
+
+
 def test_batched_mixed_error_against_oracle():
     probs = _problems(2, 5)
     As = [torch.from_numpy(A).to(DEV) for A, _, _ in probs]

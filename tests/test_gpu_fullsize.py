@@ -126,3 +126,34 @@ def test_fullsize_svd(instance, precision):
         assert abs(e_gpu - e_ref) <= 1e-4 * e_ref
     else:
         assert abs(e_gpu - e_ref) <= 2e-2 * e_ref
+
+
+def test_fullsize_mixed_sigma_weyl_bound(instance):
+    """Mixed form at full size: B = Q^T A is taken on BF16 MFMA with A and Q
+    rounded to BF16 as they are loaded.  By Weyl's inequality its singular values
+    differ from those of the exact Q^T A (FP64, the mixed form's own Q) by at
+    most ||Q^T dA||_2 + ||dQ^T bf16(A)||_2 (dA, dQ the BF16 rounding errors) plus
+    FP32 accumulation (~sqrt(m) u32 sigma_1); the FP64 Ritz step adds
+    1e-5 sigma_i + 2e-6 sigma_1 at most, as in the FP32 form.  Q is the mixed
+    range finder's output (the same kernels as inside rf_svd)."""
+    A32, A64, _ = instance
+    U, sig, Vt, info = rf.rf_svd(A32, K, L, Q, S, SEED, "mixed")
+    Qm, _ = rf.rf_range_finder(A32, K, L, Q, S, SEED, "mixed")
+    torch.cuda.synchronize()
+    Qd = Qm.double()
+    def svals(X):  # singular values of a wide k x n matrix from the FP64 eigenvalues of X X^T
+        lam = torch.linalg.eigvalsh(X @ X.t()).clamp_min(0).sqrt()
+        return torch.flip(lam, [0])
+    B = Qd.t() @ A64
+    exact = svals(B).cpu().numpy()
+    Ab = A32.to(torch.bfloat16).double()
+    dQ = Qd - Qm.to(torch.bfloat16).double()
+    e1 = float(svals(Qd.t() @ (A64 - Ab))[0])
+    e2 = float(svals(dQ.t() @ Ab)[0])
+    acc = math.sqrt(M) * U32 * exact[0]
+    sig = sig.cpu().numpy()
+    tol = e1 + e2 + acc + 1e-5 * exact + 2e-6 * exact[0]
+    d = np.abs(sig - exact)
+    print("mixed sigma: ||Q^T dA|| %.3e ||dQ^T A|| %.3e  max |dsigma| %.3e  max |dsigma|/tol %.3f  "
+          "max rel (top 100) %.2e" % (e1, e2, d.max(), np.max(d / tol), np.max(d[:100] / exact[:100])))
+    assert np.all(d <= tol)

@@ -163,6 +163,28 @@ def test_classical_reduction_converges_to_truncated_svd():
     assert np.allclose(res.sigma, sv[:k], rtol=1e-10)
 
 
+def test_classical_form_equals_identity_sketch():
+    """classical=True (At = A, Omega n x k) is Algorithm 1 with S = I_n: the
+    identity table with r1 = n, s = 1 gives At = A exactly in FP64, so the two
+    paths agree to rounding, for the range finder, RandSVD and Algorithm 2
+    with S1 = I."""
+    A = small(70, 40, seed=21, decay=0.8)
+    n = A.shape[1]
+    for q in (0, 2):
+        p_cl = me.Params(k=6, l=12, q=q, s=3, seed=9)
+        cl = me.range_finder(A, p_cl, classical=True)
+        Om = sk.omega(n, 6, 9)
+        via = me.range_finder(A, me.Params(k=6, l=n, q=q, s=1, seed=9), table=identity_table(n), Om=Om)
+        assert np.array_equal(cl.extras["Omega"], Om)
+        assert np.allclose(cl.Q, via.Q, atol=1e-12)
+        sv = me.rand_svd(A, p_cl, classical=True)
+        assert np.allclose(sv.sigma, np.linalg.svd(via.Q.T @ A, compute_uv=False), rtol=1e-12)
+    lr = me.lowrank(A, me.Params(k=6, l=12, q=1, s=3, seed=9), classical=True)
+    P, T = lr.extras["P"], lr.extras["T"]
+    assert P.shape == (12, 6) and T.shape == (12, n)
+    assert np.allclose(P.T @ (P @ lr.X - T), 0, atol=1e-10)
+
+
 def test_sketched_converges_to_top_subspace_of_At():
     """With a sparse S the iteration converges to the top-k left singular
     subspace of At = A S, not of A (proof sketch of Theorem 3.5, Section 3.1;
