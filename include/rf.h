@@ -257,6 +257,20 @@ size_t rf_sketch_apply_ws(const rf_matrix* A, const rf_params* p);
 rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, int64_t ldo,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* Allocation-free form of rf_sketch_apply, for callers that cannot allocate
+   device memory (code under stream capture, tight serving loops, harnesses that
+   forbid allocation): same arguments and same result bits, no workspace.  The
+   sketch table, its kernel-ready form and the per-chunk occupancy live in a
+   library-owned device array of 8 MiB per GPU, held until the process ends.
+   Limit: 8 n s + 4 (n/1024 + 16) bytes, each of the three parts rounded up to
+   256, must fit in 8 MiB (n s <= 1,048,000 or so; e.g. n = 65536 with s = 8);
+   larger requests return RF_EUNSUPPORTED with nothing enqueued.  Every call on a
+   GPU shares that GPU's array: calls that overlap on one GPU (other streams,
+   other threads) race and must be serialised by the caller.  No hipMalloc, no
+   synchronisation; RF_EINVAL as rf_sketch_apply, RF_EHIP if the array's device
+   address cannot be looked up. */
+rf_status rf_sketch_apply_noalloc(const rf_matrix* A, const rf_params* p, float* out, int64_t ldo, void* stream);
+
 /* T = S2^T A, the left sketch of Algorithm 2 (line 2) as rf_lowrank applies it:
    S2 is m x r1 (r1 = p->sketch) with s = p->nnz_per_col entries +-1/sqrt(s) per row,
    drawn from (seed, stream id 2); out r1 x n FP32 row-major (ldo >= n).  Any

@@ -23,7 +23,7 @@ __all__ = [
     "lib", "library_path", "rf_status_string", "rf_workspace_size", "rf_sketch_table", "rf_gaussian",
     "rf_sketch_apply", "rf_sketch_apply_left", "rf_range_finder", "rf_svd", "rf_lowrank", "rf_nystrom", "RFError",
     "BatchPlan", "rf_svd_batched", "set_gemm_rules", "load_tuning", "rf_range_finder_ex", "RF_FLAG_CLASSICAL",
-    "rf_quantize_bf16", "rf_quantize_fp8_b128",
+    "rf_quantize_bf16", "rf_quantize_fp8_b128", "rf_sketch_apply_noalloc",
 ]
 
 RF_OK, RF_EINVAL, RF_EWORKSPACE, RF_EUNSUPPORTED, RF_EHIP = 0, 1, 2, 3, 4
@@ -84,6 +84,8 @@ def lib():
         L.rf_sketch_apply_ws.argtypes = [M, P]
         L.rf_sketch_apply.restype = i32
         L.rf_sketch_apply.argtypes = [M, P, vp, i64, vp, sz, vp]
+        L.rf_sketch_apply_noalloc.restype = i32
+        L.rf_sketch_apply_noalloc.argtypes = [M, P, vp, i64, vp]
         L.rf_sketch_apply_left_ws.restype = sz
         L.rf_sketch_apply_left_ws.argtypes = [M, P]
         L.rf_sketch_apply_left.restype = i32
@@ -276,6 +278,19 @@ def rf_sketch_apply(A, sketch, nnz_per_col, seed, scales=None):
     out = torch.empty((A.shape[0], sketch), dtype=torch.float32, device=A.device)
     _check("rf_sketch_apply", lib().rf_sketch_apply(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(out),
                                                     sketch, _ptr(ws), nws, _stream(A.device)))
+    return out
+
+
+def rf_sketch_apply_noalloc(A, sketch, nnz_per_col, seed, scales=None, out=None):
+    """A S as rf_sketch_apply computes it, through the library's allocation-free
+    entry point (no workspace; calls on one GPU must not overlap)."""
+    p = params(1, sketch, 0, nnz_per_col, seed)
+    if out is None:
+        out = torch.empty((A.shape[0], sketch), dtype=torch.float32, device=A.device)
+    else:
+        _check_out("out", out, (A.shape[0], sketch), torch.float32, A.device)
+    _check("rf_sketch_apply_noalloc", lib().rf_sketch_apply_noalloc(ctypes.byref(matrix(A, scales)), ctypes.byref(p),
+                                                                    _ptr(out), sketch, _stream(A.device)))
     return out
 
 
