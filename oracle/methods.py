@@ -102,7 +102,17 @@ def power_loop(At, Om, q):
     return Q, rank
 
 
-def range_finder(A, p: Params, table=None, Om=None, classical=False):
+def sketch_dense_family(n, p: Params, family):
+    """S of a dense family of Lemma 3.2 (item 1: "rademacher" / "gaussian";
+    item 3: "srht") as an n x r1 matrix, drawn from p.seed."""
+    if family in ("rademacher", "gaussian"):
+        return sk.dense_sketch(n, p.l, p.seed, family, p.b)
+    if family == "srht":
+        return sk.srht_matrix(n, p.l, p.seed, p.b)
+    raise ValueError(family)
+
+
+def range_finder(A, p: Params, table=None, Om=None, classical=False, family="sparse"):
     """Algorithm 1.  Pinned by: Eckart-Young lower bound, exact recovery for
     rank(A) <= k, q = 0 span identity, S = I reduction to the classical range
     finder and its convergence to the truncated SVD, convergence to the top-k
@@ -117,6 +127,12 @@ def range_finder(A, p: Params, table=None, Om=None, classical=False):
         Om = sk.omega(A.shape[1], p.k, p.seed, p.b) if Om is None else Om
         Q, rank = power_loop(A, Om, p.q)
         return Result(Q=Q, At=A, rank_found=rank, extras={"table": None, "Omega": Om})
+    if family != "sparse":
+        # Lemma 3.2 items 1 and 3: the same Algorithm 1 with a dense S
+        Om = sk.omega(p.l, p.k, p.seed, p.b) if Om is None else Om
+        At = A @ sketch_dense_family(A.shape[1], p, family)
+        Q, rank = power_loop(At, Om, p.q)
+        return Result(Q=Q, At=At, rank_found=rank, extras={"table": None, "Omega": Om})
     table, Om = draws(A.shape[1], p, table, Om)
     At = sketch_right(A, table, p.l)
     Q, rank = power_loop(At, Om, p.q)
@@ -132,12 +148,12 @@ def svd_sign_fix(U, Vt):
     return U * sgn[None, :], Vt * sgn[:, None]
 
 
-def rand_svd(A, p: Params, table=None, Om=None, classical=False):
+def rand_svd(A, p: Params, table=None, Om=None, classical=False, family="sparse"):
     """Randomised SVD on top of Algorithm 1 (Section 2; Section 4 protocol).
     Pinned by: U Sigma V^T = Q Q^T A, sigma_i(B) <= sigma_i(A) (interlacing),
     orthonormality of U and V."""
     A = np.asarray(A, dtype=np.float64)
-    res = range_finder(A, p, table, Om, classical)
+    res = range_finder(A, p, table, Om, classical, family)
     B = res.Q.T @ A
     Ub, sig, Vt = np.linalg.svd(B, full_matrices=False)
     U = res.Q @ Ub
@@ -147,13 +163,13 @@ def rand_svd(A, p: Params, table=None, Om=None, classical=False):
     return res
 
 
-def lowrank(A, p: Params, table1=None, Om=None, table2=None, classical=False):
+def lowrank(A, p: Params, table1=None, Om=None, table2=None, classical=False, family="sparse"):
     """Algorithm 2.  Pinned by: S2 = I reduces Y X to Q Q^T A; the normal
     equations (S2^T Q)^T (S2^T Q X - S2^T A) = 0.  classical=True runs it with
     S1 = I (the baseline of the additional experiments); S2 keeps p.l rows."""
     A = np.asarray(A, dtype=np.float64)
     m = A.shape[0]
-    res = range_finder(A, p, table1, Om, classical)
+    res = range_finder(A, p, table1, Om, classical, family)
     if table2 is None:
         table2 = sk.sketch_table(m, p.s, p.l, p.seed, sk.STREAM_S2, p.b)
     P = sketch_left(res.Q, table2, p.l)

@@ -28,7 +28,12 @@ from .philox import draw
 STREAM_S1 = 0      # S of Algorithm 1 / S1 of Algorithm 2 / S of Algorithm 3
 STREAM_OMEGA = 1   # Omega
 STREAM_S2 = 2      # S2 of Algorithm 2
+STREAM_DENSE = 4   # dense sub-Gaussian S (Lemma 3.2, item 1)
+STREAM_SRHT_D = 5  # random signs D of the SRHT (Lemma 3.2, item 3)
+STREAM_SRHT_P = 6  # the sampled column subset of the SRHT
 SIGN_BIT = np.int64(1) << 31
+
+SKETCH_FAMILIES = ("sparse", "rademacher", "gaussian", "srht")
 
 
 def block_bounds(r1, s):
@@ -97,3 +102,77 @@ def gaussian(rows, cols, seed, stream=STREAM_OMEGA, b=0):
 def omega(r1, r2, seed, b=0, dtype=np.float32):
     """Omega as the GPU stores it (rounded to `dtype`), returned in float64."""
     return gaussian(r1, r2, seed, STREAM_OMEGA, b).astype(dtype).astype(np.float64)
+
+
+# ---- Lemma 3.2, item 1: dense sub-Gaussian sketches ----------------------------
+def dense_sketch(n, r1, seed, kind, b=0):
+    """S (n x r1) with independent entries scaled by 1/sqrt(r1) (Lemma 3.2 item 1).
+
+    kind "rademacher": +-1/sqrt(r1); entry e = i*r1 + j is negative iff the top
+    bit of word x0 of Philox counter e (stream 4) is set.
+    kind "gaussian": N(0, 1/r1) = gaussian(n, r1, seed, stream 4) / sqrt(r1),
+    with the FP32 rounding of the N(0,1) draws the GPU stores."""
+    if kind == "rademacher":
+        x0, _, _, _ = draw(np.arange(n * r1, dtype=np.uint64), seed, STREAM_DENSE, b)
+        sign = np.where(x0 >> np.uint64(31), -1.0, 1.0)
+        return sign.reshape(n, r1) / math.sqrt(r1)
+    if kind == "gaussian":
+        z = gaussian(n, r1, seed, STREAM_DENSE, b).astype(np.float32).astype(np.float64)
+        return z / math.sqrt(r1)
+    raise ValueError(kind)
+
+
+# ---- Lemma 3.2, item 3: subsampled randomised Hadamard transform ---------------
+def srht_size(n):
+    """n' = the smallest power of two >= n (A is padded with zero columns)."""
+    p = 1
+    while p < n:
+        p *= 2
+    return p
+
+
+def _feistel(x, bits, seed, b):
+    """Keyed permutation of [0, 2**bits) (bits even): four Feistel rounds on two
+    halves of bits/2 bits, round function = word x0 of Philox counter
+    (half | round << 32) on stream 6 (Luby-Rackoff construction)."""
+    h = bits // 2
+    mask = np.uint64((1 << h) - 1)
+    left = (x >> np.uint64(h)) & mask
+    right = x & mask
+    for rnd in range(4):
+        f, _, _, _ = draw(right | (np.uint64(rnd) << np.uint64(32)), seed, STREAM_SRHT_P, b)
+        left, right = right, (left ^ f) & mask
+    return (left << np.uint64(h)) | right
+
+
+def srht_draws(n, r1, seed, b=0):
+    """(d, picks) of S = D H I_{:,P} / sqrt(r1) (Lemma 3.2 item 3) on n' = srht_size(n).
+
+    d: n' signs, d_j = -1 iff the top bit of x0 of Philox counter j (stream 5) is set.
+    picks: the r1-element subset P of [0, n'), ascending: the images of 0..r1-1
+    under a keyed permutation of [0, n') -- a 4-round Feistel network on the
+    even number of bits >= log2 n', walked along its cycle until the value falls
+    below n' (cycle walking keeps it a permutation of [0, n'))."""
+    n2 = srht_size(n)
+    if not (1 <= r1 <= n2):
+        raise ValueError("need 1 <= r1 <= n'")
+    x0, _, _, _ = draw(np.arange(n2, dtype=np.uint64), seed, STREAM_SRHT_D, b)
+    d = np.where(x0 >> np.uint64(31), -1.0, 1.0)
+    bits = max(2, (n2 - 1).bit_length())
+    bits += bits & 1
+    v = _feistel(np.arange(r1, dtype=np.uint64), bits, seed, b)
+    out = v >= np.uint64(n2)
+    while np.any(out):                      # cycle walking, element by element
+        v[out] = _feistel(v[out], bits, seed, b)
+        out = v >= np.uint64(n2)
+    return d, np.sort(v.astype(np.int64))
+
+
+def srht_matrix(n, r1, seed, b=0):
+    """The SRHT as a dense n x r1 matrix: S = D H[:, P] / sqrt(r1), H the
+    Sylvester-Hadamard matrix of order n' (entries +-1, H H^T = n' I), rows
+    restricted to the first n (the zero padding of A)."""
+    import scipy.linalg as sla
+    d, picks = srht_draws(n, r1, seed, b)
+    H = sla.hadamard(srht_size(n))
+    return (d[:, None] * H[:, picks])[:n] / math.sqrt(r1)

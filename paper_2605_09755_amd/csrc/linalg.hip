@@ -417,6 +417,17 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
     return;
   }
   if (threadIdx.x == 0) w.ident[x] = 0;
+  // the pairs (lo, hi) of every inner round of the circle schedule, computed once:
+  // the inner loop then reads them instead of repeating the modular arithmetic
+  __shared__ unsigned char pair_lo[JS - 1][JS / 2], pair_hi[JS - 1][JS / 2];
+  for (int e = threadIdx.x; e < (JS - 1) * (JS / 2); e += blockDim.x) {
+    const int rr = e / (JS / 2), u = e % (JS / 2);
+    int a = circle(rr, u, JS), b = circle(rr, JS - 1 - u, JS);
+    if (a > b) { const int t = a; a = b; b = t; }
+    pair_lo[rr][u] = (unsigned char)a;
+    pair_hi[rr][u] = (unsigned char)b;
+  }
+  __syncthreads();
   for (int sw = 0; sw < inner_sweeps; ++sw) {
     if (threadIdx.x == 0) done = 1;
     __syncthreads();
@@ -427,12 +438,11 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
     __syncthreads();
     if (done) break;
     for (int rr = 0; rr < JS - 1; ++rr) {
-      // pair u of inner round rr: (lo, hi) of circle positions u and JS-1-u,
-      // recomputed by every thread; the rotations go through LDS as (c, s) pairs
+      // pair u of inner round rr: (lo, hi) of circle positions u and JS-1-u, from
+      // the table; the rotations go through LDS as (c, s) pairs
       auto pair_of = [&](int u, int& a, int& b) {
-        a = circle(rr, u, JS);
-        b = circle(rr, JS - 1 - u, JS);
-        if (a > b) { const int t = a; a = b; b = t; }
+        a = pair_lo[rr][u];
+        b = pair_hi[rr][u];
       };
       if (threadIdx.x < JS / 2) {
         const int u = threadIdx.x;

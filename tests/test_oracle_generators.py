@@ -93,3 +93,79 @@ def test_gaussian_prefix_consistency():
     a = sk.gaussian(10, 7, seed=3)
     b = sk.gaussian(20, 7, seed=3)
     assert np.array_equal(a, b[:10])
+
+
+# ---- Lemma 3.2 items 1 and 3: dense sub-Gaussian sketches and the SRHT ----------
+def _fwht_recursive(x):
+    """Walsh-Hadamard transform by the textbook recursion H_2n = [[H, H], [H, -H]]
+    (written out independently of scipy's hadamard)."""
+    x = list(x)
+    if len(x) == 1:
+        return x
+    h = len(x) // 2
+    a, b = _fwht_recursive(x[:h]), _fwht_recursive(x[h:])
+    return [u + v for u, v in zip(a, b)] + [u - v for u, v in zip(a, b)]
+
+
+def test_dense_rademacher_structure():
+    n, r1 = 300, 40
+    S = sk.dense_sketch(n, r1, 7, "rademacher")
+    assert np.all(np.abs(np.abs(S) - 1 / np.sqrt(r1)) < 1e-15)
+    # every row has squared norm exactly 1 (diag of S S^T), the signs balance
+    assert np.allclose(np.sum(S * S, axis=1), 1.0, atol=1e-12)
+    assert abs(np.mean(np.sign(S))) < 4 / np.sqrt(n * r1)
+    # independent of the sparse sketch's stream and of other seeds
+    assert not np.array_equal(S, sk.dense_sketch(n, r1, 8, "rademacher"))
+    off = (S @ S.T)[~np.eye(n, dtype=bool)]
+    assert abs(off.mean()) < 3 / np.sqrt(r1 * n) and 0.5 / r1 < off.var() < 2 / r1
+
+
+def test_dense_gaussian_moments():
+    from scipy import stats
+    n, r1 = 400, 50
+    S = sk.dense_sketch(n, r1, 3, "gaussian") * np.sqrt(r1)
+    assert abs(S.mean()) < 4 / np.sqrt(S.size) and abs(S.var() - 1) < 0.05
+    assert stats.kstest(S.ravel(), "norm").pvalue > 1e-3
+
+
+@pytest.mark.parametrize("n", [1, 2, 8, 64])
+def test_hadamard_matches_recursive_walsh_hadamard(n):
+    """x^T H (the oracle's H) equals the recursive transform of x."""
+    import scipy.linalg as sla
+    x = np.random.default_rng(n).standard_normal(n)
+    assert np.allclose(x @ sla.hadamard(n), _fwht_recursive(x), atol=1e-12)
+
+
+@pytest.mark.parametrize("bits", [2, 4, 6])
+def test_feistel_is_a_permutation(bits):
+    v = sk._feistel(np.arange(1 << bits, dtype=np.uint64), bits, 11, 0)
+    assert sorted(v.tolist()) == list(range(1 << bits))
+
+
+@pytest.mark.parametrize("n,r1", [(100, 20), (128, 128), (1000, 300), (5, 3)])
+def test_srht_draws_structure(n, r1):
+    d, picks = sk.srht_draws(n, r1, 5)
+    n2 = sk.srht_size(n)
+    assert n2 >= n and n2 & (n2 - 1) == 0 and n2 < 2 * max(n, 1)
+    assert len(d) == n2 and set(np.unique(d)) <= {-1.0, 1.0}
+    assert len(picks) == r1 and len(set(picks.tolist())) == r1
+    assert np.all(np.diff(picks) > 0) and picks[0] >= 0 and picks[-1] < n2
+
+
+def test_srht_columns_orthogonal():
+    """S^T S = (n'/r1) I exactly when n = n' (H H^T = n' I, D^2 = I)."""
+    S = sk.srht_matrix(256, 40, 3)
+    assert np.allclose(S.T @ S, (256 / 40) * np.eye(40), atol=1e-12)
+    # and S is isotropic: S S^T has expectation I (its trace is exactly n' * r1 / r1 ... = 256)
+    assert np.isclose(np.trace(S @ S.T), 256.0)
+
+
+def test_srht_subset_is_uniform():
+    """Each index of [0, n') is picked with probability r1/n' (chi-squared over seeds)."""
+    n, r1, trials = 64, 16, 400
+    cnt = np.zeros(n)
+    for sd in range(trials):
+        cnt[sk.srht_draws(n, r1, 1000 + sd)[1]] += 1
+    exp = trials * r1 / n
+    chi2 = np.sum((cnt - exp) ** 2 / exp)
+    assert chi2 < n + 5 * np.sqrt(2 * n)

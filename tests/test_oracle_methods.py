@@ -267,3 +267,24 @@ def test_nystrom_identity_theorem_2_5(q):
     lhs = np.linalg.norm(A - Ahat, 2)
     rhs = np.linalg.norm(Ah - proj(rf.Q) @ Ah, 2) ** 2
     assert abs(lhs - rhs) < 1e-10
+
+
+@pytest.mark.parametrize("family", ["rademacher", "gaussian", "srht"])
+def test_dense_families_algorithm_1(family):
+    """Algorithm 1 with the dense sketches of Lemma 3.2 (items 1 and 3): exact
+    recovery for rank(A) <= k, the q = 0 span is that of A S Omega, and the
+    Eckart-Young lower bound holds."""
+    rng = np.random.default_rng(4)
+    m, n, r, k, l = 90, 70, 5, 8, 20
+    A = rng.standard_normal((m, r)) @ rng.standard_normal((r, n))
+    p = me.Params(k=k, l=l, q=1, s=1, seed=6)
+    res = me.range_finder(A, p, family=family)
+    assert ev.frob_error_explicit(A, res.Q) <= 1e-10 * np.linalg.norm(A)
+    B = small(60, 50, seed=3, decay=0.7)
+    p0 = me.Params(k=6, l=16, q=0, s=1, seed=2)
+    res0 = me.range_finder(B, p0, family=family)
+    S = me.sketch_dense_family(50, p0, family)
+    Y = B @ S @ res0.extras["Omega"]
+    assert np.allclose(proj(res0.Q), proj(np.linalg.qr(Y)[0]), atol=1e-10)
+    sv = np.linalg.svd(B, compute_uv=False)
+    assert ev.frob_error(B, res0.Q) >= ev.opt_frob(sv, 6) * (1 - 1e-12)
