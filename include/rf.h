@@ -91,6 +91,31 @@ enum { RF_OP_RANGE_FINDER = 0, RF_OP_SVD = 1, RF_OP_LOWRANK = 2, RF_OP_NYSTROM =
                                  last product At Z stays FP32.  Not accepted by rf_nystrom
                                  (RF_EUNSUPPORTED). */
 
+/* Sketch family of S in Algorithm 1 (Lemma 3.2), in bits 2-3 of rf_params.flags
+   (not with RF_FLAG_CLASSICAL; rf_nystrom and the batched path take the sparse
+   sign sketch only, RF_EUNSUPPORTED otherwise):
+   RF_SKETCH_SPARSE     item 2: s = nnz_per_col nonzeros +-1/sqrt(s) per row (default).
+   RF_SKETCH_RADEMACHER item 1: dense, entries +-1/sqrt(r1) (sign = top bit of word x0
+                        of Philox counter i*r1 + j, stream 4).
+   RF_SKETCH_GAUSSIAN   item 1: dense, entries N(0,1)/sqrt(r1) (the Box-Muller
+                        generator of rf_gaussian on stream 4, rounded to FP32).
+   RF_SKETCH_SRHT       item 3: S = D H I_{:,P} / sqrt(r1) on n' = the smallest power of
+                        two >= n (A padded with zero columns): D signs from stream 5,
+                        H Sylvester-Hadamard (+-1), P = the images of 0..r1-1 under a
+                        keyed 4-round Feistel permutation of [0, n') (round function
+                        from stream 6, cycle walking), sorted.  n' <= 32768 and
+                        r1 <= 8192 (RF_EUNSUPPORTED otherwise).
+   The dense families run A S as a dense product: FP32 MFMA in the plain form, BF16
+   MFMA (A and S rounded to BF16) in the mixed form or for BF16-stored A; FP8-stored
+   A is RF_EUNSUPPORTED with them.  nnz_per_col is ignored by the dense families
+   and the SRHT (it must still be valid).  rf_range_finder_ex takes a table only
+   with RF_SKETCH_SPARSE (RF_EINVAL otherwise). */
+#define RF_SKETCH_SPARSE 0u
+#define RF_SKETCH_RADEMACHER (1u << 2)
+#define RF_SKETCH_GAUSSIAN (2u << 2)
+#define RF_SKETCH_SRHT (3u << 2)
+#define RF_SKETCH_MASK (3u << 2)
+
 typedef struct {
   const void* data;           /* device, row-major rows x cols, leading dim ld (elements) */
   const float* block_scales;  /* device; required iff dtype == RF_FP8E4M3_B128, else NULL */
@@ -251,8 +276,9 @@ rf_status rf_gaussian(int64_t rows, int64_t cols, uint64_t seed, uint32_t stream
                       float* out, void* stream);
 
 /* At = A S for the sketch given by (s = p->nnz_per_col, r1 = p->sketch, seed,
-   stream id 0): out m x r1 FP32 (ldo >= r1).  Any r1 >= s is accepted (p->k,
-   p->q ignored).  ws >= rf_sketch_apply_ws(A, p) bytes. */
+   stream id 0, and the family in p->flags, RF_SKETCH_*): out m x r1 FP32
+   (ldo >= r1).  Any r1 >= s is accepted (p->k, p->q ignored; p->precision picks
+   the product form of the dense families).  ws >= rf_sketch_apply_ws(A, p) bytes. */
 size_t rf_sketch_apply_ws(const rf_matrix* A, const rf_params* p);
 rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, int64_t ldo,
                           void* ws, size_t ws_bytes, void* stream);

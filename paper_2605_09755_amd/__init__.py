@@ -32,6 +32,8 @@ RF_PREC_FP32, RF_PREC_MIXED = 0, 1
 RF_OP_RANGE_FINDER, RF_OP_SVD, RF_OP_LOWRANK, RF_OP_NYSTROM = 0, 1, 2, 3
 RF_FLAG_ORTH_ERR = 1
 RF_FLAG_CLASSICAL = 2
+# sketch family of Algorithm 1's S (Lemma 3.2), bits 2-3 of the flags
+RF_SKETCH = {"sparse": 0, "rademacher": 1 << 2, "gaussian": 2 << 2, "srht": 3 << 2}
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 library_path = os.path.join(_HERE, "librf.so")
@@ -269,8 +271,9 @@ def rf_gaussian(rows, cols, seed, stream_id=1, b=0, device="cuda"):
     return out
 
 
-def rf_sketch_apply(A, sketch, nnz_per_col, seed, scales=None):
-    p = params(1, sketch, 0, nnz_per_col, seed)
+def rf_sketch_apply(A, sketch, nnz_per_col, seed, scales=None, family="sparse", precision="fp32"):
+    """A S (m x sketch) for the sketch family of Algorithm 1's S (the parity hook)."""
+    p = params(1, sketch, 0, nnz_per_col, seed, precision, RF_SKETCH[family])
     nws = int(lib().rf_sketch_apply_ws(ctypes.byref(matrix(A, scales)), ctypes.byref(p)))
     if nws == 0:
         raise RFError("rf_sketch_apply_ws", RF_EINVAL)
@@ -308,14 +311,15 @@ def rf_sketch_apply_left(A, sketch, nnz_per_col, seed, scales=None):
     return out
 
 
-def _flags(orth_err=False, classical=False):
-    return (RF_FLAG_ORTH_ERR if orth_err else 0) | (RF_FLAG_CLASSICAL if classical else 0)
+def _flags(orth_err=False, classical=False, family="sparse"):
+    return (RF_FLAG_ORTH_ERR if orth_err else 0) | (RF_FLAG_CLASSICAL if classical else 0) | RF_SKETCH[family]
 
 
 def rf_range_finder(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, orth_err=False,
-                    workspace=None, classical=False):
-    """Algorithm 1.  classical=True runs S = I (Omega n x k): the baseline of Section 2."""
-    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(orth_err, classical))
+                    workspace=None, classical=False, family="sparse"):
+    """Algorithm 1.  classical=True runs S = I (Omega n x k): the baseline of Section 2.
+    family: "sparse" (Lemma 3.2 item 2), "rademacher" / "gaussian" (item 1), "srht" (item 3)."""
+    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(orth_err, classical, family))
     ws, nws = _workspace(RF_OP_RANGE_FINDER, A, p, scales, workspace)
     Q = torch.empty((A.shape[0], k), dtype=torch.float32, device=A.device)
     info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
@@ -325,11 +329,11 @@ def rf_range_finder(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", 
 
 
 def rf_range_finder_ex(A, k, sketch, S_table=None, Omega=None, q=0, nnz_per_col=8, seed=0, precision="fp32",
-                       scales=None, orth_err=False, classical=False, workspace=None):
+                       scales=None, orth_err=False, classical=False, workspace=None, family="sparse"):
     """Algorithm 1 with a caller-given sketch table (int32 n x s, the layout of
     rf_sketch_table) and/or Omega (float32 rows x k; rows = sketch, or n when
     classical).  None draws that input from the seed."""
-    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(orth_err, classical))
+    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(orth_err, classical, family))
     ws, nws = _workspace(RF_OP_RANGE_FINDER, A, p, scales, workspace)
     n = A.shape[1]
     if S_table is not None:
@@ -345,8 +349,8 @@ def rf_range_finder_ex(A, k, sketch, S_table=None, Omega=None, q=0, nnz_per_col=
 
 
 def rf_svd(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, orth_err=False,
-           workspace=None, out=None, classical=False):
-    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(orth_err, classical))
+           workspace=None, out=None, classical=False, family="sparse"):
+    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(orth_err, classical, family))
     ws, nws = _workspace(RF_OP_SVD, A, p, scales, workspace)
     m, n = A.shape
     if out is None:
@@ -366,9 +370,9 @@ def rf_svd(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=No
 
 
 def rf_lowrank(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scales=None, workspace=None,
-               classical=False):
+               classical=False, family="sparse"):
     """Algorithm 2; classical=True runs it with S1 = I (S2 still has `sketch` rows)."""
-    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(False, classical))
+    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(False, classical, family))
     ws, nws = _workspace(RF_OP_LOWRANK, A, p, scales, workspace)
     m, n = A.shape
     Y = torch.empty((m, k), dtype=torch.float32, device=A.device)

@@ -57,6 +57,17 @@ hipError_t launch_sketch_left(int dtype, const void* X, int64_t ldx, const int32
                               int64_t N, int r1, float* out, int64_t ldo, float* partial, hipStream_t st,
                               const float* scales = nullptr, int* work = nullptr);
 
+// ---- sketch families of Lemma 3.2 items 1 and 3 (families.hip) ----
+// kind 1: Rademacher +-1, kind 2: N(0,1) (stream 4), n x r1 row-major FP32, unscaled
+hipError_t launch_dense_sketch(int kind, int64_t n, int r1, uint64_t seed, uint32_t b, float* out, hipStream_t st);
+int64_t srht_size(int64_t n);  // smallest power of two >= n
+bool srht_supported(int64_t n, int r1);  // n' <= 32768, r1 <= min(n', 8192)
+// d: srht_size(n) floats (+-1), picks: r1 ints (ascending)
+hipError_t launch_srht_prep(int64_t n, int r1, uint64_t seed, uint32_t b, float* d, int* picks, hipStream_t st);
+// out (m x r1, ldo) = A D H I_{:,picks} / sqrt(r1); dtype 0 FP32, 2 BF16, 3 FP8 with 128x128 scales
+hipError_t launch_srht_rows(int dtype, const void* A, int64_t lda, const float* scales, int64_t m, int64_t n,
+                            const float* d, const int* picks, int r1, float* out, int64_t ldo, hipStream_t st);
+
 // ---- storage forms of A (quant.hip) ----
 // out (rows x cols, ldo) = BF16 of A (round to nearest even)
 hipError_t launch_quant_bf16(const float* A, int64_t rows, int64_t cols, int64_t lda, uint16_t* out, int64_t ldo,

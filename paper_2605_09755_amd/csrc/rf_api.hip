@@ -32,10 +32,13 @@ struct Dims {
   int dtype, prec;
   bool classical;  // S = I_n (RF_FLAG_CLASSICAL): At = A, Omega n x k; r1 then sizes S2 only
   int64_t rw;      // rows of Omega, Z and At^T Q: n when classical, else r1
+  int family;      // S of Algorithm 1: 0 sparse sign, 1 Rademacher, 2 Gaussian, 3 SRHT (Lemma 3.2)
 };
 
 struct RFBufs {
   int32_t* table; uint32_t* ready; int* cmax;
+  float* Sd; uint16_t* Sd16;  // dense S (Rademacher / Gaussian), unscaled
+  float* srd; int* picks;     // SRHT signs and sampled columns
   float* om; uint16_t* om16;
   float* At; uint16_t* At16;
   float* Ya; float* Yb; uint16_t* Q16;
@@ -50,10 +53,15 @@ static size_t max3(size_t a, size_t b, size_t c) { return a > b ? (a > c ? a : c
 static RFBufs carve_rf(Arena& ar, const Dims& d) {
   RFBufs b;
   const bool mixed = d.prec == RF_PREC_MIXED;
-  const bool sk = !d.classical;  // the sketch pass and its tables exist only for S != I
-  b.table = sk ? ar.get<int32_t>((size_t)d.n * d.s) : nullptr;
-  b.ready = sk ? ar.get<uint32_t>((size_t)d.n * d.s) : nullptr;
-  b.cmax = sk ? ar.get<int>(sketch_right_cmax_ints(d.n)) : nullptr;
+  const bool sk = !d.classical;  // At = A S exists only for S != I
+  const bool sparse = sk && d.family == 0, dense = sk && (d.family == 1 || d.family == 2), srht = sk && d.family == 3;
+  b.table = sparse ? ar.get<int32_t>((size_t)d.n * d.s) : nullptr;
+  b.ready = sparse ? ar.get<uint32_t>((size_t)d.n * d.s) : nullptr;
+  b.cmax = sparse ? ar.get<int>(sketch_right_cmax_ints(d.n)) : nullptr;
+  b.Sd = dense ? ar.get<float>((size_t)d.n * d.r1) : nullptr;
+  b.Sd16 = (dense && (mixed || d.dtype == RF_BF16)) ? ar.get<uint16_t>((size_t)d.n * d.r1) : nullptr;
+  b.srd = srht ? ar.get<float>((size_t)srht_size(d.n)) : nullptr;
+  b.picks = srht ? ar.get<int>((size_t)d.r1) : nullptr;
   b.om = ar.get<float>((size_t)d.rw * d.k);
   b.om16 = mixed ? ar.get<uint16_t>((size_t)d.rw * d.k) : nullptr;
   b.At = sk ? ar.get<float>((size_t)d.m * d.r1) : nullptr;
@@ -88,7 +96,7 @@ struct Ctx {
 static void gemm(Ctx& c, int dtype, const void* A, int64_t lda, int a_kc, const void* B, int64_t ldb, int b_kc, void* C,
                  int64_t ldc, int64_t M, int64_t N, int64_t K, float* partial, const float* colscale = nullptr,
                  int c_trans = 0, int b_upper = 0, int c_bf16 = 0, const float* a_scales = nullptr,
-                 int64_t a_ldsc = 0, int split_cap = 0) {
+                 int64_t a_ldsc = 0, int split_cap = 0, float alpha = 1.f) {
   GemmArgs g;
   memset(&g, 0, sizeof(g));
   g.a_scales = a_scales;
@@ -97,7 +105,7 @@ static void gemm(Ctx& c, int dtype, const void* A, int64_t lda, int a_kc, const 
   g.B = B; g.ldb = ldb; g.b_kc = b_kc;
   g.C = C; g.ldc = ldc; g.c_trans = c_trans; g.c_bf16 = c_bf16;
   g.M = M; g.N = N; g.K = K;
-  g.alpha = 1.f;
+  g.alpha = alpha;
   g.colscale = colscale;
   g.b_upper = b_upper;
   g.split_cap = split_cap;
@@ -126,6 +134,43 @@ static void cholqr_pass(Ctx& c, RFBufs& b, float* X, float* out, int64_t rows, i
   gemm(c, 0, X, k, 1, b.Rinv, k, 0, out, k, rows, k, k, nullptr, nullptr, 0, 1);
 }
 
+// At = A S (m x r1 FP32, ld r1) for the sketch family of d, drawn from `seed`
+// (or from `table_in` for the sparse sign sketch).  One pass over A for the
+// sparse sketch and the SRHT; a dense product on MFMA for the dense families
+// (A S / sqrt(r1) with S = +-1 or N(0,1): FP32 MFMA in the plain form, BF16 MFMA
+// in the mixed form or for BF16-stored A).
+static void sketch_right_any(Ctx& c, const rf_matrix* A, const Dims& d, uint64_t seed, RFBufs& b, float* out,
+                             int64_t ldo, const int32_t* table_in) {
+  const bool mixed = d.prec == RF_PREC_MIXED;
+  if (d.family == 1 || d.family == 2) {
+    c.chk(launch_dense_sketch(d.family, d.n, d.r1, seed, 0, b.Sd, c.st));
+    const float alpha = 1.0f / sqrtf((float)d.r1);
+    if (A->dtype == RF_F32 && !mixed) {
+      gemm(c, 0, A->data, A->ld, 1, b.Sd, d.r1, 0, out, ldo, d.m, d.r1, d.n, nullptr, nullptr, 0, 0, 0, nullptr, 0, 0,
+           alpha);
+    } else {
+      c.chk(launch_cast_f32_bf16(b.Sd, d.r1, b.Sd16, d.r1, d.n, d.r1, c.st));
+      gemm(c, A->dtype == RF_BF16 ? 2 : 4, A->data, A->ld, 1, b.Sd16, d.r1, 0, out, ldo, d.m, d.r1, d.n, nullptr,
+           nullptr, 0, 0, 0, nullptr, 0, 0, alpha);
+    }
+    return;
+  }
+  if (d.family == 3) {
+    c.chk(launch_srht_prep(d.n, d.r1, seed, 0, b.srd, b.picks, c.st));
+    c.chk(launch_srht_rows(A->dtype, A->data, A->ld, A->block_scales, d.m, d.n, b.srd, b.picks, d.r1, out, ldo, c.st));
+    return;
+  }
+  const int32_t* table = table_in;
+  if (!table) {
+    c.chk(launch_sketch_table(d.n, d.s, d.r1, seed, 0, 0, b.table, c.st));
+    table = b.table;
+  }
+  const bool fast = sketch_right_fast_ok(d.s);
+  if (fast) c.chk(launch_sketch_ready(table, d.n, d.s, d.r1, sketch_right_cpl(d.s), b.ready, c.st));
+  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, table, fast ? b.ready : nullptr, b.cmax, d.s,
+                            d.m, d.n, d.r1, out, ldo, c.st));
+}
+
 // Operand At of the power products.  Sketched: At = A S (FP32, and its BF16 copy
 // in the mixed form).  Classical (S = I): At = A itself, FP32 operands read as
 // stored, BF16 operands by rounding A to BF16 as it is loaded (GEMM dtype 4).
@@ -152,16 +197,8 @@ static void range_finder_core(Ctx& c, const rf_matrix* A, const Dims& d, uint64_
   if (d.classical) {
     at = AtOp{A->data, A->ld, A->data, A->ld, 4};
   } else {
-    const int32_t* table = table_in;
-    if (!table) {
-      c.chk(launch_sketch_table(d.n, d.s, d.r1, seed, 0, 0, b.table, c.st));
-      table = b.table;
-    }
-    const bool fast = sketch_right_fast_ok(d.s);
-    if (fast) c.chk(launch_sketch_ready(table, d.n, d.s, d.r1, sketch_right_cpl(d.s), b.ready, c.st));
-    // At = A S  (one pass over A)
-    c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, table, fast ? b.ready : nullptr, b.cmax, d.s,
-                              d.m, d.n, d.r1, b.At, d.r1, c.st));
+    // At = A S  (one pass over A for the sparse sketch and the SRHT)
+    sketch_right_any(c, A, d, seed, b, b.At, d.r1, table_in);
     if (mixed) c.chk(launch_cast_f32_bf16(b.At, d.r1, b.At16, d.r1, d.m, d.r1, c.st));
     at = AtOp{b.At, d.r1, b.At16, d.r1, 2};
   }
@@ -212,7 +249,8 @@ static bool valid_matrix(const rf_matrix* A) {
 
 static bool valid_params(const rf_matrix* A, const rf_params* p, bool square) {
   if (!p) return false;
-  if (p->flags & ~(RF_FLAG_ORTH_ERR | RF_FLAG_CLASSICAL)) return false;
+  if (p->flags & ~(RF_FLAG_ORTH_ERR | RF_FLAG_CLASSICAL | RF_SKETCH_MASK)) return false;
+  if ((p->flags & RF_FLAG_CLASSICAL) && (p->flags & RF_SKETCH_MASK)) return false;  // S = I has no family
   int64_t mn = A->rows < A->cols ? A->rows : A->cols;
   if (square) {
     if (A->rows != A->cols) return false;
@@ -232,7 +270,16 @@ static Dims dims_of(const rf_matrix* A, const rf_params* p) {
   d.dtype = A->dtype; d.prec = p->precision;
   d.classical = (p->flags & RF_FLAG_CLASSICAL) != 0;
   d.rw = d.classical ? d.n : d.r1;
+  d.family = (int)((p->flags & RF_SKETCH_MASK) >> 2);
   return d;
+}
+
+// A family this build cannot run for A (FP8 storage with a dense S has no
+// product kernel; the SRHT needs n' <= 32768 and r1 <= 8192).
+static bool family_unsupported(const rf_matrix* A, const Dims& d) {
+  if ((d.family == 1 || d.family == 2) && A->dtype == RF_FP8E4M3_B128) return true;
+  if (d.family == 3 && !srht_supported(d.n, d.r1)) return true;
+  return false;
 }
 
 // Split-K parts the B^T = A^T Q product may use (its partial buffer holds this many
@@ -336,11 +383,35 @@ const char* rf_status_string(rf_status s) {
   return "unknown status";
 }
 
+// Buffers of the sketch pass alone (rf_sketch_apply): the At-producing draws of
+// carve_rf without the power loop's buffers.
+static RFBufs carve_sketch(Arena& ar, const Dims& d) {
+  RFBufs b;
+  memset(&b, 0, sizeof(b));
+  const bool mixed = d.prec == RF_PREC_MIXED;
+  const bool sparse = d.family == 0, dense = d.family == 1 || d.family == 2, srht = d.family == 3;
+  b.table = sparse ? ar.get<int32_t>((size_t)d.n * d.s) : nullptr;
+  b.ready = sparse ? ar.get<uint32_t>((size_t)d.n * d.s) : nullptr;
+  b.cmax = sparse ? ar.get<int>(sketch_right_cmax_ints(d.n)) : nullptr;
+  b.Sd = dense ? ar.get<float>((size_t)d.n * d.r1) : nullptr;
+  b.Sd16 = (dense && (mixed || d.dtype == RF_BF16)) ? ar.get<uint16_t>((size_t)d.n * d.r1) : nullptr;
+  b.srd = srht ? ar.get<float>((size_t)srht_size(d.n)) : nullptr;
+  b.picks = srht ? ar.get<int>((size_t)d.r1) : nullptr;
+  return b;
+}
+
+static bool sketch_apply_args_ok(const rf_matrix* A, const rf_params* p) {
+  // the sketch itself needs only 1 <= s <= r1 (any r1, any shape of A)
+  if (!valid_matrix(A) || !p || p->sketch < 1 || p->nnz_per_col < 1 || p->nnz_per_col > p->sketch) return false;
+  if (p->flags & ~(RF_FLAG_ORTH_ERR | RF_SKETCH_MASK)) return false;
+  return p->precision == RF_PREC_FP32 || p->precision == RF_PREC_MIXED;
+}
+
 size_t rf_sketch_apply_ws(const rf_matrix* A, const rf_params* p) {
-  if (!valid_matrix(A) || !p || p->sketch < 1 || p->nnz_per_col < 1 || p->nnz_per_col > p->sketch) return 0;
-  Dims d = dims_of(A, p);
-  d.k = 1;
-  return ws_size(RF_OP_RANGE_FINDER, d);
+  if (!sketch_apply_args_ok(A, p)) return 0;
+  Arena ar(nullptr);
+  carve_sketch(ar, dims_of(A, p));
+  return ar.off + 256;
 }
 
 size_t rf_workspace_size(int op, const rf_matrix* A, const rf_params* p) {
@@ -364,23 +435,16 @@ rf_status rf_gaussian(int64_t rows, int64_t cols, uint64_t seed, uint32_t stream
 
 rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, int64_t ldo, void* ws, size_t ws_bytes,
                           void* stream) {
-  // the sketch itself needs only 1 <= s <= r1 (any r1, any shape of A)
-  if (!valid_matrix(A) || !p || p->sketch < 1 || p->nnz_per_col < 1 || p->nnz_per_col > p->sketch || !out ||
-      ldo < p->sketch)
-    return RF_EINVAL;
+  if (!sketch_apply_args_ok(A, p) || !out || ldo < p->sketch) return RF_EINVAL;
   Dims d = dims_of(A, p);
   d.k = 1;
-  size_t need = ws_size(RF_OP_RANGE_FINDER, d);
-  if (!ws || ws_bytes < need) return RF_EWORKSPACE;
+  if (family_unsupported(A, d)) return RF_EUNSUPPORTED;
+  if (!ws || ws_bytes < rf_sketch_apply_ws(A, p)) return RF_EWORKSPACE;
   Arena ar(align_ws(ws));
-  RFBufs b = carve_rf(ar, d);
+  RFBufs b = carve_sketch(ar, d);
   Ctx c;
   c.st = (hipStream_t)stream;
-  c.chk(launch_sketch_table(d.n, d.s, d.r1, p->seed, 0, 0, b.table, c.st));
-  const bool fast = sketch_right_fast_ok(d.s);
-  if (fast) c.chk(launch_sketch_ready(b.table, d.n, d.s, d.r1, sketch_right_cpl(d.s), b.ready, c.st));
-  c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, b.table, fast ? b.ready : nullptr, b.cmax, d.s, d.m,
-                            d.n, d.r1, out, ldo, c.st));
+  sketch_right_any(c, A, d, p->seed, b, out, ldo, nullptr);
   return finish(c);
 }
 
@@ -425,7 +489,8 @@ static rf_status range_finder_entry(const rf_matrix* A, const rf_params* p, cons
                                     rf_info* info, void* stream) {
   if (!valid_matrix(A) || !valid_params(A, p, false) || !Q || ldq < p->k) return RF_EINVAL;
   Dims d = dims_of(A, p);
-  if (d.classical && S_table) return RF_EINVAL;  // S = I has no table
+  if ((d.classical || d.family != 0) && S_table) return RF_EINVAL;  // only the sparse sign sketch has a table
+  if (family_unsupported(A, d)) return RF_EUNSUPPORTED;
   if (d.classical && A->dtype != RF_F32) return RF_EUNSUPPORTED;
   if (!ws || ws_bytes < ws_size(RF_OP_RANGE_FINDER, d)) return RF_EWORKSPACE;
   Arena ar(align_ws(ws));
@@ -467,7 +532,7 @@ rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, 
     return RF_EINVAL;
   if (p->k > 4096) return RF_EUNSUPPORTED;
   Dims d = dims_of(A, p);
-  if (d.classical && A->dtype != RF_F32) return RF_EUNSUPPORTED;
+  if ((d.classical && A->dtype != RF_F32) || family_unsupported(A, d)) return RF_EUNSUPPORTED;
   if (!ws || ws_bytes < ws_size(RF_OP_SVD, d)) return RF_EWORKSPACE;
   Arena ar(align_ws(ws));
   RFBufs b = carve_rf(ar, d);
@@ -516,7 +581,7 @@ rf_status rf_lowrank(const rf_matrix* A, const rf_params* p, float* Y, int64_t l
                      size_t ws_bytes, rf_info* info, void* stream) {
   if (!valid_matrix(A) || !valid_params(A, p, false) || !Y || !X || ldy < p->k || ldx < A->cols) return RF_EINVAL;
   Dims d = dims_of(A, p);
-  if (d.classical && A->dtype != RF_F32) return RF_EUNSUPPORTED;
+  if ((d.classical && A->dtype != RF_F32) || family_unsupported(A, d)) return RF_EUNSUPPORTED;
   if (!ws || ws_bytes < ws_size(RF_OP_LOWRANK, d)) return RF_EWORKSPACE;
   Arena ar(align_ws(ws));
   RFBufs b = carve_rf(ar, d);
@@ -547,7 +612,7 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
   if (!valid_matrix(A) || !valid_params(A, p, true) || !C || !W || ldc < p->k || ldw < p->k || (F && ldf < p->k))
     return RF_EINVAL;
   if (F && p->k > 4096) return RF_EUNSUPPORTED;
-  if (p->flags & RF_FLAG_CLASSICAL) return RF_EUNSUPPORTED;
+  if (p->flags & (RF_FLAG_CLASSICAL | RF_SKETCH_MASK)) return RF_EUNSUPPORTED;  // sparse sign S only
   Dims d = dims_of(A, p);
   if (!ws || ws_bytes < ws_size(RF_OP_NYSTROM, d)) return RF_EWORKSPACE;
   Arena ar(align_ws(ws));
