@@ -138,7 +138,9 @@ typedef struct {
   int32_t status;       /* 0 = ok; bit 1 = Cholesky breakdown repaired; bit 2 = non-finite seen;
                            bit 4 = a device task queue gave up waiting (results invalid);
                            bit 8 = a caller-given sketch table had entries outside their
-                           block (rf_range_finder_ex; results are not Algorithm 1's) */
+                           block (rf_range_finder_ex; results are not Algorithm 1's);
+                           bit 16 = a CSR matrix had column indices outside [0, cols),
+                           which were skipped (rf_*_csr) */
   int32_t rank_found;   /* k minus columns refilled during orthonormalisation (last call) */
   int32_t chol_retries; /* number of CholeskyQR passes that needed column refill */
   int32_t nonfinite;    /* 1 if a NaN/Inf was seen in a Gram matrix */
@@ -193,6 +195,41 @@ rf_status rf_lowrank(const rf_matrix* A, const rf_params* p, float* Y, int64_t l
 rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t ldc, double* W,
                      int64_t ldw, float* F, int64_t ldf, void* ws, size_t ws_bytes,
                      rf_info* info, void* stream);
+
+/* ---- sparse A (CSR) ------------------------------------------------------
+   The paper states every cost in nnz(A) (Theorems 2.1, 2.3 and 2.5): the sketch
+   At = A S touches each nonzero s times and the power loop runs on the dense
+   m x r1 At.  A CSR matrix: row_ptr (device int64[rows + 1], row_ptr[0] = 0,
+   nondecreasing, row_ptr[rows] = nnz), col_idx (device int32[nnz], in [0, cols)),
+   values (device FP32[nnz]); nnz < 2^31.  Entries are read as stored: row
+   pointers are clamped to [0, nnz], column indices outside [0, cols) are skipped
+   and reported in info->status bit 16 (rf_sketch_apply_csr: not reported).
+
+   rf_range_finder_csr / rf_svd_csr: as rf_range_finder / rf_svd (outputs, sign
+   convention, precision forms, workspace from rf_workspace_size_csr with
+   RF_OP_RANGE_FINDER / RF_OP_SVD) with the sparse sign sketch only: the sketch
+   pass accumulates each row's r1 outputs exactly in 64-bit fixed point (grid
+   2^F with nnz_row * max|a| * 2^F < 2^62, so each term is rounded to at most
+   2^-(61 - log2 nnz_row) of the row's largest |a|; the sums do not depend on the
+   order of the additions); a row holding a non-finite value gives a NaN row.
+   B^T = A^T Q is a sparse product over a CSC copy of A built on the device (each
+   column in CSR order, FP32 in both forms).  RF_EUNSUPPORTED for RF_FLAG_CLASSICAL,
+   a dense sketch family, or a sketch too large for one row's accumulators in LDS
+   (r1 > 20480).  rf_sketch_apply_csr: At = A S alone (the parity hook; p->flags
+   must be 0), ws >= 4 cols nnz_per_col + 768 bytes. */
+typedef struct {
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  const float* values;
+  int64_t rows, cols, nnz;
+} rf_csr;
+size_t rf_workspace_size_csr(int op, const rf_csr* A, const rf_params* p);
+rf_status rf_range_finder_csr(const rf_csr* A, const rf_params* p, float* Q, int64_t ldq, void* ws, size_t ws_bytes,
+                              rf_info* info, void* stream);
+rf_status rf_svd_csr(const rf_csr* A, const rf_params* p, float* U, int64_t ldu, double* sigma, float* Vt,
+                     int64_t ldvt, void* ws, size_t ws_bytes, rf_info* info, void* stream);
+rf_status rf_sketch_apply_csr(const rf_csr* A, const rf_params* p, float* out, int64_t ldo, void* ws, size_t ws_bytes,
+                              void* stream);
 
 /* ---- storage forms of A (the precision workload: A stored once in BF16 and
    once in FP8-e4m3 with per-128x128-block scales) -------------------------------

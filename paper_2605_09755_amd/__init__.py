@@ -24,6 +24,7 @@ __all__ = [
     "rf_sketch_apply", "rf_sketch_apply_left", "rf_range_finder", "rf_svd", "rf_lowrank", "rf_nystrom", "RFError",
     "BatchPlan", "rf_svd_batched", "set_gemm_rules", "load_tuning", "rf_range_finder_ex", "RF_FLAG_CLASSICAL",
     "rf_quantize_bf16", "rf_quantize_fp8_b128", "rf_sketch_apply_noalloc",
+    "Csr", "rf_range_finder_csr", "rf_svd_csr", "rf_sketch_apply_csr",
 ]
 
 RF_OK, RF_EINVAL, RF_EWORKSPACE, RF_EUNSUPPORTED, RF_EHIP = 0, 1, 2, 3, 4
@@ -49,6 +50,11 @@ class RfParams(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int32), ("sketch", ctypes.c_int32), ("q", ctypes.c_int32),
                 ("nnz_per_col", ctypes.c_int32), ("seed", ctypes.c_uint64), ("precision", ctypes.c_int32),
                 ("flags", ctypes.c_uint32)]
+
+
+class RfCsr(ctypes.Structure):
+    _fields_ = [("row_ptr", ctypes.c_void_p), ("col_idx", ctypes.c_void_p), ("values", ctypes.c_void_p),
+                ("rows", ctypes.c_int64), ("cols", ctypes.c_int64), ("nnz", ctypes.c_int64)]
 
 
 INFO_BYTES = 24  # int32 x 4 + double
@@ -113,6 +119,15 @@ def lib():
         L.rf_svd_batched_run.argtypes = [vp, vp]
         L.rf_svd_batched_destroy.restype = None
         L.rf_svd_batched_destroy.argtypes = [vp]
+        C = ctypes.POINTER(RfCsr)
+        L.rf_workspace_size_csr.restype = sz
+        L.rf_workspace_size_csr.argtypes = [ctypes.c_int, C, P]
+        L.rf_range_finder_csr.restype = i32
+        L.rf_range_finder_csr.argtypes = [C, P, vp, i64, vp, sz, vp, vp]
+        L.rf_svd_csr.restype = i32
+        L.rf_svd_csr.argtypes = [C, P, vp, i64, vp, vp, i64, vp, sz, vp, vp]
+        L.rf_sketch_apply_csr.restype = i32
+        L.rf_sketch_apply_csr.argtypes = [C, P, vp, i64, vp, sz, vp]
         L.rf_quantize_bf16.restype = i32
         L.rf_quantize_bf16.argtypes = [vp, i64, i64, i64, vp, i64, vp]
         L.rf_quantize_fp8_b128.restype = i32
@@ -395,6 +410,79 @@ def rf_nystrom(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", scale
     _check("rf_nystrom", lib().rf_nystrom(ctypes.byref(matrix(A, scales)), ctypes.byref(p), _ptr(C), k, _ptr(W), k,
                                           _ptr(F), k, _ptr(ws), nws, _ptr(info), _stream(A.device)))
     return C, W, F, info
+
+
+class Csr:
+    """A sparse m x n matrix in CSR form on the device: row_ptr (int64, m + 1),
+    col_idx (int32, nnz), values (float32, nnz)."""
+
+    def __init__(self, row_ptr, col_idx, values, shape):
+        m, n = int(shape[0]), int(shape[1])
+        dev = values.device
+        if row_ptr.dtype != torch.int64 or row_ptr.numel() != m + 1 or not row_ptr.is_contiguous():
+            raise ValueError("row_ptr must be a contiguous int64 tensor of m + 1 entries")
+        if col_idx.dtype != torch.int32 or values.dtype != torch.float32 or col_idx.numel() != values.numel():
+            raise ValueError("col_idx (int32) and values (float32) must have nnz entries each")
+        if not (col_idx.is_contiguous() and values.is_contiguous()) or dev.type != "cuda" or \
+                row_ptr.device != dev or col_idx.device != dev:
+            raise ValueError("CSR arrays must be contiguous device tensors on one device")
+        self.row_ptr, self.col_idx, self.values, self.shape, self.device = row_ptr, col_idx, values, (m, n), dev
+        self.nnz = values.numel()
+
+    @classmethod
+    def from_scipy(cls, S, device="cuda"):
+        S = S.tocsr()
+        S.sort_indices()
+        return cls(torch.from_numpy(S.indptr.astype("int64")).to(device),
+                   torch.from_numpy(S.indices.astype("int32")).to(device),
+                   torch.from_numpy(S.data.astype("float32")).to(device), S.shape)
+
+    def desc(self):
+        return RfCsr(self.row_ptr.data_ptr(), self.col_idx.data_ptr(), self.values.data_ptr(), self.shape[0],
+                     self.shape[1], self.nnz)
+
+
+def _csr_ws(op, A, p):
+    n = int(lib().rf_workspace_size_csr(int(op), ctypes.byref(A.desc()), ctypes.byref(p)))
+    if n == 0:
+        raise RFError("rf_workspace_size_csr", RF_EINVAL)
+    return torch.empty(n, dtype=torch.uint8, device=A.device), n
+
+
+def rf_range_finder_csr(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", orth_err=False):
+    """Algorithm 1 on a sparse A (Csr)."""
+    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(orth_err))
+    ws, nws = _csr_ws(RF_OP_RANGE_FINDER, A, p)
+    Q = torch.empty((A.shape[0], k), dtype=torch.float32, device=A.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    _check("rf_range_finder_csr", lib().rf_range_finder_csr(ctypes.byref(A.desc()), ctypes.byref(p), _ptr(Q), k,
+                                                            _ptr(ws), nws, _ptr(info), _stream(A.device)))
+    return Q, info
+
+
+def rf_svd_csr(A, k, sketch, q=0, nnz_per_col=8, seed=0, precision="fp32", orth_err=False):
+    """Randomised SVD on top of Algorithm 1 for a sparse A (Csr)."""
+    p = params(k, sketch, q, nnz_per_col, seed, precision, _flags(orth_err))
+    ws, nws = _csr_ws(RF_OP_SVD, A, p)
+    m, n = A.shape
+    U = torch.empty((m, k), dtype=torch.float32, device=A.device)
+    sig = torch.empty(k, dtype=torch.float64, device=A.device)
+    Vt = torch.empty((k, n), dtype=torch.float32, device=A.device)
+    info = torch.zeros(INFO_BYTES, dtype=torch.uint8, device=A.device)
+    _check("rf_svd_csr", lib().rf_svd_csr(ctypes.byref(A.desc()), ctypes.byref(p), _ptr(U), k, _ptr(sig), _ptr(Vt),
+                                          n, _ptr(ws), nws, _ptr(info), _stream(A.device)))
+    return U, sig, Vt, info
+
+
+def rf_sketch_apply_csr(A, sketch, nnz_per_col, seed):
+    """A S for a sparse A (Csr), the sketch of rf_sketch_apply."""
+    p = params(1, sketch, 0, nnz_per_col, seed)
+    nws = 4 * A.shape[1] * nnz_per_col + 1024
+    ws = torch.empty(nws, dtype=torch.uint8, device=A.device)
+    out = torch.empty((A.shape[0], sketch), dtype=torch.float32, device=A.device)
+    _check("rf_sketch_apply_csr", lib().rf_sketch_apply_csr(ctypes.byref(A.desc()), ctypes.byref(p), _ptr(out),
+                                                            sketch, _ptr(ws), nws, _stream(A.device)))
+    return out
 
 
 def _check_f32_2d(name, A):

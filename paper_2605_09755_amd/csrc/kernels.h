@@ -68,6 +68,20 @@ hipError_t launch_srht_prep(int64_t n, int r1, uint64_t seed, uint32_t b, float*
 hipError_t launch_srht_rows(int dtype, const void* A, int64_t lda, const float* scales, int64_t m, int64_t n,
                             const float* d, const int* picks, int r1, float* out, int64_t ldo, hipStream_t st);
 
+// ---- sparse A in CSR form (csr.hip) ----
+// out (m x r1, ldo) = A S / ... for CSR A (table as launch_sketch_right); *bad += invalid column indices
+hipError_t launch_sketch_csr(const int64_t* row_ptr, const int32_t* col, const float* val, int64_t m, int64_t n,
+                             int64_t nnz, const int32_t* table, int s, int r1, float* out, int64_t ldo, int* bad,
+                             hipStream_t st);
+bool sketch_csr_ok(int r1);  // one row's r1 64-bit accumulators fit in LDS
+// CSC of A: colptr (n+1), cursor (n, scratch), csc_pos (nnz: CSR positions by column, in CSR order), row_of (nnz)
+hipError_t launch_csc_build(const int64_t* row_ptr, const int32_t* col, int64_t m, int64_t n, int64_t nnz,
+                            int64_t* colptr, unsigned long long* cursor, int32_t* csc_pos, int32_t* row_of,
+                            hipStream_t st);
+// out (n x k, ldo) = A^T Q for Q (m x k, ldq)
+hipError_t launch_spmm_atq(const int64_t* colptr, const int32_t* csc_pos, const int32_t* row_of, const float* val,
+                           int64_t n, const float* Q, int64_t ldq, int k, float* out, int64_t ldo, hipStream_t st);
+
 // ---- storage forms of A (quant.hip) ----
 // out (rows x cols, ldo) = BF16 of A (round to nearest even)
 hipError_t launch_quant_bf16(const float* A, int64_t rows, int64_t cols, int64_t lda, uint16_t* out, int64_t ldo,

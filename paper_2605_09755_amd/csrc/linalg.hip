@@ -1302,8 +1302,9 @@ struct InfoOut {
   double orth_err;
 };
 RF_DEV void k_info_body(InfoOut* info, const int* counters, int k, const double* orth) {
-  int retries = counters[1], nonf = counters[2], last = counters[3], fault = counters[5], bad = counters[6];
-  info->status = (retries > 0 ? 1 : 0) | (nonf ? 2 : 0) | (fault ? 4 : 0) | (bad ? 8 : 0);
+  int retries = counters[1], nonf = counters[2], last = counters[3], fault = counters[5], bad = counters[6],
+      badcsr = counters[7];
+  info->status = (retries > 0 ? 1 : 0) | (nonf ? 2 : 0) | (fault ? 4 : 0) | (bad ? 8 : 0) | (badcsr ? 16 : 0);
   info->rank_found = k - last;
   info->chol_retries = retries;
   info->nonfinite = nonf;

@@ -183,7 +183,8 @@ struct AtOp {
 // table_in / om_in: a caller-given sketch table (already checked for the block
 // layout) and Omega (rw x k, ld k), or null to draw them from the seed.
 static void range_finder_core(Ctx& c, const rf_matrix* A, const Dims& d, uint64_t seed, RFBufs& b, float* Qout,
-                              const int32_t* table_in = nullptr, const float* om_in = nullptr) {
+                              const int32_t* table_in = nullptr, const float* om_in = nullptr,
+                              const rf_csr* csr = nullptr) {
   const bool mixed = d.prec == RF_PREC_MIXED;
   const int k = d.k;
   const int64_t rw = d.rw;
@@ -196,6 +197,13 @@ static void range_finder_core(Ctx& c, const rf_matrix* A, const Dims& d, uint64_
   AtOp at;
   if (d.classical) {
     at = AtOp{A->data, A->ld, A->data, A->ld, 4};
+  } else if (csr) {
+    // sparse A: each nonzero scattered into its s buckets (fixed point, exact sums)
+    c.chk(launch_sketch_table(d.n, d.s, d.r1, seed, 0, 0, b.table, c.st));
+    c.chk(launch_sketch_csr(csr->row_ptr, csr->col_idx, csr->values, d.m, d.n, csr->nnz, b.table, d.s, d.r1, b.At,
+                            d.r1, &b.counters[7], c.st));
+    if (mixed) c.chk(launch_cast_f32_bf16(b.At, d.r1, b.At16, d.r1, d.m, d.r1, c.st));
+    at = AtOp{b.At, d.r1, b.At16, d.r1, 2};
   } else {
     // At = A S  (one pass over A for the sparse sketch and the SRHT)
     sketch_right_any(c, A, d, seed, b, b.At, d.r1, table_in);
@@ -526,6 +534,25 @@ rf_status rf_range_finder_ex(const rf_matrix* A, const int32_t* S_table, const f
   return range_finder_entry(A, p, S_table, Omega, Q, ldq, ws, ws_bytes, info, stream);
 }
 
+}  // extern "C"
+
+// Rayleigh-Ritz on B = Q^T A given B^T (s.Bt, n x k) and Q (s.Q): B B^T =
+// Ub diag(lam) Ub^T in FP64, sigma = sqrt(lam), U = Q Ub, V^T = Sigma^-1 Ub^T B.
+static void svd_tail(Ctx& c, const Dims& d, SvdBufs& s, double* gbig, float* U, int64_t ldu, double* sigma, float* Vt,
+                     int64_t ldvt) {
+  const int k = d.k;
+  c.chk(launch_gram(s.Bt, k, 0, s.Bt, k, 0, d.n, k, k, 1, s.GB, k, gbig, nullptr, c.st));
+  c.chk(launch_eig(s.GB, k, k, s.lam, s.Ub, k, s.eigw, c.st, kEigTolFP32));
+  c.chk(launch_sigma(s.lam, k, sigma, s.inv, c.st));
+  c.chk(launch_cast_f64_f32(s.Ub, k, s.Ub32, k, k, k, c.st));
+  // U = Q Ub ; V = B^T Ub Sigma^{-1} stored transposed as Vt
+  gemm(c, 0, s.Q, k, 1, s.Ub32, k, 0, U, ldu, d.m, k, k, nullptr);
+  gemm(c, 0, s.Bt, k, 1, s.Ub32, k, 0, Vt, ldvt, d.n, k, k, nullptr, s.inv, 1);
+  c.chk(launch_sign_fix(U, ldu, d.m, k, Vt, ldvt, d.n, s.signw, c.st));
+}
+
+extern "C" {
+
 rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, double* sigma, float* Vt, int64_t ldvt,
                  void* ws, size_t ws_bytes, rf_info* info, void* stream) {
   if (!valid_matrix(A) || !valid_params(A, p, false) || !U || !sigma || !Vt || ldu < p->k || ldvt < A->cols)
@@ -564,15 +591,7 @@ rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, 
     gemm(c, 0, A->data, A->ld, 0, s.Q, k, 0, s.Bt, k, d.n, k, d.m, s.qpart, nullptr, 0, 0, 0, nullptr, 0,
          kQtaSplitCap);
   }
-  // Ritz: B B^T = Ub diag(lam) Ub^T in FP64
-  c.chk(launch_gram(s.Bt, k, 0, s.Bt, k, 0, d.n, k, k, 1, s.GB, k, gbig, nullptr, c.st));
-  c.chk(launch_eig(s.GB, k, k, s.lam, s.Ub, k, s.eigw, c.st, kEigTolFP32));
-  c.chk(launch_sigma(s.lam, k, sigma, s.inv, c.st));
-  c.chk(launch_cast_f64_f32(s.Ub, k, s.Ub32, k, k, k, c.st));
-  // U = Q Ub ; V = B^T Ub Sigma^{-1} stored transposed as Vt
-  gemm(c, 0, s.Q, k, 1, s.Ub32, k, 0, U, ldu, d.m, k, k, nullptr);
-  gemm(c, 0, s.Bt, k, 1, s.Ub32, k, 0, Vt, ldvt, d.n, k, k, nullptr, s.inv, 1);
-  c.chk(launch_sign_fix(U, ldu, d.m, k, Vt, ldvt, d.n, s.signw, c.st));
+  svd_tail(c, d, s, gbig, U, ldu, sigma, Vt, ldvt);
   c.chk(launch_info(info, b.counters, k, (p->flags & RF_FLAG_ORTH_ERR) ? b.orth : nullptr, c.st));
   return finish(c);
 }
@@ -668,6 +687,145 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
     gemm(c, 0, y.Cbuf, k, 1, y.V32, k, 0, F, ldf, n, k, k, nullptr, y.scale, 0);
   }
   c.chk(launch_info(info, b.counters, k, nullptr, c.st));
+  return finish(c);
+}
+
+// ------------------------------------------------------------------ sparse A (CSR)
+}  // extern "C"
+
+static bool valid_csr(const rf_csr* A) {
+  if (!A || !A->row_ptr || A->rows < 1 || A->cols < 1 || A->nnz < 0 || A->nnz >= ((int64_t)1 << 31)) return false;
+  if (A->nnz > 0 && (!A->col_idx || !A->values)) return false;
+  return true;
+}
+
+// The rf_matrix-shaped view of a CSR matrix for the shared checks (dtype FP32).
+static rf_matrix csr_shape(const rf_csr* A) {
+  rf_matrix v;
+  memset(&v, 0, sizeof(v));
+  v.data = A->row_ptr;
+  v.rows = A->rows;
+  v.cols = A->cols;
+  v.ld = A->cols;
+  v.dtype = RF_F32;
+  return v;
+}
+
+struct CscBufs { int64_t* colptr; unsigned long long* cursor; int32_t* pos; int32_t* row_of; };
+static CscBufs carve_csc(Arena& ar, const rf_csr* A) {
+  CscBufs b;
+  b.colptr = ar.get<int64_t>((size_t)A->cols + 1);
+  b.cursor = ar.get<unsigned long long>((size_t)A->cols);
+  b.pos = ar.get<int32_t>((size_t)A->nnz + 1);
+  b.row_of = ar.get<int32_t>((size_t)A->nnz + 1);
+  return b;
+}
+
+// Checks shared by the CSR entry points: the sparse sign sketch only (S = I
+// would make the power loop a sparse product and the dense families a dense
+// one), FP32 values, r1 small enough for one row's 64-bit accumulators in LDS.
+static rf_status csr_check(const rf_csr* A, const rf_params* p, rf_matrix& shape) {
+  if (!valid_csr(A)) return RF_EINVAL;
+  shape = csr_shape(A);
+  if (!valid_params(&shape, p, false)) return RF_EINVAL;
+  if (p->flags & (RF_FLAG_CLASSICAL | RF_SKETCH_MASK)) return RF_EUNSUPPORTED;
+  if (!sketch_csr_ok(p->sketch)) return RF_EUNSUPPORTED;
+  return RF_OK;
+}
+
+static size_t csr_ws(int op, const rf_csr* A, const Dims& d) {
+  Arena ar(nullptr);
+  carve_rf(ar, d);
+  if (op == RF_OP_SVD) {
+    carve_svd(ar, d);
+    carve_gpart_big(ar, d);
+    carve_csc(ar, A);
+  } else {
+    ar.get<float>((size_t)d.m * d.k);
+  }
+  return ar.off + 256;
+}
+
+extern "C" {
+
+size_t rf_workspace_size_csr(int op, const rf_csr* A, const rf_params* p) {
+  rf_matrix shape;
+  if ((op != RF_OP_RANGE_FINDER && op != RF_OP_SVD) || csr_check(A, p, shape) != RF_OK) return 0;
+  return csr_ws(op, A, dims_of(&shape, p));
+}
+
+rf_status rf_range_finder_csr(const rf_csr* A, const rf_params* p, float* Q, int64_t ldq, void* ws, size_t ws_bytes,
+                              rf_info* info, void* stream) {
+  rf_matrix shape;
+  const rf_status st = csr_check(A, p, shape);
+  if (st != RF_OK) return st;
+  if (!Q || ldq < p->k) return RF_EINVAL;
+  Dims d = dims_of(&shape, p);
+  if (!ws || ws_bytes < csr_ws(RF_OP_RANGE_FINDER, A, d)) return RF_EWORKSPACE;
+  Arena ar(align_ws(ws));
+  RFBufs b = carve_rf(ar, d);
+  float* Qw = ar.get<float>((size_t)d.m * d.k);
+  if (ldq == d.k) Qw = Q;
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  range_finder_core(c, &shape, d, p->seed, b, Qw, nullptr, nullptr, A);
+  if (p->flags & RF_FLAG_ORTH_ERR) {
+    c.chk(launch_gram(Qw, d.k, 0, Qw, d.k, 0, d.m, d.k, d.k, 1, b.G, d.k, b.gpart, nullptr, c.st));
+    c.chk(launch_orth_err(b.G, d.k, d.k, b.orth, c.st));
+  }
+  if (Qw != Q) c.chk(launch_copy_f32(Qw, d.k, Q, ldq, d.m, d.k, c.st));
+  c.chk(launch_info(info, b.counters, d.k, (p->flags & RF_FLAG_ORTH_ERR) ? b.orth : nullptr, c.st));
+  return finish(c);
+}
+
+rf_status rf_svd_csr(const rf_csr* A, const rf_params* p, float* U, int64_t ldu, double* sigma, float* Vt,
+                     int64_t ldvt, void* ws, size_t ws_bytes, rf_info* info, void* stream) {
+  rf_matrix shape;
+  const rf_status st = csr_check(A, p, shape);
+  if (st != RF_OK) return st;
+  if (!U || !sigma || !Vt || ldu < p->k || ldvt < A->cols) return RF_EINVAL;
+  if (p->k > 4096) return RF_EUNSUPPORTED;
+  Dims d = dims_of(&shape, p);
+  if (!ws || ws_bytes < csr_ws(RF_OP_SVD, A, d)) return RF_EWORKSPACE;
+  Arena ar(align_ws(ws));
+  RFBufs b = carve_rf(ar, d);
+  SvdBufs s = carve_svd(ar, d);
+  double* gbig = carve_gpart_big(ar, d);
+  CscBufs t = carve_csc(ar, A);
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  const int k = d.k;
+  range_finder_core(c, &shape, d, p->seed, b, s.Q, nullptr, nullptr, A);
+  if (p->flags & RF_FLAG_ORTH_ERR) {
+    c.chk(launch_gram(s.Q, k, 0, s.Q, k, 0, d.m, k, k, 1, b.G, k, b.gpart, nullptr, c.st));
+    c.chk(launch_orth_err(b.G, k, k, b.orth, c.st));
+  }
+  // B^T = A^T Q as a sparse product over the CSC form of A (FP32 in both forms)
+  c.chk(launch_csc_build(A->row_ptr, A->col_idx, d.m, d.n, A->nnz, t.colptr, t.cursor, t.pos, t.row_of, c.st));
+  c.chk(launch_spmm_atq(t.colptr, t.pos, t.row_of, A->values, d.n, s.Q, k, k, s.Bt, k, c.st));
+  svd_tail(c, d, s, gbig, U, ldu, sigma, Vt, ldvt);
+  c.chk(launch_info(info, b.counters, k, (p->flags & RF_FLAG_ORTH_ERR) ? b.orth : nullptr, c.st));
+  return finish(c);
+}
+
+rf_status rf_sketch_apply_csr(const rf_csr* A, const rf_params* p, float* out, int64_t ldo, void* ws, size_t ws_bytes,
+                              void* stream) {
+  if (!valid_csr(A) || !p || p->sketch < 1 || p->nnz_per_col < 1 || p->nnz_per_col > p->sketch || !out ||
+      ldo < p->sketch || p->flags != 0)
+    return RF_EINVAL;
+  if (!sketch_csr_ok(p->sketch)) return RF_EUNSUPPORTED;
+  // workspace: the sketch table and the invalid-entry counter
+  const size_t need = ((size_t)A->cols * p->nnz_per_col * sizeof(int32_t) + 255) / 256 * 256 + 512;
+  if (!ws || ws_bytes < need) return RF_EWORKSPACE;
+  Arena ar(align_ws(ws));
+  int32_t* table = ar.get<int32_t>((size_t)A->cols * p->nnz_per_col);
+  int* bad = ar.get<int>(1);
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  c.chk(launch_fill_i32(bad, 1, 0, c.st));
+  c.chk(launch_sketch_table(A->cols, p->nnz_per_col, p->sketch, p->seed, 0, 0, table, c.st));
+  c.chk(launch_sketch_csr(A->row_ptr, A->col_idx, A->values, A->rows, A->cols, A->nnz, table, p->nnz_per_col,
+                          p->sketch, out, ldo, bad, c.st));
   return finish(c);
 }
 
