@@ -20,6 +20,17 @@ converges to the top subspace of A S, Section 4) the target is the smallest
 ratio every form reaches, rounded up to 0.01.  Then `--steps` steps at the
 first q reaching the target are timed with HIP events, inputs resident in HBM.
 value = mixed-form seconds per factorisation.
+
+The same line also carries (each an extra key, `--sections` to choose):
+* precision_forms_exp65k: A 65536 x 32768 stored FP32 / BF16 / FP8-e4m3 with block
+  scales (the library's quantiser kernels), q swept 0..3, per-form errors;
+* classical_comparison_polydecay: the paper's polydecay matrix (30000 x 15000,
+  sigma_i = 30000/i), sketched (CountSketch) against classical (S = I) RandSVD and
+  Algorithm 2, l in {800, 1200, 1600}, time and ||A - A_hat||_2 / sigma_{k+1} - 1;
+* nystrom32k: Algorithm 3 on a Gaussian kernel matrix, plain FP32 and mixed;
+* batched: 512 uneven matrices in one hipGraph replay;
+* cpu_baseline: the FP64 oracle on the host (row sample, scaled) with the CPU model
+  and a single-thread figure for the CPU-sized workload.
 """
 import argparse
 import json
@@ -103,6 +114,8 @@ def main():
     ap.add_argument("--forms", default="fp32,mixed")
     ap.add_argument("--q", type=int, default=None, help="fixed q (skip the accuracy sweep)")
     ap.add_argument("--batch", type=int, default=512, help="matrices in the batched workload (0: skip it)")
+    ap.add_argument("--sections", default="exp65k,polydecay,nystrom32k",
+                    help="extra workloads reported in the default line (comma list, or 'none')")
     ap.add_argument("--workload", choices=["poly65k", "exp65k", "nystrom32k"], default="poly65k",
                     help="poly65k: the headline workload (default); exp65k: A 65536 x 32768 stored FP32, BF16 and "
                          "FP8 with block scales, k=2000, sketch 4000, q=3; nystrom32k: Gaussian kernel matrix of "
@@ -137,7 +150,7 @@ def main():
     t0 = time.time()
     opt, fro2 = opt_tail(torch, A, k)
     log("opt_F = %.6e (||A||_F^2 = %.6e) in %.1fs" % (opt, fro2, time.time() - t0))
-    A16 = A.to(torch.bfloat16)
+    A16 = rf.rf_quantize_bf16(A)          # the library's storage-form kernel (round to nearest even)
     stream = torch.cuda.current_stream(dev)
 
     forms = args.forms.split(",")
@@ -168,6 +181,21 @@ def main():
             if ratio <= 1.05:
                 break
         results[form] = {"sweep": sweep}
+    # error measures of every form at the largest q it ran, against the FP64 values
+    # of the same stored A: ||Q^T Q - I|| (RF_FLAG_ORTH_ERR), ||A - U Sigma V^T||_F / opt,
+    # and its singular values against the plain FP32 form's
+    sig_ref = None
+    for form in forms:
+        Ain, prec, (ws, nws), (U, sig, Vt, info) = bufs[form]
+        q = results[form]["sweep"][-1]["q"]
+        rf.rf_svd(Ain, k, l, q, s, 42, prec, orth_err=True, workspace=(ws, nws), out=(U, sig, Vt, info))
+        torch.cuda.synchronize()
+        sg = sig.cpu().numpy()
+        if sig_ref is None:
+            sig_ref = sg
+        err = form_errors(torch, A, U, sig, Vt, opt, rf.info_dict(info), sg, sig_ref)
+        results[form]["errors_at_q"] = dict(err, q=q)
+        log("%s errors at q=%d: %s" % (form, q, err))
     # 2) accuracy target: 1.05 opt if every form reaches it, else the smallest
     #    ratio (rounded up to 0.01) that every form reaches: the sketched method
     #    plateaus above opt (Section 4), sketch size l fixes the plateau
@@ -263,6 +291,14 @@ def main():
     if args.batch > 0:
         batched = batched_bench(torch, rf, args.batch, max(args.steps, 5), max(args.warmup, 1), 105, dev)
 
+    extra = {}
+    secs = [x for x in args.sections.split(",") if x and x != "none"]
+    for name, fn in (("exp65k", exp65k_section), ("polydecay", polydecay_section), ("nystrom32k", nystrom_section)):
+        if name in secs:
+            t0 = time.time()
+            extra[name] = fn(torch, rf, args)
+            log("%s section in %.1fs" % (name, time.time() - t0))
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(m, n, k, l, s, args.seed, main_form["q"])
@@ -294,9 +330,33 @@ def main():
         "roofline": roofline,
         "roofline_other": others,
         "batched": batched,
+        "precision_forms_exp65k": extra.get("exp65k"),
+        "classical_comparison_polydecay": extra.get("polydecay"),
+        "nystrom32k": extra.get("nystrom32k"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
+
+
+def form_errors(torch, A, U, sig, Vt, opt, info, sg, sig_ref):
+    """Errors a factorisation U diag(sigma) V^T of the stored A reports: ||Q^T Q - I||
+    (max |.|, from the library), ||A - U Sigma V^T||_F / opt_F in FP64 (exact algebra,
+    valid for non-orthonormal factors), ||A - U U^T A||_F / opt_F, and the largest
+    relative difference of the top 100 singular values from `sig_ref`."""
+    U64, V64, s64 = U.double(), Vt.double(), sig.double()
+    A64 = A.double()
+    UA = U64.t() @ A64                                  # k x n
+    fro2 = float((A64 * A64).sum())
+    del A64
+    cross = float((s64.unsqueeze(1) * UA * V64).sum())  # <A, U Sigma V^T>
+    G = (U64.t() @ U64) * s64.unsqueeze(0) * s64.unsqueeze(1)
+    rec2 = float((G * (V64 @ V64.t())).sum())          # ||U Sigma V^T||_F^2
+    e_usv = math.sqrt(max(fro2 - 2.0 * cross + rec2, 0.0)) / opt
+    e_proj = frob_err(torch, A, U) / opt
+    top = min(100, len(sg))
+    dsig = float(np.max(np.abs(sg[:top] - sig_ref[:top]) / sig_ref[:top]))
+    return {"orth_err": info["orth_err"], "ratio_usvt": e_usv, "ratio_uuta": e_proj,
+            "max_rel_sigma_vs_fp32_top100": dsig}
 
 
 def time_calls(torch, fn, warmup, steps, stream):
@@ -313,33 +373,12 @@ def time_calls(torch, fn, warmup, steps, stream):
     return e0.elapsed_time(e1) / steps
 
 
-def quantize_fp8_blocks(torch, A, blk=128):
-    """OCP e4m3 codes (round to nearest even) and one FP32 scale amax/448 per 128 x 128
-    block (1 for an all-zero block): the FP8 storage form of A."""
-    m, n = A.shape
-    bm, bn = -(-m // blk), -(-n // blk)
-    amax = torch.zeros((bm, bn), dtype=torch.float32, device=A.device)
-    for i in range(bm):
-        rows = A[i * blk:(i + 1) * blk]
-        pad = bn * blk - n
-        t = torch.nn.functional.pad(rows.abs(), (0, pad)) if pad else rows.abs()
-        amax[i] = t.view(rows.shape[0], bn, blk).amax(dim=(0, 2))
-    scales = torch.where(amax > 0, amax / 448.0, torch.ones_like(amax))
-    codes = torch.empty((m, n), dtype=torch.uint8, device=A.device)
-    for i in range(bm):
-        rows = A[i * blk:(i + 1) * blk]
-        sc = scales[i].repeat_interleave(blk)[:n].unsqueeze(0)
-        codes[i * blk:(i + 1) * blk] = (rows / sc).to(torch.float8_e4m3fn).view(torch.uint8)
-    return codes, scales
-
-
-def exp65k_bench(args):
+def exp65k_section(torch, rf, args, timing_steps=3):
     """Precision forms on A 65536 x 32768, sigma_i = max(0.995^i, 1e-3 sigma_1) (no additive
     noise, so opt_F is exact from the spectrum): A stored FP32 (plain FP32 form and mixed form
-    with BF16 products), BF16 and FP8-e4m3 with 128 x 128 block scales (mixed form).
-    k = 2000, sketch 4000, 8 nonzeros per column, q = 0..3 swept; timed at q = 3."""
-    import torch
-    import paper_2605_09755_amd as rf
+    with BF16 products), BF16 and FP8-e4m3 with 128 x 128 block scales (mixed form), both
+    storage forms made by the library's quantiser kernels.  k = 2000, sketch 4000, 8 nonzeros
+    per column, q = 0..3 swept; timed at q = 3.  Errors of every form against the FP32 A."""
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     m, n, k, l, s, qcfg = 65536, 32768, 2000, 4000, 8, 3
@@ -353,7 +392,6 @@ def exp65k_bench(args):
     U, R = torch.linalg.qr(G)
     U *= torch.sign(torch.diagonal(R)).unsqueeze(0)
     del G, R
-    log("exp65k: U %dx%d in %.1fs" % (m, r, time.time() - t0))
     G = torch.randn(n, r, generator=g, device=dev, dtype=torch.float32)
     V, R = torch.linalg.qr(G)
     V *= torch.sign(torch.diagonal(R)).unsqueeze(0)
@@ -362,13 +400,17 @@ def exp65k_bench(args):
     del U, V
     torch.cuda.synchronize()
     log("exp65k: generated A %dx%d in %.1fs, opt_F %.6e" % (m, n, time.time() - t0, opt))
-    A16 = A.to(torch.bfloat16)
-    A8, sc8 = quantize_fp8_blocks(torch, A)
+    A16 = rf.rf_quantize_bf16(A)
+    A8, sc8 = rf.rf_quantize_fp8_b128(A)
+    t_q = {"bf16": time_calls(torch, lambda: rf.rf_quantize_bf16(A), 1, 3, stream),
+           "fp8_b128": time_calls(torch, lambda: rf.rf_quantize_fp8_b128(A), 1, 3, stream)}
     torch.cuda.synchronize()
-    log("exp65k: BF16 and FP8 storage forms ready")
+    log("exp65k: BF16 and FP8 storage forms by the library quantiser (%.2f / %.2f ms)" % (t_q["bf16"],
+                                                                                         t_q["fp8_b128"]))
     forms = [("fp32", A, None, "fp32"), ("mixed", A, None, "mixed"), ("bf16a", A16, None, "mixed"),
              ("fp8a", A8, sc8, "mixed")]
     res = {}
+    sig_ref = None
     for name, Ain, scales, prec in forms:
         p = rf.params(k, l, qcfg, s, 42, prec)
         nws = rf.rf_workspace_size(rf.RF_OP_SVD, Ain, p, scales)
@@ -378,22 +420,26 @@ def exp65k_bench(args):
                torch.zeros(rf.INFO_BYTES, dtype=torch.uint8, device=dev))
         sweep = []
         for q in range(0, qcfg + 1):
-            rf.rf_svd(Ain, k, l, q, s, 42, prec, scales=scales, workspace=(ws, nws), out=out)
+            rf.rf_svd(Ain, k, l, q, s, 42, prec, scales=scales, orth_err=(q == qcfg), workspace=(ws, nws), out=out)
             torch.cuda.synchronize()
             ratio = frob_err(torch, A, out[0]) / opt
             sweep.append({"q": q, "ratio": ratio})
             log("exp65k %s q=%d ratio %.5f info %s" % (name, q, ratio, rf.info_dict(out[3])))
+        sg = out[1].cpu().numpy()
+        if sig_ref is None:
+            sig_ref = sg
+        err = form_errors(torch, A, out[0], out[1], out[2], opt, rf.info_dict(out[3]), sg, sig_ref)
         ms = time_calls(torch, lambda: rf.rf_svd(Ain, k, l, qcfg, s, 42, prec, scales=scales, workspace=(ws, nws),
-                                                 out=out), args.warmup, max(1, min(args.steps, 5)), stream)
-        res[name] = {"q": qcfg, "ms_per_step": ms, "ratio": sweep[-1]["ratio"], "sweep": sweep}
-        log("exp65k %s: q=%d %.3f ms / factorisation" % (name, qcfg, ms))
+                                                 out=out), 1, timing_steps, stream)
+        res[name] = {"q": qcfg, "ms_per_step": ms, "ratio": sweep[-1]["ratio"], "sweep": sweep, "errors": err}
+        log("exp65k %s: q=%d %.3f ms / factorisation, errors %s" % (name, qcfg, ms, err))
         del ws, out
         torch.cuda.empty_cache()
     # live rooflines: the sketch pass per storage form, Q^T A per storage form
     roof = {}
     for name, Ain, scales, nbytes in (("sketch_f32", A, None, 4), ("sketch_bf16", A16, None, 2),
                                       ("sketch_fp8", A8, sc8, 1)):
-        t = time_calls(torch, lambda: rf.rf_sketch_apply(Ain, l, s, 42, scales=scales), 1, 5, stream) / 1e3
+        t = time_calls(torch, lambda: rf.rf_sketch_apply(Ain, l, s, 42, scales=scales), 1, 3, stream) / 1e3
         byts = m * n * nbytes + m * l * 4 + (sc8.numel() * 4 if scales is not None else 0)
         roof[name] = {"bound": "hbm", "achieved": byts / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                       "frac": byts / t / HBM_PEAK, "ms": t * 1e3}
@@ -402,23 +448,121 @@ def exp65k_bench(args):
     for name, fn in (("qta_f32", lambda: rf.rf_test_gemm(A, Q, n, k, m, 0, 0, split=False)),
                      ("qta_bf16", lambda: rf.rf_test_gemm(A16, Q16, n, k, m, 0, 0, split=False)),
                      ("qta_fp8", lambda: rf.rf_test_gemm_fp8a(A8, sc8, Q16, n, k, m, 0))):
-        t = time_calls(torch, fn, 1, 5, stream) / 1e3
+        t = time_calls(torch, fn, 1, 3, stream) / 1e3
         pk = PEAKS["f32" if name == "qta_f32" else "bf16"]
         roof[name] = {"bound": "mfma", "achieved": 2.0 * m * n * k / t / 1e12, "peak": pk / 1e12,
                       "unit": "TFLOP/s", "frac": 2.0 * m * n * k / t / pk, "ms": t * 1e3}
-    for kname, r in roof.items():
-        log("exp65k %s: %.3f ms, %.1f %s (%.1f%% of peak)" % (kname, r["ms"], r["achieved"], r["unit"],
-                                                             100 * r["frac"]))
-    line = {"metric": "s per rf_svd factorisation at q=3 by storage form of A; error ratio ‖A−QQᵀA‖_F/opt_F",
-            "value": res["fp8a"]["ms_per_step"] / 1e3, "unit": "s", "n_gpus": 1, "higher_is_better": False,
-            "dtype": "fp8-e4m3 A, bf16 products", "data": "synthetic",
-            "config": {"workload": "exp65k: A 65536x32768 = U diag(max(0.995^i, 1e-3 sigma_1)) V^T, Haar U,V; "
-                                   "rf_svd k=2000 sketch=2000x2 nnz/col=8 q=3 seed=42", "opt_F": opt,
-                       "forms": res,
-                       "speedup_vs_plain_fp32": {f: res["fp32"]["ms_per_step"] / res[f]["ms_per_step"]
-                                                 for f in res}},
+    for kname, rr in roof.items():
+        log("exp65k %s: %.3f ms, %.1f %s (%.1f%% of peak)" % (kname, rr["ms"], rr["achieved"], rr["unit"],
+                                                             100 * rr["frac"]))
+    del A, A16, A8, sc8, Q, Q16
+    torch.cuda.empty_cache()
+    return {"workload": "exp65k: A 65536x32768 = U diag(max(0.995^i, 1e-3 sigma_1)) V^T, Haar U,V; stored FP32, "
+                        "BF16 and FP8-e4m3 + 128x128 FP32 block scales (library quantiser); rf_svd k=2000 "
+                        "sketch=4000 nnz/col=8 q=0..3 seed=42, timed at q=3",
+            "opt_F": opt, "forms": res, "quantiser_ms": t_q,
+            "speedup_vs_plain_fp32": {f: res["fp32"]["ms_per_step"] / res[f]["ms_per_step"] for f in res},
             "roofline": roof}
+
+
+def exp65k_bench(args):
+    import torch
+    import paper_2605_09755_amd as rf
+    out = exp65k_section(torch, rf, args, max(1, min(args.steps, 5)))
+    line = {"metric": "s per rf_svd factorisation at q=3 by storage form of A; error ratio ‖A−QQᵀA‖_F/opt_F",
+            "value": out["forms"]["fp8a"]["ms_per_step"] / 1e3, "unit": "s", "n_gpus": 1, "higher_is_better": False,
+            "dtype": "fp8-e4m3 A, bf16 products", "data": "synthetic", "config": out, "roofline": out["roofline"]}
     print(json.dumps(line), flush=True)
+
+
+def polydecay_section(torch, rf, args):
+    """The paper's comparison (Section 4 and the additional experiments) on its synthetic
+    polydecay matrix: 30000 x 15000, sigma_i = 30000 / i, random orthogonal factors; k = 40,
+    l in {800, 1200, 1600}, CountSketch (s = 1), Gaussian Omega.  For each l: sketch-powered
+    RandSVD (q = 0..14) and Algorithm 2, against the classical forms (S = I, q = 0..4;
+    Algorithm 2 with S1 = I): seconds per call (HIP events, median of 3) and the paper's
+    relative error ||A - A_hat||_2 / sigma_{k+1} - 1 (spectral norm by block subspace
+    iteration on the residual), with A_hat = U Sigma V^T (RandSVD) or Y X (Algorithm 2)."""
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.current_stream(dev)
+    m, n, k = 30000, 15000, 40
+    t0 = time.time()
+    g = torch.Generator(device=dev)
+    g.manual_seed(106)
+    r = n
+    sig = 30000.0 / torch.arange(1, r + 1, device=dev, dtype=torch.float64)
+    U, R = torch.linalg.qr(torch.randn(m, r, generator=g, device=dev, dtype=torch.float32))
+    U *= torch.sign(torch.diagonal(R)).unsqueeze(0)
+    del R
+    V, R = torch.linalg.qr(torch.randn(n, r, generator=g, device=dev, dtype=torch.float32))
+    V *= torch.sign(torch.diagonal(R)).unsqueeze(0)
+    del R
+    A = (U * sig.to(torch.float32).unsqueeze(0)) @ V.t()
+    del U, V
+    torch.cuda.synchronize()
+    sk1 = 30000.0 / (k + 1)
+    log("polydecay: A %dx%d in %.1fs" % (m, n, time.time() - t0))
+
+    def spectral_err(res, iters=20, width=16):
+        """||residual||_2 by block subspace iteration (width 16) and a final SVD of
+        the residual applied to the block (A in FP32, the low-rank part in FP64)."""
+        X = torch.linalg.qr(torch.randn(n, width, generator=g, device=dev, dtype=torch.float64))[0]
+        for _ in range(iters):
+            X = torch.linalg.qr(res(res(X), True))[0]
+        return float(torch.linalg.svdvals(res(X))[0])
+
+    def usv_res(U, sg, Vt):
+        U64, V64, s64 = U.double(), Vt.double(), sg.double()
+
+        def f(x, transpose=False):
+            if not transpose:
+                return (A @ x.float()).double() - U64 @ (s64.unsqueeze(1) * (V64 @ x))
+            return (A.t() @ x.float()).double() - V64.t() @ (s64.unsqueeze(1) * (U64.t() @ x))
+        return f
+
+    def yx_res(Y, X):
+        Y64, X64 = Y.double(), X.double()
+
+        def f(x, transpose=False):
+            if not transpose:
+                return (A @ x.float()).double() - Y64 @ (X64 @ x)
+            return (A.t() @ x.float()).double() - X64.t() @ (Y64.t() @ x)
+        return f
+
+    out = {}
+    for l in (800, 1200, 1600):
+        rows = {"sketched_randsvd": [], "classical_randsvd": [], "sketched_alg2": [], "classical_alg2": []}
+        for name, classical, qmax in (("sketched", False, 14), ("classical", True, 4)):
+            for q in range(qmax + 1):
+                fn = lambda: rf.rf_svd(A, k, l, q, 1, 42, "fp32", classical=classical)
+                Ug, sg, Vg, _ = fn()
+                torch.cuda.synchronize()
+                e = spectral_err(usv_res(Ug, sg, Vg)) / sk1 - 1.0
+                ts = sorted(time_calls(torch, fn, 0, 1, stream) for _ in range(3))
+                rows[name + "_randsvd"].append({"q": q, "ms": ts[1], "rel_err": e})
+                fn2 = lambda: rf.rf_lowrank(A, k, l, q, 1, 42, "fp32", classical=classical)
+                Y, X, _ = fn2()
+                torch.cuda.synchronize()
+                e2 = spectral_err(yx_res(Y, X)) / sk1 - 1.0
+                ts2 = sorted(time_calls(torch, fn2, 0, 1, stream) for _ in range(3))
+                rows[name + "_alg2"].append({"q": q, "ms": ts2[1], "rel_err": e2})
+                del Ug, sg, Vg, Y, X
+            log("polydecay l=%d %s: %s" % (l, name, [(x["q"], round(x["ms"], 2), round(x["rel_err"], 4))
+                                                   for x in rows[name + "_randsvd"]]))
+
+        def first_time(rs, level):
+            hit = [x["ms"] for x in rs if x["rel_err"] <= level]
+            return min(hit) if hit else None
+        rows["time_to_rel_err_0.1_ms"] = {key: first_time(rows[key], 0.1) for key in
+                                          ("sketched_randsvd", "classical_randsvd", "sketched_alg2", "classical_alg2")}
+        out["l=%d" % l] = rows
+        log("polydecay l=%d time to relative error 0.1: %s" % (l, rows["time_to_rel_err_0.1_ms"]))
+    del A
+    torch.cuda.empty_cache()
+    return {"workload": "polydecay (Section 4): A 30000x15000 = U diag(30000/i) V^T, Haar U,V, FP32; k=40, "
+                        "CountSketch s=1, Gaussian Omega, seed 42; sketched q=0..14, classical (S=I) q=0..4",
+            "error": "||A - A_hat||_2 / sigma_{k+1} - 1 (block subspace iteration on the residual)",
+            "by_sketch_size": out}
 
 
 def top_eig_sum_sq(torch, K64, k, width=1024, iters=12, seed=7):
@@ -441,14 +585,12 @@ def top_eig_sum_sq(torch, K64, k, width=1024, iters=12, seed=7):
     return float((lam[:k] ** 2).sum()), float(res)
 
 
-def nystrom_bench(args):
+def nystrom_section(torch, rf, args):
     """Algorithm 3 on a Gaussian kernel matrix: x_i ~ N(0, I_32), n = 32768, h = median
     Euclidean distance over the pairs of the first 4096 points (mean of the two middle
     values), K_ij = exp(-|x_i - x_j|^2 / (2 h^2)) computed in FP64 and stored FP32; k = 512,
     sketch 1024, 8 nonzeros per column, q = 2.  Plain FP32 against mixed (BF16 products,
     FP64 small factorisations)."""
-    import torch
-    import paper_2605_09755_amd as rf
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream(dev)
     n, d, k, l, s, q = 32768, 32, 512, 1024, 8, 2
@@ -496,14 +638,22 @@ def nystrom_bench(args):
     roof = {"bound": "hbm", "achieved": byts / t / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
             "frac": byts / t / HBM_PEAK, "ms": t * 1e3, "kernel": "K S (sketch pass over K)"}
     log("nystrom32k sketch K S: %.3f ms, %.1f GB/s (%.1f%%)" % (t * 1e3, roof["achieved"], 100 * roof["frac"]))
-    line = {"metric": "s per rf_nystrom call; error ratio ‖K−FFᵀ‖_F/opt_F", "value": out["mixed"]["ms_per_step"] / 1e3,
-            "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "bf16 products, f64 small factorisations",
-            "data": "synthetic",
-            "config": {"workload": "nystrom32k: Gaussian kernel of 32768 points ~ N(0, I_32), h = median distance "
-                                   "of the first 4096 points; rf_nystrom k=512 sketch=1024 nnz/col=8 q=2 seed=42",
-                       "h": h, "opt_F": opt, "opt_ritz_residual": res, "forms": out,
-                       "speedup_mixed_vs_plain": out["fp32"]["ms_per_step"] / out["mixed"]["ms_per_step"]},
-            "roofline": roof}
+    del K, K64
+    torch.cuda.empty_cache()
+    return {"workload": "nystrom32k: Gaussian kernel of 32768 points ~ N(0, I_32), h = median distance of the first "
+                        "4096 points; rf_nystrom k=512 sketch=1024 nnz/col=8 q=2 seed=42; mixed = BF16 products for "
+                        "the first q-1 powers of Wt, the last one and C = Ct Y FP32",
+            "h": h, "opt_F": opt, "opt_ritz_residual": res, "forms": out,
+            "speedup_mixed_vs_plain": out["fp32"]["ms_per_step"] / out["mixed"]["ms_per_step"], "roofline": roof}
+
+
+def nystrom_bench(args):
+    import torch
+    import paper_2605_09755_amd as rf
+    out = nystrom_section(torch, rf, args)
+    line = {"metric": "s per rf_nystrom call; error ratio ‖K−FFᵀ‖_F/opt_F", "value": out["forms"]["mixed"]["ms_per_step"] / 1e3,
+            "unit": "s", "n_gpus": 1, "higher_is_better": False, "dtype": "f32 A, bf16 products (first q-1)",
+            "data": "synthetic", "config": out, "roofline": out["roofline"]}
     print(json.dumps(line), flush=True)
 
 
@@ -655,11 +805,37 @@ def cpu_baseline(m, n, k, l, s, seed, q):
     if threadpool_info:
         threads = max((d.get("num_threads", 0) for d in threadpool_info()), default=None)
     cores = threads or len(os.sched_getaffinity(0))
+    # per-core figure: the CPU-sized workload (2000 x 1000 FP64, k 50, sketch 100, s 8,
+    # q 2) on one thread, median of 3
+    c1 = None
+    try:
+        from threadpoolctl import threadpool_limits
+        A1, _ = synth.workload("cpu2000")
+        ts = []
+        with threadpool_limits(limits=1):
+            for _ in range(3):
+                t1 = time.perf_counter()
+                me.rand_svd(A1, me.Params(k=50, l=100, q=2, s=8, seed=42))
+                ts.append(time.perf_counter() - t1)
+        c1 = sorted(ts)[1]
+    except Exception:                                      # pragma: no cover
+        pass
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return {"value": (dt - t_svd) * (m / ms_rows) + t_svd, "unit": "s", "cores": cores, "kind": "oracle",
             "sample": "oracle rand_svd (q=%d) on a %d x %d instance of the same law (row sample), %.1f s measured; "
                       "all but the k x n SVD of B (%.1f s, size-independent of m) scaled x%.0f to %d rows"
                       % (q, ms_rows, n, dt, t_svd, m / ms_rows, m),
-            "measured_s": dt, "host_cores_visible": len(os.sched_getaffinity(0))}
+            "measured_s": dt, "host_cores_visible": len(os.sched_getaffinity(0)), "cpu_model": model,
+            "cpu2000_single_thread_s": c1,
+            "cpu2000_note": "oracle rand_svd on the CPU-sized workload 2000 x 1000 FP64, k 50, sketch 100, s 8, "
+                            "q 2, one BLAS thread, median of 3"}
 
 
 if __name__ == "__main__":
