@@ -398,11 +398,12 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
 // With AF32 the A operand is FP32 in memory and rounded to BF16 (RNE) on its way
 // into LDS.
 typedef __bf16 bf16x4v __attribute__((__vector_size__(4 * sizeof(__bf16))));
-constexpr int HB = 256, HBK = 32;
+constexpr int HB = 256, HBK = 64;  // 64 k-rows per stage keep two stages of loads in flight per CU
 constexpr int BT = 512;        // threads of a 256 x 256 workgroup: 8 waves, two per SIMD
 constexpr int NCH = HB * HBK / 8 / BT;  // 8-element chunks per thread and operand per stage
 constexpr int TRL = HB + 32;   // m/n-contiguous LDS row, bf16 elements
-constexpr int KRL = HBK + 8;   // k-contiguous LDS row, bf16 elements
+constexpr int KRL = HBK + 8;   // k-contiguous LDS row, bf16 elements (144 B: odd multiple of 16)
+constexpr int KCH = HBK / 8;   // 8-element chunks per k-contiguous row
 
 template <bool KC>
 constexpr int big_stage_elems() { return KC ? HB * KRL : HBK * TRL; }
@@ -427,7 +428,8 @@ RF_DEV uint4 pack8_bf16(float4 a, float4 b) {
 }
 
 // One operand's share of a stage: NCH chunks of 8 consecutive elements per thread.
-// KC: chunk c -> row c/4 of the tile, k offset 8 (c%4); else k row c/32, column 8 (c%32).
+// KC: chunk c -> row c/KCH of the tile, k offset 8 (c%KCH) (KCH = HBK/8 chunks per
+// row); else k row c/32, column 8 (c%32).
 template <bool KC, int MODE>  // MODE 0: BF16, 1: FP32, 2: FP8 e4m3 x block scale (m/n-contiguous only)
 struct BigStage {
   static constexpr bool F32 = (MODE == 1);
@@ -442,8 +444,8 @@ struct BigStage {
 #pragma unroll
     for (int q = 0; q < NCH; ++q) {
       const int c = tid + BT * q;
-      const int64_t r = KC ? r0 + (c >> 2) : r0 + 8 * (c & 31);       // first m/n index of the chunk
-      const int64_t k = KC ? k0 + 8 * (c & 3) : k0 + (c >> 5);        // first k index of the chunk
+      const int64_t r = KC ? r0 + c / KCH : r0 + 8 * (c & 31);         // first m/n index of the chunk
+      const int64_t k = KC ? k0 + 8 * (c % KCH) : k0 + (c >> 5);       // first k index of the chunk
       const bool full = KC ? (r < rmax && k + 8 <= kend) : (k < kend && r + 8 <= rmax);
       if constexpr (F8) {
         const uint8_t* P = reinterpret_cast<const uint8_t*>(P_);
@@ -496,7 +498,7 @@ struct BigStage {
 #pragma unroll
     for (int q = 0; q < NCH; ++q) {
       const int c = tid + BT * q;
-      uint16_t* dst = KC ? S + (c >> 2) * KRL + 8 * (c & 3) : S + (c >> 5) * TRL + 8 * (c & 31);
+      uint16_t* dst = KC ? S + (c / KCH) * KRL + 8 * (c % KCH) : S + (c >> 5) * TRL + 8 * (c & 31);
       uint4 x;
       if constexpr (F8) {
         float t[8];

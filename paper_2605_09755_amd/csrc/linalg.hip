@@ -463,9 +463,9 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
         const double2 ju = csn[u], jv = csn[v];
         const double cu = ju.x, su = ju.y, cv = jv.x, sv = jv.y;
         const double m00 = M[a][cc], m01 = M[a][d], m10 = M[b][cc], m11 = M[b][d];
-        double v0[JS / 32], v1[JS / 32];
+        double v0[2], v1[2];  // rows u and u + JS/2 of V
 #pragma unroll
-        for (int h = 0; h < JS / 32; ++h) {
+        for (int h = 0; h < 2; ++h) {
           v0[h] = V[u + (JS / 2) * h][cc];
           v1[h] = V[u + (JS / 2) * h][d];
         }
@@ -474,7 +474,7 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
         M[a][cc] = cv * t00 - sv * t01; M[a][d] = sv * t00 + cv * t01;
         M[b][cc] = cv * t10 - sv * t11; M[b][d] = sv * t10 + cv * t11;
 #pragma unroll
-        for (int h = 0; h < JS / 32; ++h) {
+        for (int h = 0; h < 2; ++h) {
           V[u + (JS / 2) * h][cc] = cv * v0[h] - sv * v1[h];
           V[u + (JS / 2) * h][d] = sv * v0[h] + cv * v1[h];
         }
@@ -765,6 +765,7 @@ template <int JB>
 __global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
   eig_apply_body<JB>(w, round, blockIdx.x);
 }
+
 __global__ __launch_bounds__(256) void k_eig_check(EigWork w) { eig_check_body(w, blockIdx.x); }
 __global__ void k_eig_decide(EigWork w, double tol, double* trace, int sw) { eig_decide_body(w, tol, trace, sw); }
 __global__ __launch_bounds__(1024) void k_eig_sort(EigWork w, int64_t N, double* lam) { eig_sort_body(w, N, lam); }
@@ -823,9 +824,11 @@ static void eig_rounds(EigWork w, int64_t N, hipStream_t st, double* trace) {
   const int rounds = 2 * w.p - 1;
   const int max_sweeps = eig_max_sweeps();
   const int ntile = eig_apply_items(w.p, w.K, JS);
+  // the subproblem kernel: one thread per 2 x 2 block of the JS x JS subproblem
+  const int solve_threads = (JS / 2) * (JS / 2) > 1024 ? 1024 : (JS / 2) * (JS / 2);
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int r = 0; r < rounds; ++r) {
-      hipLaunchKernelGGL(k_eig_solve<JB>, dim3(w.p), dim3(1024), lds_solve, st, w, r, 1);
+      hipLaunchKernelGGL(k_eig_solve<JB>, dim3(w.p), dim3(solve_threads), lds_solve, st, w, r, 1);
       hipLaunchKernelGGL(k_eig_apply<JB>, dim3(ntile), dim3(256), lds_apply, st, w, r);
     }
     hipLaunchKernelGGL(k_eig_check, dim3(eig_check_blocks(w.K)), dim3(256), 0, st, w);
@@ -833,6 +836,10 @@ static void eig_rounds(EigWork w, int64_t N, hipStream_t st, double* trace) {
   }
 }
 
+// 32-wide blocks (64 x 64 subproblems).  16-wide blocks were measured slower at
+// k = 1000: their 31-step subproblem sweep is bound by the per-step latency
+// (rotation, two barriers), not by LDS traffic, and twice the rounds double the
+// launches and the apply work.
 int eig_block_width(int64_t N) { (void)N; return 32; }
 
 // The launch sequence of one eigen-decomposition (about 1300 launches at N = 1000).
