@@ -70,9 +70,14 @@ typedef enum {
                            power product At Z stays FP32.  An FP32 A is rounded to
                            BF16 as Q^T A loads it, so sigma and V carry BF16
                            product error (~1e-3 relative) while the range of Q
-                           (and U) does not.  FP8 A (either form): Q^T A
-                           dequantises A and rounds it to BF16 as it loads it
-                           (BF16 MFMA); the sketch passes dequantise in FP32. */
+                           (and U) does not.  FP8 A: in the mixed form Q^T A
+                           runs on FP8 MFMA, A's codes and block scales as
+                           stored and Q rounded to e4m3 with one power-of-two
+                           scale per 32 rows and column (sigma and V then carry
+                           e4m3 rounding of Q, ~2^-4 relative per element); in
+                           the plain form A is dequantised and rounded to BF16
+                           as it is loaded (BF16 MFMA, Q in BF16).  The sketch
+                           passes dequantise FP8 A in FP32. */
 } rf_precision;
 /* In both forms the Gram matrices of CholeskyQR2, the Cholesky factors, the
    triangular inverses and the Rayleigh-Ritz eigenproblem are FP64. */
@@ -373,6 +378,28 @@ rf_status rf_test_gemm(int dtype, int a_kc, int b_kc, const void* A, int64_t lda
    loaded, and B BF16 (b_kc as in rf_test_gemm); BF16 MFMA, FP32 accumulation. */
 rf_status rf_test_gemm_fp8a(const uint8_t* A, int64_t lda, const float* scales, const uint16_t* B, int64_t ldb,
                             int b_kc, float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, void* stream);
+/* rf_test_quant_q_fp8: the FP8 operand form of Q (m x k FP32, ldq) that the FP8
+   product A^T Q reads: e4m3 codes (rf_test_qf8_bytes(m, k, 0) bytes) and E8M0
+   scales (rf_test_qf8_bytes(m, k, 1) bytes), device buffers.  With
+   njb = 8 ceil(k / 256): codes[((((st*njb + jb)*2 + ch)*2 + p)*64 + lane)*16 + e]
+   = code of Q[128 st + 64 ch + 32 p + 16 (lane/32) + e][32 jb + lane%32] and
+   scales[((st*njb + jb)*64 + lane)*2 + ch] = E8M0 byte (127 + x for 2^x) of rows
+   128 st + 64 ch + 32 (lane/32) + [0, 32) of column 32 jb + lane%32: the smallest
+   2^x, -127 <= x <= 127, with 448 2^x >= the block's largest finite |q|; codes =
+   nearest e4m3 of q 2^-x, ties to even, saturating; non-finite q -> NaN code;
+   rows >= m and columns >= k -> code 0 (their blocks scale 2^-127).
+   rf_test_gemm_fp8: C (M x N FP32, ldc) = op(A) Q with A as in rf_test_gemm_fp8a
+   (e4m3 K x M row-major, 128 x 128 FP32 block scales) and Q (K x N) given in the
+   FP8 operand form above (q_codes, q_scales from rf_test_quant_q_fp8 with m = K,
+   k = N); both on FP8 MFMA, FP32 accumulation.  ws: >= rf_test_gemm_fp8_ws(M, N, K)
+   bytes (split-K partials) or NULL (no split-K). */
+size_t rf_test_qf8_bytes(int64_t m, int64_t k, int which);
+rf_status rf_test_quant_q_fp8(const float* Q, int64_t m, int64_t k, int64_t ldq, uint8_t* codes, uint8_t* scales,
+                              void* stream);
+size_t rf_test_gemm_fp8_ws(int64_t M, int64_t N, int64_t K);
+rf_status rf_test_gemm_fp8(const uint8_t* A, int64_t lda, const float* scales, const uint8_t* q_codes,
+                           const uint8_t* q_scales, float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, void* ws,
+                           size_t ws_bytes, void* stream);
 size_t rf_test_gram_ws(int64_t K, int64_t M, int64_t N);
 rf_status rf_test_gram(const float* X, const float* Y, int64_t K, int64_t M, int64_t N, int sym, double* C,
                        void* ws, void* stream);

@@ -139,6 +139,14 @@ def lib():
                                    i64, ctypes.c_int, vp, vp]
         L.rf_test_gemm_fp8a.restype = i32
         L.rf_test_gemm_fp8a.argtypes = [vp, i64, vp, vp, i64, ctypes.c_int, vp, i64, i64, i64, i64, vp]
+        L.rf_test_qf8_bytes.restype = sz
+        L.rf_test_qf8_bytes.argtypes = [i64, i64, ctypes.c_int]
+        L.rf_test_quant_q_fp8.restype = i32
+        L.rf_test_quant_q_fp8.argtypes = [vp, i64, i64, i64, vp, vp, vp]
+        L.rf_test_gemm_fp8_ws.restype = sz
+        L.rf_test_gemm_fp8_ws.argtypes = [i64, i64, i64]
+        L.rf_test_gemm_fp8.restype = i32
+        L.rf_test_gemm_fp8.argtypes = [vp, i64, vp, vp, vp, vp, i64, i64, i64, i64, vp, sz, vp]
         L.rf_test_gram_ws.restype = sz
         L.rf_test_gram_ws.argtypes = [i64, i64, i64]
         L.rf_test_gram.restype = i32
@@ -585,6 +593,43 @@ def rf_test_gemm_fp8a(A8, scales, B, M, N, K, b_kc):
     C = torch.empty((M, N), dtype=torch.float32, device=A8.device)
     _check("rf_test_gemm_fp8a", lib().rf_test_gemm_fp8a(_ptr(A8), A8.stride(0), _ptr(scales), _ptr(B), B.stride(0),
                                                         int(b_kc), _ptr(C), N, M, N, K, _stream(A8.device)))
+    return C
+
+
+def rf_test_quant_q_fp8(Q):
+    """FP8 operand form of Q (m x k FP32): (codes, scales) uint8 device buffers in
+    the layout of include/rf.h (rf_test_quant_q_fp8)."""
+    m, k = Q.shape
+    if Q.dtype != torch.float32 or Q.stride(1) != 1:
+        raise ValueError("Q must be float32 with unit column stride")
+    codes = torch.empty(int(lib().rf_test_qf8_bytes(m, k, 0)), dtype=torch.uint8, device=Q.device)
+    scales = torch.empty(int(lib().rf_test_qf8_bytes(m, k, 1)), dtype=torch.uint8, device=Q.device)
+    _check("rf_test_quant_q_fp8", lib().rf_test_quant_q_fp8(_ptr(Q), m, k, Q.stride(0), _ptr(codes), _ptr(scales),
+                                                            _stream(Q.device)))
+    return codes, scales
+
+
+def rf_test_gemm_fp8(A8, scales, Q, M, N, K, qform=None, split=True):
+    """C = op(A) Q on FP8 MFMA: A8 (K x M uint8 e4m3 codes, 128 x 128 block scales),
+    Q (K x N FP32) taken to its FP8 operand form first (or qform = (codes, scales)
+    from rf_test_quant_q_fp8(Q) to skip that step)."""
+    if A8.dtype != torch.uint8 or A8.stride(1) != 1 or A8.shape != (K, M):
+        raise ValueError("A8 must be K x M uint8 with unit column stride")
+    if scales.shape != ((K + 127) // 128, (M + 127) // 128) or scales.dtype != torch.float32 \
+            or not scales.is_contiguous():
+        raise ValueError("scales must be contiguous float32 ceil(K/128) x ceil(M/128)")
+    if qform is None:
+        if Q.shape != (K, N):
+            raise ValueError("Q must be K x N")
+        qform = rf_test_quant_q_fp8(Q)
+    qc, qs = qform
+    if qc.numel() < int(lib().rf_test_qf8_bytes(K, N, 0)) or qs.numel() < int(lib().rf_test_qf8_bytes(K, N, 1)):
+        raise ValueError("Q operand form too small for K x N")
+    C = torch.empty((M, N), dtype=torch.float32, device=A8.device)
+    nws = int(lib().rf_test_gemm_fp8_ws(M, N, K)) if split else 0
+    ws = torch.empty(nws, dtype=torch.uint8, device=A8.device) if split else None
+    _check("rf_test_gemm_fp8", lib().rf_test_gemm_fp8(_ptr(A8), A8.stride(0), _ptr(scales), _ptr(qc), _ptr(qs),
+                                                      _ptr(C), N, M, N, K, _ptr(ws), nws, _stream(A8.device)))
     return C
 
 

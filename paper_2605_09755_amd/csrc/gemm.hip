@@ -14,6 +14,7 @@
 // k-contiguous.  Split-K writes FP32 partials that a second kernel sums in
 // fixed order (deterministic).
 #include <algorithm>
+#include <mutex>
 
 #include "common.h"
 #include "kernels.h"
@@ -519,6 +520,39 @@ struct BigStage {
   }
 };
 
+// Epilogue of the 256 x 256 kernels (wave (wm, wn) holds rows wm*128 + 32a + ..,
+// columns wn*64 + 32b + .. in acc[a][b]), through LDS one 64-row slab (rows 32a.. of
+// both wave rows) at a time: the accumulator copy is fully unrolled (registers only),
+// the global stores are row-contiguous across the workgroup.
+// NB: 32-column blocks per wave (wave column wn starts at column 32 NB wn); NT: threads.
+template <int NB = 2, int NT = BT>
+RF_DEV void big_epilogue(const GemmArgs& g, f32x16 (&acc)[4][NB], int64_t i0, int64_t j0, int split, int wm, int wn,
+                         int lane, int tid, void* smem) {
+  constexpr int SLD = HB + 8;  // 264 floats: lanes 32..63 (4 rows down) land on the other 32 banks
+  float* St = reinterpret_cast<float*>(smem);
+#pragma unroll
+  for (int a = 0; a < 4; ++a) {
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r)
+        St[(wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * SLD + wn * 32 * NB + 32 * b + (lane & 31)] =
+            acc[a][b][r];
+    __syncthreads();
+    for (int e = tid; e < 64 * HB; e += NT) {
+      const int rr = g.c_trans ? (e & 63) : (e / HB), cc = g.c_trans ? (e >> 6) : (e % HB);
+      const int64_t i = i0 + (rr >> 5) * 128 + 32 * a + (rr & 31), j = j0 + cc;
+      const float v = St[rr * SLD + cc];
+      if (g.partial) {
+        if (i < g.M && j < g.N) g.partial[((int64_t)split * g.M + i) * g.N + j] = v;
+      } else {
+        store_out(g, i, j, v);
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <bool AKC, bool BKC, int AMODE>
 RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
   extern __shared__ __attribute__((aligned(16))) uint16_t smem[];
@@ -591,31 +625,7 @@ RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
     __syncthreads();
   }
 
-  // Epilogue through LDS, one 64-row slab (rows 32a.. of both wave rows) at a time:
-  // the accumulator copy is fully unrolled (registers only), the global stores
-  // are row-contiguous across the workgroup.
-  constexpr int SLD = HB + 8;  // 264 floats: lanes 32..63 (4 rows down) land on the other 32 banks
-  float* St = reinterpret_cast<float*>(smem);
-#pragma unroll
-  for (int a = 0; a < 4; ++a) {
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r)
-        St[(wm * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3)) * SLD + wn * 64 + 32 * b + (lane & 31)] = acc[a][b][r];
-    __syncthreads();
-    for (int e = tid; e < 64 * HB; e += BT) {
-      const int rr = g.c_trans ? (e & 63) : (e / HB), cc = g.c_trans ? (e >> 6) : (e % HB);
-      const int64_t i = i0 + (rr >> 5) * 128 + 32 * a + (rr & 31), j = j0 + cc;
-      const float v = St[rr * SLD + cc];
-      if (g.partial) {
-        if (i < g.M && j < g.N) g.partial[((int64_t)split * g.M + i) * g.N + j] = v;
-      } else {
-        store_out(g, i, j, v);
-      }
-    }
-    __syncthreads();
-  }
+  big_epilogue(g, acc, i0, j0, split, wm, wn, lane, tid, smem);
 }
 
 template <bool AKC, bool BKC>
@@ -630,6 +640,204 @@ template <bool AKC, bool BKC, int AMODE>
 __global__ __launch_bounds__(BT, 1) void k_gemm_bf16_big(GemmArgs g) {
   gemm_bf16_big_body<AKC, BKC, AMODE>(g, blockIdx.x, blockIdx.y);
 }
+
+// ---------------- FP8 operands: A^T Q with FP8-stored A --------------------------------
+// C (M x N) = op(A) op(B) with op(A)(i,k) = A[k*lda+i] * a_scales[(k/128)*a_ldsc + i/128]
+// (A stored K x M as e4m3 codes with one FP32 scale per 128 x 128 block) and op(B)(k,j)
+// from the Q operand form of launch_quant_q_fp8 (e4m3 codes in MFMA order, one E8M0
+// scale per 32 rows and column).  Both operands reach v_mfma_scale_f32_32x32x64_f8f6f4
+// as stored, and every scale is applied without touching the codes:
+//  * Q scales ride in the instruction (scale of column j, 32-deep k block b: lane 32 b + j);
+//  * the A scale is one number per wave and 128-deep stage (a wave's 128 output rows
+//    lie in one 128-column block of A).  Written s = 2^e mu (mu in [1/2, 1)), 2^e rides
+//    in the instruction as the A-side E8M0 scale and mu is carried by the accumulators:
+//    they hold the partial sum divided by the current stage's mu, are multiplied by
+//    mu_prev / mu when a stage brings a different mu, and by the last mu at the end
+//    (one rounding per change of mu, no second set of accumulators).
+// k order inside one MFMA, the same for both operands: lane half h, byte p ->
+// k = 32 (p / 16) + 16 h + p % 16 (bytes 16 b .. 16 b + 15 form scale block b).
+// Workgroup tile 256 x 256, 8 waves of 128 x 64 (two per SIMD).  The A tile is kept
+// in LDS in its memory layout (128 k rows of 256 bytes, pitch 272 = 16 mod 256, so the
+// 8 rows x 16 bytes of one 16-lane transposed read fall on distinct banks) and read
+// with ds_read_b64_tr_b8, which hands lane i of a 16-lane group byte i % 8 of the
+// 8-byte chunks addressed by lanes i / 8 + 2 t (t = 0..7): when lane s addresses row
+// r0 + s / 2, column c0 + 8 (s % 2), lane i receives column c0 + i at rows r0 .. r0+7.
+// The Q tile of a stage is one contiguous 32 KB run of its operand form, copied and
+// read as 16-byte vectors.
+typedef int f8i32x2 __attribute__((ext_vector_type(2)));
+constexpr int F8K = 128;                   // k rows per stage: one A scale block
+constexpr int F8P = HB + 16;               // LDS pitch of the A tile, bytes
+constexpr int F8AS = F8K * F8P;            // A stage bytes
+constexpr int F8QS = F8K * HB;             // Q stage bytes (2 chunks x 8 column blocks x 2 KB)
+constexpr int F8CH = F8K * HB / 16 / BT;   // 16-byte chunks per thread and operand per stage
+
+struct F8Stage {
+  uint4 a[F8CH], q[F8CH];
+  uint32_t qs[2];
+  float sa;
+  RF_DEV void load(const GemmArgs& g, int64_t i0, int64_t j0, int64_t k0, int64_t kend, bool avec, int tid,
+                   int wm, int wn, int lane) {
+    const uint8_t* A = reinterpret_cast<const uint8_t*>(g.A);
+#pragma unroll
+    for (int q = 0; q < F8CH; ++q) {
+      const int c = tid + BT * q;
+      const int64_t k = k0 + (c >> 4), i = i0 + 16 * (c & 15);
+      const uint8_t* src = A + k * g.lda + i;
+      if (avec && k < kend && i + 16 <= g.M) {
+        a[q] = *reinterpret_cast<const uint4*>(src);
+      } else {
+        uint32_t w[4] = {0u, 0u, 0u, 0u};
+        if (k < kend)
+          for (int e = 0; e < 16 && i + e < g.M; ++e) w[e >> 2] |= (uint32_t)src[e] << (8 * (e & 3));
+        a[q] = make_uint4(w[0], w[1], w[2], w[3]);
+      }
+    }
+    // Q operand form: stage k0 / 128, column blocks j0 / 32 .. + 8 (always present: padded)
+    const int64_t st = k0 >> 7, njb = g.ldb, jb0 = j0 >> 5;
+    const uint8_t* Qc = reinterpret_cast<const uint8_t*>(g.B) + (st * njb + jb0) * 4096;
+#pragma unroll
+    for (int q = 0; q < F8CH; ++q) this->q[q] = *reinterpret_cast<const uint4*>(Qc + 16 * (tid + BT * q));
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+      qs[b] = *reinterpret_cast<const uint16_t*>(g.b_scales + ((st * njb + jb0 + 2 * wn + b) * 64 + lane) * 2);
+    const int64_t ib = (i0 >> 7) + wm;
+    sa = ib < g.a_ldsc ? g.a_scales[st * g.a_ldsc + ib] : 0.f;
+  }
+  RF_DEV void store(uint8_t* SA, uint8_t* SQ, int tid) const {
+#pragma unroll
+    for (int q = 0; q < F8CH; ++q) {
+      const int c = tid + BT * q;
+      *reinterpret_cast<uint4*>(SA + (c >> 4) * F8P + 16 * (c & 15)) = a[q];
+      *reinterpret_cast<uint4*>(SQ + 16 * c) = this->q[q];
+    }
+  }
+};
+
+// A operand of row block a, chunk ch (k rows 64 ch .. 64 ch + 63 of the stage).
+RF_DEV i32x8 f8_frag_a(const uint8_t* S, int wm, int a, int ch, int lane) {
+  const int G = lane >> 4, s = lane & 15;
+  const int col = wm * 128 + 32 * a + 16 * (G & 1) + 8 * (s & 1);
+  const int row = 64 * ch + 16 * (G >> 1) + (s >> 1);
+  i32x8 f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const uint8_t* p = S + (row + 32 * (j >> 1) + 8 * (j & 1)) * F8P + col;
+    const f8i32x2 t = __builtin_amdgcn_ds_read_tr8_b64_v2i32((__attribute__((address_space(3))) f8i32x2*)p);
+    f[2 * j] = t.x;
+    f[2 * j + 1] = t.y;
+  }
+  return f;
+}
+
+// B operand of column block b of wave column wn, chunk ch.
+RF_DEV i32x8 f8_frag_q(const uint8_t* S, int wn, int b, int ch, int lane) {
+  const uint8_t* p = S + (((2 * wn + b) * 2 + ch) * 2) * 1024 + 16 * lane;
+  const uint4 lo = *reinterpret_cast<const uint4*>(p), hi = *reinterpret_cast<const uint4*>(p + 1024);
+  i32x8 f;
+  f[0] = (int)lo.x; f[1] = (int)lo.y; f[2] = (int)lo.z; f[3] = (int)lo.w;
+  f[4] = (int)hi.x; f[5] = (int)hi.y; f[6] = (int)hi.z; f[7] = (int)hi.w;
+  return f;
+}
+
+// s = 2^e mu with e + 127 a valid E8M0 byte; mu NaN for a non-finite s.
+RF_DEV void f8_split_scale(float s, int& e8, float& mu) {
+  if (!isfinite(s)) {
+    e8 = 127;
+    mu = __builtin_nanf("");
+    return;
+  }
+  int e;
+  float f = frexpf(s, &e);  // s = f 2^e, |f| in [1/2, 1)
+  if (e > 127) { f = ldexpf(f, e - 127); e = 127; }
+  if (e < -127) { f = ldexpf(f, e + 127); e = -127; }
+  e8 = e + 127;
+  mu = f;
+}
+
+RF_DEV void gemm_fp8_body(const GemmArgs& g, int bid, int split) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t smem8[];
+  uint8_t* const A0 = smem8;
+  uint8_t* const Q0 = smem8 + 2 * F8AS;
+
+  const int ntm = (int)((g.M + HB - 1) / HB), ntn = (int)((g.N + HB - 1) / HB);
+  int tm, tn;
+  tile_coords(bid, ntm, ntn, tm, tn);
+  const int64_t i0 = (int64_t)tm * HB, j0 = (int64_t)tn * HB;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 2, wn = wave & 3;  // wave tile: rows wm*128 + [0, 128), columns wn*64 + [0, 64)
+  const int64_t kbeg = (int64_t)split * g.kps;  // kps is a multiple of 128
+  const int64_t kend = min(g.K, kbeg + g.kps);
+  const bool avec = ((((uintptr_t)g.A) & 15) == 0) && (g.lda % 16 == 0);
+
+  f32x16 acc[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
+
+  F8Stage sg;
+  const int nk = kend > kbeg ? (int)((kend - kbeg + F8K - 1) / F8K) : 0;
+  uint32_t qs[2] = {0u, 0u};
+  float sa = 0.f, mu_acc = 0.f;  // mu_acc: the mu the accumulators are divided by (0: nothing added yet)
+  if (nk > 0) {
+    sg.load(g, i0, j0, kbeg, kend, avec, tid, wm, wn, lane);
+    sg.store(A0, Q0, tid);
+    qs[0] = sg.qs[0]; qs[1] = sg.qs[1]; sa = sg.sa;
+    __syncthreads();
+  }
+  for (int kt = 0; kt < nk; ++kt) {
+    const int buf = kt & 1;
+    if (kt + 1 < nk) sg.load(g, i0, j0, kbeg + (int64_t)(kt + 1) * F8K, kend, avec, tid, wm, wn, lane);
+    // the stage's A scale is the same word for every lane of the wave
+    const float s_w = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, sa)));
+    if (s_w != 0.f) {
+      int e8;
+      float mu;
+      f8_split_scale(s_w, e8, mu);
+      if (mu_acc != 0.f && mu != mu_acc) {
+        const float r = mu_acc / mu;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int x = 0; x < 16; ++x) acc[a][b][x] *= r;
+      }
+      mu_acc = mu;
+      const uint8_t* A_ = A0 + buf * F8AS;
+      const uint8_t* Q_ = Q0 + buf * F8QS;
+#pragma unroll
+      for (int ch = 0; ch < 2; ++ch) {
+        const i32x8 b0 = f8_frag_q(Q_, wn, 0, ch, lane), b1 = f8_frag_q(Q_, wn, 1, ch, lane);
+        const int s0 = (int)((qs[0] >> (8 * ch)) & 0xffu), s1 = (int)((qs[1] >> (8 * ch)) & 0xffu);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          const i32x8 af = f8_frag_a(A_, wm, a, ch, lane);
+          acc[a][0] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af, b0, acc[a][0], 0, 0, 0, e8, 0, s0);
+          acc[a][1] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(af, b1, acc[a][1], 0, 0, 0, e8, 0, s1);
+        }
+      }
+    }
+    if (kt + 1 < nk) {
+      sg.store(A0 + (buf ^ 1) * F8AS, Q0 + (buf ^ 1) * F8QS, tid);
+      qs[0] = sg.qs[0]; qs[1] = sg.qs[1]; sa = sg.sa;
+    }
+    __syncthreads();
+  }
+  if (mu_acc != 0.f && mu_acc != 1.f) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int x = 0; x < 16; ++x) acc[a][b][x] *= mu_acc;
+  }
+  big_epilogue(g, acc, i0, j0, split, wm, wn, lane, tid, smem8);
+}
+
+__global__ __launch_bounds__(BT, 1) void k_gemm_fp8(GemmArgs g) { gemm_fp8_body(g, blockIdx.x, blockIdx.y); }
 
 // ---- grouped launches: many independent products in one grid --------------------
 // Work list: group i owns tiles [tile_start[i], tile_start[i+1]) of the flat grid;
@@ -746,7 +954,7 @@ static const GemmRule* find_rule(int dtype, int64_t M, int64_t N, int64_t K) {
 }
 
 bool gemm_use_big(int dtype, int64_t M, int64_t N) {
-  if (dtype == 4 || dtype == 6) return true;
+  if (dtype == 4 || dtype == 6 || dtype == 7) return true;
   return dtype == 2 && M >= 512 && N >= 512;
 }
 
@@ -774,7 +982,8 @@ hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
   const GemmRule* rule = (dtype == 0 || dtype == 2) ? find_rule(dtype, g.M, g.N, g.K) : nullptr;
   if (dtype == 4 || dtype == 6) {
     // FP32- and FP8-stored A run the 256-tile BF16 kernel: they take the split of
-    // its BF16 rule for the shape, when that rule picks the 256 tile
+    // its BF16 rule for the shape, when that rule picks the 256 tile (the FP8 x FP8
+    // kernel, dtype 7, keeps the heuristic: its stage time differs)
     const GemmRule* r2 = find_rule(2, g.M, g.N, g.K);
     if (r2 && r2->tile == 256) rule = r2;
   }
@@ -786,7 +995,7 @@ hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
   }
   if (g.split_cap > 0) splits = std::min(splits, g.split_cap);
   if (g.b_upper) splits = 1;
-  int64_t bk = 32;
+  const int64_t bk = dtype == 7 ? F8K : 32;  // FP8 split parts start on A scale blocks
   g.kps = ((g.K + splits - 1) / splits + bk - 1) / bk * bk;
   if (g.kps == 0) g.kps = bk;
   splits = (int)((g.K + g.kps - 1) / g.kps);
@@ -815,6 +1024,15 @@ hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
     if (g.a_kc || !g.a_scales) return hipErrorInvalidValue;
     if (g.b_kc) go_big<false, true, 2>(g, grid, st);
     else go_big<false, false, 2>(g, grid, st);
+  } else if (dtype == 7) {
+    if (g.a_kc || g.b_kc || !g.a_scales || !g.b_scales || g.b_upper || g.ldb != qf8_col_blocks(g.N))
+      return hipErrorInvalidValue;
+    constexpr int lds = 2 * (F8AS + F8QS);
+    static std::once_flag attr;
+    std::call_once(attr, [] {
+      (void)hipFuncSetAttribute((const void*)k_gemm_fp8, hipFuncAttributeMaxDynamicSharedMemorySize, lds);
+    });
+    hipLaunchKernelGGL(k_gemm_fp8, grid, dim3(BT), lds, st, g);
   } else if (dtype == 4) {
     if (g.a_kc && g.b_kc) go_big<true, true, 1>(g, grid, st);
     else if (g.a_kc && !g.b_kc) go_big<true, false, 1>(g, grid, st);

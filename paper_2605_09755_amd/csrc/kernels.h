@@ -90,6 +90,14 @@ hipError_t launch_quant_bf16(const float* A, int64_t rows, int64_t cols, int64_t
 // row-major FP32, scale = amax / 448 of the 128 x 128 block (1 if all zero)
 hipError_t launch_quant_fp8_b128(const float* A, int64_t rows, int64_t cols, int64_t lda, uint8_t* out, int64_t ldo,
                                  float* scales, hipStream_t st);
+// Q (m x k FP32) -> e4m3 codes in the B-operand order of the FP8 product (128-row
+// stages x 32-column blocks of 4 KB) and E8M0 scales per 32 rows and column
+// (128 bytes per stage and column block); layout in quant.hip.
+int qf8_col_blocks(int64_t k);  // 32-column blocks, padded to a multiple of 8
+size_t qf8_code_bytes(int64_t m, int64_t k);
+size_t qf8_scale_bytes(int64_t m, int64_t k);
+hipError_t launch_quant_q_fp8(const float* Q, int64_t m, int64_t k, int64_t ldq, uint8_t* codes, uint8_t* scales,
+                              hipStream_t st);
 
 // ---- K5 / K6 ----
 struct GemmArgs {
@@ -105,6 +113,7 @@ struct GemmArgs {
   const float* a_scales;  // FP8 A only: 128 x 128 block scales of the stored A (k-block rows)
   int64_t a_ldsc;         //   scale of element (k, i) = a_scales[(k/128) * a_ldsc + i/128]
   int split_cap;          // > 0: at most this many split-K parts (the partial buffer's size)
+  const uint8_t* b_scales;  // dtype 7 only: E8M0 scales of the Q operand form (B = its codes, ldb = column blocks)
 };
 // Tuning rule: dtype 0 (FP32) or 2 (BF16); applies when M <= max_m, N <= max_n,
 // K <= max_k; tile 128 or 256 (BF16 only); split 0 (heuristic) or 1..16.
@@ -112,7 +121,9 @@ struct GemmRule { int32_t dtype, tile, split, reserved; int64_t max_m, max_n, ma
 int set_gemm_rules(const GemmRule* rules, int count);  // 0 ok, -1 invalid (table unchanged)
 int gemm_splits(int64_t M, int64_t N, int64_t K);
 size_t gemm_partial_floats(int64_t M, int64_t N, int64_t K);
-// dtype: 0 FP32 operands, 2 BF16 operands.  partial may be NULL (no split-K).
+// dtype: 0 FP32 operands, 2 BF16 operands, 4 FP32 A rounded to BF16 on load, 6 FP8
+// block-scaled A dequantised to BF16 on load, 7 FP8 block-scaled A times the FP8 Q
+// operand form (FP8 MFMA; a_kc = b_kc = 0).  partial may be NULL (no split-K).
 hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st);
 // Grouped products: count independent GemmArgs (device array, kps = K, partial = 0)
 // in one grid; tile_start (device, count + 1 entries) is the prefix sum of

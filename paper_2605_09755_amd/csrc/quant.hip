@@ -140,3 +140,80 @@ hipError_t launch_quant_fp8_b128(const float* A, int64_t rows, int64_t cols, int
 }
 
 }  // namespace rf
+
+namespace rf {
+
+// ---- Q in the operand form of the FP8 product A^T Q ----------------------------------
+// Q (m x k FP32, ld) -> e4m3 codes with one power-of-two (E8M0) scale per 32 rows and
+// column, the codes written in the order the 32x32x64 FP8 MFMA takes its B operand:
+//   codes[st][jb][ch][p][lane][e] (st < ceil(m/128), jb < qf8_col_blocks(k), ch, p < 2,
+//   lane < 64, e < 16) holds row 128 st + 64 ch + 32 p + 16 (lane / 32) + e, column
+//   32 jb + lane % 32;
+//   scales[st][jb][lane][ch] (bytes) holds the scale of rows 128 st + 64 ch +
+//   32 (lane / 32) + [0, 32), column 32 jb + lane % 32.
+// Scale of a 32-row block = the smallest 2^e (-127 <= e <= 127) with 448 2^e >= its
+// largest finite |q| (2^-127 for an all-zero block); each element is multiplied by
+// 2^-e (exact) and rounded to the nearest e4m3 value, ties to even, saturating at 448;
+// non-finite elements encode as NaN.  Rows >= m and columns >= k encode as 0.
+RF_DEV int e8m0_exponent(float amax) {
+  if (!(amax > 0.f)) return -127;
+  const double a = (double)amax;
+  int e;
+  (void)frexp(a / 448.0, &e);  // a / 448 in [2^(e-1), 2^e)
+  // step to the smallest e with 448 2^e >= a (the division above may round)
+  while (e > -127 && ldexp(448.0, e - 1) >= a) --e;
+  while (e < 127 && ldexp(448.0, e) < a) ++e;
+  return e < -127 ? -127 : (e > 127 ? 127 : e);
+}
+
+__global__ __launch_bounds__(256) void k_quant_q_fp8(const float* __restrict__ Q, int64_t m, int64_t k, int64_t ldq,
+                                                     int njb, uint8_t* __restrict__ codes,
+                                                     uint8_t* __restrict__ scales) {
+  // thread: one column j and one 32-row block rb
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t rb = blockIdx.y;
+  if (j >= (int64_t)njb * 32) return;
+  float v[32];
+  float amax = 0.f;
+#pragma unroll
+  for (int r = 0; r < 32; ++r) {
+    const int64_t row = rb * 32 + r;
+    const float x = (row < m && j < k) ? Q[row * ldq + j] : 0.f;
+    v[r] = x;
+    if (isfinite(x)) amax = fmaxf(amax, fabsf(x));
+  }
+  const int e = e8m0_exponent(amax);
+  const int64_t st = rb >> 2;
+  const int ch = (int)((rb >> 1) & 1), p = (int)(rb & 1), jb = (int)(j >> 5), jl = (int)(j & 31);
+  uint8_t* base = codes + ((((st * njb + jb) * 2 + ch) * 2 + p) * 64) * 16;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    uint32_t w[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint32_t x = 0;
+#pragma unroll
+      for (int b = 0; b < 4; ++b) x |= (uint32_t)e4m3_rne(ldexp((double)v[16 * h + 4 * q + b], -e)) << (8 * b);
+      w[q] = x;
+    }
+    *reinterpret_cast<uint4*>(base + (32 * h + jl) * 16) = make_uint4(w[0], w[1], w[2], w[3]);
+  }
+  scales[((st * njb + jb) * 64 + 32 * p + jl) * 2 + ch] = (uint8_t)(e + 127);
+}
+
+int qf8_col_blocks(int64_t k) { return (int)((k + 255) / 256) * 8; }
+size_t qf8_code_bytes(int64_t m, int64_t k) { return (size_t)((m + 127) / 128) * qf8_col_blocks(k) * 4096; }
+size_t qf8_scale_bytes(int64_t m, int64_t k) { return (size_t)((m + 127) / 128) * qf8_col_blocks(k) * 128; }
+
+hipError_t launch_quant_q_fp8(const float* Q, int64_t m, int64_t k, int64_t ldq, uint8_t* codes, uint8_t* scales,
+                              hipStream_t st) {
+  if (m == 0 || k == 0) return hipSuccess;
+  const int njb = qf8_col_blocks(k);
+  const int64_t nrb = (m + 127) / 128 * 4;  // 32-row blocks, padded to whole 128-row stages
+  if (nrb > 65535) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_quant_q_fp8, dim3((unsigned)((njb * 32 + 255) / 256), (unsigned)nrb), dim3(256), 0, st, Q, m,
+                     k, ldq, njb, codes, scales);
+  return hipGetLastError();
+}
+
+}  // namespace rf

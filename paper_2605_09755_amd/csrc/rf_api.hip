@@ -96,10 +96,11 @@ struct Ctx {
 static void gemm(Ctx& c, int dtype, const void* A, int64_t lda, int a_kc, const void* B, int64_t ldb, int b_kc, void* C,
                  int64_t ldc, int64_t M, int64_t N, int64_t K, float* partial, const float* colscale = nullptr,
                  int c_trans = 0, int b_upper = 0, int c_bf16 = 0, const float* a_scales = nullptr,
-                 int64_t a_ldsc = 0, int split_cap = 0, float alpha = 1.f) {
+                 int64_t a_ldsc = 0, int split_cap = 0, float alpha = 1.f, const uint8_t* b_scales = nullptr) {
   GemmArgs g;
   memset(&g, 0, sizeof(g));
   g.a_scales = a_scales;
+  g.b_scales = b_scales;
   g.a_ldsc = a_ldsc;
   g.A = A; g.lda = lda; g.a_kc = a_kc;
   g.B = B; g.ldb = ldb; g.b_kc = b_kc;
@@ -297,6 +298,7 @@ constexpr int kQtaSplitCap = 4;
 struct SvdBufs {
   float* Q; float* Bt; double* GB; double* lam; double* Ub; float* Ub32; float* inv; void* eigw; int* signw;
   float* qpart;
+  uint8_t* qf8c; uint8_t* qf8s;  // FP8 operand form of Q (FP8-stored A, mixed form)
 };
 static SvdBufs carve_svd(Arena& ar, const Dims& d) {
   SvdBufs s;
@@ -310,6 +312,9 @@ static SvdBufs carve_svd(Arena& ar, const Dims& d) {
   s.eigw = ar.get<char>(eig_work_bytes(d.k));
   s.signw = ar.get<int>(3 * (size_t)d.k);
   s.qpart = ar.get<float>((size_t)kQtaSplitCap * d.n * d.k);
+  const bool f8 = d.dtype == RF_FP8E4M3_B128 && d.prec == RF_PREC_MIXED;
+  s.qf8c = f8 ? ar.get<uint8_t>(qf8_code_bytes(d.m, d.k)) : nullptr;
+  s.qf8s = f8 ? ar.get<uint8_t>(qf8_scale_bytes(d.m, d.k)) : nullptr;
   return s;
 }
 static double* carve_gpart_big(Arena& ar, const Dims& d) {
@@ -576,8 +581,14 @@ rf_status rf_svd(const rf_matrix* A, const rf_params* p, float* U, int64_t ldu, 
   // B^T = A^T Q (n x k): the one extra pass over A of the randomised SVD.  BF16
   // products when A is stored in BF16, or in the mixed form (FP32 A is then
   // rounded to BF16 as it is loaded).
-  if (A->dtype == RF_FP8E4M3_B128) {
-    // block-scaled FP8 A is dequantised and rounded to BF16 as it is loaded
+  if (A->dtype == RF_FP8E4M3_B128 && d.prec == RF_PREC_MIXED) {
+    // FP8 x FP8 on MFMA: Q rounded to e4m3 (E8M0 scale per 32 rows and column), A's
+    // codes and block scales used as stored
+    c.chk(launch_quant_q_fp8(s.Q, d.m, k, k, s.qf8c, s.qf8s, c.st));
+    gemm(c, 7, A->data, A->ld, 0, s.qf8c, qf8_col_blocks(k), 0, s.Bt, k, d.n, k, d.m, s.qpart, nullptr, 0, 0, 0,
+         A->block_scales, (d.n + 127) / 128, kQtaSplitCap, 1.f, s.qf8s);
+  } else if (A->dtype == RF_FP8E4M3_B128) {
+    // plain form: block-scaled FP8 A is dequantised and rounded to BF16 as it is loaded
     uint16_t* q16 = b.Q16 ? b.Q16 : (uint16_t*)b.Ya;
     c.chk(launch_cast_f32_bf16(s.Q, k, q16, k, d.m, k, c.st));
     gemm(c, 6, A->data, A->ld, 0, q16, k, 0, s.Bt, k, d.n, k, d.m, s.qpart, nullptr, 0, 0, 0, A->block_scales,
@@ -871,6 +882,36 @@ rf_status rf_test_gemm_fp8a(const uint8_t* A, int64_t lda, const float* scales, 
   Ctx c;
   c.st = (hipStream_t)stream;
   gemm(c, 6, A, lda, 0, B, ldb, b_kc ? 1 : 0, C, ldc, M, N, K, nullptr, nullptr, 0, 0, 0, scales, (M + 127) / 128);
+  return finish(c);
+}
+
+size_t rf_test_qf8_bytes(int64_t m, int64_t k, int which) {
+  if (m < 1 || k < 1) return 0;
+  return which == 0 ? qf8_code_bytes(m, k) : qf8_scale_bytes(m, k);
+}
+
+rf_status rf_test_quant_q_fp8(const float* Q, int64_t m, int64_t k, int64_t ldq, uint8_t* codes, uint8_t* scales,
+                              void* stream) {
+  if (!Q || !codes || !scales || m < 1 || k < 1 || ldq < k) return RF_EINVAL;
+  return launch_quant_q_fp8(Q, m, k, ldq, codes, scales, (hipStream_t)stream) == hipSuccess ? RF_OK : RF_EHIP;
+}
+
+size_t rf_test_gemm_fp8_ws(int64_t M, int64_t N, int64_t K) {
+  if (M < 1 || N < 1 || K < 1) return 0;
+  return gemm_partial_floats(M, N, K) * sizeof(float) + 256;
+}
+
+rf_status rf_test_gemm_fp8(const uint8_t* A, int64_t lda, const float* scales, const uint8_t* q_codes,
+                           const uint8_t* q_scales, float* C, int64_t ldc, int64_t M, int64_t N, int64_t K, void* ws,
+                           size_t ws_bytes, void* stream) {
+  if (!A || !scales || !q_codes || !q_scales || !C || M < 1 || N < 1 || K < 1 || lda < M || ldc < N)
+    return RF_EINVAL;
+  const size_t np = gemm_partial_floats(M, N, K);
+  if (ws && ws_bytes < rf_test_gemm_fp8_ws(M, N, K)) return RF_EWORKSPACE;
+  Ctx c;
+  c.st = (hipStream_t)stream;
+  gemm(c, 7, A, lda, 0, q_codes, qf8_col_blocks(N), 0, C, ldc, M, N, K, (ws && np) ? (float*)align_ws(ws) : nullptr,
+       nullptr, 0, 0, 0, scales, (M + 127) / 128, 0, 1.f, q_scales);
   return finish(c);
 }
 

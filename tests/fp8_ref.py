@@ -58,3 +58,42 @@ def dequantize(codes, scales, blk=128):
     m, n = codes.shape
     S = np.repeat(np.repeat(scales.astype(np.float64), blk, 0), blk, 1)[:m, :n]
     return decode(codes) * S
+
+
+def e8m0_exponent(amax):
+    """Smallest x in [-127, 127] with 448 * 2**x >= amax (-127 where amax == 0).
+    With amax = f 2**E (f in [1/2, 1)) and 448 = 0.875 * 2**9 the condition reads
+    2**(9 + x - E) >= f / 0.875, so x = E - 9 when f <= 0.875, else E - 8."""
+    amax = np.asarray(amax, dtype=np.float64)
+    f, E = np.frexp(amax)
+    x = E.astype(np.int64) - 9 + (f > 0.875)
+    x = np.where(amax > 0, x, -127)
+    return np.clip(x, -127, 127)
+
+
+def quantize_q_operand(Q):
+    """The FP8 operand form of Q (m x k) read by the FP8 product A^T Q: e4m3 codes
+    with one power-of-two scale per 32 rows and column, laid out as
+    codes[st, jb, ch, p, lane, e] = code of row 128 st + 64 ch + 32 p + 16 (lane // 32) + e,
+    column 32 jb + lane % 32, and scales[st, jb, lane, ch] = 127 + x of rows
+    128 st + 64 ch + 32 (lane // 32) + [0, 32), column 32 jb + lane % 32 (jb < 8 ceil(k / 256)).
+    Returns (codes, scales) flattened to bytes and the dequantised Q (m x k)."""
+    Q = np.asarray(Q, dtype=np.float64)
+    m, k = Q.shape
+    S = -(-m // 128)
+    njb = -(-k // 256) * 8
+    Mp, Kp = 128 * S, 32 * njb
+    Qp = np.zeros((Mp, Kp))
+    Qp[:m, :k] = Q
+    fin = np.isfinite(Qp)
+    blocks = np.where(fin, np.abs(Qp), 0.0).reshape(Mp // 32, 32, Kp)
+    x = e8m0_exponent(blocks.max(axis=1))                      # (Mp/32, Kp)
+    X = np.repeat(x, 32, axis=0)                               # per element
+    with np.errstate(invalid="ignore"):
+        codes_full = encode(np.where(fin, np.ldexp(np.where(fin, Qp, 0.0), -X), 0.0))
+    bad = ~fin
+    codes_full[bad] = np.where(Qp[bad] < 0, 0xFF, 0x7F).astype(np.uint8)
+    deq = decode(codes_full) * np.ldexp(1.0, X)
+    codes = codes_full.reshape(S, 2, 2, 2, 16, njb, 32).transpose(0, 5, 1, 2, 3, 6, 4).reshape(-1)
+    scales = (x + 127).astype(np.uint8).reshape(S, 2, 2, njb, 32).transpose(0, 3, 2, 4, 1).reshape(-1)
+    return codes, scales, deq[:m, :k]

@@ -103,3 +103,27 @@ def test_fp8_large_sampled_blocks():
         assert np.array_equal(codes[bi * 128:(bi + 1) * 128, bj * 128:(bj + 1) * 128].cpu().numpy(), c_ref)
     bf = rf.rf_quantize_bf16(A)
     assert torch.equal(bf.cpu(), A.cpu().to(torch.bfloat16))
+
+
+@pytest.mark.parametrize("m,k", [(300, 70), (128, 256), (1, 1), (513, 300), (4096, 2000)])
+def test_q_operand_form_bit_exact(m, k):
+    """The FP8 operand form of Q (e4m3 codes in MFMA order, E8M0 scale per 32 rows
+    and column) against tests/fp8_ref.quantize_q_operand, byte for byte: rows of
+    very different magnitude, an all-zero 32-row block, exact e4m3 ties after the
+    power-of-two scaling, a NaN and an Inf."""
+    rng = np.random.default_rng(m + 7 * k)
+    Q = rng.standard_normal((m, k)) * 10.0 ** rng.uniform(-20, 20, (m, 1)) / np.sqrt(m)
+    if m >= 64:
+        Q[32:64] = 0.0
+    if m > 96 and k > 3:
+        # ties: 448 * 2^x sets the block exponent, mids of adjacent codes below it
+        Q[96, :3] = [448.0, 0.5 * (fp8_ref.DECODE[0x50] + fp8_ref.DECODE[0x51]), -3.25]
+        Q[97, 0] = 0.5 * (fp8_ref.DECODE[0x52] + fp8_ref.DECODE[0x53])
+    if m > 200 and k > 5:
+        Q[200, 4] = np.nan
+        Q[201, 5] = -np.inf
+    Q32 = Q.astype(np.float32)
+    codes_ref, scales_ref, _ = fp8_ref.quantize_q_operand(Q32.astype(np.float64))
+    codes, scales = rf.rf_test_quant_q_fp8(torch.from_numpy(Q32).to(DEV))
+    assert np.array_equal(scales.cpu().numpy(), scales_ref)
+    assert np.array_equal(codes.cpu().numpy(), codes_ref)
