@@ -4,14 +4,28 @@
 // Blocked right-looking factorisation on 64 x 64 tiles, run as a persistent
 // kernel over a task list in dependency order.  Step kb has
 //   A(kb)     factor the diagonal tile: R_kk and X_kk = R_kk^{-1} (one workgroup);
-//   B(kb, j)  panel R_kb,j = X_kk^T G_kb,j for j > kb, and
-//   X(kb, i)  inverse column X_i,kb = -(sum_{l=i..kb-1} X_il R_l,kb) X_kk for i < kb;
-//   C(kb,i,j) trailing update G_ij -= R_kb,i^T R_kb,j for kb < i <= j.
-// Workgroups take task tickets from an atomic counter in this order and wait on
-// per-step completion counters: A(kb) on all C(kb-1), B(kb) on A(kb), X(kb) on A(kb)
-// and all X(kb-1), C(kb) on all B(kb) (the X columns run beside the factorisation).  A task only waits on tasks with smaller tickets, which are held
-// by running workgroups, so the queue drains without co-residency guarantees;
-// every wait is bounded and raises the fault word instead of hanging.
+//   B(kb, j)  panel R_kb,j = X_kk^T G_kb,j for j > kb;
+//   X(kb, i)  inverse tile X_i,kb = -T_i,kb X_kk for i < kb;
+//   C(kb,i,j) trailing update G_ij -= R_kb,i^T R_kb,j for kb < i <= j;
+//   U(kb,i,j) inverse update T_ij += X_i,kb R_kb,j for i <= kb < j.
+// T_ij = sum_{l=i..j-1} X_il R_lj (from X R = I: X_ij R_jj = -T_ij) is accumulated
+// in the X tile (i, j) as the columns of X become final (right-looking, like the
+// factorisation), so the inverse adds two tile products per step to the critical
+// path instead of a sum over all earlier columns.
+// Workgroups take task tickets from an atomic counter, step by step in the order
+// A(kb), B(kb, .), X(kb, .), C(kb, .), U(kb, .), and wait on per-tile counters (the
+// dependencies of the tile algorithm, so later steps start as soon as their own
+// tiles are ready):
+//   gcnt(i,j): trailing updates applied to G tile (i,j); A(kb) waits gcnt(kb,kb) = kb,
+//     B(kb,j) waits gcnt(kb,j) = kb, C(kb,i,j) waits gcnt(i,j) = kb (its previous writer);
+//   pdone(kb,j): panel R_kb,j written (B(kb,j), or A(kb) for j = kb); C(kb,i,j) waits
+//     pdone(kb,i) and pdone(kb,j), U(kb,i,j) waits pdone(kb,j), B and X wait pdone(kb,kb);
+//   tcnt(i,j): inverse updates applied to T tile (i,j); X(kb,i) waits tcnt(i,kb) = kb - i,
+//     U(kb,i,j) waits tcnt(i,j) = kb - i (its previous writer);
+//   xdone(i,kb): X tile (i,kb) final; U(kb,i,j) waits it (i < kb).
+// A task only waits on tasks with smaller tickets, which are held by running
+// workgroups, so the queue drains without co-residency guarantees; every wait is
+// bounded and raises the fault word instead of hanging.
 // Completion is published with an agent-scope release (L2 write-back, the
 // workgroups sit on different XCDs) and observed with an acquire.
 #include "common.h"
@@ -25,6 +39,12 @@ constexpr unsigned kSpinLimit = 1u << 20;  // polls of ~1 us: a stuck dependency
 
 
 RF_DEV int nC_of(int nb, int kb) { int t = nb - 1 - kb; return t * (t + 1) / 2; }
+RF_DEV int nU_of(int nb, int kb) { return (kb + 1) * (nb - 1 - kb); }
+RF_DEV int step_tasks(int nb, int kb) { return nb + nC_of(nb, kb) + nU_of(nb, kb); }
+static int host_step_tasks(int nb, int kb) {
+  const int t = nb - 1 - kb;
+  return nb + t * (t + 1) / 2 + (kb + 1) * t;
+}
 
 // Called by a whole wave (uniform branch); every lane polls the same word.  Gives
 // up after kSpinLimit polls, or at once when another wait has already given up.
@@ -334,6 +354,52 @@ RF_DEV void task_xcol(const CholInvArgs& a, int kb, int ib, double (*P)[TLD], do
       }
 }
 
+// X(kb, i) of the task queue: X_i,kb = -T_i,kb X_kk with T_i,kb complete in the X
+// tile (i, kb); the mirrored lower tile is cleared.
+RF_DEV void task_xfin(const CholInvArgs& a, int kb, int ib, double (*P)[TLD], double (*Q)[TLD]) {
+  const int64_t b0 = (int64_t)kb * TB, i0 = (int64_t)ib * TB;
+  load_tile(P, a.X64, a.ldx64, i0, b0, a.N);
+  load_tile(Q, a.X64, a.ldx64, b0, b0, a.N);
+  __syncthreads();
+  f64x4 o[2][2];
+  acc_zero(o);
+  tile_mac<false>(o, P, Q);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = tile_row(i, q), c = tile_col(j);
+        put_x(a, i0 + r, b0 + c, -o[i][j][q]);
+        put_x(a, b0 + c, i0 + r, 0.0);
+      }
+}
+
+// U(kb, i, j): T_ij += X_i,kb R_kb,j (i <= kb < j), held in the X tile (i, j); the
+// first term (kb == i) writes it.
+RF_DEV void task_tupd(const CholInvArgs& a, int kb, int ib, int jb, double (*P)[TLD], double (*Q)[TLD]) {
+  const int64_t k0 = (int64_t)kb * TB, i0 = (int64_t)ib * TB, c0 = (int64_t)jb * TB;
+  load_tile(P, a.X64, a.ldx64, i0, k0, a.N);
+  load_tile(Q, a.G, a.ld, k0, c0, a.N);
+  __syncthreads();
+  f64x4 acc[2][2];
+  acc_zero(acc);
+  tile_mac<false>(acc, P, Q);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = i0 + tile_row(i, q), c = c0 + tile_col(j);
+        if (r < a.N && c < a.N) {
+          double* t = a.X64 + r * a.ldx64 + c;
+          *t = (ib == kb) ? acc[i][j][q] : *t + acc[i][j][q];
+        }
+      }
+}
+
 // C(kb, i, j): G_ij -= R_kb,i^T R_kb,j (upper tiles).
 RF_DEV void task_update(const CholInvArgs& a, int kb, int ib, int jb, double (*P)[TLD], double (*Q)[TLD]) {
   const int64_t b0 = (int64_t)kb * TB, r0 = (int64_t)ib * TB, c0 = (int64_t)jb * TB;
@@ -363,12 +429,12 @@ __global__ __launch_bounds__(256) void k_cholinv(CholInvArgs a) {
   __shared__ int ticket;
   const int nb = a.nb;
   int* err = a.fault;
-  int* doneA = a.work + 2;
-  int* doneP = doneA + nb;
-  int* doneX = doneP + nb;
-  int* doneC = doneX + nb;
+  int* gcnt = a.work + 2;        // nb x nb
+  int* pdone = gcnt + nb * nb;   // nb x nb
+  int* tcnt = pdone + nb * nb;   // nb x nb
+  int* xdone = tcnt + nb * nb;   // nb x nb
   int total = 0;
-  for (int kb = 0; kb < nb; ++kb) total += 1 + (nb - 1) + nC_of(nb, kb);
+  for (int kb = 0; kb < nb; ++kb) total += step_tasks(nb, kb);
   // Control flow around the barriers must be uniform: the ticket and the waits are
   // handled by wave 0 as a whole (a branch on the wave index, never on the lane),
   // and the ticket is read back as a wave-uniform value.
@@ -385,39 +451,59 @@ __global__ __launch_bounds__(256) void k_cholinv(CholInvArgs a) {
     if (t >= total) return;
     int kb = 0;
     for (;; ++kb) {
-      const int sz = 1 + (nb - 1) + nC_of(nb, kb);
+      const int sz = step_tasks(nb, kb);
       if (t < sz) break;
       t -= sz;
     }
+    const int w = nb - 1 - kb;  // tiles right of the diagonal at step kb
     int* done;
     if (t == 0) {  // A(kb)
-      if (wave == 0 && kb > 0) wait_at_least(&doneC[kb - 1], nC_of(nb, kb - 1), err);
+      if (wave == 0 && kb > 0) wait_at_least(&gcnt[kb * nb + kb], kb, err);
       __syncthreads();
       task_diag(a, kb, T0, T1, T2);
-      done = &doneA[kb];
+      done = &pdone[kb * nb + kb];
     } else if (t < nb) {  // B(kb, j) or X(kb, i)
       const int u = t - 1;  // 0 .. nb-2
-      const bool panel = u < nb - 1 - kb;
+      const bool panel = u < w;
+      const int j = kb + 1 + u, i = u - w;
       if (wave == 0) {
-        wait_at_least(&doneA[kb], 1, err);
-        // X(kb, .) reads the X columns of earlier steps
-        if (!panel && kb >= 2) wait_at_least(&doneX[kb - 1], kb - 1, err);
+        wait_at_least(&pdone[kb * nb + kb], 1, err);
+        if (panel) {
+          if (kb > 0) wait_at_least(&gcnt[kb * nb + j], kb, err);
+        } else {
+          wait_at_least(&tcnt[i * nb + kb], kb - i, err);
+        }
       }
       __syncthreads();
-      if (panel) task_panel(a, kb, kb + 1 + u, T0, T1);
-      else task_xcol(a, kb, u - (nb - 1 - kb), T0, T1);
-      done = panel ? &doneP[kb] : &doneX[kb];
-    } else {  // C(kb, i, j): needs the panels of step kb only
-      if (wave == 0) wait_at_least(&doneP[kb], nb - 1 - kb, err);
+      if (panel) task_panel(a, kb, j, T0, T1);
+      else task_xfin(a, kb, i, T0, T1);
+      done = panel ? &pdone[kb * nb + j] : &xdone[i * nb + kb];
+    } else if (t < nb + nC_of(nb, kb)) {  // C(kb, i, j), kb < i <= j
+      int u = t - nb, ib = kb + 1, ww = w;
+      while (u >= ww) { u -= ww; ++ib; --ww; }
+      const int jb = ib + u;
+      if (wave == 0) {
+        wait_at_least(&pdone[kb * nb + ib], 1, err);
+        wait_at_least(&pdone[kb * nb + jb], 1, err);
+        if (kb > 0) wait_at_least(&gcnt[ib * nb + jb], kb, err);
+      }
       __syncthreads();
-      int u = t - nb, ib = kb + 1, w = nb - 1 - kb;
-      while (u >= w) { u -= w; ++ib; --w; }
-      task_update(a, kb, ib, ib + u, T0, T1);
-      done = &doneC[kb];
+      task_update(a, kb, ib, jb, T0, T1);
+      done = &gcnt[ib * nb + jb];
+    } else {  // U(kb, i, j), i <= kb < j
+      const int u = t - nb - nC_of(nb, kb), ib = u / w, jb = kb + 1 + u % w;
+      if (wave == 0) {
+        wait_at_least(ib == kb ? &pdone[kb * nb + kb] : &xdone[ib * nb + kb], 1, err);
+        wait_at_least(&pdone[kb * nb + jb], 1, err);
+        if (kb > ib) wait_at_least(&tcnt[ib * nb + jb], kb - ib, err);
+      }
+      __syncthreads();
+      task_tupd(a, kb, ib, jb, T0, T1);
+      done = &tcnt[ib * nb + jb];
     }
     __syncthreads();
     if (wave == 0) {
-      __atomic_thread_fence(__ATOMIC_RELEASE);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       __hip_atomic_fetch_add(done, lane == 0 ? 1 : 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
   }
@@ -496,7 +582,7 @@ hipError_t launch_cholinv_batched(const CholInvArgs* as, int count, hipStream_t 
 
 size_t cholinv_work_ints(int64_t N) {
   const int64_t nb = (N + TB - 1) / TB;
-  return (size_t)(2 + 4 * nb);
+  return (size_t)(2 + 4 * nb * nb);
 }
 
 static int cu_count_ci() {
@@ -526,7 +612,7 @@ hipError_t launch_cholinv(double* G, int64_t ld, int64_t N, double tol_ratio, do
   a.X64 = X64; a.ldx64 = ldx64; a.X32 = X32; a.ldx32 = ldx32;
   a.work = work; a.fault = fault; a.nb = nb;
   int total = 0;
-  for (int kb = 0; kb < nb; ++kb) total += 1 + (nb - 1) + (nb - 1 - kb) * (nb - kb) / 2;
+  for (int kb = 0; kb < nb; ++kb) total += host_step_tasks(nb, kb);
   int grid = cu_count_ci();
   if (grid > total) grid = total;
   const size_t lds = 3 * (size_t)TB * TLD * sizeof(double);

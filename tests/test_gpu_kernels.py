@@ -374,7 +374,7 @@ def test_gram_f64(K, M, N, sym):
         assert np.array_equal(C, C.T)
 
 
-@pytest.mark.parametrize("N", [1, 5, 64, 100, 129, 300, 1000])
+@pytest.mark.parametrize("N", [1, 5, 64, 100, 129, 300, 1000, 2000, 4096])
 def test_cholesky_and_inverse(N):
     rng = np.random.default_rng(N)
     X = rng.standard_normal((N + 20, N)) * np.logspace(0, -3, N)[None, :]
