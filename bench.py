@@ -120,7 +120,8 @@ def main():
                     help="poly65k: the headline workload (default); exp65k: A 65536 x 32768 stored FP32, BF16 and "
                          "FP8 with block scales, k=2000, sketch 4000, q=3; nystrom32k: Gaussian kernel matrix of "
                          "32768 points in 32 dimensions, k=512, sketch 1024, q=2")
-    ap.add_argument("--counter-run", choices=["sketch", "copy"], default=None,
+    ap.add_argument("--counter-run", choices=["sketch", "copy", "sketch_left", "qta_f32", "qta_bf16", "qta_fp8", "gram"],
+                    default=None,
                     help="for rocprofv3 --pmc runs: three sketch passes over the workload matrix, or three copies "
                          "of 1 GiB (FETCH_SIZE / WRITE_SIZE calibration); prints nothing else")
     args = ap.parse_args()
@@ -664,17 +665,44 @@ def counter_run(args):
     import torch
     import paper_2605_09755_amd as rf
     dev = torch.device("cuda:0")
+    m, n, k = args.m, args.n, args.k
+    g = torch.Generator(device=dev)
+    g.manual_seed(args.seed)
     if args.counter_run == "copy":
         x = torch.empty(1 << 28, dtype=torch.float32, device=dev).uniform_()
         y = torch.empty_like(x)
         for _ in range(3):
             y.copy_(x)
+    elif args.counter_run == "sketch_left":
+        # S2^T A of Algorithm 2 (m x n FP32 in, sketch x n out); traffic does not depend on values
+        A = torch.randn((m, n), generator=g, device=dev)
+        for _ in range(3):
+            rf.rf_sketch_apply_left(A, args.sketch, args.s, 42)
+    elif args.counter_run in ("qta_f32", "qta_bf16", "qta_fp8"):
+        # B^T = A^T Q of the randomised SVD at the workload's shape (n x k, contraction over m)
+        Q = torch.randn((m, k), generator=g, device=dev) / math.sqrt(m)
+        if args.counter_run == "qta_f32":
+            A = torch.randn((m, n), generator=g, device=dev)
+            fn = lambda: rf.rf_test_gemm(A, Q, n, k, m, 0, 0, split=False)
+        elif args.counter_run == "qta_bf16":
+            A = torch.randn((m, n), generator=g, device=dev).to(torch.bfloat16)
+            Q16 = Q.to(torch.bfloat16)
+            fn = lambda: rf.rf_test_gemm(A, Q16, n, k, m, 0, 0, split=False)
+        else:
+            A8, sc8 = rf.rf_quantize_fp8_b128(torch.randn((m, n), generator=g, device=dev))
+            qf = rf.rf_test_quant_q_fp8(Q)
+            fn = lambda: rf.rf_test_gemm_fp8(A8, sc8, Q, n, k, m, qform=qf)
+        for _ in range(3):
+            fn()
+    elif args.counter_run == "gram":
+        # the FP64 Gram of CholeskyQR2 on an m x k FP32 basis
+        X = torch.randn((m, k), generator=g, device=dev)
+        for _ in range(3):
+            rf.rf_test_gram(X, sym=True)
     else:
         # the sketch's memory traffic does not depend on the values, so a Gaussian
         # matrix of the workload's shape stands in (no QR, which the counter
         # collection does not survive)
-        g = torch.Generator(device=dev)
-        g.manual_seed(args.seed)
         A = torch.randn((args.m, args.n), generator=g, device=dev)
         for _ in range(3):
             rf.rf_sketch_apply(A, args.sketch, args.s, 42)

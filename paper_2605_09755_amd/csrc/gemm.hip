@@ -657,8 +657,9 @@ __global__ __launch_bounds__(BT, 1) void k_gemm_bf16_big(GemmArgs g) {
 // k order inside one MFMA, the same for both operands: lane half h, byte p ->
 // k = 32 (p / 16) + 16 h + p % 16 (bytes 16 b .. 16 b + 15 form scale block b).
 // Workgroup tile 256 x 256, 8 waves of 128 x 64 (two per SIMD).  The A tile is kept
-// in LDS in its memory layout (128 k rows of 256 bytes, pitch 272 = 16 mod 256, so the
-// 8 rows x 16 bytes of one 16-lane transposed read fall on distinct banks) and read
+// in LDS in its memory layout (128 k rows of 256 bytes, pitch 288 = 32 mod 256, so the
+// 8 rows x 32 bytes read by two 16-lane groups of one transposed read fall on
+// distinct banks) and read
 // with ds_read_b64_tr_b8, which hands lane i of a 16-lane group byte i % 8 of the
 // 8-byte chunks addressed by lanes i / 8 + 2 t (t = 0..7): when lane s addresses row
 // r0 + s / 2, column c0 + 8 (s % 2), lane i receives column c0 + i at rows r0 .. r0+7.
@@ -666,7 +667,7 @@ __global__ __launch_bounds__(BT, 1) void k_gemm_bf16_big(GemmArgs g) {
 // read as 16-byte vectors.
 typedef int f8i32x2 __attribute__((ext_vector_type(2)));
 constexpr int F8K = 128;                   // k rows per stage: one A scale block
-constexpr int F8P = HB + 16;               // LDS pitch of the A tile, bytes
+constexpr int F8P = HB + 32;               // LDS pitch of the A tile, bytes
 constexpr int F8AS = F8K * F8P;            // A stage bytes
 constexpr int F8QS = F8K * HB;             // Q stage bytes (2 chunks x 8 column blocks x 2 KB)
 constexpr int F8CH = F8K * HB / 16 / BT;   // 16-byte chunks per thread and operand per stage
