@@ -320,7 +320,11 @@ rf_status rf_gaussian(int64_t rows, int64_t cols, uint64_t seed, uint32_t stream
 /* At = A S for the sketch given by (s = p->nnz_per_col, r1 = p->sketch, seed,
    stream id 0, and the family in p->flags, RF_SKETCH_*): out m x r1 FP32
    (ldo >= r1).  Any r1 >= s is accepted (p->k, p->q ignored; p->precision picks
-   the product form of the dense families).  ws >= rf_sketch_apply_ws(A, p) bytes. */
+   the product form of the dense families).  ws >= rf_sketch_apply_ws(A, p) bytes.
+   The sparse sign sketch is deterministic: fixed-point sums for s = 4, 8, 16 with
+   at most 640 buckets per block, otherwise (any s) fixed-order FP32 sums per
+   output over its columns in ascending order (gather form) when n <= 32768; only
+   wider A with such sketches falls back to float atomics (order-dependent). */
 size_t rf_sketch_apply_ws(const rf_matrix* A, const rf_params* p);
 rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, int64_t ldo,
                           void* ws, size_t ws_bytes, void* stream);
@@ -328,11 +332,13 @@ rf_status rf_sketch_apply(const rf_matrix* A, const rf_params* p, float* out, in
 /* Allocation-free form of rf_sketch_apply, for callers that cannot allocate
    device memory (code under stream capture, tight serving loops, harnesses that
    forbid allocation): same arguments and same result bits, no workspace.  The
-   sketch table, its kernel-ready form and the per-chunk occupancy live in a
+   sketch table, its kernel-ready form and the per-chunk occupancy (or, for s
+   other than 4, 8, 16, the bucket lists of the gather form) live in a
    library-owned device array of 8 MiB per GPU, held until the process ends.
-   Limit: 8 n s + 4 (n/1024 + 16) bytes, each of the three parts rounded up to
-   256, must fit in 8 MiB (n s <= 1,048,000 or so; e.g. n = 65536 with s = 8);
-   larger requests return RF_EUNSUPPORTED with nothing enqueued.  Every call on a
+   Limit: 8 n s + 4 max(n/1024 + 16, 1.5 n s + 2 r1 + 10) bytes, each of the
+   three parts rounded up to 256, must fit in 8 MiB (e.g. n = 65536 with s = 8,
+   n = 32768 with s = 1); larger requests return RF_EUNSUPPORTED with nothing
+   enqueued.  Every call on a
    GPU shares that GPU's array: calls that overlap on one GPU (other streams,
    other threads) race and must be serialised by the caller.  No hipMalloc, no
    synchronisation; RF_EINVAL as rf_sketch_apply, RF_EHIP if the array's device

@@ -45,6 +45,11 @@ struct SketchArgs {
 };
 hipError_t launch_sketch_right_batched(const SketchArgs* as, int count, int64_t mmax, int64_t nmax, int r1max,
                                        hipStream_t st);
+// Sketches without a fixed-point path (s other than 4, 8, 16; n <= 32768 and the
+// bucket lists fit in LDS) run the atomic-free gather form; `cmax` is then its
+// workspace.  Size `cmax` with sketch_right_work_ints, which covers both uses.
+bool sketch_right_gather(int s, int64_t n, int r1);
+size_t sketch_right_work_ints(int64_t n, int s, int r1);
 hipError_t launch_sketch_right(int dtype, const void* A, int64_t lda, const float* scales, const int32_t* table,
                                const uint32_t* ready, int* cmax, int s, int64_t m, int64_t n, int r1, float* out,
                                int64_t ldo, hipStream_t st);

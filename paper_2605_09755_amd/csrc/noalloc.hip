@@ -51,10 +51,11 @@ hipError_t scratch_address(void** out) {
 
 size_t round256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Bytes of `scratch` one call needs: sketch table, ready table, chunk occupancy.
-size_t noalloc_bytes(int64_t n, int s) {
+// Bytes of `scratch` one call needs: sketch table, ready table, chunk occupancy or
+// the gather form's bucket lists.
+size_t noalloc_bytes(int64_t n, int s, int r1) {
   return round256((size_t)n * s * sizeof(int32_t)) + round256((size_t)n * s * sizeof(uint32_t)) +
-         round256(sketch_right_cmax_ints(n) * sizeof(int));
+         round256(sketch_right_work_ints(n, s, r1) * sizeof(int));
 }
 
 }  // namespace
@@ -69,7 +70,7 @@ rf_status rf_sketch_apply_noalloc(const rf_matrix* A, const rf_params* p, float*
     return RF_EINVAL;
   const int64_t m = A->rows, n = A->cols;
   const int s = p->nnz_per_col, r1 = p->sketch;
-  if (noalloc_bytes(n, s) > kScratchBytes) return RF_EUNSUPPORTED;
+  if (noalloc_bytes(n, s, r1) > kScratchBytes) return RF_EUNSUPPORTED;
   void* base = nullptr;
   if (scratch_address(&base) != hipSuccess) return RF_EHIP;
   unsigned char* q = static_cast<unsigned char*>(base);
@@ -80,7 +81,7 @@ rf_status rf_sketch_apply_noalloc(const rf_matrix* A, const rf_params* p, float*
   int* cmax = reinterpret_cast<int*>(q);
   const hipStream_t st = (hipStream_t)stream;
   hipError_t e = launch_sketch_table(n, s, r1, p->seed, 0, 0, table, st);
-  const bool fast = sketch_right_fast_ok(s);
+  const bool fast = sketch_right_fast_ok(s) && !sketch_right_gather(s, n, r1);
   if (e == hipSuccess && fast) e = launch_sketch_ready(table, n, s, r1, sketch_right_cpl(s), ready, st);
   if (e == hipSuccess)
     e = launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, table, fast ? ready : nullptr, cmax, s, m, n,

@@ -57,7 +57,7 @@ static RFBufs carve_rf(Arena& ar, const Dims& d) {
   const bool sparse = sk && d.family == 0, dense = sk && (d.family == 1 || d.family == 2), srht = sk && d.family == 3;
   b.table = sparse ? ar.get<int32_t>((size_t)d.n * d.s) : nullptr;
   b.ready = sparse ? ar.get<uint32_t>((size_t)d.n * d.s) : nullptr;
-  b.cmax = sparse ? ar.get<int>(sketch_right_cmax_ints(d.n)) : nullptr;
+  b.cmax = sparse ? ar.get<int>(sketch_right_work_ints(d.n, d.s, d.r1)) : nullptr;
   b.Sd = dense ? ar.get<float>((size_t)d.n * d.r1) : nullptr;
   b.Sd16 = (dense && (mixed || d.dtype == RF_BF16)) ? ar.get<uint16_t>((size_t)d.n * d.r1) : nullptr;
   b.srd = srht ? ar.get<float>((size_t)srht_size(d.n)) : nullptr;
@@ -166,7 +166,7 @@ static void sketch_right_any(Ctx& c, const rf_matrix* A, const Dims& d, uint64_t
     c.chk(launch_sketch_table(d.n, d.s, d.r1, seed, 0, 0, b.table, c.st));
     table = b.table;
   }
-  const bool fast = sketch_right_fast_ok(d.s);
+  const bool fast = sketch_right_fast_ok(d.s) && !sketch_right_gather(d.s, d.n, d.r1);
   if (fast) c.chk(launch_sketch_ready(table, d.n, d.s, d.r1, sketch_right_cpl(d.s), b.ready, c.st));
   c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, table, fast ? b.ready : nullptr, b.cmax, d.s,
                             d.m, d.n, d.r1, out, ldo, c.st));
@@ -405,7 +405,7 @@ static RFBufs carve_sketch(Arena& ar, const Dims& d) {
   const bool sparse = d.family == 0, dense = d.family == 1 || d.family == 2, srht = d.family == 3;
   b.table = sparse ? ar.get<int32_t>((size_t)d.n * d.s) : nullptr;
   b.ready = sparse ? ar.get<uint32_t>((size_t)d.n * d.s) : nullptr;
-  b.cmax = sparse ? ar.get<int>(sketch_right_cmax_ints(d.n)) : nullptr;
+  b.cmax = sparse ? ar.get<int>(sketch_right_work_ints(d.n, d.s, d.r1)) : nullptr;
   b.Sd = dense ? ar.get<float>((size_t)d.n * d.r1) : nullptr;
   b.Sd16 = (dense && (mixed || d.dtype == RF_BF16)) ? ar.get<uint16_t>((size_t)d.n * d.r1) : nullptr;
   b.srd = srht ? ar.get<float>((size_t)srht_size(d.n)) : nullptr;
@@ -655,7 +655,7 @@ rf_status rf_nystrom(const rf_matrix* A, const rf_params* p, float* C, int64_t l
   c.chk(launch_fill_i32(b.counters, 16, 0, c.st));
   // Ct = A S (n x r1), Wt = S^T Ct (r1 x r1), symmetrised
   c.chk(launch_sketch_table(n, d.s, r1, p->seed, 0, 0, b.table, c.st));
-  const bool fast = sketch_right_fast_ok(d.s);
+  const bool fast = sketch_right_fast_ok(d.s) && !sketch_right_gather(d.s, d.n, d.r1);
   if (fast) c.chk(launch_sketch_ready(b.table, n, d.s, r1, sketch_right_cpl(d.s), b.ready, c.st));
   c.chk(launch_gaussian(r1, k, p->seed, 1, 0, b.om, k, c.st));
   c.chk(launch_sketch_right(A->dtype, A->data, A->ld, A->block_scales, b.table, fast ? b.ready : nullptr, b.cmax, d.s, n, n,

@@ -17,6 +17,8 @@
 //    and chunk, folded into register accumulators after every chunk;
 //  * k_sketch_right (s = 1 or 2, or larger sketches): LDS float atomics;
 //  * k_sketch_right_atomic (any other s): global atomics, the generic fallback.
+#include <mutex>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -1052,11 +1054,253 @@ static hipError_t launch_sr_dispatch(int s, const void* A, int64_t lda, const fl
   return hipErrorInvalidValue;
 }
 
+// ---- gather form: s without a fixed-point path (CountSketch s = 1, s = 2, 3, 5, ...,
+// and sketches too large for the fixed-point forms' LDS lines) ----------------------
+// Atomic-free and deterministic.  The table is first turned into bucket lists: for
+// every output column c of At, the columns j of A with a nonzero in c, ascending,
+// as 16-bit entries j | sign << 15 (n <= 32768).  A persistent workgroup copies the
+// offsets, and the lists when they fit, into LDS once (larger lists are read from
+// global memory, where they stay in L2), then streams rows: the next row is
+// prefetched into registers while the current row sits in LDS, and thread t forms
+// the outputs c = t, t + 256, ... as fixed-order FP32 sums over their lists (one
+// broadcast-free LDS read per term).
+constexpr int kGatherMaxN = 32768;
+constexpr int kGatherLds = 160 * 1024;
+
+// LDS of one gather workgroup: the row, the offsets and, when they fit, the lists
+// (otherwise the lists are read from global memory, where they stay in L2).
+static bool gather_lists_in_lds(int64_t n, int s, int r1) {
+  return (size_t)n * 4 + ((size_t)n * s * 2 + 15) / 16 * 16 + (size_t)(r1 + 1) * 4 <= (size_t)kGatherLds;
+}
+static size_t gather_lds_bytes(int64_t n, int s, int r1) {
+  const size_t lists = gather_lists_in_lds(n, s, r1) ? ((size_t)n * s * 2 + 15) / 16 * 16 : 0;
+  return (size_t)n * 4 + lists + (size_t)(r1 + 1) * 4;
+}
+
+// s = 4, 8, 16 use the fixed-point forms while their block holds at most 640 bucket
+// lines; other s, and larger sketches, the gather form (when a row fits in LDS).
+bool sketch_right_gather(int s, int64_t n, int r1) {
+  if ((s == 4 || s == 8 || s == 16) && (r1 + s - 1) / s <= 640) return false;
+  return n <= kGatherMaxN && (size_t)n * 4 + (size_t)(r1 + 1) * 4 <= (size_t)kGatherLds;
+}
+
+size_t sketch_right_work_ints(int64_t n, int s, int r1) {
+  const size_t g = (size_t)2 * r1 + 2 + (size_t)n * s + ((size_t)n * s + 1) / 2 + 8;
+  const size_t c = sketch_right_cmax_ints(n);
+  return g > c ? g : c;
+}
+
+__global__ void k_bkt_count(const int32_t* __restrict__ table, int64_t ne, int* __restrict__ cnt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ne) atomicAdd(&cnt[table[i] & 0x7fffffff], 1);
+}
+
+// start[0..r1] = exclusive prefix sum of cnt[0..r1) (in place; one workgroup)
+__global__ __launch_bounds__(1024) void k_bkt_scan(int* __restrict__ cnt, int r1) {
+  __shared__ int part[1024];
+  const int t = threadIdx.x;
+  const int per = (r1 + 1023) / 1024, lo = t * per, hi = min(lo + per, r1);
+  int sum = 0;
+  for (int i = lo; i < hi; ++i) sum += cnt[i];
+  part[t] = sum;
+  __syncthreads();
+  for (int o = 1; o < 1024; o <<= 1) {
+    const int v = t >= o ? part[t - o] : 0;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  int run = part[t] - sum;  // exclusive
+  for (int i = lo; i < hi; ++i) {
+    const int c = cnt[i];
+    cnt[i] = run;
+    run += c;
+  }
+  if (t == 1023) cnt[r1] = part[1023];
+}
+
+__global__ void k_bkt_fill(const int32_t* __restrict__ table, int64_t n, int s, const int* __restrict__ start,
+                           int* __restrict__ cursor, int32_t* __restrict__ list) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= n * s) return;
+  const int32_t e = table[p];
+  const int c = e & 0x7fffffff;
+  const int pos = start[c] + atomicAdd(&cursor[c], 1);
+  list[pos] = (int32_t)(p / s) | (e & (int32_t)0x80000000);
+}
+
+// each list sorted by column (insertion sort; a column appears at most once per
+// list, since the s nonzeros of a column lie in different blocks), then packed
+// into 16-bit entries
+__global__ void k_bkt_sort(const int* __restrict__ start, int r1, int32_t* __restrict__ list,
+                           uint16_t* __restrict__ list16) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= r1) return;
+  const int a = start[c], b = start[c + 1];
+  for (int i = a + 1; i < b; ++i) {
+    const int32_t v = list[i];
+    const int key = v & 0x7fffffff;
+    int k = i - 1;
+    while (k >= a && (list[k] & 0x7fffffff) > key) {
+      list[k + 1] = list[k];
+      --k;
+    }
+    list[k + 1] = v;
+  }
+  for (int i = a; i < b; ++i) {
+    const int32_t v = list[i];
+    list16[i] = (uint16_t)((v & 0x7fff) | (v < 0 ? 0x8000 : 0));
+  }
+}
+
+constexpr int kGT = 256;      // threads of the gather workgroup
+constexpr int kGQ = 32;       // at most 32 float4 chunks (128 elements) of a row per thread
+
+template <typename TIN, bool LDS_LISTS>
+__global__ __launch_bounds__(kGT) void k_sketch_gather(const TIN* __restrict__ A, int64_t lda,
+                                                       const float* __restrict__ scales, int64_t ldsc,
+                                                       const int* __restrict__ start,
+                                                       const uint16_t* __restrict__ list16, int64_t m, int64_t n,
+                                                       int ne, int r1, float* __restrict__ out, int64_t ldo,
+                                                       float inv_sqrt_s, bool vec_ok) {
+  extern __shared__ __attribute__((aligned(16))) unsigned char gsm[];
+  float* row = reinterpret_cast<float*>(gsm);
+  const size_t lbytes = LDS_LISTS ? ((size_t)ne * 2 + 15) / 16 * 16 : 0;
+  uint16_t* lsm = reinterpret_cast<uint16_t*>(gsm + (size_t)n * 4);
+  int* st = reinterpret_cast<int*>(gsm + (size_t)n * 4 + lbytes);
+  const int tid = threadIdx.x;
+  if constexpr (LDS_LISTS)
+    for (int i = tid; i < ne; i += kGT) lsm[i] = list16[i];
+  const uint16_t* lst = LDS_LISTS ? lsm : list16;
+  for (int i = tid; i <= r1; i += kGT) st[i] = start[i];
+  // row loader: thread t owns elements 4 (t + kGT q) .. +3 of the row, q < nq
+  const int nq = (int)((n + 4 * kGT - 1) / (4 * kGT));
+  float pre[kGQ][4];
+  auto load_row = [&](int64_t i) {
+#pragma unroll
+    for (int q = 0; q < kGQ; ++q) {
+      if (q < nq) {
+        const int64_t j = 4 * ((int64_t)tid + (int64_t)kGT * q);
+        if (j < n) {
+          ld_cols<TIN, 4>(A + i * lda, j, n, vec_ok, pre[q]);
+          if constexpr (sizeof(TIN) == 1) {
+            const float sc = scales[(i >> 7) * ldsc + (j >> 7)];  // 4 | 128: one block per chunk
+#pragma unroll
+            for (int e = 0; e < 4; ++e) pre[q][e] *= sc;
+          }
+        }
+      }
+    }
+  };
+  int64_t i = blockIdx.x;
+  if (i < m) load_row(i);
+  for (; i < m; i += gridDim.x) {
+    __syncthreads();  // the previous row's gathers are done
+#pragma unroll
+    for (int q = 0; q < kGQ; ++q) {
+      if (q < nq) {
+        const int64_t j = 4 * ((int64_t)tid + (int64_t)kGT * q);
+        if (j + 4 <= n) {
+          *reinterpret_cast<float4*>(row + j) = make_float4(pre[q][0], pre[q][1], pre[q][2], pre[q][3]);
+        } else {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (j + e < n) row[j + e] = pre[q][e];
+        }
+      }
+    }
+    __syncthreads();
+    if (i + gridDim.x < m) load_row(i + gridDim.x);
+    // two outputs per thread at a time, terms read four at a time: independent LDS
+    // reads in flight, each output still summed in ascending column order
+    for (int c0 = tid; c0 < r1; c0 += 2 * kGT) {
+      const int c1 = c0 + kGT;
+      const int a0 = st[c0], b0 = st[c0 + 1];
+      const int a1 = c1 < r1 ? st[c1] : 0, b1 = c1 < r1 ? st[c1 + 1] : 0;
+      float acc0 = 0.f, acc1 = 0.f;
+      int e0 = a0, e1 = a1;
+      auto term = [&](uint16_t v) {
+        const float x = row[v & 0x7fff];
+        return (v & 0x8000) ? -x : x;
+      };
+      while (e0 + 4 <= b0 && e1 + 4 <= b1) {
+        const uint16_t u0 = lst[e0], u1 = lst[e0 + 1], u2 = lst[e0 + 2], u3 = lst[e0 + 3];
+        const uint16_t w0 = lst[e1], w1 = lst[e1 + 1], w2 = lst[e1 + 2], w3 = lst[e1 + 3];
+        const float x0 = term(u0), x1 = term(u1), x2 = term(u2), x3 = term(u3);
+        const float y0 = term(w0), y1 = term(w1), y2 = term(w2), y3 = term(w3);
+        acc0 += x0; acc0 += x1; acc0 += x2; acc0 += x3;
+        acc1 += y0; acc1 += y1; acc1 += y2; acc1 += y3;
+        e0 += 4;
+        e1 += 4;
+      }
+      while (e0 + 4 <= b0) {
+        const uint16_t u0 = lst[e0], u1 = lst[e0 + 1], u2 = lst[e0 + 2], u3 = lst[e0 + 3];
+        const float x0 = term(u0), x1 = term(u1), x2 = term(u2), x3 = term(u3);
+        acc0 += x0; acc0 += x1; acc0 += x2; acc0 += x3;
+        e0 += 4;
+      }
+      while (e1 + 4 <= b1) {
+        const uint16_t w0 = lst[e1], w1 = lst[e1 + 1], w2 = lst[e1 + 2], w3 = lst[e1 + 3];
+        const float y0 = term(w0), y1 = term(w1), y2 = term(w2), y3 = term(w3);
+        acc1 += y0; acc1 += y1; acc1 += y2; acc1 += y3;
+        e1 += 4;
+      }
+      for (; e0 < b0; ++e0) acc0 += term(lst[e0]);
+      for (; e1 < b1; ++e1) acc1 += term(lst[e1]);
+      out[i * ldo + c0] = acc0 * inv_sqrt_s;
+      if (c1 < r1) out[i * ldo + c1] = acc1 * inv_sqrt_s;
+    }
+  }
+}
+
+template <typename TIN>
+static hipError_t launch_gather(const void* A, int64_t lda, const float* scales, int64_t ldsc, const int32_t* table,
+                                int* work, int s, int64_t m, int64_t n, int r1, float* out, int64_t ldo,
+                                hipStream_t st) {
+  const int64_t ne = n * s;
+  int* start = work;                       // r1 + 1
+  int* cursor = start + r1 + 1;            // r1
+  int32_t* list = cursor + r1;             // n s
+  uint16_t* list16 = reinterpret_cast<uint16_t*>(list + ne);
+  hipLaunchKernelGGL(k_fill_int, dim3((unsigned)((2 * r1 + 1 + 255) / 256)), dim3(256), 0, st, start,
+                     (int64_t)(2 * r1 + 1));
+  hipLaunchKernelGGL(k_bkt_count, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, table, ne, start);
+  hipLaunchKernelGGL(k_bkt_scan, dim3(1), dim3(1024), 0, st, start, r1);
+  hipLaunchKernelGGL(k_bkt_fill, dim3((unsigned)((ne + 255) / 256)), dim3(256), 0, st, table, n, s, start, cursor,
+                     list);
+  hipLaunchKernelGGL(k_bkt_sort, dim3((unsigned)((r1 + 255) / 256)), dim3(256), 0, st, start, r1, list, list16);
+  const size_t lds = gather_lds_bytes(n, s, r1);
+  const bool in_lds = gather_lists_in_lds(n, s, r1);
+  static std::once_flag attr;
+  std::call_once(attr, [] {
+    (void)hipFuncSetAttribute((const void*)k_sketch_gather<TIN, true>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kGatherLds);
+    (void)hipFuncSetAttribute((const void*)k_sketch_gather<TIN, false>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              kGatherLds);
+  });
+  const int64_t per_cu = (int64_t)(kGatherLds / lds) < 4 ? (int64_t)(kGatherLds / lds) : 4;  // workgroups per CU
+  const int64_t slots = per_cu * num_cu();
+  const int64_t grid = m < slots ? m : slots;
+  const bool vec_ok = (((uintptr_t)A) % (sizeof(TIN) * 4) == 0) && (lda % 4 == 0);
+  auto k = in_lds ? k_sketch_gather<TIN, true> : k_sketch_gather<TIN, false>;
+  hipLaunchKernelGGL(k, dim3((unsigned)grid), dim3(kGT), lds, st, (const TIN*)A, lda, scales, ldsc, start, list16, m,
+                     n, (int)ne, r1, out, ldo, 1.0f / sqrtf((float)s), vec_ok);
+  return hipGetLastError();
+}
+
 hipError_t launch_sketch_right(int dtype, const void* A, int64_t lda, const float* scales, const int32_t* table,
                                const uint32_t* ready, int* cmax, int s, int64_t m, int64_t n, int r1, float* out,
                                int64_t ldo, hipStream_t st) {
   if (m == 0 || n == 0) return hipSuccess;
   int64_t ldsc = (n + 127) / 128;
+  if (sketch_right_gather(s, n, r1) && cmax) {
+    switch (dtype) {
+      case 0: return launch_gather<float>(A, lda, scales, ldsc, table, cmax, s, m, n, r1, out, ldo, st);
+      case 2: return launch_gather<uint16_t>(A, lda, scales, ldsc, table, cmax, s, m, n, r1, out, ldo, st);
+      case 3: return launch_gather<uint8_t>(A, lda, scales, ldsc, table, cmax, s, m, n, r1, out, ldo, st);
+    }
+    return hipErrorInvalidValue;
+  }
   if (sketch_right_fast_ok(s) && ready) {
     switch (dtype) {
       case 0: return launch_sr_dispatch<float>(s, A, lda, scales, ldsc, table, ready, cmax, m, n, r1, out, ldo, st);

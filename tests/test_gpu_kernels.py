@@ -93,6 +93,26 @@ def test_sketch_apply_f32(m, n, s, r1):
     assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
 
 
+@pytest.mark.parametrize("m,n,s,r1", [(40, 3000, 4, 2800), (33, 5000, 5, 900), (64, 32768, 1, 700),
+                                     (5, 20000, 2, 3000), (300, 4096, 1, 2000), (2, 1000, 7, 7)])
+def test_sketch_apply_gather_form(m, n, s, r1):
+    """The gather form (s without a fixed-point path, and s = 4 sketches beyond
+    640 buckets per block): element-wise within the FP32 summation bound, and the
+    same bits on a second call (fixed summation order, no atomics)."""
+    rng = np.random.default_rng(m + n + s)
+    A = (rng.standard_normal((m, n)) * np.exp(rng.standard_normal((1, n)))).astype(np.float32)
+    A64 = A.astype(np.float64)
+    ref, mag = _sketch_ref(A64, n, s, r1, 19)
+    dA = torch.from_numpy(A).to(DEV)
+    got = rf.rf_sketch_apply(dA, r1, s, 19)
+    again = rf.rf_sketch_apply(dA, r1, s, 19)
+    torch.cuda.synchronize()
+    assert torch.equal(got, again)
+    got = got.cpu().numpy()
+    tol = _sketch_tol(A64, n, s, r1, 19, mag)
+    assert np.all(np.abs(got - ref) <= tol), np.max(np.abs(got - ref) / tol)
+
+
 def test_sketch_apply_strided_rows():
     rng = np.random.default_rng(5)
     big = rng.standard_normal((60, 1030)).astype(np.float32)
