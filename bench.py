@@ -28,6 +28,8 @@ The same line also carries (each an extra key, `--sections` to choose):
   sigma_i = 30000/i), sketched (CountSketch) against classical (S = I) RandSVD and
   Algorithm 2, l in {800, 1200, 1600}, time and ||A - A_hat||_2 / sigma_{k+1} - 1;
 * nystrom32k: Algorithm 3 on a Gaussian kernel matrix, plain FP32 and mixed;
+* config.s_sweep_mixed: s in {1, 2, 4, 8, 16} at the main workload (sketch pass and
+  rf_svd time, error ratio);
 * batched: 512 uneven matrices in one hipGraph replay;
 * cpu_baseline: the FP64 oracle on the host (row sample, scaled) with the CPU model
   and a single-thread figure for the CPU-sized workload.
@@ -238,6 +240,26 @@ def main():
             log("%s (mixed, q=%d): %.3f ms" % (name, q_run, entry_ms[name]))
             del ws
 
+    # s-sweep (Lemma 3.2 item 2: nonzeros per column of S), mixed form at the timed q:
+    # the sketch pass alone and the whole factorisation, with its error ratio
+    s_sweep = {}
+    if "mixed" in results:
+        q_run = results["mixed"]["q"]
+        for s_ in (1, 2, 4, 8, 16):
+            p = rf.params(k, l, q_run, s_, 42, "mixed")
+            nws = rf.rf_workspace_size(rf.RF_OP_SVD, A, p)
+            ws = torch.empty(nws, dtype=torch.uint8, device=dev)
+            out = (torch.empty((m, k), dtype=torch.float32, device=dev), torch.empty(k, dtype=torch.float64, device=dev),
+                   torch.empty((k, n), dtype=torch.float32, device=dev),
+                   torch.zeros(rf.INFO_BYTES, dtype=torch.uint8, device=dev))
+            t_sk = time_calls(torch, lambda: rf.rf_sketch_apply(A, l, s_, 42), 1, 3, stream)
+            t_svd = time_calls(torch, lambda: rf.rf_svd(A, k, l, q_run, s_, 42, "mixed", workspace=(ws, nws), out=out),
+                               1, 2, stream)
+            ratio = frob_err(torch, A, out[0]) / opt
+            s_sweep[s_] = {"sketch_ms": t_sk, "rf_svd_ms": t_svd, "ratio": ratio}
+            log("s-sweep s=%d: sketch %.3f ms, rf_svd %.3f ms, ratio %.5f" % (s_, t_sk, t_svd, ratio))
+            del ws, out
+
     # ---- roofline of the dominant kernels, timed live with HIP events on the launch stream
     roof = {}
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -327,6 +349,7 @@ def main():
             "mixed": results.get("mixed"), "plain_fp32": results.get("fp32"),
             "speedup_mixed_vs_plain": (plain["ms_per_step"] / mixed["ms_per_step"]) if (mixed and plain) else None,
             "other_entry_points_mixed_ms": entry_ms,
+            "s_sweep_mixed": s_sweep,
         },
         "roofline": roofline,
         "roofline_other": others,
