@@ -260,7 +260,7 @@ hipError_t launch_gram(const void* X, int64_t ldx, int xdt, const void* Y, int64
 // its rotation V (64 x 64) is applied to the rows/columns of G and to Z in a
 // second kernel, tile by tile, in place.  Converged when every off-diagonal
 // entry is <= tol * sqrt(|G_ii G_jj| + floor^2).
-constexpr int JBMAX = 32, JSMAX = 64;  // largest block width supported by the workspace layout
+int eig_block_width(int64_t N);
 
 
 static EigWork eig_layout(void* work, int64_t N, int JB) {
@@ -273,9 +273,9 @@ static EigWork eig_layout(void* work, int64_t N, int JB) {
   char* p = (char*)work;
   w.Gp = (double*)p; p += K * K * 8;
   w.Z = (double*)p; p += K * K * 8;
-  w.V = (double*)p; p += (size_t)w.p * JS * JS * 8;
+  w.V = (double*)p; p += (size_t)2 * w.p * JS * JS * 8;  // two slots: rounds alternate
   w.perm = (int*)p; p += ((K * 4 + 255) / 256) * 256;
-  w.ident = (int*)p; p += ((w.p * 4 + 255) / 256) * 256;
+  w.ident = (int*)p; p += ((2 * w.p * 4 + 255) / 256) * 256;
   w.maxoff = (unsigned long long*)p; p += 256;
   w.conv = (int*)p; p += 256;
   w.floor2 = (double*)p; p += 256;
@@ -285,15 +285,12 @@ static EigWork eig_layout(void* work, int64_t N, int JB) {
 
 int eig_max_sweeps() { return 20; }
 
+// Bytes of the layout eig_layout lays out (taken from the layout itself, so the
+// two cannot disagree), plus alignment slack.
 size_t eig_work_bytes(int64_t N) {
-  // sized for the smallest block width (most pairs) and the largest padding
-  const int JB = 16, JS = 32;
-  int64_t K = ((N + 2 * JBMAX - 1) / (2 * JBMAX)) * (2 * JBMAX);
-  if (K < 2 * JBMAX) K = 2 * JBMAX;
-  int64_t p = K / (2 * JB);
-  (void)JB;
-  return (size_t)(2 * K * K * 8 + p * JS * JS * 8 + ((K * 4 + 255) / 256) * 256 + ((p * 4 + 255) / 256) * 256 +
-                  4 * 256) + 4096;
+  const uintptr_t base = 4096;
+  const EigWork w = eig_layout(reinterpret_cast<void*>(base), N, eig_block_width(N));
+  return (size_t)(reinterpret_cast<uintptr_t>(w.fabs_) + 256 - base) + 4096;
 }
 
 RF_DEV int circle(int round, int i, int n) {  // position i of round in an n-player circle schedule
@@ -367,9 +364,17 @@ RF_DEV void jacobi_rot(double app, double aqq, double apq, double floor2, double
 }
 
 template <int JB>
-RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x) {
+RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x, int slot) {
   constexpr int JS = 2 * JB;
-  if (*w.conv) return;
+  // this round's rotations and "unchanged" flags go to slot `slot` (rounds
+  // alternate between two, so the eigenvector update of one round can run
+  // while the next round is solved)
+  int* const ident = w.ident + slot * w.p;
+  double* const Vout = w.V + (int64_t)slot * w.p * JS * JS;
+  if (*w.conv) {
+    if (threadIdx.x == 0) ident[x] = 1;
+    return;
+  }
   extern __shared__ double sm[];
   double(*M)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm);
   double(*V)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm + JS * (JS + 1));
@@ -413,70 +418,134 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
   }
   __syncthreads();
   if (!needed) {
-    if (threadIdx.x == 0) w.ident[x] = 1;
+    if (threadIdx.x == 0) ident[x] = 1;
     return;
   }
-  if (threadIdx.x == 0) w.ident[x] = 0;
-  // the pairs (lo, hi) of every inner round of the circle schedule, computed once:
-  // the inner loop then reads them instead of repeating the modular arithmetic
-  __shared__ unsigned char pair_lo[JS - 1][JS / 2], pair_hi[JS - 1][JS / 2];
-  for (int e = threadIdx.x; e < (JS - 1) * (JS / 2); e += blockDim.x) {
-    const int rr = e / (JS / 2), u = e % (JS / 2);
-    int a = circle(rr, u, JS), b = circle(rr, JS - 1 - u, JS);
-    if (a > b) { const int t = a; a = b; b = t; }
-    pair_lo[rr][u] = (unsigned char)a;
-    pair_hi[rr][u] = (unsigned char)b;
-  }
-  __syncthreads();
-  for (int sw = 0; sw < inner_sweeps; ++sw) {
-    if (threadIdx.x == 0) done = 1;
-    __syncthreads();
-    for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
-      int a = e / JS, b = e % JS;
-      if (a < b && fabs(M[a][b]) > 1e-15 * sqrt(fabs(M[a][a]) * fabs(M[b][b]) + floor2)) done = 0;
+  if (threadIdx.x == 0) ident[x] = 0;
+  // The first round of an outer sweep rotates every pair of the subproblem; the
+  // other rounds only the pairs across its two blocks.  Over one outer sweep
+  // every pair of indices is then rotated once (a cyclic Jacobi sweep in block
+  // order), in about half the sequential inner rounds of full subproblem sweeps.
+  const bool full = round == 0;
+  if (full) {
+    // a full cyclic sweep over every pair of the 2 JB indices (the pairs inside
+    // each block included)
+    // the pairs (lo, hi) of every inner round of the circle schedule, computed once:
+    // the inner loop then reads them instead of repeating the modular arithmetic
+    __shared__ unsigned char pair_lo[JS - 1][JS / 2], pair_hi[JS - 1][JS / 2];
+    for (int e = threadIdx.x; e < (JS - 1) * (JS / 2); e += blockDim.x) {
+      const int rr = e / (JS / 2), u = e % (JS / 2);
+      int a = circle(rr, u, JS), b = circle(rr, JS - 1 - u, JS);
+      if (a > b) { const int t = a; a = b; b = t; }
+      pair_lo[rr][u] = (unsigned char)a;
+      pair_hi[rr][u] = (unsigned char)b;
     }
     __syncthreads();
-    if (done) break;
-    for (int rr = 0; rr < JS - 1; ++rr) {
-      // pair u of inner round rr: (lo, hi) of circle positions u and JS-1-u, from
-      // the table; the rotations go through LDS as (c, s) pairs
-      auto pair_of = [&](int u, int& a, int& b) {
-        a = pair_lo[rr][u];
-        b = pair_hi[rr][u];
-      };
-      if (threadIdx.x < JS / 2) {
-        const int u = threadIdx.x;
-        int a, b;
-        pair_of(u, a, b);
+    for (int sw = 0; sw < inner_sweeps; ++sw) {
+      if (threadIdx.x == 0) done = 1;
+      __syncthreads();
+      for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
+        int a = e / JS, b = e % JS;
+        if (a < b && fabs(M[a][b]) > 1e-15 * sqrt(fabs(M[a][a]) * fabs(M[b][b]) + floor2)) done = 0;
+      }
+      __syncthreads();
+      if (done) break;
+      for (int rr = 0; rr < JS - 1; ++rr) {
+        // pair u of inner round rr: (lo, hi) of circle positions u and JS-1-u, from
+        // the table; the rotations go through LDS as (c, s) pairs
+        auto pair_of = [&](int u, int& a, int& b) {
+          a = pair_lo[rr][u];
+          b = pair_hi[rr][u];
+        };
+        if (threadIdx.x < JS / 2) {
+          const int u = threadIdx.x;
+          int a, b;
+          pair_of(u, a, b);
+          double c, s;
+          jacobi_rot(M[a][a], M[b][b], M[a][b], floor2, c, s);  // FP32 angle, exact FP64 rotation
+          csn[u] = double2{c, s};
+        }
+        __syncthreads();
+        // thread t: 2x2 block (u, v) = (t / (JS/2), t % (JS/2)), M' = J_u^T M J_v, and
+        // rows t / (JS/2) + 32 h of V <- V J_v (the same pair v)
+        for (int e = threadIdx.x; e < (JS / 2) * (JS / 2); e += blockDim.x) {
+          const int u = e / (JS / 2), v = e % (JS / 2);
+          int a, b, cc, d;
+          pair_of(u, a, b);
+          pair_of(v, cc, d);
+          const double2 ju = csn[u], jv = csn[v];
+          const double cu = ju.x, su = ju.y, cv = jv.x, sv = jv.y;
+          const double m00 = M[a][cc], m01 = M[a][d], m10 = M[b][cc], m11 = M[b][d];
+          double v0[2], v1[2];  // rows u and u + JS/2 of V
+  #pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            v0[h] = V[u + (JS / 2) * h][cc];
+            v1[h] = V[u + (JS / 2) * h][d];
+          }
+          const double t00 = cu * m00 - su * m10, t01 = cu * m01 - su * m11;
+          const double t10 = su * m00 + cu * m10, t11 = su * m01 + cu * m11;
+          M[a][cc] = cv * t00 - sv * t01; M[a][d] = sv * t00 + cv * t01;
+          M[b][cc] = cv * t10 - sv * t11; M[b][d] = sv * t10 + cv * t11;
+  #pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            V[u + (JS / 2) * h][cc] = cv * v0[h] - sv * v1[h];
+            V[u + (JS / 2) * h][d] = sv * v0[h] + cv * v1[h];
+          }
+        }
+        __syncthreads();
+      }
+    }
+  } else {
+    // cross pairs only: inner round r pairs index u of the first block with index
+    // (u + r) mod JB of the second, so the JB rounds meet each cross pair once.
+    // Only the upper triangle of M is kept current (M[i][j], i <= j): thread t
+    // < JB (JB + 1) / 2 owns the 2 x 2 block of pairs (u, v), u <= v, for the
+    // whole sweep, which also stands for its mirror block (v, u).
+    constexpr int NUP = JB * (JB + 1) / 2;
+    int bu = -1, bv = -1;
+    if ((int)threadIdx.x < NUP) upper_tile(threadIdx.x, JB, bu, bv);
+    const int vu = threadIdx.x & (JB - 1), vx = threadIdx.x / JB;  // V: pair vu, rows vx + JB h
+    for (int r = 0; r < JB; ++r) {
+      if (threadIdx.x < JB) {
+        const int u = threadIdx.x, q = JB + ((u + r) & (JB - 1));
         double c, s;
-        jacobi_rot(M[a][a], M[b][b], M[a][b], floor2, c, s);  // FP32 angle, exact FP64 rotation
+        jacobi_rot(M[u][u], M[q][q], M[u][q], floor2, c, s);
         csn[u] = double2{c, s};
       }
       __syncthreads();
-      // thread t: 2x2 block (u, v) = (t / (JS/2), t % (JS/2)), M' = J_u^T M J_v, and
-      // rows t / (JS/2) + 32 h of V <- V J_v (the same pair v)
-      for (int e = threadIdx.x; e < (JS / 2) * (JS / 2); e += blockDim.x) {
-        const int u = e / (JS / 2), v = e % (JS / 2);
-        int a, b, cc, d;
-        pair_of(u, a, b);
-        pair_of(v, cc, d);
-        const double2 ju = csn[u], jv = csn[v];
+      if (bu >= 0) {
+        const int su_ = (bu + r) & (JB - 1), sv_ = (bv + r) & (JB - 1);
+        const int a = bu, b = JB + su_, cc = bv, d = JB + sv_;
+        const double2 ju = csn[bu], jv = csn[bv];
         const double cu = ju.x, su = ju.y, cv = jv.x, sv = jv.y;
-        const double m00 = M[a][cc], m01 = M[a][d], m10 = M[b][cc], m11 = M[b][d];
-        double v0[2], v1[2];  // rows u and u + JS/2 of V
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          v0[h] = V[u + (JS / 2) * h][cc];
-          v1[h] = V[u + (JS / 2) * h][d];
+        if (bu == bv) {
+          const double app = M[a][a], apq = M[a][b], aqq = M[b][b];
+          const double t00 = cu * app - su * apq, t01 = cu * apq - su * aqq;
+          const double t10 = su * app + cu * apq, t11 = su * apq + cu * aqq;
+          M[a][a] = cv * t00 - sv * t01;
+          M[a][b] = sv * t00 + cv * t01;
+          M[b][b] = sv * t10 + cv * t11;
+        } else {
+          const int dlo = JB + (su_ < sv_ ? su_ : sv_), dhi = JB + (su_ < sv_ ? sv_ : su_);
+          // rows (a, b), columns (cc, d); M[b][cc] is kept as M[cc][b] (cc < JB <= b)
+          const double m00 = M[a][cc], m01 = M[a][d], m10 = M[cc][b], m11 = M[dlo][dhi];
+          const double t00 = cu * m00 - su * m10, t01 = cu * m01 - su * m11;
+          const double t10 = su * m00 + cu * m10, t11 = su * m01 + cu * m11;
+          M[a][cc] = cv * t00 - sv * t01;
+          M[a][d] = sv * t00 + cv * t01;
+          M[cc][b] = cv * t10 - sv * t11;
+          M[dlo][dhi] = sv * t10 + cv * t11;
         }
-        const double t00 = cu * m00 - su * m10, t01 = cu * m01 - su * m11;
-        const double t10 = su * m00 + cu * m10, t11 = su * m01 + cu * m11;
-        M[a][cc] = cv * t00 - sv * t01; M[a][d] = sv * t00 + cv * t01;
-        M[b][cc] = cv * t10 - sv * t11; M[b][d] = sv * t10 + cv * t11;
+      }
+      {
+        const double2 j = csn[vu];
+        const int q = JB + ((vu + r) & (JB - 1));
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          V[u + (JS / 2) * h][cc] = cv * v0[h] - sv * v1[h];
-          V[u + (JS / 2) * h][d] = sv * v0[h] + cv * v1[h];
+          const int row = vx + JB * h;
+          const double x0 = V[row][vu], x1 = V[row][q];
+          V[row][vu] = j.x * x0 - j.y * x1;
+          V[row][q] = j.y * x0 + j.x * x1;
         }
       }
       __syncthreads();
@@ -497,7 +566,7 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
     rnk[a] = (P < Q) ? r : (r + JB) % JS;
   }
   __syncthreads();
-  double* out = w.V + (int64_t)x * JS * JS;
+  double* out = Vout + (int64_t)x * JS * JS;
   for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) out[(e / JS) * JS + rnk[e % JS]] = V[e / JS][e % JS];
 }
 
@@ -509,6 +578,7 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x)
 struct Mfma64 {
   int lane, wm, wn;
   RF_DEV Mfma64() : lane(threadIdx.x & 63), wm((threadIdx.x >> 6) >> 1), wn((threadIdx.x >> 6) & 1) {}
+  RF_DEV explicit Mfma64(int tid) : lane(tid & 63), wm((tid >> 6) >> 1), wn((tid >> 6) & 1) {}  // 256-thread group
   RF_DEV int arow(int i) const { return wm * 32 + i * 16 + (lane & 15); }
   RF_DEV int bcol(int j) const { return wn * 32 + j * 16 + (lane & 15); }
   RF_DEV int krow(int kk) const { return 4 * kk + (lane >> 4); }
@@ -572,15 +642,55 @@ struct Mfma64 {
   }
 };
 
+// Z strip zid = rb p + x: Z[rows of strip rb, I_x] <- Z[..] V_x for the round and
+// rotation slot given, by a group of 256 threads (tid) staging the strip in T.
+// Every thread of the workgroup passes the same barriers whether its group is
+// active or not.  No test of the convergence flag: this update may run after
+// the flag was set; a round whose solve saw it marked every subproblem unchanged.
+template <int JB>
+RF_DEV void eig_zstrip_body(const EigWork& w, int round, int slot, int zid, int tid, double (*T)[2 * JB + 1],
+                            bool active) {
+  constexpr int JS = 2 * JB;
+  const int np = 2 * w.p;
+  const int x = zid % w.p, rb = zid / w.p;
+  active = active && !w.ident[slot * w.p + x];
+  const Mfma64 mm(tid);
+  f64x4 acc[2][2];
+  double opb[16][2];
+  const int Px = circle(round, x, np), Qx = circle(round, np - 1 - x, np);
+  auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
+  const int64_t r0 = (int64_t)rb * JS;  // K is a multiple of JS: the strip is whole
+  if (active) {
+    mm.load_b(w.V + ((int64_t)slot * w.p + x) * JS * JS, opb);
+    for (int e = tid; e < JS * JS / 2; e += 256) {
+      const int a = e >> 5, b = (e & 31) * 2;
+      const double2 z = *reinterpret_cast<const double2*>(w.Z + (r0 + a) * w.K + ix(b));
+      T[a][b] = z.x;
+      T[a][b + 1] = z.y;
+    }
+  }
+  __syncthreads();
+  if (active) mm.mul_lds_reg(T, opb, acc);
+  __syncthreads();
+  if (active) mm.store(acc, T);
+  __syncthreads();
+  if (active)
+    for (int e = tid; e < JS * JS / 2; e += 256) {
+      const int a = e >> 5, b = (e & 31) * 2;
+      *reinterpret_cast<double2*>(w.Z + (r0 + a) * w.K + ix(b)) = double2{T[a][b], T[a][b + 1]};
+    }
+}
+
 // Work item id < p(p+1)/2: tile (x, y), x <= y, G[I_x, I_y] <- V_x^T G[I_x, I_y] V_y,
 // written to both (x, y) and (y, x) so G stays exactly symmetric.  Other ids:
 // Z[rows, I_x] <- Z[rows, I_x] V_x for one 64-row strip.  256 threads; the tile
 // is staged in LDS, the V operands go from global memory straight to registers.
 template <int JB>
-RF_DEV void eig_apply_body(const EigWork& w, int round, int id) {
+RF_DEV void eig_apply_body(const EigWork& w, int round, int id, int slot) {
   constexpr int JS = 2 * JB;
   static_assert(JS == 64, "the MFMA tile product is written for 64 x 64 subproblems");
-  if (*w.conv) return;
+  const int* const ident = w.ident + slot * w.p;
+  const double* const Vr = w.V + (int64_t)slot * w.p * JS * JS;
   extern __shared__ double sm[];
   double(*T)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm);
   const int np = 2 * w.p;
@@ -589,16 +699,17 @@ RF_DEV void eig_apply_body(const EigWork& w, int round, int id) {
   f64x4 acc[2][2];
   double opa[16][2], opb[16][2];
   if (id < nsym) {
+    if (*w.conv) return;
     int x, y;
     upper_tile(id, w.p, x, y);
-    const int idx_ = w.ident[x], idy_ = w.ident[y];
+    const int idx_ = ident[x], idy_ = ident[y];
     if (idx_ && idy_) return;
     const int Px = circle(round, x, np), Qx = circle(round, np - 1 - x, np);
     const int Py = circle(round, y, np), Qy = circle(round, np - 1 - y, np);
     auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
     auto iy = [&](int a) -> int64_t { return a < JB ? (int64_t)Py * JB + a : (int64_t)Qy * JB + (a - JB); };
-    if (!idy_) mm.load_b(w.V + (int64_t)y * JS * JS, opb);
-    if (!idx_) mm.load_at(w.V + (int64_t)x * JS * JS, opa);
+    if (!idy_) mm.load_b(Vr + (int64_t)y * JS * JS, opb);
+    if (!idx_) mm.load_at(Vr + (int64_t)x * JS * JS, opa);
     for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
       const int a = e >> 5, b = (e & 31) * 2;
       const double2 g = *reinterpret_cast<const double2*>(w.Gp + ix(a) * w.K + iy(b));
@@ -633,28 +744,7 @@ RF_DEV void eig_apply_body(const EigWork& w, int round, int id) {
       }
     }
   } else {
-    const int zid = id - nsym;
-    const int x = zid % w.p, rb = zid / w.p;
-    if (w.ident[x]) return;
-    const int Px = circle(round, x, np), Qx = circle(round, np - 1 - x, np);
-    auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
-    const int64_t r0 = (int64_t)rb * JS;  // K is a multiple of JS: the strip is whole
-    mm.load_b(w.V + (int64_t)x * JS * JS, opb);
-    for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
-      const int a = e >> 5, b = (e & 31) * 2;
-      const double2 z = *reinterpret_cast<const double2*>(w.Z + (r0 + a) * w.K + ix(b));
-      T[a][b] = z.x;
-      T[a][b + 1] = z.y;
-    }
-    __syncthreads();
-    mm.mul_lds_reg(T, opb, acc);
-    __syncthreads();
-    mm.store(acc, T);
-    __syncthreads();
-    for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
-      const int a = e >> 5, b = (e & 31) * 2;
-      *reinterpret_cast<double2*>(w.Z + (r0 + a) * w.K + ix(b)) = double2{T[a][b], T[a][b + 1]};
-    }
+    eig_zstrip_body<JB>(w, round, slot, id - nsym, threadIdx.x, T, true);
   }
 }
 
@@ -758,12 +848,34 @@ __global__ __launch_bounds__(1024) void k_eig_floor(const double* __restrict__ G
   eig_floor_body(G, ld, N, w);
 }
 template <int JB>
-__global__ __launch_bounds__(1024) void k_eig_solve(EigWork w, int round, int inner_sweeps) {
-  eig_solve_body<JB>(w, round, inner_sweeps, blockIdx.x);
+__global__ __launch_bounds__(1024) void k_eig_solve(EigWork w, int round, int inner_sweeps, int slot) {
+  eig_solve_body<JB>(w, round, inner_sweeps, blockIdx.x, slot);
 }
+// work items id0 + blockIdx.x (G tiles first, then Z strips)
 template <int JB>
-__global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round) {
-  eig_apply_body<JB>(w, round, blockIdx.x);
+__global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round, int slot, int id0) {
+  eig_apply_body<JB>(w, round, id0 + (int)blockIdx.x, slot);
+}
+// Dynamic LDS of k_eig_solve_z: the larger of the subproblem (M and V, JS x JS+1
+// doubles each) and four Z strips (JS x JS+1 doubles each).
+constexpr size_t eig_solve_z_lds(int JB) { return (size_t)4 * (2 * JB) * (2 * JB + 1) * sizeof(double); }
+
+// The solve of one round (workgroups 0 .. p-1) and, in the workgroups after them,
+// the eigenvector update Z <- Z V of the previous round (four 64-row strips per
+// workgroup, one per 256-thread group): the update needs only that round's
+// rotations, so it fills the CUs the p subproblems leave idle.
+template <int JB>
+__global__ __launch_bounds__(1024) void k_eig_solve_z(EigWork w, int round, int slot, int zround, int zslot) {
+  constexpr int JS = 2 * JB;
+  if ((int)blockIdx.x < w.p) {
+    eig_solve_body<JB>(w, round, 1, blockIdx.x, slot);
+    return;
+  }
+  extern __shared__ double sm[];
+  const int grp = (int)threadIdx.x >> 8;
+  double(*T)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm + grp * JS * (JS + 1));
+  const int zid = ((int)blockIdx.x - w.p) * 4 + grp;
+  eig_zstrip_body<JB>(w, zround, zslot, zid, (int)threadIdx.x & 255, T, zid < (int)(w.K / JS) * w.p);
 }
 
 __global__ __launch_bounds__(256) void k_eig_check(EigWork w) { eig_check_body(w, blockIdx.x); }
@@ -788,13 +900,13 @@ template <int JB>
 __global__ __launch_bounds__(1024) void k_eigb_solve(const EigBatch* __restrict__ bs, int round) {
   const EigBatch b = bs[blockIdx.y];
   if ((int)blockIdx.x >= b.w.p || round >= 2 * b.w.p - 1) return;
-  eig_solve_body<JB>(b.w, round, 1, blockIdx.x);
+  eig_solve_body<JB>(b.w, round, 1, blockIdx.x, 0);
 }
 template <int JB>
 __global__ __launch_bounds__(256) void k_eigb_apply(const EigBatch* __restrict__ bs, int round) {
   const EigBatch b = bs[blockIdx.y];
   if ((int)blockIdx.x >= eig_apply_items(b.w.p, b.w.K, 2 * JB) || round >= 2 * b.w.p - 1) return;
-  eig_apply_body<JB>(b.w, round, blockIdx.x);
+  eig_apply_body<JB>(b.w, round, blockIdx.x, 0);
 }
 __global__ __launch_bounds__(256) void k_eigb_check(const EigBatch* __restrict__ bs) {
   const EigBatch b = bs[blockIdx.y];
@@ -818,22 +930,30 @@ __global__ void k_eigb_gather(const EigBatch* __restrict__ bs) {
 template <int JB>
 static void eig_rounds(EigWork w, int64_t N, hipStream_t st, double* trace) {
   constexpr int JS = 2 * JB;
-  int64_t KK = w.K * w.K;
-  size_t lds_solve = 2 * JS * (JS + 1) * sizeof(double);
-  size_t lds_apply = JS * (JS + 1) * sizeof(double);
+  const size_t lds_solve_z = eig_solve_z_lds(JB);
+  const size_t lds_apply = JS * (JS + 1) * sizeof(double);
   const int rounds = 2 * w.p - 1;
   const int max_sweeps = eig_max_sweeps();
-  const int ntile = eig_apply_items(w.p, w.K, JS);
-  // the subproblem kernel: one thread per 2 x 2 block of the JS x JS subproblem
-  const int solve_threads = (JS / 2) * (JS / 2) > 1024 ? 1024 : (JS / 2) * (JS / 2);
+  const int nsym = w.p * (w.p + 1) / 2;
+  const int nz = eig_apply_items(w.p, w.K, JS) - nsym;
+  const int zgroups = (nz + 3) / 4;
+  // Round g: its solve, fused with the Z update of round g - 1; then its G
+  // update.  Rotations alternate between two slots, so the solve of round g
+  // never overwrites what the Z update in the same launch reads.
+  int g = 0, prev = 0;
   for (int sw = 0; sw < max_sweeps; ++sw) {
-    for (int r = 0; r < rounds; ++r) {
-      hipLaunchKernelGGL(k_eig_solve<JB>, dim3(w.p), dim3(solve_threads), lds_solve, st, w, r, 1);
-      hipLaunchKernelGGL(k_eig_apply<JB>, dim3(ntile), dim3(256), lds_apply, st, w, r);
+    for (int r = 0; r < rounds; ++r, ++g) {
+      const int slot = g & 1;
+      const unsigned grid = (unsigned)(w.p + (g > 0 ? zgroups : 0));
+      hipLaunchKernelGGL(k_eig_solve_z<JB>, dim3(grid), dim3(1024), lds_solve_z, st, w, r, slot, prev, slot ^ 1);
+      hipLaunchKernelGGL(k_eig_apply<JB>, dim3(nsym), dim3(256), lds_apply, st, w, r, slot, 0);
+      prev = r;
     }
     hipLaunchKernelGGL(k_eig_check, dim3(eig_check_blocks(w.K)), dim3(256), 0, st, w);
     hipLaunchKernelGGL(k_eig_decide, dim3(1), dim3(1), 0, st, w, 1.0, trace, sw);
   }
+  // the Z update of the last round
+  if (g > 0) hipLaunchKernelGGL(k_eig_apply<JB>, dim3(nz), dim3(256), lds_apply, st, w, prev, (g - 1) & 1, nsym);
 }
 
 // 32-wide blocks (64 x 64 subproblems).  16-wide blocks were measured slower at
@@ -901,6 +1021,8 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
                                 (int)(2 * JS * (JS + 1) * sizeof(double)));
       (void)hipFuncSetAttribute((const void*)k_eig_apply<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(JS * (JS + 1) * sizeof(double)));
+      (void)hipFuncSetAttribute((const void*)k_eig_solve_z<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)eig_solve_z_lds(32));
     });
   }
   if (N < kEigGraphMinN) return eig_sequence(G, ld, N, lam, V, ldv, work, st, tol, trace);
