@@ -360,7 +360,7 @@ static size_t carve(rf_batch_plan& pl, char* base, size_t off) {
     p.Ub = (double*)get(k * k * 8);
     p.Ub32 = (float*)get(k * k * 4);
     p.inv = (float*)get(k * 4);
-    p.eigw = (void*)get(eig_work_bytes(p.k));
+    p.eigw = (void*)get(eig_work_bytes(p.k, true));
     p.signw = (int*)get(3 * k * 4);
   }
   for (int i = 0; i < pl.count; ++i) pl.P[i].counters = pl.counters ? pl.counters + (size_t)i * kCounterStride : nullptr;

@@ -205,6 +205,7 @@ hipError_t launch_cholinv(double* G, int64_t ld, int64_t N, double tol_ratio, do
 // Block-Jacobi workspace view (carved from the caller's workspace by the library).
 struct EigWork {
   double* Gp;      // K x K
+  double* Gp2;     // K x K second buffer (single-problem solver; null for a batched problem)
   double* Z;       // K x K
   double* V;       // p x 64 x 64
   int* perm;       // K
@@ -229,7 +230,7 @@ EigBatch eig_batch_desc(const double* G, int64_t ld, int64_t N, double* lam, dou
 hipError_t launch_eig_batched(const EigBatch* descs, int count, int64_t Nmax, hipStream_t st);
 // Symmetric eigen-decomposition (block Jacobi).  G (N x N, ld) is destroyed.
 // lam (N, descending), V (N x N, ldv, column c = eigenvector of lam[c]).
-size_t eig_work_bytes(int64_t N);
+size_t eig_work_bytes(int64_t N, bool batched = false);
 // trace (optional, device, >= eig_max_sweeps() doubles): per-sweep convergence measure
 // (<= 1 means converged; 0 after convergence).
 // Relative tolerance used for FP32 outputs (U, V, F): eigenvalue errors are second

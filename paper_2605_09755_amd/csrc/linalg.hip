@@ -263,7 +263,7 @@ hipError_t launch_gram(const void* X, int64_t ldx, int xdt, const void* Y, int64
 int eig_block_width(int64_t N);
 
 
-static EigWork eig_layout(void* work, int64_t N, int JB) {
+static EigWork eig_layout(void* work, int64_t N, int JB, bool dbuf = true) {
   EigWork w;
   int64_t K = ((N + 2 * JB - 1) / (2 * JB)) * (2 * JB);
   if (K < 2 * JB) K = 2 * JB;
@@ -272,6 +272,11 @@ static EigWork eig_layout(void* work, int64_t N, int JB) {
   const int JS = 2 * JB;
   char* p = (char*)work;
   w.Gp = (double*)p; p += K * K * 8;
+  w.Gp2 = nullptr;
+  if (dbuf) {
+    w.Gp2 = (double*)p;
+    p += K * K * 8;
+  }
   w.Z = (double*)p; p += K * K * 8;
   w.V = (double*)p; p += (size_t)2 * w.p * JS * JS * 8;  // two slots: rounds alternate
   w.perm = (int*)p; p += ((K * 4 + 255) / 256) * 256;
@@ -283,13 +288,15 @@ static EigWork eig_layout(void* work, int64_t N, int JB) {
   return w;
 }
 
-int eig_max_sweeps() { return 20; }
+// At most 24 outer sweeps (the graph holds them all; sweeps after convergence
+// exit at once).  k = 2000 matrices with the spectrum i^-3 need 20.
+int eig_max_sweeps() { return 24; }
 
 // Bytes of the layout eig_layout lays out (taken from the layout itself, so the
 // two cannot disagree), plus alignment slack.
-size_t eig_work_bytes(int64_t N) {
+size_t eig_work_bytes(int64_t N, bool batched) {
   const uintptr_t base = 4096;
-  const EigWork w = eig_layout(reinterpret_cast<void*>(base), N, eig_block_width(N));
+  const EigWork w = eig_layout(reinterpret_cast<void*>(base), N, eig_block_width(N), !batched);
   return (size_t)(reinterpret_cast<uintptr_t>(w.fabs_) + 256 - base) + 4096;
 }
 
@@ -364,7 +371,14 @@ RF_DEV void jacobi_rot(double app, double aqq, double apq, double floor2, double
 }
 
 template <int JB>
-RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x, int slot) {
+RF_DEV void eig_prologue(const EigWork& w, const double* __restrict__ Gs, int round, int x, int pslot, double* sm);
+
+// One subproblem of the round.  Its 64 x 64 block of G comes straight from w.Gp
+// (Gs == nullptr) or, with Gs set, is built from Gs, the G before the previous
+// round's update, and that round's rotations in slot pslot (eig_prologue).
+template <int JB>
+RF_DEV void eig_solve_body(const EigWork& w, int round, bool full, int x, int slot,
+                           const double* __restrict__ Gs = nullptr, int pslot = 0) {
   constexpr int JS = 2 * JB;
   // this round's rotations and "unchanged" flags go to slot `slot` (rounds
   // alternate between two, so the eigenvector update of one round can run
@@ -388,10 +402,15 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x,
   __shared__ int needed;
   if (threadIdx.x == 0) needed = 0;
   __syncthreads();
-  for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
-    int a = e / JS, b = e % JS;
-    M[a][b] = w.Gp[gidx(a) * w.K + gidx(b)];
-    V[a][b] = (a == b) ? 1.0 : 0.0;
+  if (Gs) {
+    eig_prologue<JB>(w, Gs, round, x, pslot, sm);
+    for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) V[e / JS][e % JS] = (e / JS == e % JS) ? 1.0 : 0.0;
+  } else {
+    for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
+      int a = e / JS, b = e % JS;
+      M[a][b] = w.Gp[gidx(a) * w.K + gidx(b)];
+      V[a][b] = (a == b) ? 1.0 : 0.0;
+    }
   }
   __syncthreads();
   // nothing to do when every off-diagonal entry of the pair already meets the
@@ -422,11 +441,11 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x,
     return;
   }
   if (threadIdx.x == 0) ident[x] = 0;
-  // The first round of an outer sweep rotates every pair of the subproblem; the
-  // other rounds only the pairs across its two blocks.  Over one outer sweep
-  // every pair of indices is then rotated once (a cyclic Jacobi sweep in block
-  // order), in about half the sequential inner rounds of full subproblem sweeps.
-  const bool full = round == 0;
+  // A full round rotates every pair of the subproblem, the others only the pairs
+  // across its two blocks.  With the first round of each outer sweep full, every
+  // pair of indices is rotated at least once per outer sweep (a cyclic Jacobi
+  // sweep in block order), in about half the sequential inner rounds of full
+  // subproblem sweeps.
   if (full) {
     // a full cyclic sweep over every pair of the 2 JB indices (the pairs inside
     // each block included)
@@ -441,7 +460,7 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, int inner_sweeps, int x,
       pair_hi[rr][u] = (unsigned char)b;
     }
     __syncthreads();
-    for (int sw = 0; sw < inner_sweeps; ++sw) {
+    for (int sw = 0; sw < 1; ++sw) {
       if (threadIdx.x == 0) done = 1;
       __syncthreads();
       for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
@@ -641,6 +660,256 @@ struct Mfma64 {
         for (int r = 0; r < 4; ++r) S[wm * 32 + i * 16 + (lane >> 4) + 4 * r][bcol(j)] = acc[i][j][r];
   }
 };
+
+// The same 64 x 64 FP64 products with 16 waves (1024 threads): wave (bi, bj) owns
+// the 16 x 16 block (bi, bj), so each wave runs a quarter of the MFMA chain of the
+// 4-wave form.  Operand layouts as in Mfma64.
+struct Mfma16 {
+  int lane, bi, bj;
+  RF_DEV Mfma16() : lane(threadIdx.x & 63), bi((threadIdx.x >> 6) >> 2), bj((threadIdx.x >> 6) & 3) {}
+  RF_DEV int kr(int kk) const { return 4 * kk + (lane >> 4); }
+  // B operand X[k][col] of column block bj, and A operand of X^T (X^T[row][k] = X[k][row]) of row block bi
+  RF_DEV void load_b(const double* __restrict__ X, double (&r)[16]) const {
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) r[kk] = X[kr(kk) * 64 + bj * 16 + (lane & 15)];
+  }
+  RF_DEV void load_at(const double* __restrict__ X, double (&r)[16]) const {
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) r[kk] = X[kr(kk) * 64 + bi * 16 + (lane & 15)];
+  }
+  // S B with S in LDS (A operand), and A S with S in LDS (B operand)
+  RF_DEV f64x4 mul_lds_reg(const double (*S)[65], const double (&bv)[16]) const {
+    f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[bi * 16 + (lane & 15)][kr(kk)], bv[kk], acc, 0, 0, 0);
+    return acc;
+  }
+  RF_DEV f64x4 mul_reg_lds(const double (&av)[16], const double (*S)[65]) const {
+    f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], S[kr(kk)][bj * 16 + (lane & 15)], acc, 0, 0, 0);
+    return acc;
+  }
+  RF_DEV void store(const f64x4& acc, double (*S)[65]) const {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S[bi * 16 + (lane >> 4) + 4 * r][bj * 16 + (lane & 15)] = acc[r];
+  }
+  // the same two products with the V operand read from LDS (same values, same
+  // instruction order, so the same results bit for bit)
+  RF_DEV f64x4 mul_lds_lds(const double (*S)[65], const double (*Vy)[65]) const {
+    f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(S[bi * 16 + (lane & 15)][kr(kk)], Vy[kr(kk)][bj * 16 + (lane & 15)],
+                                                 acc, 0, 0, 0);
+    return acc;
+  }
+  RF_DEV f64x4 mul_ldst_lds(const double (*Vx)[65], const double (*S)[65]) const {
+    f64x4 acc = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(Vx[kr(kk)][bi * 16 + (lane & 15)], S[kr(kk)][bj * 16 + (lane & 15)],
+                                                 acc, 0, 0, 0);
+    return acc;
+  }
+};
+
+// Subproblem of pair x in round `round` (> 0 within an outer sweep), built from
+// Gs, the G before the previous round's update, and that round's rotations (slot
+// pslot).  Block P of the pair sat in half hP of the previous round's pair a,
+// block Q in half hQ of pair b (a != b: two blocks meet once per sweep), so
+//   M = [ X_a^T Gs[I_a, I_a] X_a   X_a^T Gs[I_a, I_b] X_b ]
+//       [        (mirror)          X_b^T Gs[I_b, I_b] X_b ]
+// with X_c the half of V_c's columns that now hold that block (no product where
+// the previous solve left pair c unchanged).  Only the three needed 32 x 32
+// quadrants are formed, each entry exactly as the tile update forms it (tile
+// orientation, operands, MFMA order, symmetrisation of diagonal tiles), so M
+// holds, bit for bit, the entries that update writes to the other buffer.
+// Tile t = 0: (a, a), 1: (b, b), 2: (min(a,b), max(a,b)); for tile t the update
+// takes W = T V_y (64 x 32: the needed half hy of the columns) and C = X^T W
+// (32 x 32: half hx of the rows).  Waves 0-11: wave w forms row block w & 3 of
+// W for tile w >> 2, then block (w >> 1 & 1, w & 1) of C for tile w >> 2.
+// LDS: M at sm, V_a at sm + JS (JS+1) (where V goes afterwards), V_b after it,
+// then the three W (JS x JB+1 each): 150528 bytes for JS = 64.
+template <int JB>
+RF_DEV void eig_prologue(const EigWork& w, const double* __restrict__ Gs, int round, int x, int pslot, double* sm) {
+  constexpr int JS = 2 * JB, LD = JS + 1, LW = JB + 1;
+  static_assert(JS == 64, "the MFMA tile product is written for 64 x 64 subproblems");
+  double(*M)[LD] = reinterpret_cast<double(*)[LD]>(sm);
+  double(*VA)[LD] = reinterpret_cast<double(*)[LD]>(sm + JS * LD);
+  double(*VB)[LD] = reinterpret_cast<double(*)[LD]>(sm + 2 * JS * LD);
+  double* const Wbase = sm + 3 * JS * LD;
+  const int p = w.p, np = 2 * p, rp = round - 1;
+  auto posof = [&](int B) { return B == 0 ? 0 : 1 + ((B - 1 - rp) % (np - 1) + (np - 1)) % (np - 1); };
+  const int iP = posof(circle(round, x, np)), iQ = posof(circle(round, np - 1 - x, np));
+  const int a = iP < p ? iP : np - 1 - iP, hP = iP < p ? 0 : 1;
+  const int b = iQ < p ? iQ : np - 1 - iQ, hQ = iQ < p ? 0 : 1;
+  const int* const ident = w.ident + pslot * p;
+  const double* const Vp = w.V + (int64_t)pslot * p * JS * JS;
+  const bool ida = ident[a] != 0, idb = ident[b] != 0;
+  const int Pa = circle(rp, a, np), Qa = circle(rp, np - 1 - a, np);
+  const int Pb = circle(rp, b, np), Qb = circle(rp, np - 1 - b, np);
+  auto ia = [&](int c) -> int64_t { return c < JB ? (int64_t)Pa * JB + c : (int64_t)Qa * JB + (c - JB); };
+  auto ib = [&](int c) -> int64_t { return c < JB ? (int64_t)Pb * JB + c : (int64_t)Qb * JB + (c - JB); };
+  const bool alo = a < b;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // this wave's tile t: x side (rows) and y side (columns) are pair a (true) or b
+  const int t = wv >> 2;
+  const bool xa = t == 0 || (t == 2 && alo), ya = t == 0 || (t == 2 && !alo);
+  const bool idx = xa ? ida : idb, idy = ya ? ida : idb;
+  const int hx = t == 0 ? hP : t == 1 ? hQ : (alo ? hP : hQ);
+  const int hy = t == 0 ? hP : t == 1 ? hQ : (alo ? hQ : hP);
+  auto grow = [&](int r) { return xa ? ia(r) : ib(r); };
+  auto gcol = [&](int c) { return ya ? ia(c) : ib(c); };
+  // every global load first: V_a and V_b (4 + 4 per thread), and this wave's
+  // operand of W = T V_y (row block bi = wv & 3 of T), or W itself where V_y is
+  // the identity
+  double va[4], vb[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    va[i] = Vp[(int64_t)a * JS * JS + threadIdx.x + 1024 * i];
+    vb[i] = Vp[(int64_t)b * JS * JS + threadIdx.x + 1024 * i];
+  }
+  const int bi = wv & 3;
+  double tv[16];
+  f64x4 wacc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
+  if (wv < 12) {
+    if (!idy) {
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk) tv[kk] = Gs[grow(bi * 16 + (lane & 15)) * w.K + gcol(4 * kk + (lane >> 4))];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          wacc[j][r] = Gs[grow(bi * 16 + (lane >> 4) + 4 * r) * w.K + gcol(JB * hy + 16 * j + (lane & 15))];
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int e = threadIdx.x + 1024 * i;
+    if (!ida) VA[e / JS][e % JS] = va[i];
+    if (!idb) VB[e / JS][e % JS] = vb[i];
+  }
+  __syncthreads();
+  double(*W)[LW] = reinterpret_cast<double(*)[LW]>(Wbase + (t < 3 ? t : 0) * JS * LW);
+  if (wv < 12) {
+    if (!idy) {
+      const double(*VY)[LD] = ya ? VA : VB;
+#pragma unroll
+      for (int j = 0; j < 2; ++j)
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk)
+          wacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[kk], VY[4 * kk + (lane >> 4)][JB * hy + 16 * j + (lane & 15)],
+                                                         wacc[j], 0, 0, 0);
+    }
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) W[bi * 16 + (lane >> 4) + 4 * r][16 * j + (lane & 15)] = wacc[j][r];
+  }
+  __syncthreads();
+  // C = X^T W, block (ci, cj) of the 32 x 32 quadrant, into M
+  if (wv < 12) {
+    const int ci = (wv >> 1) & 1, cj = wv & 1;
+    f64x4 c = {0, 0, 0, 0};
+    if (!idx) {
+      const double(*VX)[LD] = xa ? VA : VB;
+#pragma unroll
+      for (int kk = 0; kk < 16; ++kk)
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(VX[4 * kk + (lane >> 4)][JB * hx + 16 * ci + (lane & 15)],
+                                                 W[4 * kk + (lane >> 4)][16 * cj + (lane & 15)], c, 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) c[r] = W[JB * hx + 16 * ci + (lane >> 4) + 4 * r][16 * cj + (lane & 15)];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * ci + (lane >> 4) + 4 * r, j = 16 * cj + (lane & 15);  // C[i][j]
+      if (t == 0) M[i][j] = c[r];
+      else if (t == 1) M[JB + i][JB + j] = c[r];
+      else if (alo) {
+        M[i][JB + j] = c[r];
+        M[JB + j][i] = c[r];
+      } else {
+        M[j][JB + i] = c[r];
+        M[JB + i][j] = c[r];
+      }
+    }
+  }
+  __syncthreads();
+  // diagonal tiles are written from their upper half
+  {
+    const int i = (int)threadIdx.x >> 5, j = (int)threadIdx.x & 31;  // one entry per thread
+    if (i > j) {
+      M[i][j] = M[j][i];
+      M[JB + i][JB + j] = M[JB + j][JB + i];
+    }
+  }
+  __syncthreads();
+}
+
+// G tile id < p(p+1)/2 of the round: (x, y), x <= y, G[I_x, I_y] <- V_x^T G[I_x, I_y]
+// V_y, written to both (x, y) and (y, x) so G stays exactly symmetric (a diagonal
+// tile from its upper half).  1024 threads; the tile is staged in LDS, the V
+// operands go from global memory straight to registers.
+template <int JB>
+RF_DEV void eig_gtile_body(const EigWork& w, int round, int slot, int id, const double* __restrict__ Gs, double* Gd) {
+  constexpr int JS = 2 * JB;
+  static_assert(JS == 64, "the MFMA tile product is written for 64 x 64 subproblems");
+  if (*w.conv) return;
+  const int* const ident = w.ident + slot * w.p;
+  const double* const Vr = w.V + (int64_t)slot * w.p * JS * JS;
+  extern __shared__ double sm[];
+  double(*T)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm);
+  const int np = 2 * w.p;
+  int x, y;
+  upper_tile(id, w.p, x, y);
+  const int idx_ = ident[x], idy_ = ident[y];
+  if (idx_ && idy_ && Gs == Gd) return;  // unchanged in place; into the other buffer it is copied
+  const int Px = circle(round, x, np), Qx = circle(round, np - 1 - x, np);
+  const int Py = circle(round, y, np), Qy = circle(round, np - 1 - y, np);
+  auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
+  auto iy = [&](int a) -> int64_t { return a < JB ? (int64_t)Py * JB + a : (int64_t)Qy * JB + (a - JB); };
+  const Mfma16 mm;
+  double opa[16], opb[16];
+  if (!idy_) mm.load_b(Vr + (int64_t)y * JS * JS, opb);
+  if (!idx_) mm.load_at(Vr + (int64_t)x * JS * JS, opa);
+  for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
+    const int a = e >> 5, b = (e & 31) * 2;
+    const double2 g = *reinterpret_cast<const double2*>(Gs + ix(a) * w.K + iy(b));
+    T[a][b] = g.x;
+    T[a][b + 1] = g.y;
+  }
+  __syncthreads();
+  if (!idy_) {  // T <- T V_y
+    const f64x4 acc = mm.mul_lds_reg(T, opb);
+    __syncthreads();
+    mm.store(acc, T);
+    __syncthreads();
+  }
+  if (!idx_) {  // T <- V_x^T T
+    const f64x4 acc = mm.mul_reg_lds(opa, T);
+    __syncthreads();
+    mm.store(acc, T);
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
+    const int a = e >> 5, b = (e & 31) * 2;
+    double2 g;
+    g.x = (x == y && a > b) ? T[b][a] : T[a][b];
+    g.y = (x == y && a > b + 1) ? T[b + 1][a] : T[a][b + 1];
+    *reinterpret_cast<double2*>(Gd + ix(a) * w.K + iy(b)) = g;
+  }
+  if (x != y) {
+    for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
+      const int b = e >> 5, a = (e & 31) * 2;
+      *reinterpret_cast<double2*>(Gd + iy(b) * w.K + ix(a)) = double2{T[a][b], T[a + 1][b]};
+    }
+  }
+}
 
 // Z strip zid = rb p + x: Z[rows of strip rb, I_x] <- Z[..] V_x for the round and
 // rotation slot given, by a group of 256 threads (tid) staging the strip in T.
@@ -847,35 +1116,53 @@ __global__ void k_eig_init(const double* __restrict__ G, int64_t ld, int64_t N, 
 __global__ __launch_bounds__(1024) void k_eig_floor(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
   eig_floor_body(G, ld, N, w);
 }
-template <int JB>
-__global__ __launch_bounds__(1024) void k_eig_solve(EigWork w, int round, int inner_sweeps, int slot) {
-  eig_solve_body<JB>(w, round, inner_sweeps, blockIdx.x, slot);
-}
 // work items id0 + blockIdx.x (G tiles first, then Z strips)
 template <int JB>
 __global__ __launch_bounds__(256) void k_eig_apply(EigWork w, int round, int slot, int id0) {
   eig_apply_body<JB>(w, round, id0 + (int)blockIdx.x, slot);
 }
-// Dynamic LDS of k_eig_solve_z: the larger of the subproblem (M and V, JS x JS+1
-// doubles each) and four Z strips (JS x JS+1 doubles each).
-constexpr size_t eig_solve_z_lds(int JB) { return (size_t)4 * (2 * JB) * (2 * JB + 1) * sizeof(double); }
-
-// The solve of one round (workgroups 0 .. p-1) and, in the workgroups after them,
-// the eigenvector update Z <- Z V of the previous round (four 64-row strips per
-// workgroup, one per 256-thread group): the update needs only that round's
-// rotations, so it fills the CUs the p subproblems leave idle.
 template <int JB>
-__global__ __launch_bounds__(1024) void k_eig_solve_z(EigWork w, int round, int slot, int zround, int zslot) {
+__global__ __launch_bounds__(1024) void k_eig_gtile(EigWork w, int round, int slot) {
+  eig_gtile_body<JB>(w, round, slot, (int)blockIdx.x, w.Gp, w.Gp);  // in place
+}
+
+// Dynamic LDS of k_eig_round: the subproblem while it is built (M, V_a where V
+// goes afterwards, V_b: JS x JS+1 doubles each; three JS x JB+1 products), which
+// also covers four Z strips (JS x JS+1 doubles each).
+constexpr size_t eig_round_lds(int JB) {
+  return (size_t)(3 * (2 * JB) * (2 * JB + 1) + 3 * (2 * JB) * (JB + 1)) * sizeof(double);
+}
+
+// One launch per round r of an outer sweep:
+//   workgroups [0, p)           the subproblems of round r; for r > 0 each builds
+//                               its block from the G before round r-1's update
+//                               (buffer gsrc) and round r-1's rotations;
+//   next nzw workgroups         Z <- Z V of round r-1 (four 64-row strips each,
+//                               one per 256-thread group);
+//   last ntile workgroups       G tiles of round r-1, buffer gsrc -> gdst.
+// Everything but the subproblems uses only round r-1's rotations, so the launch
+// fills the CUs the p subproblems leave idle and no G update waits between two
+// solves.  Rotations alternate between two slots (slot: this round, zslot: the
+// previous one).
+template <int JB>
+__global__ __launch_bounds__(1024) void k_eig_round(EigWork w, int round, int full, int slot, int zround, int zslot,
+                                                    int nzw, int gsrc, int gdst) {
   constexpr int JS = 2 * JB;
-  if ((int)blockIdx.x < w.p) {
-    eig_solve_body<JB>(w, round, 1, blockIdx.x, slot);
+  const int bid = (int)blockIdx.x;
+  const double* Gs = gsrc ? w.Gp2 : w.Gp;
+  if (bid < w.p) {
+    eig_solve_body<JB>(w, round, full != 0, bid, slot, gsrc >= 0 && round > 0 ? Gs : nullptr, zslot);
     return;
   }
-  extern __shared__ double sm[];
-  const int grp = (int)threadIdx.x >> 8;
-  double(*T)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm + grp * JS * (JS + 1));
-  const int zid = ((int)blockIdx.x - w.p) * 4 + grp;
-  eig_zstrip_body<JB>(w, zround, zslot, zid, (int)threadIdx.x & 255, T, zid < (int)(w.K / JS) * w.p);
+  if (bid < w.p + nzw) {
+    extern __shared__ double sm[];
+    const int grp = (int)threadIdx.x >> 8;
+    double(*T)[JS + 1] = reinterpret_cast<double(*)[JS + 1]>(sm + grp * JS * (JS + 1));
+    const int zid = (bid - w.p) * 4 + grp;
+    eig_zstrip_body<JB>(w, zround, zslot, zid, (int)threadIdx.x & 255, T, zid < (int)(w.K / JS) * w.p);
+    return;
+  }
+  eig_gtile_body<JB>(w, zround, zslot, bid - w.p - nzw, Gs, gdst ? w.Gp2 : w.Gp);
 }
 
 __global__ __launch_bounds__(256) void k_eig_check(EigWork w) { eig_check_body(w, blockIdx.x); }
@@ -900,7 +1187,7 @@ template <int JB>
 __global__ __launch_bounds__(1024) void k_eigb_solve(const EigBatch* __restrict__ bs, int round) {
   const EigBatch b = bs[blockIdx.y];
   if ((int)blockIdx.x >= b.w.p || round >= 2 * b.w.p - 1) return;
-  eig_solve_body<JB>(b.w, round, 1, blockIdx.x, 0);
+  eig_solve_body<JB>(b.w, round, round == 0, blockIdx.x, 0);
 }
 template <int JB>
 __global__ __launch_bounds__(256) void k_eigb_apply(const EigBatch* __restrict__ bs, int round) {
@@ -930,25 +1217,30 @@ __global__ void k_eigb_gather(const EigBatch* __restrict__ bs) {
 template <int JB>
 static void eig_rounds(EigWork w, int64_t N, hipStream_t st, double* trace) {
   constexpr int JS = 2 * JB;
-  const size_t lds_solve_z = eig_solve_z_lds(JB);
+  const size_t lds_round = eig_round_lds(JB);
   const size_t lds_apply = JS * (JS + 1) * sizeof(double);
-  const int rounds = 2 * w.p - 1;
+  const int rounds = 2 * w.p - 1;  // odd: a sweep's G updates into the other buffer come in pairs
   const int max_sweeps = eig_max_sweeps();
   const int nsym = w.p * (w.p + 1) / 2;
   const int nz = eig_apply_items(w.p, w.K, JS) - nsym;
   const int zgroups = (nz + 3) / 4;
-  // Round g: its solve, fused with the Z update of round g - 1; then its G
-  // update.  Rotations alternate between two slots, so the solve of round g
-  // never overwrites what the Z update in the same launch reads.
+  // G_j (before round j's update) sits in buffer j & 1 within a sweep: round r
+  // builds its subproblems from buffer (r-1) & 1 while round r-1's tiles go from
+  // there to buffer r & 1.  The last round (even) is updated in place in buffer
+  // 0, where the convergence test and the next sweep read G.
   int g = 0, prev = 0;
   for (int sw = 0; sw < max_sweeps; ++sw) {
     for (int r = 0; r < rounds; ++r, ++g) {
       const int slot = g & 1;
-      const unsigned grid = (unsigned)(w.p + (g > 0 ? zgroups : 0));
-      hipLaunchKernelGGL(k_eig_solve_z<JB>, dim3(grid), dim3(1024), lds_solve_z, st, w, r, slot, prev, slot ^ 1);
-      hipLaunchKernelGGL(k_eig_apply<JB>, dim3(nsym), dim3(256), lds_apply, st, w, r, slot, 0);
+      const int nzw = g > 0 ? zgroups : 0;
+      const int ntile = r > 0 ? nsym : 0;
+      const int full = r == 0;  // more full rounds per sweep were measured no faster
+      const int gsrc = r > 0 ? (r - 1) & 1 : -1, gdst = r & 1;
+      hipLaunchKernelGGL(k_eig_round<JB>, dim3((unsigned)(w.p + nzw + ntile)), dim3(1024), lds_round, st, w, r, full,
+                         slot, prev, slot ^ 1, nzw, gsrc, gdst);
       prev = r;
     }
+    hipLaunchKernelGGL(k_eig_gtile<JB>, dim3(nsym), dim3(1024), lds_apply, st, w, prev, (g - 1) & 1);
     hipLaunchKernelGGL(k_eig_check, dim3(eig_check_blocks(w.K)), dim3(256), 0, st, w);
     hipLaunchKernelGGL(k_eig_decide, dim3(1), dim3(1), 0, st, w, 1.0, trace, sw);
   }
@@ -1017,12 +1309,10 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
     constexpr int JS = 64;
     static std::once_flag attr;
     std::call_once(attr, [] {
-      (void)hipFuncSetAttribute((const void*)k_eig_solve<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)(2 * JS * (JS + 1) * sizeof(double)));
       (void)hipFuncSetAttribute((const void*)k_eig_apply<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)(JS * (JS + 1) * sizeof(double)));
-      (void)hipFuncSetAttribute((const void*)k_eig_solve_z<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)eig_solve_z_lds(32));
+      (void)hipFuncSetAttribute((const void*)k_eig_round<32>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)eig_round_lds(32));
     });
   }
   if (N < kEigGraphMinN) return eig_sequence(G, ld, N, lam, V, ldv, work, st, tol, trace);
@@ -1094,7 +1384,7 @@ hipError_t launch_eig(double* G, int64_t ld, int64_t N, double* lam, double* V, 
 EigBatch eig_batch_desc(const double* G, int64_t ld, int64_t N, double* lam, double* V, int64_t ldv, void* work,
                         double tol) {
   EigBatch b;
-  b.w = eig_layout(work, N, 32);
+  b.w = eig_layout(work, N, 32, false);
   b.w.tol = tol;
   b.G = G; b.ld = ld; b.N = N; b.lam = lam; b.V = V; b.ldv = ldv;
   return b;
@@ -1103,7 +1393,7 @@ EigBatch eig_batch_desc(const double* G, int64_t ld, int64_t N, double* lam, dou
 hipError_t launch_eig_batched(const EigBatch* descs, int count, int64_t Nmax, hipStream_t st) {
   if (count == 0 || Nmax == 0) return hipSuccess;
   constexpr int JB = 32, JS = 64;
-  EigWork shape = eig_layout(nullptr, Nmax, JB);
+  EigWork shape = eig_layout(nullptr, Nmax, JB, false);
   const int64_t Kmax = shape.K;
   const int pmax = shape.p;
   if (Kmax > 4096) return hipErrorInvalidValue;

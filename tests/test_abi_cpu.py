@@ -111,8 +111,8 @@ def test_workspace_monotone_in_size():
 
 @pytest.mark.parametrize("N", [1, 64, 65, 500, 1000, 2000, 4000])
 def test_eig_workspace_covers_the_solver_layout(N):
-    """The eigensolver lays out G and Z (K x K FP64, K = N rounded up to a
-    multiple of 64), two slots of p = K / 64 rotation blocks of 64 x 64 FP64,
+    """The eigensolver lays out two G buffers and Z (K x K FP64, K = N rounded up
+    to a multiple of 64), two slots of p = K / 64 rotation blocks of 64 x 64 FP64,
     a K-int permutation and small flags; the size the library reports must cover
     all of it (a regression check: the block storage was once sized for 32 x 32
     blocks and the solver wrote past the end of its workspace)."""
@@ -121,7 +121,7 @@ def test_eig_workspace_covers_the_solver_layout(N):
     L.rf_test_eig_ws.argtypes = [ctypes.c_int64]
     K = max(64, -(-N // 64) * 64)
     p = K // 64
-    need = 2 * K * K * 8 + 2 * p * 64 * 64 * 8 + K * 4 + 2 * p * 4 + 4 * 8
+    need = 3 * K * K * 8 + 2 * p * 64 * 64 * 8 + K * 4 + 2 * p * 4 + 4 * 8
     assert L.rf_test_eig_ws(N) >= need + 255   # the entry aligns its workspace to 256 bytes
 
 

@@ -445,7 +445,7 @@ def test_eig(N, kind):
     assert e_orth <= 1e-10
     if kind == "cluster":
         # three exactly multiple eigenvalues: Jacobi (block or classic cyclic)
-        # converges only linearly here; bound what 20 sweeps deliver
+        # converges only linearly here; bound what 24 sweeps deliver
         assert e_lam <= 1e-11 and e_res <= 1e-6
     else:
         assert e_lam <= 1e-12 * max(1, math.sqrt(N))
