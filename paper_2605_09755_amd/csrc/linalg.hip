@@ -722,25 +722,25 @@ struct Mfma16 {
 // block Q in half hQ of pair b (a != b: two blocks meet once per sweep), so
 //   M = [ X_a^T Gs[I_a, I_a] X_a   X_a^T Gs[I_a, I_b] X_b ]
 //       [        (mirror)          X_b^T Gs[I_b, I_b] X_b ]
-// with X_c the half of V_c's columns that now hold that block (no product where
-// the previous solve left pair c unchanged).  Only the three needed 32 x 32
-// quadrants are formed, each entry exactly as the tile update forms it (tile
-// orientation, operands, MFMA order, symmetrisation of diagonal tiles), so M
-// holds, bit for bit, the entries that update writes to the other buffer.
-// Tile t = 0: (a, a), 1: (b, b), 2: (min(a,b), max(a,b)); for tile t the update
-// takes W = T V_y (64 x 32: the needed half hy of the columns) and C = X^T W
-// (32 x 32: half hx of the rows).  Waves 0-11: wave w forms row block w & 3 of
-// W for tile w >> 2, then block (w >> 1 & 1, w & 1) of C for tile w >> 2.
-// LDS: M at sm, V_a at sm + JS (JS+1) (where V goes afterwards), V_b after it,
-// then the three W (JS x JB+1 each): 150528 bytes for JS = 64.
+// with X_a = V_a[:, JB hP : JB hP + JB], X_b likewise (no product where the
+// previous solve left the pair unchanged).  Only the three needed quadrants are
+// formed, each entry exactly as the tile update forms it (tile orientation,
+// operands, MFMA order, symmetrisation of diagonal tiles), so M holds, bit for
+// bit, the entries that update writes to the other buffer.  Tile t = 0: (a, a),
+// 1: (b, b), 2: (min(a,b), max(a,b)); the update takes W = T X_y (64 x 32) and
+// C = X_x^T W (32 x 32).  The tiles are read coalesced and staged in LDS; tiles
+// 0 and 1 are formed together (16 waves, one 16 x 16 block each), then tile 2.
+// LDS: M at sm, tiles at sm + JS (JS+1) (where V goes afterwards) and sm +
+// 2 JS (JS+1) (each W over its tile), then X_a and X_b (JS x JB+1 each).
 template <int JB>
 RF_DEV void eig_prologue(const EigWork& w, const double* __restrict__ Gs, int round, int x, int pslot, double* sm) {
-  constexpr int JS = 2 * JB, LD = JS + 1, LW = JB + 1;
+  constexpr int JS = 2 * JB, LD = JS + 1, LH = JB + 1;
   static_assert(JS == 64, "the MFMA tile product is written for 64 x 64 subproblems");
   double(*M)[LD] = reinterpret_cast<double(*)[LD]>(sm);
-  double(*VA)[LD] = reinterpret_cast<double(*)[LD]>(sm + JS * LD);
-  double(*VB)[LD] = reinterpret_cast<double(*)[LD]>(sm + 2 * JS * LD);
-  double* const Wbase = sm + 3 * JS * LD;
+  double(*TT[2])[LD] = {reinterpret_cast<double(*)[LD]>(sm + JS * LD), reinterpret_cast<double(*)[LD]>(sm + 2 * JS * LD)};
+  double(*WW[2])[LH] = {reinterpret_cast<double(*)[LH]>(sm + JS * LD), reinterpret_cast<double(*)[LH]>(sm + 2 * JS * LD)};
+  double(*XA)[LH] = reinterpret_cast<double(*)[LH]>(sm + 3 * JS * LD);
+  double(*XB)[LH] = reinterpret_cast<double(*)[LH]>(sm + 3 * JS * LD + JS * LH);
   const int p = w.p, np = 2 * p, rp = round - 1;
   auto posof = [&](int B) { return B == 0 ? 0 : 1 + ((B - 1 - rp) % (np - 1) + (np - 1)) % (np - 1); };
   const int iP = posof(circle(round, x, np)), iQ = posof(circle(round, np - 1 - x, np));
@@ -755,97 +755,124 @@ RF_DEV void eig_prologue(const EigWork& w, const double* __restrict__ Gs, int ro
   auto ib = [&](int c) -> int64_t { return c < JB ? (int64_t)Pb * JB + c : (int64_t)Qb * JB + (c - JB); };
   const bool alo = a < b;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  // this wave's tile t: x side (rows) and y side (columns) are pair a (true) or b
-  const int t = wv >> 2;
-  const bool xa = t == 0 || (t == 2 && alo), ya = t == 0 || (t == 2 && !alo);
-  const bool idx = xa ? ida : idb, idy = ya ? ida : idb;
-  const int hx = t == 0 ? hP : t == 1 ? hQ : (alo ? hP : hQ);
-  const int hy = t == 0 ? hP : t == 1 ? hQ : (alo ? hQ : hP);
-  auto grow = [&](int r) { return xa ? ia(r) : ib(r); };
-  auto gcol = [&](int c) { return ya ? ia(c) : ib(c); };
-  // every global load first: V_a and V_b (4 + 4 per thread), and this wave's
-  // operand of W = T V_y (row block bi = wv & 3 of T), or W itself where V_y is
-  // the identity
-  double va[4], vb[4];
+  // every global load first: the three tiles (two double2 per thread each) and
+  // the needed halves of V_a and V_b (two doubles per thread each)
+  double2 tl[3][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    va[i] = Vp[(int64_t)a * JS * JS + threadIdx.x + 1024 * i];
-    vb[i] = Vp[(int64_t)b * JS * JS + threadIdx.x + 1024 * i];
-  }
-  const int bi = wv & 3;
-  double tv[16];
-  f64x4 wacc[2] = {{0, 0, 0, 0}, {0, 0, 0, 0}};
-  if (wv < 12) {
-    if (!idy) {
+  for (int t = 0; t < 3; ++t)
 #pragma unroll
-      for (int kk = 0; kk < 16; ++kk) tv[kk] = Gs[grow(bi * 16 + (lane & 15)) * w.K + gcol(4 * kk + (lane >> 4))];
-    } else {
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int r = 0; r < 4; ++r)
-          wacc[j][r] = Gs[grow(bi * 16 + (lane >> 4) + 4 * r) * w.K + gcol(JB * hy + 16 * j + (lane & 15))];
+    for (int h = 0; h < 2; ++h) {
+      const int e = (int)threadIdx.x + h * 1024, r = e >> 5, c = (e & 31) * 2;
+      const bool ra = t == 0 || (t == 2 && alo), ca = t == 0 || (t == 2 && !alo);
+      tl[t][h] = *reinterpret_cast<const double2*>(Gs + (ra ? ia(r) : ib(r)) * w.K + (ca ? ia(c) : ib(c)));
     }
-  }
+  double xa[2], xb[2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int e = threadIdx.x + 1024 * i;
-    if (!ida) VA[e / JS][e % JS] = va[i];
-    if (!idb) VB[e / JS][e % JS] = vb[i];
+  for (int h = 0; h < 2; ++h) {
+    const int e = (int)threadIdx.x + h * 1024, r = e >> 5, c = e & 31;
+    xa[h] = Vp[(int64_t)a * JS * JS + r * JS + JB * hP + c];
+    xb[h] = Vp[(int64_t)b * JS * JS + r * JS + JB * hQ + c];
+  }
+  auto stage = [&](int t, int slot) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int e = (int)threadIdx.x + h * 1024, r = e >> 5, c = (e & 31) * 2;
+      TT[slot][r][c] = tl[t][h].x;
+      TT[slot][r][c + 1] = tl[t][h].y;
+    }
+  };
+  stage(0, 0);
+  stage(1, 1);
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int e = (int)threadIdx.x + h * 1024, r = e >> 5, c = e & 31;
+    if (!ida) XA[r][c] = xa[h];
+    if (!idb) XB[r][c] = xb[h];
   }
   __syncthreads();
-  double(*W)[LW] = reinterpret_cast<double(*)[LW]>(Wbase + (t < 3 ? t : 0) * JS * LW);
-  if (wv < 12) {
+  // W block (bi, j) of the tile in slot s: T X_y, or T's half hy itself
+  auto wblock = [&](int s, int bi, int j, const double (*XY)[LH], bool idy, int hy) {
+    f64x4 acc = {0, 0, 0, 0};
     if (!idy) {
-      const double(*VY)[LD] = ya ? VA : VB;
-#pragma unroll
-      for (int j = 0; j < 2; ++j)
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk)
-          wacc[j] = __builtin_amdgcn_mfma_f64_16x16x4f64(tv[kk], VY[4 * kk + (lane >> 4)][JB * hy + 16 * j + (lane & 15)],
-                                                         wacc[j], 0, 0, 0);
-    }
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) W[bi * 16 + (lane >> 4) + 4 * r][16 * j + (lane & 15)] = wacc[j][r];
-  }
-  __syncthreads();
-  // C = X^T W, block (ci, cj) of the 32 x 32 quadrant, into M
-  if (wv < 12) {
-    const int ci = (wv >> 1) & 1, cj = wv & 1;
-    f64x4 c = {0, 0, 0, 0};
-    if (!idx) {
-      const double(*VX)[LD] = xa ? VA : VB;
 #pragma unroll
       for (int kk = 0; kk < 16; ++kk)
-        c = __builtin_amdgcn_mfma_f64_16x16x4f64(VX[4 * kk + (lane >> 4)][JB * hx + 16 * ci + (lane & 15)],
-                                                 W[4 * kk + (lane >> 4)][16 * cj + (lane & 15)], c, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(TT[s][bi * 16 + (lane & 15)][4 * kk + (lane >> 4)],
+                                                   XY[4 * kk + (lane >> 4)][16 * j + (lane & 15)], acc, 0, 0, 0);
     } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) c[r] = W[JB * hx + 16 * ci + (lane >> 4) + 4 * r][16 * cj + (lane & 15)];
+      for (int r = 0; r < 4; ++r) acc[r] = TT[s][bi * 16 + (lane >> 4) + 4 * r][JB * hy + 16 * j + (lane & 15)];
     }
+    return acc;
+  };
+  // C block (ci, cj) of the tile whose W is in slot s: X_x^T W, or W's half hx
+  auto cblock = [&](int s, int ci, int cj, const double (*XX)[LH], bool idx, int hx) {
+    f64x4 c = {0, 0, 0, 0};
+    if (!idx) {
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int i = 16 * ci + (lane >> 4) + 4 * r, j = 16 * cj + (lane & 15);  // C[i][j]
-      if (t == 0) M[i][j] = c[r];
-      else if (t == 1) M[JB + i][JB + j] = c[r];
-      else if (alo) {
-        M[i][JB + j] = c[r];
-        M[JB + j][i] = c[r];
-      } else {
-        M[j][JB + i] = c[r];
-        M[JB + i][j] = c[r];
-      }
+      for (int kk = 0; kk < 16; ++kk)
+        c = __builtin_amdgcn_mfma_f64_16x16x4f64(XX[4 * kk + (lane >> 4)][16 * ci + (lane & 15)],
+                                                 WW[s][4 * kk + (lane >> 4)][16 * cj + (lane & 15)], c, 0, 0, 0);
+    } else {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) c[r] = WW[s][JB * hx + 16 * ci + (lane >> 4) + 4 * r][16 * cj + (lane & 15)];
     }
+    return c;
+  };
+  // tiles 0 and 1: W (wave wv: tile wv >> 3, block ((wv >> 1) & 3, wv & 1))
+  {
+    const int t = wv >> 3, bi = (wv >> 1) & 3, j = wv & 1;
+    const f64x4 acc = wblock(t, bi, j, t ? XB : XA, t ? idb : ida, t ? hQ : hP);
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 4; ++r) WW[t][bi * 16 + (lane >> 4) + 4 * r][16 * j + (lane & 15)] = acc[r];
   }
   __syncthreads();
-  // diagonal tiles are written from their upper half
+  // tiles 0 and 1: C (waves 0-7: tile wv >> 2, block ((wv >> 1) & 1, wv & 1)) into the diagonal quadrants of M
+  if (wv < 8) {
+    const int t = wv >> 2, ci = (wv >> 1) & 1, cj = wv & 1, o = JB * t;
+    const f64x4 c = cblock(t, ci, cj, t ? XB : XA, t ? idb : ida, t ? hQ : hP);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) M[o + 16 * ci + (lane >> 4) + 4 * r][o + 16 * cj + (lane & 15)] = c[r];
+  }
+  __syncthreads();
+  // tile 2 into slot 0; the diagonal quadrants are written from their upper half
+  stage(2, 0);
   {
     const int i = (int)threadIdx.x >> 5, j = (int)threadIdx.x & 31;  // one entry per thread
     if (i > j) {
       M[i][j] = M[j][i];
       M[JB + i][JB + j] = M[JB + j][JB + i];
+    }
+  }
+  __syncthreads();
+  // tile 2 (x side a if alo, else b): W (waves 0-7), then C (waves 0-3) into the off-diagonal block
+  {
+    const double(*XX)[LH] = alo ? XA : XB;
+    const double(*XY)[LH] = alo ? XB : XA;
+    const bool idx = alo ? ida : idb, idy = alo ? idb : ida;
+    const int hx = alo ? hP : hQ, hy = alo ? hQ : hP;
+    f64x4 acc = {0, 0, 0, 0};
+    const int bi = (wv >> 1) & 3, j = wv & 1;
+    if (wv < 8) acc = wblock(0, bi, j, XY, idy, hy);
+    __syncthreads();
+    if (wv < 8)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) WW[0][bi * 16 + (lane >> 4) + 4 * r][16 * j + (lane & 15)] = acc[r];
+    __syncthreads();
+    if (wv < 4) {
+      const int ci = (wv >> 1) & 1, cj = wv & 1;
+      const f64x4 c = cblock(0, ci, cj, XX, idx, hx);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * ci + (lane >> 4) + 4 * r, jj = 16 * cj + (lane & 15);  // C[i][jj]
+        if (alo) {
+          M[i][JB + jj] = c[r];
+          M[JB + jj][i] = c[r];
+        } else {
+          M[jj][JB + i] = c[r];
+          M[JB + i][jj] = c[r];
+        }
+      }
     }
   }
   __syncthreads();
@@ -1126,11 +1153,11 @@ __global__ __launch_bounds__(1024) void k_eig_gtile(EigWork w, int round, int sl
   eig_gtile_body<JB>(w, round, slot, (int)blockIdx.x, w.Gp, w.Gp);  // in place
 }
 
-// Dynamic LDS of k_eig_round: the subproblem while it is built (M, V_a where V
-// goes afterwards, V_b: JS x JS+1 doubles each; three JS x JB+1 products), which
-// also covers four Z strips (JS x JS+1 doubles each).
+// Dynamic LDS of k_eig_round: the subproblem while it is built (M and two G
+// tiles, JS x JS+1 doubles each; two halves of rotation blocks, JS x JB+1 each),
+// which also covers four Z strips (JS x JS+1 doubles each).
 constexpr size_t eig_round_lds(int JB) {
-  return (size_t)(3 * (2 * JB) * (2 * JB + 1) + 3 * (2 * JB) * (JB + 1)) * sizeof(double);
+  return (size_t)(3 * (2 * JB) * (2 * JB + 1) + 2 * (2 * JB) * (JB + 1)) * sizeof(double);
 }
 
 // One launch per round r of an outer sweep:
