@@ -55,7 +55,7 @@ struct Prob {
   float* At; uint16_t* At16;
   float* Ya; float* Yb; float* Q; uint16_t* Q16;
   float* Zh; float* Z; uint16_t* Z16;
-  double* G; double* d0; int* flags; int* counters; float* Rinv; double* X64;
+  double* G; double* d0; int* flags; int* counters; float* Rinv; double* X64; double* gpart;
   float* Bt; double* GB; double* lam; double* Ub; float* Ub32; float* inv; void* eigw; int* signw;
 };
 
@@ -116,13 +116,32 @@ struct Sched {
   void gram(F make) {
     std::vector<GramArgs> gs(count());
     std::vector<int> ts(count() + 1, 0);
+    int64_t max_mm = 0;
+    bool any_split = false;
     for (int i = 0; i < count(); ++i) {
-      gs[i] = make(i);
-      ts[i + 1] = ts[i] + gram_group_tiles(gs[i].M);
+      GramArgs g = make(i);
+      // split-K into the problem's partial buffer (sized for its longest basis)
+      int s = pl.P[i].gpart ? gram_group_splits(g.K) : 1;
+      if (s > 1) {
+        g.kps = ((g.K + s - 1) / s + 31) / 32 * 32;
+        s = (int)((g.K + g.kps - 1) / g.kps);
+      }
+      if (s > 1) {
+        g.partial = pl.P[i].gpart;
+        g.splits = s;
+        any_split = true;
+      } else {
+        g.partial = nullptr;
+        g.splits = 1;
+        g.kps = g.K;
+      }
+      gs[i] = g;
+      max_mm = std::max<int64_t>(max_mm, g.M * g.M);
+      ts[i + 1] = ts[i] + gram_group_tiles(g.M) * (s > 1 ? s : 1);
     }
     const GramArgs* dg = tp.put(gs);
     const int* dt = tp.put(ts);
-    if (launch) chk(launch_gram_grouped(dg, dt, count(), ts[count()], st));
+    if (launch) chk(launch_gram_grouped(dg, dt, count(), ts[count()], max_mm, any_split, st));
   }
 
   template <typename F>
@@ -350,6 +369,12 @@ static size_t carve(rf_batch_plan& pl, char* base, size_t off) {
     p.Z = (float*)get(r1 * k * 4);
     p.Z16 = pl.mixed ? (uint16_t*)get(r1 * k * 2) : nullptr;
     p.G = (double*)get(k * k * 8);
+    {
+      // split-K parts of the Grams of this problem's bases (m, sketch and n rows)
+      const int sp = std::max(gram_group_splits((int64_t)m), std::max(gram_group_splits((int64_t)r1),
+                                                                      gram_group_splits((int64_t)n)));
+      p.gpart = sp > 1 ? (double*)get((size_t)sp * k * k * 8) : nullptr;
+    }
     p.d0 = (double*)get(k * 8);
     p.flags = (int*)get(k * 4);
     p.Rinv = (float*)get(k * k * 4);

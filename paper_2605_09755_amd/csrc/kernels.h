@@ -173,10 +173,15 @@ struct GramArgs {
   const float* X; int64_t ldx; int64_t K, M;
   double* C; int64_t ldc;
   const int* run_if;
+  double* partial;  // splits > 1: splits x M x M doubles of split-K parts (reduced in fixed order)
+  int splits;       // parts of K (0 or 1: one)
+  int64_t kps;      // rows of K per part
 };
-int gram_group_tiles(int64_t M);
-hipError_t launch_gram_grouped(const GramArgs* gs, const int* tile_start, int count, int total_tiles,
-                               hipStream_t st);
+__host__ __device__ int gram_group_tiles(int64_t M);
+int gram_group_splits(int64_t K);
+// total_tiles counts (tile, part) items; max_mm = the largest M x M over the group.
+hipError_t launch_gram_grouped(const GramArgs* gs, const int* tile_start, int count, int total_tiles, int64_t max_mm,
+                               bool any_split, hipStream_t st);
 // In-place upper Cholesky G = R^T R and X = R^{-1} (upper, lower triangle zeroed) in
 // one persistent launch.  Pivots below tol_ratio * (original diagonal) are declared
 // deficient: flags[c] = 1, row c of R set to e_c, *count += 1; d0 (N doubles)

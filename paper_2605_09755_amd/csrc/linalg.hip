@@ -151,7 +151,9 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int64_t 
 }
 
 // Grouped symmetric Grams C_i = X_i^T X_i (FP32 X_i, K_i x M_i): group i owns the
-// upper tiles [tile_start[i], tile_start[i+1]) of the flat grid.
+// items [tile_start[i], tile_start[i+1]) of the flat grid, (part, upper tile) with
+// the tile fastest; with more than one part of K each writes its share to the
+// group's partial buffer and k_gram_reduce_grouped sums them in part order.
 __global__ __launch_bounds__(256) void k_gram_grouped(const GramArgs* __restrict__ gs, const int* tile_start,
                                                       int count) {
   int lo = 0, hi = count - 1;
@@ -161,19 +163,51 @@ __global__ __launch_bounds__(256) void k_gram_grouped(const GramArgs* __restrict
   }
   const GramArgs g = gs[lo];
   if (g.run_if && *g.run_if == 0) return;
-  gram_body<float, float>(g.X, g.ldx, g.X, g.ldx, g.K, g.M, g.M, 1, g.C, g.ldc, nullptr, g.K + GK,
-                          blockIdx.x - tile_start[lo], 0);
+  const int local = (int)blockIdx.x - tile_start[lo];
+  if (g.splits > 1) {
+    const int tiles = gram_group_tiles(g.M);
+    gram_body<float, float>(g.X, g.ldx, g.X, g.ldx, g.K, g.M, g.M, 1, g.C, g.ldc, g.partial, g.kps, local % tiles,
+                            local / tiles);
+  } else {
+    gram_body<float, float>(g.X, g.ldx, g.X, g.ldx, g.K, g.M, g.M, 1, g.C, g.ldc, nullptr, g.K + GK, local, 0);
+  }
 }
 
-int gram_group_tiles(int64_t M) {
+// C_i (upper entries and their mirror) = sum of the parts in order; group i = blockIdx.y.
+__global__ void k_gram_reduce_grouped(const GramArgs* __restrict__ gs) {
+  const GramArgs g = gs[blockIdx.y];
+  if (g.splits <= 1 || (g.run_if && *g.run_if == 0)) return;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x, MM = g.M * g.M;
+  if (idx >= MM) return;
+  const int64_t i = idx / g.M, j = idx % g.M;
+  if (i > j) return;
+  double s = 0.0;
+  for (int z = 0; z < g.splits; ++z) s += g.partial[(int64_t)z * MM + idx];
+  g.C[i * g.ldc + j] = s;
+  if (i != j) g.C[j * g.ldc + i] = s;
+}
+
+__host__ __device__ int gram_group_tiles(int64_t M) {
   const int64_t nt = (M + GT - 1) / GT;
   return (int)(nt * (nt + 1) / 2);
 }
 
-hipError_t launch_gram_grouped(const GramArgs* gs, const int* tile_start, int count, int total_tiles,
-                               hipStream_t st) {
+// Parts of K for one grouped Gram: about 1024 rows each, at most 8 (the long
+// bases of a batch would otherwise run their tiles one 32-row step at a time
+// while the short ones idle).
+int gram_group_splits(int64_t K) {
+  int64_t s = K / 1024;
+  if (s > 8) s = 8;
+  return s < 1 ? 1 : (int)s;
+}
+
+hipError_t launch_gram_grouped(const GramArgs* gs, const int* tile_start, int count, int total_tiles, int64_t max_mm,
+                               bool any_split, hipStream_t st) {
   if (count == 0 || total_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(k_gram_grouped, dim3((unsigned)total_tiles), dim3(256), 0, st, gs, tile_start, count);
+  if (any_split)
+    hipLaunchKernelGGL(k_gram_reduce_grouped, dim3((unsigned)((max_mm + 255) / 256), (unsigned)count), dim3(256), 0,
+                       st, gs);
   return hipGetLastError();
 }
 
