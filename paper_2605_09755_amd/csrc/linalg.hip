@@ -449,10 +449,14 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, bool full, int x, int sl
   __syncthreads();
   // nothing to do when every off-diagonal entry of the pair already meets the
   // global convergence test and the diagonal is already in the sorted order
+  // (square roots of the diagonal taken once)
+  __shared__ double sq[JS];
+  if (threadIdx.x < JS) sq[threadIdx.x] = sqrt(fabs(M[threadIdx.x][threadIdx.x]));
+  __syncthreads();
   for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
     int a = e / JS, b = e % JS;
     if (a != b) {
-      double d = sqrt(fabs(M[a][a])) * sqrt(fabs(M[b][b]));
+      double d = sq[a] * sq[b];
       if (!(fabs(M[a][b]) <= fmax(w.tol * d, fabs_))) needed = 1;
     }
   }
@@ -607,16 +611,22 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, bool full, int x, int sl
   // Order the subproblem's eigenpairs: the larger half goes to the block with the
   // lower index, so eigenvalues settle in descending order along the diagonal
   // (speeds up convergence on clustered spectra; the padding sinks to the end).
+  // (16 threads per entry, each counting over JS/16 others, summed across lanes)
   __shared__ int rnk[JS];
-  if (threadIdx.x < JS) {
-    const int a = threadIdx.x;
+  static_assert(JS * 16 <= 1024, "16 threads per diagonal entry");
+  if (threadIdx.x < JS * 16) {
+    const int a = threadIdx.x >> 4, c = threadIdx.x & 15;
     const double d = M[a][a];
     int r = 0;
-    for (int b = 0; b < JS; ++b) {
+#pragma unroll
+    for (int i = 0; i < JS / 16; ++i) {
+      const int b = c * (JS / 16) + i;
       const double e = M[b][b];
       r += (e > d || (e == d && b < a)) ? 1 : 0;
     }
-    rnk[a] = (P < Q) ? r : (r + JB) % JS;
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) r += __shfl_xor(r, o, 16);
+    if (c == 0) rnk[a] = (P < Q) ? r : (r + JB) % JS;
   }
   __syncthreads();
   double* out = Vout + (int64_t)x * JS * JS;
