@@ -83,6 +83,27 @@ def test_svd_parity(name, m, n, k, l, s, q):
     assert np.max(np.abs(Vg @ Vg.T - np.eye(good.sum()))) < 1e-3
 
 
+def test_svd_parity_k2000_sketch4000():
+    """The precision workload's rank and sketch (k = 2000, sketch 4000, q = 3,
+    sigma_i = max(0.995^i, 1e-3 sigma_1)) on a 6144 x 4608 instance: 32 block pairs
+    in the eigensolver (K = 2048) and the sketch variant with 257-512 bucket
+    lines per block, end to end against the oracle at the bars of test_svd_parity."""
+    m, n, k, l, s, q = 6144, 4608, 2000, 4000, 8, 3
+    A32, A = _instance("exp65k", m, n)
+    U, sig, Vt, info = rf.rf_svd(dev32(A32), k, l, q, s, seed=42)
+    U, sig, Vt = (U.cpu().numpy().astype(np.float64), sig.cpu().numpy(), Vt.cpu().numpy().astype(np.float64))
+    ref = me.rand_svd(A, me.Params(k=k, l=l, q=q, s=s, seed=42))
+    tol = 1e-5 * ref.sigma + 2e-6 * ref.sigma[0]
+    print("k=2000: max |dsigma|/tol = %.3f" % np.max(np.abs(sig - ref.sigma) / tol))
+    assert np.all(np.abs(sig - ref.sigma) <= tol)
+    assert np.all(np.diff(sig) <= 0)
+    assert np.max(np.abs(U.T @ U - np.eye(k))) < 2e-5
+    eg = np.linalg.norm(A - (U * sig) @ Vt)
+    eo = np.linalg.norm(A - (ref.U * ref.sigma) @ ref.Vt)
+    print("k=2000: err gpu %.10e oracle %.10e rel %.2e" % (eg, eo, abs(eg - eo) / eo))
+    assert abs(eg - eo) <= 1e-4 * eo + 1e-6 * np.linalg.norm(A)
+
+
 def test_svd_matches_oracle_vectors_on_separated_spectrum():
     m, n, k = 800, 500, 20
     sigma = np.concatenate([np.linspace(10, 1, k), 1e-3 * np.ones(n - k)])
