@@ -289,11 +289,15 @@ hipError_t launch_gram(const void* X, int64_t ldx, int xdt, const void* Y, int64
 // ============================== block-Jacobi eigensolver ==============================
 // G (K x K, K = 2 p JB, padded with decoupled -1e300 diagonal) is driven to
 // diagonal form by rounds of p independent 64 x 64 subproblems (pairs of 32-wide
-// blocks, round-robin "circle" schedule).  Each subproblem is diagonalised in
-// LDS by cyclic two-sided Jacobi rotations (Golub & Van Loan, sym.schur2) and
-// its rotation V (64 x 64) is applied to the rows/columns of G and to Z in a
-// second kernel, tile by tile, in place.  Converged when every off-diagonal
-// entry is <= tol * sqrt(|G_ii G_jj| + floor^2).
+// blocks, round-robin "circle" schedule).  Each subproblem takes one sweep of
+// two-sided Jacobi rotations in LDS (Golub & Van Loan, sym.schur2): over all of
+// its index pairs in the first round of an outer sweep, over the pairs across its
+// two blocks in the others.  Its rotation V (64 x 64) is then applied to the
+// rows/columns of G and to the eigenvector matrix Z: in the single-problem
+// solver within the next round's launch (G into a second buffer, the next
+// subproblems built from the previous G and V), in the batched solver by a
+// separate in-place launch.  Converged when every off-diagonal entry is <= tol *
+// sqrt(|G_ii G_jj| + floor^2).
 int eig_block_width(int64_t N);
 
 
@@ -498,59 +502,57 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, bool full, int x, int sl
       pair_hi[rr][u] = (unsigned char)b;
     }
     __syncthreads();
-    for (int sw = 0; sw < 1; ++sw) {
-      if (threadIdx.x == 0) done = 1;
-      __syncthreads();
-      for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
-        int a = e / JS, b = e % JS;
-        if (a < b && fabs(M[a][b]) > 1e-15 * sqrt(fabs(M[a][a]) * fabs(M[b][b]) + floor2)) done = 0;
+    if (threadIdx.x == 0) done = 1;
+    __syncthreads();
+    for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
+      int a = e / JS, b = e % JS;
+      if (a < b && fabs(M[a][b]) > 1e-15 * sqrt(fabs(M[a][a]) * fabs(M[b][b]) + floor2)) done = 0;
+    }
+    __syncthreads();
+    // (the pass is skipped when the pair is already diagonal to FP64 rounding)
+    for (int rr = 0; rr < (done ? 0 : JS - 1); ++rr) {
+      // pair u of inner round rr: (lo, hi) of circle positions u and JS-1-u, from
+      // the table; the rotations go through LDS as (c, s) pairs
+      auto pair_of = [&](int u, int& a, int& b) {
+        a = pair_lo[rr][u];
+        b = pair_hi[rr][u];
+      };
+      if (threadIdx.x < JS / 2) {
+        const int u = threadIdx.x;
+        int a, b;
+        pair_of(u, a, b);
+        double c, s;
+        jacobi_rot(M[a][a], M[b][b], M[a][b], floor2, c, s);  // FP32 angle, exact FP64 rotation
+        csn[u] = double2{c, s};
       }
       __syncthreads();
-      if (done) break;
-      for (int rr = 0; rr < JS - 1; ++rr) {
-        // pair u of inner round rr: (lo, hi) of circle positions u and JS-1-u, from
-        // the table; the rotations go through LDS as (c, s) pairs
-        auto pair_of = [&](int u, int& a, int& b) {
-          a = pair_lo[rr][u];
-          b = pair_hi[rr][u];
-        };
-        if (threadIdx.x < JS / 2) {
-          const int u = threadIdx.x;
-          int a, b;
-          pair_of(u, a, b);
-          double c, s;
-          jacobi_rot(M[a][a], M[b][b], M[a][b], floor2, c, s);  // FP32 angle, exact FP64 rotation
-          csn[u] = double2{c, s};
+      // thread t: 2x2 block (u, v) = (t / (JS/2), t % (JS/2)), M' = J_u^T M J_v, and
+      // rows t / (JS/2) + 32 h of V <- V J_v (the same pair v)
+      for (int e = threadIdx.x; e < (JS / 2) * (JS / 2); e += blockDim.x) {
+        const int u = e / (JS / 2), v = e % (JS / 2);
+        int a, b, cc, d;
+        pair_of(u, a, b);
+        pair_of(v, cc, d);
+        const double2 ju = csn[u], jv = csn[v];
+        const double cu = ju.x, su = ju.y, cv = jv.x, sv = jv.y;
+        const double m00 = M[a][cc], m01 = M[a][d], m10 = M[b][cc], m11 = M[b][d];
+        double v0[2], v1[2];  // rows u and u + JS/2 of V
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          v0[h] = V[u + (JS / 2) * h][cc];
+          v1[h] = V[u + (JS / 2) * h][d];
         }
-        __syncthreads();
-        // thread t: 2x2 block (u, v) = (t / (JS/2), t % (JS/2)), M' = J_u^T M J_v, and
-        // rows t / (JS/2) + 32 h of V <- V J_v (the same pair v)
-        for (int e = threadIdx.x; e < (JS / 2) * (JS / 2); e += blockDim.x) {
-          const int u = e / (JS / 2), v = e % (JS / 2);
-          int a, b, cc, d;
-          pair_of(u, a, b);
-          pair_of(v, cc, d);
-          const double2 ju = csn[u], jv = csn[v];
-          const double cu = ju.x, su = ju.y, cv = jv.x, sv = jv.y;
-          const double m00 = M[a][cc], m01 = M[a][d], m10 = M[b][cc], m11 = M[b][d];
-          double v0[2], v1[2];  // rows u and u + JS/2 of V
-  #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            v0[h] = V[u + (JS / 2) * h][cc];
-            v1[h] = V[u + (JS / 2) * h][d];
-          }
-          const double t00 = cu * m00 - su * m10, t01 = cu * m01 - su * m11;
-          const double t10 = su * m00 + cu * m10, t11 = su * m01 + cu * m11;
-          M[a][cc] = cv * t00 - sv * t01; M[a][d] = sv * t00 + cv * t01;
-          M[b][cc] = cv * t10 - sv * t11; M[b][d] = sv * t10 + cv * t11;
-  #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            V[u + (JS / 2) * h][cc] = cv * v0[h] - sv * v1[h];
-            V[u + (JS / 2) * h][d] = sv * v0[h] + cv * v1[h];
-          }
+        const double t00 = cu * m00 - su * m10, t01 = cu * m01 - su * m11;
+        const double t10 = su * m00 + cu * m10, t11 = su * m01 + cu * m11;
+        M[a][cc] = cv * t00 - sv * t01; M[a][d] = sv * t00 + cv * t01;
+        M[b][cc] = cv * t10 - sv * t11; M[b][d] = sv * t10 + cv * t11;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          V[u + (JS / 2) * h][cc] = cv * v0[h] - sv * v1[h];
+          V[u + (JS / 2) * h][d] = sv * v0[h] + cv * v1[h];
         }
-        __syncthreads();
       }
+      __syncthreads();
     }
   } else {
     // cross pairs only: inner round r pairs index u of the first block with index
