@@ -122,7 +122,8 @@ def main():
                     help="poly65k: the headline workload (default); exp65k: A 65536 x 32768 stored FP32, BF16 and "
                          "FP8 with block scales, k=2000, sketch 4000, q=3; nystrom32k: Gaussian kernel matrix of "
                          "32768 points in 32 dimensions, k=512, sketch 1024, q=2")
-    ap.add_argument("--counter-run", choices=["sketch", "copy", "sketch_left", "qta_f32", "qta_bf16", "qta_fp8", "gram"],
+    ap.add_argument("--counter-run", choices=["sketch", "copy", "sketch_left", "qta_f32", "qta_bf16", "qta_fp8", "gram",
+                                              "eig"],
                     default=None,
                     help="for rocprofv3 --pmc runs: three sketch passes over the workload matrix, or three copies "
                          "of 1 GiB (FETCH_SIZE / WRITE_SIZE calibration); prints nothing else")
@@ -722,6 +723,17 @@ def counter_run(args):
         X = torch.randn((m, k), generator=g, device=dev)
         for _ in range(3):
             rf.rf_test_gram(X, sym=True)
+    elif args.counter_run == "eig":
+        # the Rayleigh-Ritz eigensolver at k = 1000 and 2000: G = B B^T with the rows
+        # of a Gaussian k x 2k B scaled by i^-1.5 (the spectrum of the workload's B),
+        # three decompositions each at the rf_svd tolerance
+        for kk in (1000, 2000):
+            d = torch.arange(1, kk + 1, device=dev, dtype=torch.float64) ** -1.5
+            B = torch.randn((kk, 2 * kk), generator=g, device=dev, dtype=torch.float64) * d[:, None]
+            G = B @ B.t()
+            G = 0.5 * (G + G.t())
+            for _ in range(3):
+                rf.rf_test_eig(G, tol=1e-7)
     else:
         # the sketch's memory traffic does not depend on the values, so a Gaussian
         # matrix of the workload's shape stands in (no QR, which the counter

@@ -236,15 +236,17 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
       int64_t r = r0 + row, k = k0 + kc;
       if (vec && r < rmax && k + 8 <= kend) {
         dst[ps] = *reinterpret_cast<const uint4*>(P + r * ld + k);
+      } else if (r >= rmax || k >= kend) {
+        dst[ps] = make_uint4(0u, 0u, 0u, 0u);  // outside the operand: no load
       } else {
-        uint32_t w[4];
+        // straddles the k edge (or unaligned): clamped element loads, zero past the edge
+        uint32_t h[8];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          uint32_t lo = (r < rmax && k + 2 * e < kend) ? P[r * ld + k + 2 * e] : 0u;
-          uint32_t hi = (r < rmax && k + 2 * e + 1 < kend) ? P[r * ld + k + 2 * e + 1] : 0u;
-          w[e] = lo | (hi << 16);
+        for (int e = 0; e < 8; ++e) {
+          const uint32_t x = P[r * ld + min(k + e, kend - 1)];
+          h[e] = k + e < kend ? x : 0u;
         }
-        dst[ps] = make_uint4(w[0], w[1], w[2], w[3]);
+        dst[ps] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
       }
     }
   };
@@ -258,10 +260,11 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
       int64_t k = k0 + 8 * wave + e;
       if (vec && k < kend && r + 1 < rmax) {
         w[e] = *reinterpret_cast<const uint32_t*>(P + k * ld + r);
+      } else if (k >= kend || r >= rmax) {
+        w[e] = 0u;
       } else {
-        uint32_t lo = (k < kend && r < rmax) ? P[k * ld + r] : 0u;
-        uint32_t hi = (k < kend && r + 1 < rmax) ? P[k * ld + r + 1] : 0u;
-        w[e] = lo | (hi << 16);
+        const uint32_t lo = P[k * ld + r], hi = P[k * ld + min(r + 1, rmax - 1)];
+        w[e] = lo | ((r + 1 < rmax ? hi : 0u) << 16);
       }
     }
     dst[0] = make_uint4(pack_lo(w[0], w[1]), pack_lo(w[2], w[3]), pack_lo(w[4], w[5]), pack_lo(w[6], w[7]));
@@ -290,9 +293,15 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
         const float4 x0 = *reinterpret_cast<const float4*>(Af + r * g.lda + k);
         const float4 x1 = *reinterpret_cast<const float4*>(Af + r * g.lda + k + 4);
         t[0] = x0.x; t[1] = x0.y; t[2] = x0.z; t[3] = x0.w; t[4] = x1.x; t[5] = x1.y; t[6] = x1.z; t[7] = x1.w;
+      } else if (r >= rmax || k >= kend) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = 0.f;
       } else {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) t[e] = (r < rmax && k + e < kend) ? Af[r * g.lda + k + e] : 0.f;
+        for (int e = 0; e < 8; ++e) {
+          const float x = Af[r * g.lda + min(k + e, kend - 1)];
+          t[e] = k + e < kend ? x : 0.f;
+        }
       }
       dst[ps] = make_uint4(pack2_bf16(t[0], t[1]), pack2_bf16(t[2], t[3]), pack2_bf16(t[4], t[5]),
                            pack2_bf16(t[6], t[7]));
@@ -308,9 +317,12 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
       if (vec && k < kend && r + 1 < rmax) {
         const float2 x = *reinterpret_cast<const float2*>(Af + k * g.lda + r);
         lo = x.x; hi = x.y;
+      } else if (k >= kend || r >= rmax) {
+        lo = hi = 0.f;
       } else {
-        lo = (k < kend && r < rmax) ? Af[k * g.lda + r] : 0.f;
-        hi = (k < kend && r + 1 < rmax) ? Af[k * g.lda + r + 1] : 0.f;
+        lo = Af[k * g.lda + r];
+        const float x = Af[k * g.lda + min(r + 1, rmax - 1)];
+        hi = r + 1 < rmax ? x : 0.f;
       }
       w[e] = pack2_bf16(lo, hi);
     }
@@ -440,6 +452,10 @@ struct BigStage {
   float4 f[NCH][2];
   uint2 b8[NCH];
   float sc[NCH];
+  // A chunk wholly outside the operand is zero without a load; a chunk that straddles
+  // its edge (or an unaligned operand) reads each element from an address clamped into
+  // the operand and zeroes the elements outside it.  Both stay branch-free per lane so
+  // the loads of a stage stay in flight together.
   RF_DEV void load(const void* P_, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, int64_t kend, bool vec,
                    int tid, const float* scales = nullptr, int64_t ldsc = 0) {
 #pragma unroll
@@ -447,50 +463,61 @@ struct BigStage {
       const int c = tid + BT * q;
       const int64_t r = KC ? r0 + c / KCH : r0 + 8 * (c & 31);         // first m/n index of the chunk
       const int64_t k = KC ? k0 + 8 * (c % KCH) : k0 + (c >> 5);       // first k index of the chunk
+      const bool any = r < rmax && k < kend;
       const bool full = KC ? (r < rmax && k + 8 <= kend) : (k < kend && r + 8 <= rmax);
+      // element e of the chunk: in range, and its clamped offset from the operand start
+      auto in = [&](int e) { return KC ? (k + e < kend) : (r + e < rmax); };
+      auto at = [&](int e) {
+        return KC ? r * ld + min(k + e, kend - 1) : k * ld + min(r + e, rmax - 1);
+      };
       if constexpr (F8) {
         const uint8_t* P = reinterpret_cast<const uint8_t*>(P_);
-        const uint8_t* src = P + k * ld + r;
-        sc[q] = (k < kend && r < rmax) ? scales[(k >> 7) * ldsc + (r >> 7)] : 0.f;
+        sc[q] = any ? scales[(k >> 7) * ldsc + (r >> 7)] : 0.f;
         if (vec && full) {
-          b8[q] = *reinterpret_cast<const uint2*>(src);
+          b8[q] = *reinterpret_cast<const uint2*>(P + k * ld + r);
+        } else if (!any) {
+          b8[q] = make_uint2(0u, 0u);
         } else {
           uint32_t w[2] = {0u, 0u};
 #pragma unroll
-          for (int e = 0; e < 8; ++e)
-            if (k < kend && r + e < rmax) w[e >> 2] |= (uint32_t)src[e] << (8 * (e & 3));
+          for (int e = 0; e < 8; ++e) {
+            const uint32_t b = P[at(e)];
+            w[e >> 2] |= (in(e) ? b : 0u) << (8 * (e & 3));
+          }
           b8[q] = make_uint2(w[0], w[1]);
         }
       } else if constexpr (F32) {
         const float* P = reinterpret_cast<const float*>(P_);
-        const float* src = KC ? P + r * ld + k : P + k * ld + r;
         if (vec && full) {
+          const float* src = KC ? P + r * ld + k : P + k * ld + r;
           f[q][0] = *reinterpret_cast<const float4*>(src);
           f[q][1] = *reinterpret_cast<const float4*>(src + 4);
+        } else if (!any) {
+          f[q][0] = f[q][1] = make_float4(0.f, 0.f, 0.f, 0.f);
         } else {
           float t[8];
 #pragma unroll
           for (int e = 0; e < 8; ++e) {
-            const bool ok = KC ? (r < rmax && k + e < kend) : (k < kend && r + e < rmax);
-            t[e] = ok ? src[e] : 0.f;
+            const float x = P[at(e)];
+            t[e] = in(e) ? x : 0.f;
           }
           f[q][0] = make_float4(t[0], t[1], t[2], t[3]);
           f[q][1] = make_float4(t[4], t[5], t[6], t[7]);
         }
       } else {
         const uint16_t* P = reinterpret_cast<const uint16_t*>(P_);
-        const uint16_t* src = KC ? P + r * ld + k : P + k * ld + r;
         if (vec && full) {
-          v[q] = *reinterpret_cast<const uint4*>(src);
+          v[q] = *reinterpret_cast<const uint4*>(KC ? P + r * ld + k : P + k * ld + r);
+        } else if (!any) {
+          v[q] = make_uint4(0u, 0u, 0u, 0u);
         } else {
-          uint32_t w[4];
+          uint32_t h[8];
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const bool ok0 = KC ? (r < rmax && k + 2 * e < kend) : (k < kend && r + 2 * e < rmax);
-            const bool ok1 = KC ? (r < rmax && k + 2 * e + 1 < kend) : (k < kend && r + 2 * e + 1 < rmax);
-            w[e] = (ok0 ? (uint32_t)src[2 * e] : 0u) | ((ok1 ? (uint32_t)src[2 * e + 1] : 0u) << 16);
+          for (int e = 0; e < 8; ++e) {
+            const uint32_t x = P[at(e)];
+            h[e] = in(e) ? x : 0u;
           }
-          v[q] = make_uint4(w[0], w[1], w[2], w[3]);
+          v[q] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
         }
       }
     }
@@ -519,6 +546,24 @@ struct BigStage {
     }
   }
 };
+
+// L2 warm-up of a later stage: one byte of each 128-byte line of an operand's stage
+// tile (at most one line per thread), so the stage's own loads find the tile in L2.
+// Returns the byte, which the caller keeps alive.
+template <bool KC, int MODE>
+RF_DEV uint32_t big_touch(const void* P_, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, int64_t kend, int tid) {
+  constexpr int es = MODE == 1 ? 4 : (MODE == 2 ? 1 : 2);
+  constexpr int rowb = (KC ? HBK : HB) * es;        // bytes of one tile row in memory
+  constexpr int lpr = rowb >= 128 ? rowb / 128 : 1;  // lines per tile row
+  constexpr int nlines = (KC ? HB : HBK) * lpr;
+  static_assert(nlines <= BT, "one line per thread");
+  if (tid >= nlines) return 0u;
+  const int row = tid / lpr, off = (tid % lpr) * (128 / es);
+  const int64_t r = KC ? r0 + row : r0 + off, k = KC ? k0 + off : k0 + row;
+  if (r >= rmax || k >= kend) return 0u;
+  const uint8_t* P = reinterpret_cast<const uint8_t*>(P_);
+  return P[(KC ? r * ld + k : k * ld + r) * es];
+}
 
 // Epilogue of the 256 x 256 kernels (wave (wm, wn) holds rows wm*128 + 32a + ..,
 // columns wn*64 + 32b + .. in acc[a][b]), through LDS one 64-row slab (rows 32a.. of
@@ -586,6 +631,10 @@ RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
   BigStage<AKC, AMODE> sa;
   BigStage<BKC, 0> sb;
   const int nk = kend > kbeg ? (int)((kend - kbeg + HBK - 1) / HBK) : 0;
+  // FP32 A (twice the bytes of a BF16 stage) warms L2 for the stage after next; for
+  // BF16 and FP8 A the warm-up measured slower (its wait lands in the next step)
+  constexpr int PF = AMODE == 1 ? 1 : 0;
+  uint32_t pf_sink = 0, pf_prev = 0;
   if (nk > 0) {
     sa.load(g.A, g.lda, i0, g.M, kbeg, kend, avec, tid, g.a_scales, g.a_ldsc);
     sb.load(g.B, g.ldb, j0, g.N, kbeg, kend, bvec, tid);
@@ -622,9 +671,17 @@ RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
       sa.store(A0 + (buf ^ 1) * AS, tid);
       sb.store(B0 + (buf ^ 1) * BS, tid);
     }
+    // issued after this step's stage loads were waited for
+    if constexpr (PF > 0) {
+      pf_sink += pf_prev;
+      pf_prev = 0u;
+      if (kt + 1 + PF < nk)
+        pf_prev = big_touch<AKC, AMODE>(g.A, g.lda, i0, g.M, kbeg + (int64_t)(kt + 1 + PF) * HBK, kend, tid);
+    }
     __syncthreads();
   }
 
+  if constexpr (PF > 0) asm volatile("" ::"v"(pf_sink + pf_prev));
   big_epilogue(g, acc, i0, j0, split, wm, wn, lane, tid, smem);
 }
 

@@ -218,6 +218,7 @@ struct EigWork {
   unsigned long long* maxoff;  // 1
   int* conv;       // 1
   double* floor2;  // 1: (1e-15 ||G||_F)^2, regularises rotation thresholds
+  double* npart;   // 64: partial sums of squares of G (single-problem solver)
   double* fabs_;   // 1: 16 eps ||G||_F, absolute convergence floor
   double tol;      // relative off-diagonal tolerance
   int64_t K;

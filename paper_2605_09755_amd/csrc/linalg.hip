@@ -322,7 +322,8 @@ static EigWork eig_layout(void* work, int64_t N, int JB, bool dbuf = true) {
   w.maxoff = (unsigned long long*)p; p += 256;
   w.conv = (int*)p; p += 256;
   w.floor2 = (double*)p; p += 256;
-  w.fabs_ = (double*)p; p += 256;
+  w.npart = (double*)p; p += 512;
+  w.fabs_ = (double*)p; p += 256;  // last: eig_work_bytes ends the layout here
   return w;
 }
 
@@ -1186,8 +1187,37 @@ RF_DEV void eig_gather_body(const EigWork& w, int64_t N, double* V, int64_t ldv,
 __global__ void k_eig_init(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
   eig_init_body(G, ld, N, w, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
-__global__ __launch_bounds__(1024) void k_eig_floor(const double* __restrict__ G, int64_t ld, int64_t N, EigWork w) {
-  eig_floor_body(G, ld, N, w);
+// ||G||_F for the single-problem solver in kNormParts row ranges at once (one
+// workgroup reading all of G took 1.1 ms at K = 2048), summed in part order.
+constexpr int kNormParts = 64;
+__global__ __launch_bounds__(1024) void k_eig_norm_part(const double* __restrict__ G, int64_t ld, int64_t N,
+                                                         double* __restrict__ part) {
+  __shared__ double red[1024];
+  const int64_t rows = (N + kNormParts - 1) / kNormParts;
+  const int64_t r0 = (int64_t)blockIdx.x * rows, r1 = min(N, r0 + rows);
+  const int tc = threadIdx.x % 64, tr = threadIdx.x / 64;
+  double s = 0.0;
+  for (int64_t r = r0 + tr; r < r1; r += 16) {
+    const double* row = G + r * ld;
+    for (int64_t c = tc; c < N; c += 64) s = fma(row[c], row[c], s);
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+// the rotation and convergence floors from the parts (as eig_floor_body sets them)
+__global__ void k_eig_floor_fin(EigWork w) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < kNormParts; ++i) s += w.npart[i];
+  const double fro = sqrt(s);
+  const double f = 1e-15 * fro;
+  *w.floor2 = f * f + 1e-300;
+  *w.fabs_ = 16.0 * 2.220446049250313e-16 * fro + 1e-300;
 }
 // work items id0 + blockIdx.x (G tiles first, then Z strips)
 template <int JB>
@@ -1335,7 +1365,8 @@ static hipError_t eig_sequence(double* G, int64_t ld, int64_t N, double* lam, do
   w.tol = tol;
   int64_t KK = w.K * w.K;
   hipLaunchKernelGGL(k_eig_init, dim3((unsigned)((KK + 255) / 256)), dim3(256), 0, st, G, ld, N, w);
-  hipLaunchKernelGGL(k_eig_floor, dim3(1), dim3(1024), 0, st, G, ld, N, w);
+  hipLaunchKernelGGL(k_eig_norm_part, dim3(kNormParts), dim3(1024), 0, st, G, ld, N, w.npart);
+  hipLaunchKernelGGL(k_eig_floor_fin, dim3(1), dim3(64), 0, st, w);
   eig_rounds<32>(w, N, st, trace);
   hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, st, w, N, lam);
   hipLaunchKernelGGL(k_eig_gather, dim3((unsigned)((N * N + 255) / 256)), dim3(256), 0, st, w, N, V, ldv);
