@@ -82,42 +82,44 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
   float ra[2][4], rb[2][4];
+  // 16-byte loads where the operand allows them; chunks past a ragged edge are zero
+  // without a load, and a chunk straddling the edge loads clamped elements (no
+  // per-element branches, so the loads of a step stay in flight together)
+  const bool avec = ((((uintptr_t)A) & 15) == 0) && (g.lda % 4 == 0);
+  const bool bvec = ((((uintptr_t)B) & 15) == 0) && (g.ldb % 4 == 0);
+  // four consecutive elements of P along the contiguous index (x0 .. x0+3 < xmax)
+  // of line y (< ymax: the other index), into d
+  auto load4 = [&](const float* P, int64_t ld, int64_t y, int64_t ymax, int64_t x0, int64_t xmax, bool vec,
+                   float* d) {
+    if (vec && y < ymax && x0 + 4 <= xmax) {
+      const float4 v = *reinterpret_cast<const float4*>(P + y * ld + x0);
+      d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+    } else if (y >= ymax || x0 >= xmax) {
+      d[0] = d[1] = d[2] = d[3] = 0.f;
+    } else {
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const float x = P[y * ld + min(x0 + e, xmax - 1)];
+        d[e] = x0 + e < xmax ? x : 0.f;
+      }
+    }
+  };
   auto gload = [&](int64_t k0) {
 #pragma unroll
     for (int ps = 0; ps < 2; ++ps) {
       if (AKC) {
         int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 4;
-        int64_t i = i0 + row;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          int64_t k = k0 + kc + e;
-          ra[ps][e] = (i < g.M && k < kend) ? A[i * g.lda + k] : 0.f;
-        }
+        load4(A, g.lda, i0 + row, g.M, k0 + kc, kend, avec, ra[ps]);
       } else {
         int kr = (tid >> 5) + 8 * ps, ic = (tid & 31) * 4;
-        int64_t k = k0 + kr;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          int64_t i = i0 + ic + e;
-          ra[ps][e] = (i < g.M && k < kend) ? A[k * g.lda + i] : 0.f;
-        }
+        load4(A, g.lda, k0 + kr, kend, i0 + ic, g.M, avec, ra[ps]);
       }
       if (BKC) {
         int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 4;
-        int64_t j = j0 + row;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          int64_t k = k0 + kc + e;
-          rb[ps][e] = (j < g.N && k < kend) ? B[j * g.ldb + k] : 0.f;
-        }
+        load4(B, g.ldb, j0 + row, g.N, k0 + kc, kend, bvec, rb[ps]);
       } else {
         int kr = (tid >> 5) + 8 * ps, jc = (tid & 31) * 4;
-        int64_t k = k0 + kr;
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          int64_t j = j0 + jc + e;
-          rb[ps][e] = (j < g.N && k < kend) ? B[k * g.ldb + j] : 0.f;
-        }
+        load4(B, g.ldb, k0 + kr, kend, j0 + jc, g.N, bvec, rb[ps]);
       }
     }
   };
