@@ -53,7 +53,10 @@ RF_DEV void store_out(const GemmArgs& g, int64_t i, int64_t j, float v) {
 // ---------------- FP32 operands -------------------------------------------------------
 template <bool AKC, bool BKC>
 RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
-  constexpr int BK = 16;
+  constexpr int BK = 16;          // 32 (two workgroups per CU instead of three) measured slower
+  constexpr int NPS = BK / 8;     // load passes per operand and step
+  constexpr int TPR = BK / 4;     // threads per row of a k-contiguous tile
+  constexpr int RPP = 256 / TPR;  // rows per pass of a k-contiguous tile
   constexpr int AST = AKC ? (BK + 1) : GBM;  // LDS row stride (floats)
   constexpr int BST = BKC ? (BK + 1) : GBN;
   constexpr int ASZ = AKC ? GBM * (BK + 1) : BK * GBM;
@@ -81,7 +84,7 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
-  float ra[2][4], rb[2][4];
+  float ra[NPS][4], rb[NPS][4];
   // 16-byte loads where the operand allows them; chunks past a ragged edge are zero
   // without a load, and a chunk straddling the edge loads clamped elements (no
   // per-element branches, so the loads of a step stay in flight together)
@@ -106,16 +109,16 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
   };
   auto gload = [&](int64_t k0) {
 #pragma unroll
-    for (int ps = 0; ps < 2; ++ps) {
+    for (int ps = 0; ps < NPS; ++ps) {
       if (AKC) {
-        int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 4;
+        int row = tid / TPR + RPP * ps, kc = (tid % TPR) * 4;
         load4(A, g.lda, i0 + row, g.M, k0 + kc, kend, avec, ra[ps]);
       } else {
         int kr = (tid >> 5) + 8 * ps, ic = (tid & 31) * 4;
         load4(A, g.lda, k0 + kr, kend, i0 + ic, g.M, avec, ra[ps]);
       }
       if (BKC) {
-        int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 4;
+        int row = tid / TPR + RPP * ps, kc = (tid % TPR) * 4;
         load4(B, g.ldb, j0 + row, g.N, k0 + kc, kend, bvec, rb[ps]);
       } else {
         int kr = (tid >> 5) + 8 * ps, jc = (tid & 31) * 4;
@@ -125,9 +128,9 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
   };
   auto sstore = [&](int buf) {
 #pragma unroll
-    for (int ps = 0; ps < 2; ++ps) {
+    for (int ps = 0; ps < NPS; ++ps) {
       if (AKC) {
-        int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 4;
+        int row = tid / TPR + RPP * ps, kc = (tid % TPR) * 4;
 #pragma unroll
         for (int e = 0; e < 4; ++e) As[buf][row * AST + kc + e] = ra[ps][e];
       } else {
@@ -135,7 +138,7 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
         *reinterpret_cast<float4*>(&As[buf][kr * AST + ic]) = make_float4(ra[ps][0], ra[ps][1], ra[ps][2], ra[ps][3]);
       }
       if (BKC) {
-        int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 4;
+        int row = tid / TPR + RPP * ps, kc = (tid % TPR) * 4;
 #pragma unroll
         for (int e = 0; e < 4; ++e) Bs[buf][row * BST + kc + e] = rb[ps][e];
       } else {
