@@ -564,7 +564,20 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, bool full, int x, int sl
     constexpr int NUP = JB * (JB + 1) / 2;
     int bu = -1, bv = -1;
     if ((int)threadIdx.x < NUP) upper_tile(threadIdx.x, JB, bu, bv);
-    const int vu = threadIdx.x & (JB - 1), vx = threadIdx.x / JB;  // V: pair vu, rows vx + JB h
+    // V in registers: thread (vx, vu) holds rows vx and vx + JB of column vu (x0)
+    // and of the second-block column of pair vu in the current inner round (x1).
+    // That column moves to the neighbouring pair each round, so after its rotation
+    // x1 is passed one lane down within the 32-lane half (vu -> vu - 1 mod JB).
+    static_assert(JB == 32, "a pair's lanes are one 32-lane half of a wave");
+    const int vu = threadIdx.x & (JB - 1), vx = threadIdx.x / JB;
+    const int vsrc = (int)(threadIdx.x & 32) | ((vu + 1) & (JB - 1));  // lane that holds the next column
+    double x0[2], x1[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int row = vx + JB * h;
+      x0[h] = row == vu ? 1.0 : 0.0;
+      x1[h] = row == JB + vu ? 1.0 : 0.0;
+    }
     for (int r = 0; r < JB; ++r) {
       if (threadIdx.x < JB) {
         const int u = threadIdx.x, q = JB + ((u + r) & (JB - 1));
@@ -599,17 +612,24 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, bool full, int x, int sl
       }
       {
         const double2 j = csn[vu];
-        const int q = JB + ((vu + r) & (JB - 1));
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
-          const int row = vx + JB * h;
-          const double x0 = V[row][vu], x1 = V[row][q];
-          V[row][vu] = j.x * x0 - j.y * x1;
-          V[row][q] = j.y * x0 + j.x * x1;
+          const double y0 = j.x * x0[h] - j.y * x1[h];
+          const double y1 = j.y * x0[h] + j.x * x1[h];
+          x0[h] = y0;
+          x1[h] = __shfl(y1, vsrc, 64);
         }
       }
       __syncthreads();
     }
+    // after JB rounds x1 is back at column JB + vu
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int row = vx + JB * h;
+      V[row][vu] = x0[h];
+      V[row][JB + vu] = x1[h];
+    }
+    __syncthreads();
   }
   // Order the subproblem's eigenpairs: the larger half goes to the block with the
   // lower index, so eigenvalues settle in descending order along the diagonal
