@@ -1545,12 +1545,24 @@ hipError_t launch_eig_batched(const EigBatch* descs, int count, int64_t Nmax, hi
 }
 
 // ============================== utilities ==============================
+// four consecutive columns per thread: one 16-byte load and one 8-byte store where
+// both operands allow it (vec), element by element otherwise
 __global__ void k_cast_f32_bf16(const float* __restrict__ in, int64_t ldi, uint16_t* __restrict__ out, int64_t ldo,
-                                int64_t rows, int64_t cols) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * cols) return;
-  int64_t i = idx / cols, j = idx % cols;
-  out[i * ldo + j] = f32_to_bf16_rne(in[i * ldi + j]);
+                                int64_t rows, int64_t cols, bool vec) {
+  const int64_t c4 = (cols + 3) / 4;
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= rows * c4) return;
+  const int64_t i = idx / c4, j = (idx - i * c4) * 4;
+  const float* src = in + i * ldi + j;
+  uint16_t* dst = out + i * ldo + j;
+  if (vec && j + 4 <= cols) {
+    const float4 v = *reinterpret_cast<const float4*>(src);
+    *reinterpret_cast<uint2*>(dst) =
+        make_uint2((uint32_t)f32_to_bf16_rne(v.x) | ((uint32_t)f32_to_bf16_rne(v.y) << 16),
+                   (uint32_t)f32_to_bf16_rne(v.z) | ((uint32_t)f32_to_bf16_rne(v.w) << 16));
+  } else {
+    for (int e = 0; e < 4 && j + e < cols; ++e) dst[e] = f32_to_bf16_rne(src[e]);
+  }
 }
 __global__ void k_cast_f64_f32(const double* __restrict__ in, int64_t ldi, float* __restrict__ out, int64_t ldo,
                                int64_t rows, int64_t cols) {
@@ -1576,7 +1588,8 @@ static inline dim3 g1(int64_t n) { return dim3((unsigned)((n + 255) / 256)); }
 hipError_t launch_cast_f32_bf16(const float* in, int64_t ldi, uint16_t* out, int64_t ldo, int64_t rows, int64_t cols,
                                 hipStream_t st) {
   if (rows * cols == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_cast_f32_bf16, g1(rows * cols), dim3(256), 0, st, in, ldi, out, ldo, rows, cols);
+  const bool vec = ((uintptr_t)in % 16 == 0) && (ldi % 4 == 0) && ((uintptr_t)out % 8 == 0) && (ldo % 4 == 0);
+  hipLaunchKernelGGL(k_cast_f32_bf16, g1(rows * ((cols + 3) / 4)), dim3(256), 0, st, in, ldi, out, ldo, rows, cols, vec);
   return hipGetLastError();
 }
 hipError_t launch_cast_f64_f32(const double* in, int64_t ldi, float* out, int64_t ldo, int64_t rows, int64_t cols,
@@ -1667,16 +1680,34 @@ __global__ void k_sign_decide(const float* __restrict__ U, int64_t ldu, int64_t 
   int64_t rr = 0xffffffffll - (int64_t)(keys[c] & 0xffffffffull);
   sgn[c] = (U[rr * ldu + c] < 0.f) ? -1.f : 1.f;
 }
+// four consecutive entries of a row per thread (16-byte accesses where aligned):
+// U's columns and Vt's rows take the sign of their column
 __global__ void k_sign_apply(float* __restrict__ U, int64_t ldu, int64_t m, int64_t k, float* __restrict__ Vt,
-                             int64_t ldvt, int64_t n, const float* __restrict__ sgn) {
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx < m * k) {
-    int64_t r = idx / k, c = idx % k;
-    U[r * ldu + c] *= sgn[c];
-  } else if (Vt && idx < m * k + k * n) {
-    int64_t e = idx - m * k;
-    int64_t c = e / n, j = e % n;
-    Vt[c * ldvt + j] *= sgn[c];
+                             int64_t ldvt, int64_t n, const float* __restrict__ sgn, bool uvec, bool vvec) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k4 = (k + 3) / 4, n4 = (n + 3) / 4;
+  if (idx < m * k4) {
+    const int64_t r = idx / k4, c = (idx - r * k4) * 4;
+    float* p = U + r * ldu + c;
+    if (uvec && c + 4 <= k) {
+      float4 v = *reinterpret_cast<float4*>(p);
+      v.x *= sgn[c]; v.y *= sgn[c + 1]; v.z *= sgn[c + 2]; v.w *= sgn[c + 3];
+      *reinterpret_cast<float4*>(p) = v;
+    } else {
+      for (int e = 0; e < 4 && c + e < k; ++e) p[e] *= sgn[c + e];
+    }
+  } else if (Vt && idx < m * k4 + k * n4) {
+    const int64_t e0 = idx - m * k4;
+    const int64_t c = e0 / n4, j = (e0 - c * n4) * 4;
+    float* p = Vt + c * ldvt + j;
+    const float sg = sgn[c];
+    if (vvec && j + 4 <= n) {
+      float4 v = *reinterpret_cast<float4*>(p);
+      v.x *= sg; v.y *= sg; v.z *= sg; v.w *= sg;
+      *reinterpret_cast<float4*>(p) = v;
+    } else {
+      for (int e = 0; e < 4 && j + e < n; ++e) p[e] *= sg;
+    }
   }
 }
 
@@ -1691,8 +1722,10 @@ hipError_t launch_sign_fix(float* U, int64_t ldu, int64_t m, int64_t k, float* V
   dim3 grid((unsigned)((k + 255) / 256), (unsigned)((m + rows_per - 1) / rows_per));
   hipLaunchKernelGGL(k_sign_key, grid, dim3(256), 0, st, U, ldu, m, k, keys, rows_per);
   hipLaunchKernelGGL(k_sign_decide, g1(k), dim3(256), 0, st, U, ldu, k, keys, sgn);
-  int64_t tot = m * k + (Vt ? k * n : 0);
-  hipLaunchKernelGGL(k_sign_apply, g1(tot), dim3(256), 0, st, U, ldu, m, k, Vt, ldvt, n, sgn);
+  const int64_t tot = m * ((k + 3) / 4) + (Vt ? k * ((n + 3) / 4) : 0);
+  const bool uvec = ((uintptr_t)U % 16 == 0) && (ldu % 4 == 0);
+  const bool vvec = Vt && ((uintptr_t)Vt % 16 == 0) && (ldvt % 4 == 0);
+  hipLaunchKernelGGL(k_sign_apply, g1(tot), dim3(256), 0, st, U, ldu, m, k, Vt, ldvt, n, sgn, uvec, vvec);
   return hipGetLastError();
 }
 
