@@ -257,34 +257,32 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
   }
   __syncthreads();
   // Inverse, blocked by 16: wave w inverts diagonal sub-block w, then the other
-  // blocks follow by block diagonals, X_IJ = -X_II (sum_{L=I+1..J} R_IL X_LJ)
-  // (the row buffers and M are free now: M holds the partial sums).
+  // blocks follow by block diagonals, X_IJ = -X_II (sum_{L=I+1..J} R_IL X_LJ).
+  // Block pair (I, I + d) of diagonal d is one wave's: the sum and the product
+  // with X_II are 16 x 16 x 16 MFMA products (v_mfma_f64_16x16x4f64; entries past
+  // nbk are zero in R and X, so whole blocks are summed).  The sum stays in the
+  // wave's accumulators, whose register kk is the B operand of the product's k-step
+  // kk, and the blocks a diagonal writes are not read within it.
   const int nsb = (nbk + SB - 1) / SB;
-  const int wave = threadIdx.x >> 6;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   if (wave < nsb) inv_sub(wave * SB, min(SB, nbk - wave * SB), R, Xs, rsv);
   __syncthreads();
+  const int lr = lane & 15, lk = lane >> 4;
   for (int d = 1; d < nsb; ++d) {
-    const int nblk = nsb - d;
-    for (int e = threadIdx.x; e < nblk * SB * SB; e += blockDim.x) {
-      const int I = e / (SB * SB), r = (e / SB) % SB, cc = e % SB, J = I + d;
-      const int i = I * SB + r, jj = J * SB + cc;
-      if (i >= nbk || jj >= nbk) continue;
-      double acc = 0.0;
-      const int lend = min((J + 1) * SB, nbk);
-#pragma unroll 8
-      for (int l = (I + 1) * SB; l < lend; ++l) acc = fma(R[i][l], Xs[l][jj], acc);  // reads batched, same order
-      M[i][jj] = acc;
-    }
-    __syncthreads();
-    for (int e = threadIdx.x; e < nblk * SB * SB; e += blockDim.x) {
-      const int I = e / (SB * SB), r = (e / SB) % SB, cc = e % SB, J = I + d;
-      const int i = I * SB + r, jj = J * SB + cc;
-      if (i >= nbk || jj >= nbk) continue;
-      double acc = 0.0;
-      const int lend = min((I + 1) * SB, nbk);
-#pragma unroll 8
-      for (int l = i; l < lend; ++l) acc = fma(Xs[i][l], M[l][jj], acc);
-      Xs[i][jj] = -acc;
+    const int I = wave, J = wave + d;
+    if (J < nsb) {  // wave-uniform
+      f64x4 m = f64x4{0, 0, 0, 0};
+      for (int L = I + 1; L <= J; ++L)
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+          m = __builtin_amdgcn_mfma_f64_16x16x4f64(R[I * SB + lr][L * SB + 4 * kk + lk],
+                                                   Xs[L * SB + 4 * kk + lk][J * SB + lr], m, 0, 0, 0);
+      f64x4 x = f64x4{0, 0, 0, 0};
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk)
+        x = __builtin_amdgcn_mfma_f64_16x16x4f64(Xs[I * SB + lr][I * SB + 4 * kk + lk], m[kk], x, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Xs[I * SB + lk + 4 * r][J * SB + lr] = -x[r];
     }
     __syncthreads();
   }
