@@ -5,6 +5,9 @@ the fastest per shape bucket as a rule table (JSON) that rf_set_gemm_rules reads
 
     python -m paper_2605_09755_amd.autotune [--out PATH] [--quick]
 
+The BF16 rules also serve FP32-stored A rounded to BF16 on load; for the Q^T A
+shapes, whose A is FP32 in the mixed form, the BF16 candidates are timed with
+FP32 A (the other shapes' BF16 operands are BF16).
 A rule covers the bucket obtained by rounding the tuned shape up to powers of
 two; rules are ordered from the smallest bucket up, so the first match (the
 library's rule) is the tightest bucket that contains a product.  The binding
@@ -47,10 +50,10 @@ def _pow2_up(x):
     return p
 
 
-def _operands(M, N, K, a_kc, b_kc, dtype, dev):
+def _operands(M, N, K, a_kc, b_kc, dtype, dev, a_dtype=None):
     g = torch.Generator(device=dev)
     g.manual_seed(M * 31 + N * 7 + K)
-    A = torch.randn((M, K) if a_kc else (K, M), generator=g, device=dev).to(dtype)
+    A = torch.randn((M, K) if a_kc else (K, M), generator=g, device=dev).to(a_dtype or dtype)
     B = torch.randn((N, K) if b_kc else (K, N), generator=g, device=dev).to(dtype)
     return A, B
 
@@ -72,12 +75,13 @@ def candidates(dtype_code):
     return [(t, s) for t in tiles for s in (1, 2, 4, 8, 16)]
 
 
-def tune(shapes, reps=3, dev="cuda:0", log=print):
+def tune(shapes, reps=10, dev="cuda:0", log=print):
     lib()
     rules = []
     for dtype, code in ((torch.float32, 0), (torch.bfloat16, 2)):
         for name, M, N, K, a_kc, b_kc in shapes:
-            A, B = _operands(M, N, K, a_kc, b_kc, dtype, dev)
+            a_dtype = torch.float32 if (code == 2 and name.startswith("qta_")) else None
+            A, B = _operands(M, N, K, a_kc, b_kc, dtype, dev, a_dtype)
             res = {}
             for tile, split in candidates(code):
                 set_gemm_rules([(code, tile, split, MAXI, MAXI, MAXI)])
@@ -100,7 +104,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=DEFAULT_OUT)
     ap.add_argument("--quick", action="store_true", help="two small shapes only")
-    ap.add_argument("--reps", type=int, default=3)
+    ap.add_argument("--reps", type=int, default=10)
     args = ap.parse_args()
     t0 = time.time()
     rules = tune(QUICK if args.quick else SHAPES, args.reps)

@@ -23,6 +23,26 @@ namespace rf {
 
 constexpr int GBM = 128, GBN = 128;
 
+// Operands are read through global-memory pointers: the grouped kernels take their
+// arguments from a device array, and pointers loaded from memory otherwise compile
+// to flat accesses, whose waits also cover the LDS traffic of the k-step.
+// (the host pass, which never runs these bodies, sees plain pointers)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = T __attribute__((address_space(1)))*;
+#else
+template <class T>
+using gptr = T*;
+#endif
+template <class T>
+RF_DEV gptr<const T> as_global(const void* p) {
+  return (gptr<const T>)p;
+}
+template <class T>
+RF_DEV gptr<T> as_global_w(void* p) {
+  return (gptr<T>)p;
+}
+
 RF_DEV void tile_coords(int id, int ntm, int ntn, int& tm, int& tn) {
   // XCD-aware order: consecutive workgroup ids go to different XCDs (id % 8);
   // give each XCD whole M-panels and walk their N tiles back to back so the
@@ -40,12 +60,12 @@ RF_DEV void tile_coords(int id, int ntm, int ntn, int& tm, int& tn) {
 RF_DEV void store_out(const GemmArgs& g, int64_t i, int64_t j, float v) {
   if (i >= g.M || j >= g.N) return;
   v *= g.alpha;
-  if (g.colscale) v *= g.colscale[j];
+  if (g.colscale) v *= as_global<float>(g.colscale)[j];
   if (g.c_bf16) {
-    uint16_t* C = reinterpret_cast<uint16_t*>(g.C);
+    const gptr<uint16_t> C = as_global_w<uint16_t>(g.C);
     C[g.c_trans ? j * g.ldc + i : i * g.ldc + j] = f32_to_bf16_rne(v);
   } else {
-    float* C = reinterpret_cast<float*>(g.C);
+    const gptr<float> C = as_global_w<float>(g.C);
     C[g.c_trans ? j * g.ldc + i : i * g.ldc + j] = v;
   }
 }
@@ -73,8 +93,8 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
   int64_t kbeg = (int64_t)split * g.kps;
   int64_t kend = min(g.K, kbeg + g.kps);
   if (g.b_upper) kend = min(kend, j0 + GBN);
-  const float* A = reinterpret_cast<const float*>(g.A);
-  const float* B = reinterpret_cast<const float*>(g.B);
+  const gptr<const float> A = as_global<float>(g.A);
+  const gptr<const float> B = as_global<float>(g.B);
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -85,25 +105,32 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.f;
 
   float ra[NPS][4], rb[NPS][4];
-  // 16-byte loads where the operand allows them; chunks past a ragged edge are zero
-  // without a load, and a chunk straddling the edge loads clamped elements (no
-  // per-element branches, so the loads of a step stay in flight together)
-  const bool avec = ((((uintptr_t)A) & 15) == 0) && (g.lda % 4 == 0);
-  const bool bvec = ((((uintptr_t)B) & 15) == 0) && (g.ldb % 4 == 0);
+  // 16-byte loads when the operand allows them for every chunk (aligned, and its
+  // contiguous extent a multiple of 4, so a chunk is wholly inside or wholly past
+  // the edge, and one past the edge is zero without a load); otherwise clamped
+  // element loads, zero past the edge.  The choice is uniform over the launch: a
+  // per-chunk mix of the two forms made the compiler wait for every outstanding
+  // load before each 16-byte one (both write the same registers).
+  const int64_t akx = AKC ? g.K : g.M, bkx = BKC ? g.K : g.N;  // contiguous extents
+  const bool avec = ((((uintptr_t)A) & 15) == 0) && (g.lda % 4 == 0) && (akx % 4 == 0) && (g.kps % 4 == 0);
+  const bool bvec = ((((uintptr_t)B) & 15) == 0) && (g.ldb % 4 == 0) && (bkx % 4 == 0) && (g.kps % 4 == 0);
   // four consecutive elements of P along the contiguous index (x0 .. x0+3 < xmax)
   // of line y (< ymax: the other index), into d
-  auto load4 = [&](const float* P, int64_t ld, int64_t y, int64_t ymax, int64_t x0, int64_t xmax, bool vec,
+  auto load4 = [&](gptr<const float> P, int64_t ld, int64_t y, int64_t ymax, int64_t x0, int64_t xmax, bool vec,
                    float* d) {
-    if (vec && y < ymax && x0 + 4 <= xmax) {
-      const float4 v = *reinterpret_cast<const float4*>(P + y * ld + x0);
-      d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
-    } else if (y >= ymax || x0 >= xmax) {
-      d[0] = d[1] = d[2] = d[3] = 0.f;
+    if (vec) {
+      if (y < ymax && x0 < xmax) {
+        const float4 v = *reinterpret_cast<gptr<const float4>>(P + y * ld + x0);
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+      } else {
+        d[0] = d[1] = d[2] = d[3] = 0.f;
+      }
     } else {
+      const int64_t yc = min(y, ymax - 1);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        const float x = P[y * ld + min(x0 + e, xmax - 1)];
-        d[e] = x0 + e < xmax ? x : 0.f;
+        const float x = P[yc * ld + min(x0 + e, xmax - 1)];
+        d[e] = (y < ymax && x0 + e < xmax) ? x : 0.f;
       }
     }
   };
@@ -189,7 +216,7 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
         int64_t i = i0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         int64_t j = j0 + wn * 64 + b * 32 + (lane & 31);
         if (g.partial) {
-          if (i < g.M && j < g.N) g.partial[((int64_t)split * g.M + i) * g.N + j] = acc[a][b][r];
+          if (i < g.M && j < g.N) as_global_w<float>(g.partial)[((int64_t)split * g.M + i) * g.N + j] = acc[a][b][r];
         } else {
           store_out(g, i, j, acc[a][b][r]);
         }
@@ -219,8 +246,8 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
   int64_t kbeg = (int64_t)split * g.kps;
   int64_t kend = min(g.K, kbeg + g.kps);
   if (g.b_upper) kend = min(kend, j0 + GBN);
-  const uint16_t* A = reinterpret_cast<const uint16_t*>(g.A);
-  const uint16_t* B = reinterpret_cast<const uint16_t*>(g.B);
+  const gptr<const uint16_t> A = as_global<uint16_t>(g.A);
+  const gptr<const uint16_t> B = as_global<uint16_t>(g.B);
 
   f32x16 acc[2][2];
 #pragma unroll
@@ -233,43 +260,56 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
   // staging registers: 2 x uint4 per operand (16 bf16)
   uint4 sa[2], sb[2];
 
+  // Loads take one form per launch: vector loads when every chunk is either wholly
+  // inside the operand or wholly past its edge (aligned, contiguous extent a multiple
+  // of the chunk; a chunk past the edge is zero without a load), else clamped
+  // element loads, all issued before they are combined.  (Mixing the two forms per
+  // chunk made the compiler wait for all outstanding loads at each chunk.)
   // K layout: 128 rows x 32 k; thread: row (tid>>2)+64ps, k chunk (tid&3)*8.
-  auto load_kc = [&](const uint16_t* P, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, uint4* dst, bool vec) {
+  auto load_kc = [&](gptr<const uint16_t> P, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, uint4* dst, bool vec) {
 #pragma unroll
     for (int ps = 0; ps < 2; ++ps) {
       int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 8;
       int64_t r = r0 + row, k = k0 + kc;
-      if (vec && r < rmax && k + 8 <= kend) {
-        dst[ps] = *reinterpret_cast<const uint4*>(P + r * ld + k);
-      } else if (r >= rmax || k >= kend) {
-        dst[ps] = make_uint4(0u, 0u, 0u, 0u);  // outside the operand: no load
+      if (vec) {
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (r < rmax && k < kend) v = *reinterpret_cast<gptr<const uint4>>(P + r * ld + k);
+        dst[ps] = v;
       } else {
-        // straddles the k edge (or unaligned): clamped element loads, zero past the edge
+        const int64_t rc = min(r, rmax - 1);
         uint32_t h[8];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const uint32_t x = P[r * ld + min(k + e, kend - 1)];
-          h[e] = k + e < kend ? x : 0u;
-        }
+        for (int e = 0; e < 8; ++e) h[e] = P[rc * ld + min(k + e, kend - 1)];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) h[e] = (r < rmax && k + e < kend) ? h[e] : 0u;
         dst[ps] = make_uint4(h[0] | (h[1] << 16), h[2] | (h[3] << 16), h[4] | (h[5] << 16), h[6] | (h[7] << 16));
       }
     }
   };
   // T layout: element (r, k) at P[k*ld + r].  Wave w covers k rows 8w..8w+7,
   // lane covers r pair (2 lane, 2 lane + 1); produces two k-vectors of 8.
-  auto load_tc = [&](const uint16_t* P, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, uint4* dst, bool vec) {
+  auto load_tc = [&](gptr<const uint16_t> P, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, uint4* dst, bool vec) {
     uint32_t w[8];
     int64_t r = r0 + 2 * lane;
+    if (vec) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      int64_t k = k0 + 8 * wave + e;
-      if (vec && k < kend && r + 1 < rmax) {
-        w[e] = *reinterpret_cast<const uint32_t*>(P + k * ld + r);
-      } else if (k >= kend || r >= rmax) {
-        w[e] = 0u;
-      } else {
-        const uint32_t lo = P[k * ld + r], hi = P[k * ld + min(r + 1, rmax - 1)];
-        w[e] = lo | ((r + 1 < rmax ? hi : 0u) << 16);
+      for (int e = 0; e < 8; ++e) {
+        int64_t k = k0 + 8 * wave + e;
+        w[e] = (k < kend && r < rmax) ? *reinterpret_cast<gptr<const uint32_t>>(P + k * ld + r) : 0u;
+      }
+    } else {
+      const int64_t r0c = min(r, rmax - 1), r1c = min(r + 1, rmax - 1);
+      uint32_t lo[8], hi[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t kc = min(k0 + 8 * wave + e, kend - 1);
+        lo[e] = P[kc * ld + r0c];
+        hi[e] = P[kc * ld + r1c];
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool kin = k0 + 8 * wave + e < kend;
+        w[e] = (kin && r < rmax ? lo[e] : 0u) | ((kin && r + 1 < rmax ? hi[e] : 0u) << 16);
       }
     }
     dst[0] = make_uint4(pack_lo(w[0], w[1]), pack_lo(w[2], w[3]), pack_lo(w[4], w[5]), pack_lo(w[6], w[7]));
@@ -287,26 +327,26 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
     *reinterpret_cast<uint4*>(S + (2 * lane + 1) * ST + 8 * wave) = src[1];
   };
   // FP32 A, same element positions as load_kc / load_tc, rounded to BF16
-  const float* Af = reinterpret_cast<const float*>(g.A);
+  const gptr<const float> Af = as_global<float>(g.A);
   auto load_kc_f32 = [&](int64_t r0, int64_t rmax, int64_t k0, uint4* dst, bool vec) {
 #pragma unroll
     for (int ps = 0; ps < 2; ++ps) {
       int row = (tid >> 2) + 64 * ps, kc = (tid & 3) * 8;
       int64_t r = r0 + row, k = k0 + kc;
       float t[8];
-      if (vec && r < rmax && k + 8 <= kend) {
-        const float4 x0 = *reinterpret_cast<const float4*>(Af + r * g.lda + k);
-        const float4 x1 = *reinterpret_cast<const float4*>(Af + r * g.lda + k + 4);
-        t[0] = x0.x; t[1] = x0.y; t[2] = x0.z; t[3] = x0.w; t[4] = x1.x; t[5] = x1.y; t[6] = x1.z; t[7] = x1.w;
-      } else if (r >= rmax || k >= kend) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) t[e] = 0.f;
-      } else {
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-          const float x = Af[r * g.lda + min(k + e, kend - 1)];
-          t[e] = k + e < kend ? x : 0.f;
+      if (vec) {
+        float4 x0 = make_float4(0.f, 0.f, 0.f, 0.f), x1 = x0;
+        if (r < rmax && k < kend) {
+          x0 = *reinterpret_cast<gptr<const float4>>(Af + r * g.lda + k);
+          x1 = *reinterpret_cast<gptr<const float4>>(Af + r * g.lda + k + 4);
         }
+        t[0] = x0.x; t[1] = x0.y; t[2] = x0.z; t[3] = x0.w; t[4] = x1.x; t[5] = x1.y; t[6] = x1.z; t[7] = x1.w;
+      } else {
+        const int64_t rc = min(r, rmax - 1);
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = Af[rc * g.lda + min(k + e, kend - 1)];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) t[e] = (r < rmax && k + e < kend) ? t[e] : 0.f;
       }
       dst[ps] = make_uint4(pack2_bf16(t[0], t[1]), pack2_bf16(t[2], t[3]), pack2_bf16(t[4], t[5]),
                            pack2_bf16(t[6], t[7]));
@@ -315,30 +355,44 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
   auto load_tc_f32 = [&](int64_t r0, int64_t rmax, int64_t k0, uint4* dst, bool vec) {
     uint32_t w[8];
     int64_t r = r0 + 2 * lane;
+    float lo[8], hi[8];
+    if (vec) {
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-      int64_t k = k0 + 8 * wave + e;
-      float lo, hi;
-      if (vec && k < kend && r + 1 < rmax) {
-        const float2 x = *reinterpret_cast<const float2*>(Af + k * g.lda + r);
-        lo = x.x; hi = x.y;
-      } else if (k >= kend || r >= rmax) {
-        lo = hi = 0.f;
-      } else {
-        lo = Af[k * g.lda + r];
-        const float x = Af[k * g.lda + min(r + 1, rmax - 1)];
-        hi = r + 1 < rmax ? x : 0.f;
+      for (int e = 0; e < 8; ++e) {
+        int64_t k = k0 + 8 * wave + e;
+        float2 x = make_float2(0.f, 0.f);
+        if (k < kend && r < rmax) x = *reinterpret_cast<gptr<const float2>>(Af + k * g.lda + r);
+        lo[e] = x.x; hi[e] = x.y;
       }
-      w[e] = pack2_bf16(lo, hi);
+    } else {
+      const int64_t r0c = min(r, rmax - 1), r1c = min(r + 1, rmax - 1);
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t kc = min(k0 + 8 * wave + e, kend - 1);
+        lo[e] = Af[kc * g.lda + r0c];
+        hi[e] = Af[kc * g.lda + r1c];
+      }
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const bool kin = k0 + 8 * wave + e < kend;
+        lo[e] = (kin && r < rmax) ? lo[e] : 0.f;
+        hi[e] = (kin && r + 1 < rmax) ? hi[e] : 0.f;
+      }
     }
+#pragma unroll
+    for (int e = 0; e < 8; ++e) w[e] = pack2_bf16(lo[e], hi[e]);
     dst[0] = make_uint4(pack_lo(w[0], w[1]), pack_lo(w[2], w[3]), pack_lo(w[4], w[5]), pack_lo(w[6], w[7]));
     dst[1] = make_uint4(pack_hi(w[0], w[1]), pack_hi(w[2], w[3]), pack_hi(w[4], w[5]), pack_hi(w[6], w[7]));
   };
-  const bool avec = AF32 ? (AKC ? ((((uintptr_t)Af) & 15) == 0 && (g.lda & 3) == 0)
-                                : ((((uintptr_t)Af) & 7) == 0 && (g.lda & 1) == 0))
-                         : (AKC ? ((((uintptr_t)A) & 15) == 0 && (g.lda & 7) == 0)
-                                : ((((uintptr_t)A) & 3) == 0 && (g.lda & 1) == 0));
-  const bool bvec = BKC ? ((((uintptr_t)B) & 15) == 0 && (g.ldb & 7) == 0) : ((((uintptr_t)B) & 3) == 0 && (g.ldb & 1) == 0);
+  // (k chunks are 8 wide and split parts start on multiples of 32, so a K that is a
+  // multiple of 8 keeps every k chunk whole; m/n pairs need an even extent)
+  const bool kwhole = (g.K % 8 == 0) && (g.kps % 8 == 0);
+  const bool avec = AF32 ? (AKC ? ((((uintptr_t)Af) & 15) == 0 && (g.lda & 3) == 0 && kwhole)
+                                : ((((uintptr_t)Af) & 7) == 0 && (g.lda & 1) == 0 && (g.M % 2 == 0)))
+                         : (AKC ? ((((uintptr_t)A) & 15) == 0 && (g.lda & 7) == 0 && kwhole)
+                                : ((((uintptr_t)A) & 3) == 0 && (g.lda & 1) == 0 && (g.M % 2 == 0)));
+  const bool bvec = BKC ? ((((uintptr_t)B) & 15) == 0 && (g.ldb & 7) == 0 && kwhole)
+                        : ((((uintptr_t)B) & 3) == 0 && (g.ldb & 1) == 0 && (g.N % 2 == 0));
   auto gload = [&](int64_t k0) {
     if constexpr (AF32) {
       if (AKC) load_kc_f32(i0, g.M, k0, sa, avec); else load_tc_f32(i0, g.M, k0, sa, avec);
@@ -393,7 +447,7 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
         int64_t i = i0 + wm * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         int64_t j = j0 + wn * 64 + b * 32 + (lane & 31);
         if (g.partial) {
-          if (i < g.M && j < g.N) g.partial[((int64_t)split * g.M + i) * g.N + j] = acc[a][b][r];
+          if (i < g.M && j < g.N) as_global_w<float>(g.partial)[((int64_t)split * g.M + i) * g.N + j] = acc[a][b][r];
         } else {
           store_out(g, i, j, acc[a][b][r]);
         }
@@ -476,10 +530,10 @@ struct BigStage {
         return KC ? r * ld + min(k + e, kend - 1) : k * ld + min(r + e, rmax - 1);
       };
       if constexpr (F8) {
-        const uint8_t* P = reinterpret_cast<const uint8_t*>(P_);
-        sc[q] = any ? scales[(k >> 7) * ldsc + (r >> 7)] : 0.f;
+        const gptr<const uint8_t> P = as_global<uint8_t>(P_);
+        sc[q] = any ? as_global<float>(scales)[(k >> 7) * ldsc + (r >> 7)] : 0.f;
         if (vec && full) {
-          b8[q] = *reinterpret_cast<const uint2*>(P + k * ld + r);
+          b8[q] = *reinterpret_cast<gptr<const uint2>>(P + k * ld + r);
         } else if (!any) {
           b8[q] = make_uint2(0u, 0u);
         } else {
@@ -492,11 +546,11 @@ struct BigStage {
           b8[q] = make_uint2(w[0], w[1]);
         }
       } else if constexpr (F32) {
-        const float* P = reinterpret_cast<const float*>(P_);
+        const gptr<const float> P = as_global<float>(P_);
         if (vec && full) {
-          const float* src = KC ? P + r * ld + k : P + k * ld + r;
-          f[q][0] = *reinterpret_cast<const float4*>(src);
-          f[q][1] = *reinterpret_cast<const float4*>(src + 4);
+          const gptr<const float> src = KC ? P + r * ld + k : P + k * ld + r;
+          f[q][0] = *reinterpret_cast<gptr<const float4>>(src);
+          f[q][1] = *reinterpret_cast<gptr<const float4>>(src + 4);
         } else if (!any) {
           f[q][0] = f[q][1] = make_float4(0.f, 0.f, 0.f, 0.f);
         } else {
@@ -510,9 +564,9 @@ struct BigStage {
           f[q][1] = make_float4(t[4], t[5], t[6], t[7]);
         }
       } else {
-        const uint16_t* P = reinterpret_cast<const uint16_t*>(P_);
+        const gptr<const uint16_t> P = as_global<uint16_t>(P_);
         if (vec && full) {
-          v[q] = *reinterpret_cast<const uint4*>(KC ? P + r * ld + k : P + k * ld + r);
+          v[q] = *reinterpret_cast<gptr<const uint4>>(KC ? P + r * ld + k : P + k * ld + r);
         } else if (!any) {
           v[q] = make_uint4(0u, 0u, 0u, 0u);
         } else {
@@ -566,7 +620,7 @@ RF_DEV uint32_t big_touch(const void* P_, int64_t ld, int64_t r0, int64_t rmax, 
   const int row = tid / lpr, off = (tid % lpr) * (128 / es);
   const int64_t r = KC ? r0 + row : r0 + off, k = KC ? k0 + off : k0 + row;
   if (r >= rmax || k >= kend) return 0u;
-  const uint8_t* P = reinterpret_cast<const uint8_t*>(P_);
+  const gptr<const uint8_t> P = as_global<uint8_t>(P_);
   return P[(KC ? r * ld + k : k * ld + r) * es];
 }
 
@@ -594,7 +648,7 @@ RF_DEV void big_epilogue(const GemmArgs& g, f32x16 (&acc)[4][NB], int64_t i0, in
       const int64_t i = i0 + (rr >> 5) * 128 + 32 * a + (rr & 31), j = j0 + cc;
       const float v = St[rr * SLD + cc];
       if (g.partial) {
-        if (i < g.M && j < g.N) g.partial[((int64_t)split * g.M + i) * g.N + j] = v;
+        if (i < g.M && j < g.N) as_global_w<float>(g.partial)[((int64_t)split * g.M + i) * g.N + j] = v;
       } else {
         store_out(g, i, j, v);
       }

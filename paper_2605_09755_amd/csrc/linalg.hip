@@ -1633,15 +1633,17 @@ RF_DEV void refill_entry(float* __restrict__ X, int64_t ldx, int64_t rows, int64
 __global__ void k_refill(float* __restrict__ X, int64_t ldx, int64_t rows, int64_t k, const int* __restrict__ flags,
                          const int* count, const double* __restrict__ d0, uint64_t seed) {
   if (*count == 0) return;
-  int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= rows * k) return;
-  refill_entry(X, ldx, rows, k, flags, d0, seed, 0u, idx);
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < rows * k;
+       idx += (int64_t)gridDim.x * blockDim.x)
+    refill_entry(X, ldx, rows, k, flags, d0, seed, 0u, idx);
 }
 
 hipError_t launch_refill(float* X, int64_t ldx, int64_t rows, int64_t k, const int* flags, const int* count,
                          const double* d0, uint64_t seed, hipStream_t st) {
   if (rows * k == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_refill, g1(rows * k), dim3(256), 0, st, X, ldx, rows, k, flags, count, d0, seed);
+  // a bounded grid: usually nothing is flagged and every workgroup returns at once
+  const dim3 grid((unsigned)std::min<int64_t>((rows * k + 255) / 256, 4096));
+  hipLaunchKernelGGL(k_refill, grid, dim3(256), 0, st, X, ldx, rows, k, flags, count, d0, seed);
   return hipGetLastError();
 }
 
