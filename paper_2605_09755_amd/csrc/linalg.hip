@@ -804,8 +804,11 @@ RF_DEV void eig_prologue(const EigWork& w, const double* __restrict__ Gs, int ro
   constexpr int JS = 2 * JB, LD = JS + 1, LH = JB + 1;
   static_assert(JS == 64, "the MFMA tile product is written for 64 x 64 subproblems");
   double(*M)[LD] = reinterpret_cast<double(*)[LD]>(sm);
-  double(*TT[2])[LD] = {reinterpret_cast<double(*)[LD]>(sm + JS * LD), reinterpret_cast<double(*)[LD]>(sm + 2 * JS * LD)};
-  double(*WW[2])[LH] = {reinterpret_cast<double(*)[LH]>(sm + JS * LD), reinterpret_cast<double(*)[LH]>(sm + 2 * JS * LD)};
+  // slot s of the tiles (and of the W over each) computed from sm, not picked
+  // from an array of pointers: a pointer array indexed at run time loses the LDS
+  // address space and its accesses compile to flat ones
+  auto TT = [&](int slot) { return reinterpret_cast<double(*)[LD]>(sm + (1 + slot) * JS * LD); };
+  auto WW = [&](int slot) { return reinterpret_cast<double(*)[LH]>(sm + (1 + slot) * JS * LD); };
   double(*XA)[LH] = reinterpret_cast<double(*)[LH]>(sm + 3 * JS * LD);
   double(*XB)[LH] = reinterpret_cast<double(*)[LH]>(sm + 3 * JS * LD + JS * LH);
   const int p = w.p, np = 2 * p, rp = round - 1;
@@ -844,8 +847,8 @@ RF_DEV void eig_prologue(const EigWork& w, const double* __restrict__ Gs, int ro
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
       const int e = (int)threadIdx.x + h * 1024, r = e >> 5, c = (e & 31) * 2;
-      TT[slot][r][c] = tl[t][h].x;
-      TT[slot][r][c + 1] = tl[t][h].y;
+      TT(slot)[r][c] = tl[t][h].x;
+      TT(slot)[r][c + 1] = tl[t][h].y;
     }
   };
   stage(0, 0);
@@ -863,11 +866,11 @@ RF_DEV void eig_prologue(const EigWork& w, const double* __restrict__ Gs, int ro
     if (!idy) {
 #pragma unroll
       for (int kk = 0; kk < 16; ++kk)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(TT[s][bi * 16 + (lane & 15)][4 * kk + (lane >> 4)],
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(TT(s)[bi * 16 + (lane & 15)][4 * kk + (lane >> 4)],
                                                    XY[4 * kk + (lane >> 4)][16 * j + (lane & 15)], acc, 0, 0, 0);
     } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) acc[r] = TT[s][bi * 16 + (lane >> 4) + 4 * r][JB * hy + 16 * j + (lane & 15)];
+      for (int r = 0; r < 4; ++r) acc[r] = TT(s)[bi * 16 + (lane >> 4) + 4 * r][JB * hy + 16 * j + (lane & 15)];
     }
     return acc;
   };
@@ -878,10 +881,10 @@ RF_DEV void eig_prologue(const EigWork& w, const double* __restrict__ Gs, int ro
 #pragma unroll
       for (int kk = 0; kk < 16; ++kk)
         c = __builtin_amdgcn_mfma_f64_16x16x4f64(XX[4 * kk + (lane >> 4)][16 * ci + (lane & 15)],
-                                                 WW[s][4 * kk + (lane >> 4)][16 * cj + (lane & 15)], c, 0, 0, 0);
+                                                 WW(s)[4 * kk + (lane >> 4)][16 * cj + (lane & 15)], c, 0, 0, 0);
     } else {
 #pragma unroll
-      for (int r = 0; r < 4; ++r) c[r] = WW[s][JB * hx + 16 * ci + (lane >> 4) + 4 * r][16 * cj + (lane & 15)];
+      for (int r = 0; r < 4; ++r) c[r] = WW(s)[JB * hx + 16 * ci + (lane >> 4) + 4 * r][16 * cj + (lane & 15)];
     }
     return c;
   };
@@ -891,7 +894,7 @@ RF_DEV void eig_prologue(const EigWork& w, const double* __restrict__ Gs, int ro
     const f64x4 acc = wblock(t, bi, j, t ? XB : XA, t ? idb : ida, t ? hQ : hP);
     __syncthreads();
 #pragma unroll
-    for (int r = 0; r < 4; ++r) WW[t][bi * 16 + (lane >> 4) + 4 * r][16 * j + (lane & 15)] = acc[r];
+    for (int r = 0; r < 4; ++r) WW(t)[bi * 16 + (lane >> 4) + 4 * r][16 * j + (lane & 15)] = acc[r];
   }
   __syncthreads();
   // tiles 0 and 1: C (waves 0-7: tile wv >> 2, block ((wv >> 1) & 1, wv & 1)) into the diagonal quadrants of M
@@ -924,7 +927,7 @@ RF_DEV void eig_prologue(const EigWork& w, const double* __restrict__ Gs, int ro
     __syncthreads();
     if (wv < 8)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) WW[0][bi * 16 + (lane >> 4) + 4 * r][16 * j + (lane & 15)] = acc[r];
+      for (int r = 0; r < 4; ++r) WW(0)[bi * 16 + (lane >> 4) + 4 * r][16 * j + (lane & 15)] = acc[r];
     __syncthreads();
     if (wv < 4) {
       const int ci = (wv >> 1) & 1, cj = wv & 1;
