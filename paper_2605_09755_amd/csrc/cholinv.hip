@@ -63,7 +63,7 @@ RF_DEV void wait_at_least(int* ctr, int target, int* err) {
 }
 
 // 256 threads; all 16 loads of a thread are issued before the LDS stores.
-RF_DEV void load_tile(double (*T)[TLD], const double* P, int64_t ld, int64_t r0, int64_t c0, int64_t N) {
+RF_DEV void load_tile(double (*T)[TLD], gptr<const double> P, int64_t ld, int64_t r0, int64_t c0, int64_t N) {
   constexpr int NT = 256, IT = TB * TB / NT;
   const int c = threadIdx.x % TB, rr = threadIdx.x / TB;
   double v[IT];
@@ -128,8 +128,8 @@ RF_DEV double rsqrt_f64(double d) {
 
 RF_DEV void put_x(const CholInvArgs& a, int64_t r, int64_t c, double v) {
   if (r >= a.N || c >= a.N) return;
-  a.X64[r * a.ldx64 + c] = v;
-  if (a.X32) a.X32[r * a.ldx32 + c] = (float)v;
+  as_global_w<double>(a.X64)[r * a.ldx64 + c] = v;
+  if (a.X32) as_global_w<float>(a.X32)[r * a.ldx32 + c] = (float)v;
 }
 
 // Orders one wave's LDS accesses between the steps of a wave-synchronous loop.
@@ -185,14 +185,14 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
   double* rsc = &M[0][0];   // M's LDS is scratch here: 1 / sqrt(g) per column (0 when dependent),
   double* rsv = rsc + TB;   // 1 / R_cc for the inverse, pivot floors
   double* floor_ = rsv + TB;
-  if (threadIdx.x < nbk) floor_[threadIdx.x] = a.tol * a.d0[b0 + threadIdx.x];
+  if (threadIdx.x < nbk) floor_[threadIdx.x] = a.tol * as_global<double>(a.d0)[b0 + threadIdx.x];
   double m[4][4];
 #pragma unroll
   for (int p = 0; p < 4; ++p)
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int i = ty + 16 * p, j = tx + 16 * q;
-      m[p][q] = (i < nbk && j < nbk) ? a.G[(b0 + i) * a.ld + b0 + j] : 0.0;
+      m[p][q] = (i < nbk && j < nbk) ? as_global<double>(a.G)[(b0 + i) * a.ld + b0 + j] : 0.0;
     }
   for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
     R[e / TB][e % TB] = 0.0;
@@ -218,7 +218,7 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
     if (threadIdx.x == 0) {
       if (!fin) *a.nonfinite = 1;
       if (bad) {
-        a.flags[b0 + c] = 1;
+        as_global_w<int>(a.flags)[b0 + c] = 1;
         atomicAdd(a.count, 1);
       }
       rsc[c] = rs;
@@ -289,7 +289,7 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
   for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
     const int r = e / TB, c = e % TB;
     if (r < nbk && c < nbk) {
-      a.G[(b0 + r) * a.ld + b0 + c] = (c >= r) ? R[r][c] : 0.0;
+      as_global_w<double>(a.G)[(b0 + r) * a.ld + b0 + c] = (c >= r) ? R[r][c] : 0.0;
       put_x(a, b0 + r, b0 + c, (c >= r) ? Xs[r][c] : 0.0);
     }
   }
@@ -298,8 +298,8 @@ RF_DEV void task_diag(const CholInvArgs& a, int kb, double (*M)[TLD], double (*R
 // B(kb, j): G_kb,j <- X_kk^T G_kb,j, rows of dependent columns cleared.
 RF_DEV void task_panel(const CholInvArgs& a, int kb, int jb, double (*P)[TLD], double (*Q)[TLD]) {
   const int64_t b0 = (int64_t)kb * TB, c0 = (int64_t)jb * TB;
-  load_tile(P, a.X64, a.ldx64, b0, b0, a.N);
-  load_tile(Q, a.G, a.ld, b0, c0, a.N);
+  load_tile(P, as_global<double>(a.X64), a.ldx64, b0, b0, a.N);
+  load_tile(Q, as_global<double>(a.G), a.ld, b0, c0, a.N);
   __syncthreads();
   f64x4 acc[2][2];
   acc_zero(acc);
@@ -311,7 +311,7 @@ RF_DEV void task_panel(const CholInvArgs& a, int kb, int jb, double (*P)[TLD], d
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t r = b0 + tile_row(i, q), c = c0 + tile_col(j);
-        if (r < a.N && c < a.N) a.G[r * a.ld + c] = a.flags[r] ? 0.0 : acc[i][j][q];
+        if (r < a.N && c < a.N) as_global_w<double>(a.G)[r * a.ld + c] = as_global<int>(a.flags)[r] ? 0.0 : acc[i][j][q];
       }
 }
 
@@ -323,8 +323,8 @@ RF_DEV void task_xcol(const CholInvArgs& a, int kb, int ib, double (*P)[TLD], do
   for (int lb = ib; lb < kb; ++lb) {
     const int64_t l0 = (int64_t)lb * TB;
     __syncthreads();
-    load_tile(P, a.X64, a.ldx64, i0, l0, a.N);
-    load_tile(Q, a.G, a.ld, l0, b0, a.N);
+    load_tile(P, as_global<double>(a.X64), a.ldx64, i0, l0, a.N);
+    load_tile(Q, as_global<double>(a.G), a.ld, l0, b0, a.N);
     __syncthreads();
     tile_mac<false>(acc, P, Q);
   }
@@ -335,7 +335,7 @@ RF_DEV void task_xcol(const CholInvArgs& a, int kb, int ib, double (*P)[TLD], do
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) P[tile_row(i, q)][tile_col(j)] = acc[i][j][q];
-  load_tile(Q, a.X64, a.ldx64, b0, b0, a.N);
+  load_tile(Q, as_global<double>(a.X64), a.ldx64, b0, b0, a.N);
   __syncthreads();
   f64x4 o[2][2];
   acc_zero(o);
@@ -356,8 +356,8 @@ RF_DEV void task_xcol(const CholInvArgs& a, int kb, int ib, double (*P)[TLD], do
 // tile (i, kb); the mirrored lower tile is cleared.
 RF_DEV void task_xfin(const CholInvArgs& a, int kb, int ib, double (*P)[TLD], double (*Q)[TLD]) {
   const int64_t b0 = (int64_t)kb * TB, i0 = (int64_t)ib * TB;
-  load_tile(P, a.X64, a.ldx64, i0, b0, a.N);
-  load_tile(Q, a.X64, a.ldx64, b0, b0, a.N);
+  load_tile(P, as_global<double>(a.X64), a.ldx64, i0, b0, a.N);
+  load_tile(Q, as_global<double>(a.X64), a.ldx64, b0, b0, a.N);
   __syncthreads();
   f64x4 o[2][2];
   acc_zero(o);
@@ -378,8 +378,8 @@ RF_DEV void task_xfin(const CholInvArgs& a, int kb, int ib, double (*P)[TLD], do
 // first term (kb == i) writes it.
 RF_DEV void task_tupd(const CholInvArgs& a, int kb, int ib, int jb, double (*P)[TLD], double (*Q)[TLD]) {
   const int64_t k0 = (int64_t)kb * TB, i0 = (int64_t)ib * TB, c0 = (int64_t)jb * TB;
-  load_tile(P, a.X64, a.ldx64, i0, k0, a.N);
-  load_tile(Q, a.G, a.ld, k0, c0, a.N);
+  load_tile(P, as_global<double>(a.X64), a.ldx64, i0, k0, a.N);
+  load_tile(Q, as_global<double>(a.G), a.ld, k0, c0, a.N);
   __syncthreads();
   f64x4 acc[2][2];
   acc_zero(acc);
@@ -392,7 +392,7 @@ RF_DEV void task_tupd(const CholInvArgs& a, int kb, int ib, int jb, double (*P)[
       for (int q = 0; q < 4; ++q) {
         const int64_t r = i0 + tile_row(i, q), c = c0 + tile_col(j);
         if (r < a.N && c < a.N) {
-          double* t = a.X64 + r * a.ldx64 + c;
+          const gptr<double> t = as_global_w<double>(a.X64) + r * a.ldx64 + c;
           *t = (ib == kb) ? acc[i][j][q] : *t + acc[i][j][q];
         }
       }
@@ -401,8 +401,8 @@ RF_DEV void task_tupd(const CholInvArgs& a, int kb, int ib, int jb, double (*P)[
 // C(kb, i, j): G_ij -= R_kb,i^T R_kb,j (upper tiles).
 RF_DEV void task_update(const CholInvArgs& a, int kb, int ib, int jb, double (*P)[TLD], double (*Q)[TLD]) {
   const int64_t b0 = (int64_t)kb * TB, r0 = (int64_t)ib * TB, c0 = (int64_t)jb * TB;
-  load_tile(P, a.G, a.ld, b0, r0, a.N);
-  load_tile(Q, a.G, a.ld, b0, c0, a.N);
+  load_tile(P, as_global<double>(a.G), a.ld, b0, r0, a.N);
+  load_tile(Q, as_global<double>(a.G), a.ld, b0, c0, a.N);
   __syncthreads();
   f64x4 acc[2][2];
   acc_zero(acc);
@@ -414,7 +414,7 @@ RF_DEV void task_update(const CholInvArgs& a, int kb, int ib, int jb, double (*P
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int64_t r = r0 + tile_row(i, q), c = c0 + tile_col(j);
-        if (r < a.N && c < a.N && c >= r) a.G[r * a.ld + c] -= acc[i][j][q];
+        if (r < a.N && c < a.N && c >= r) as_global_w<double>(a.G)[r * a.ld + c] -= acc[i][j][q];
       }
 }
 

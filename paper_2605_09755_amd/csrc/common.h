@@ -13,6 +13,28 @@ typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 namespace rf {
 
+// Global-memory pointers.  Kernels that take their arguments from a device array
+// (the grouped and batched ones) would otherwise access memory through flat
+// instructions, whose waits also cover LDS operations; bodies take these types and
+// callers cast the pointers they hold.
+// (the host pass, which never runs these bodies, sees plain pointers)
+#if defined(__HIP_DEVICE_COMPILE__)
+template <class T>
+using gptr = T __attribute__((address_space(1)))*;
+#else
+template <class T>
+using gptr = T*;
+#endif
+template <class T>
+RF_DEV gptr<const T> as_global(const void* p) {
+  return (gptr<const T>)p;
+}
+template <class T>
+RF_DEV gptr<T> as_global_w(void* p) {
+  return (gptr<T>)p;
+}
+
+
 // ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ---------------------
 struct u32x4 { uint32_t x, y, z, w; };
 

@@ -23,26 +23,6 @@ namespace rf {
 
 constexpr int GBM = 128, GBN = 128;
 
-// Operands are read through global-memory pointers: the grouped kernels take their
-// arguments from a device array, and pointers loaded from memory otherwise compile
-// to flat accesses, whose waits also cover the LDS traffic of the k-step.
-// (the host pass, which never runs these bodies, sees plain pointers)
-#if defined(__HIP_DEVICE_COMPILE__)
-template <class T>
-using gptr = T __attribute__((address_space(1)))*;
-#else
-template <class T>
-using gptr = T*;
-#endif
-template <class T>
-RF_DEV gptr<const T> as_global(const void* p) {
-  return (gptr<const T>)p;
-}
-template <class T>
-RF_DEV gptr<T> as_global_w(void* p) {
-  return (gptr<T>)p;
-}
-
 RF_DEV void tile_coords(int id, int ntm, int ntn, int& tm, int& tn) {
   // XCD-aware order: consecutive workgroup ids go to different XCDs (id % 8);
   // give each XCD whole M-panels and walk their N tiles back to back so the

@@ -31,21 +31,21 @@ template <typename T, int GKS>
 struct GramStage {
   static constexpr int EPT = GKS * GT / 256;
   T v[EPT];
-  RF_DEV void load(const T* __restrict__ P, int64_t ld, int64_t k0, int64_t kend, int64_t c0, int64_t cmax) {
+  RF_DEV void load(gptr<const T> P, int64_t ld, int64_t k0, int64_t kend, int64_t c0, int64_t cmax) {
     const int r = threadIdx.x / (GT / EPT), c = (threadIdx.x % (GT / EPT)) * EPT;
     const int64_t k = k0 + r, i = c0 + c;
-    const T* src = P + k * ld + i;
+    const gptr<const T> src = P + k * ld + i;
     if (k < kend && i + EPT <= cmax && (((uintptr_t)src) & 15) == 0) {
       if constexpr (sizeof(T) == 4) {
 #pragma unroll
         for (int e = 0; e < EPT; e += 4) {
-          const float4 x = *reinterpret_cast<const float4*>(src + e);
+          const float4 x = *reinterpret_cast<gptr<const float4>>(src + e);
           v[e] = x.x; v[e + 1] = x.y; v[e + 2] = x.z; v[e + 3] = x.w;
         }
       } else {
 #pragma unroll
         for (int e = 0; e < EPT; e += 2) {
-          const double2 x = *reinterpret_cast<const double2*>(src + e);
+          const double2 x = *reinterpret_cast<gptr<const double2>>(src + e);
           v[e] = x.x; v[e + 1] = x.y;
         }
       }
@@ -66,9 +66,9 @@ struct GramStage {
 // panels are staged in LDS in their own type, double-buffered with a register
 // prefetch of the next k-step, one barrier per step.
 template <typename TX, typename TY>
-RF_DEV void gram_body(const TX* __restrict__ X, int64_t ldx, const TY* __restrict__ Y, int64_t ldy, int64_t K,
-                      int64_t M, int64_t N, int sym, double* __restrict__ C, int64_t ldc,
-                      double* __restrict__ partial, int64_t kps, int bid, int split) {
+RF_DEV void gram_body(gptr<const TX> X, int64_t ldx, gptr<const TY> Y, int64_t ldy, int64_t K,
+                      int64_t M, int64_t N, int sym, gptr<double> C, int64_t ldc,
+                      gptr<double> partial, int64_t kps, int bid, int split) {
   constexpr int GKS = (sizeof(TX) == 4 && sizeof(TY) == 4) ? 32 : 16;  // k rows per step: 32 KB of LDS
   __shared__ TX Xs[2][GKS][GT];
   __shared__ TY Ys[2][GKS][GT];
@@ -147,7 +147,8 @@ __global__ __launch_bounds__(256) void k_gram(const TX* __restrict__ X, int64_t 
                                               double* __restrict__ C, int64_t ldc, double* __restrict__ partial,
                                               int64_t kps, const int* run_if) {
   if (run_if && *run_if == 0) return;
-  gram_body<TX, TY>(X, ldx, Y, ldy, K, M, N, sym, C, ldc, partial, kps, blockIdx.x, blockIdx.y);
+  gram_body<TX, TY>(as_global<TX>(X), ldx, as_global<TY>(Y), ldy, K, M, N, sym, as_global_w<double>(C), ldc,
+                    as_global_w<double>(partial), kps, blockIdx.x, blockIdx.y);
 }
 
 // Grouped symmetric Grams C_i = X_i^T X_i (FP32 X_i, K_i x M_i): group i owns the
@@ -166,10 +167,12 @@ __global__ __launch_bounds__(256) void k_gram_grouped(const GramArgs* __restrict
   const int local = (int)blockIdx.x - tile_start[lo];
   if (g.splits > 1) {
     const int tiles = gram_group_tiles(g.M);
-    gram_body<float, float>(g.X, g.ldx, g.X, g.ldx, g.K, g.M, g.M, 1, g.C, g.ldc, g.partial, g.kps, local % tiles,
+    gram_body<float, float>(as_global<float>(g.X), g.ldx, as_global<float>(g.X), g.ldx, g.K, g.M, g.M, 1,
+                            as_global_w<double>(g.C), g.ldc, as_global_w<double>(g.partial), g.kps, local % tiles,
                             local / tiles);
   } else {
-    gram_body<float, float>(g.X, g.ldx, g.X, g.ldx, g.K, g.M, g.M, 1, g.C, g.ldc, nullptr, g.K + GK, local, 0);
+    gram_body<float, float>(as_global<float>(g.X), g.ldx, as_global<float>(g.X), g.ldx, g.K, g.M, g.M, 1,
+                            as_global_w<double>(g.C), g.ldc, nullptr, g.K + GK, local, 0);
   }
 }
 
@@ -670,13 +673,13 @@ struct Mfma64 {
   RF_DEV int krow(int kk) const { return 4 * kk + (lane >> 4); }
   // register operands of a row-major 64 x 64 matrix in global memory:
   // B operand (X as B: X[k][col]) or A operand of X^T (X^T[row][k] = X[k][row])
-  RF_DEV void load_b(const double* __restrict__ X, double (&r)[16][2]) const {
+  RF_DEV void load_b(gptr<const double> X, double (&r)[16][2]) const {
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk)
 #pragma unroll
       for (int j = 0; j < 2; ++j) r[kk][j] = X[krow(kk) * 64 + bcol(j)];
   }
-  RF_DEV void load_at(const double* __restrict__ X, double (&r)[16][2]) const {
+  RF_DEV void load_at(gptr<const double> X, double (&r)[16][2]) const {
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk)
 #pragma unroll
@@ -972,8 +975,8 @@ RF_DEV void eig_gtile_body(const EigWork& w, int round, int slot, int id, const 
   auto iy = [&](int a) -> int64_t { return a < JB ? (int64_t)Py * JB + a : (int64_t)Qy * JB + (a - JB); };
   const Mfma16 mm;
   double opa[16], opb[16];
-  if (!idy_) mm.load_b(Vr + (int64_t)y * JS * JS, opb);
-  if (!idx_) mm.load_at(Vr + (int64_t)x * JS * JS, opa);
+  if (!idy_) mm.load_b(as_global<double>(Vr) + (int64_t)y * JS * JS, opb);
+  if (!idx_) mm.load_at(as_global<double>(Vr) + (int64_t)x * JS * JS, opa);
   for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
     const int a = e >> 5, b = (e & 31) * 2;
     const double2 g = *reinterpret_cast<const double2*>(Gs + ix(a) * w.K + iy(b));
@@ -1027,10 +1030,10 @@ RF_DEV void eig_zstrip_body(const EigWork& w, int round, int slot, int zid, int 
   auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
   const int64_t r0 = (int64_t)rb * JS;  // K is a multiple of JS: the strip is whole
   if (active) {
-    mm.load_b(w.V + ((int64_t)slot * w.p + x) * JS * JS, opb);
+    mm.load_b(as_global<double>(w.V) + ((int64_t)slot * w.p + x) * JS * JS, opb);
     for (int e = tid; e < JS * JS / 2; e += 256) {
       const int a = e >> 5, b = (e & 31) * 2;
-      const double2 z = *reinterpret_cast<const double2*>(w.Z + (r0 + a) * w.K + ix(b));
+      const double2 z = *reinterpret_cast<gptr<const double2>>(as_global<double>(w.Z) + (r0 + a) * w.K + ix(b));
       T[a][b] = z.x;
       T[a][b + 1] = z.y;
     }
@@ -1043,7 +1046,7 @@ RF_DEV void eig_zstrip_body(const EigWork& w, int round, int slot, int zid, int 
   if (active)
     for (int e = tid; e < JS * JS / 2; e += 256) {
       const int a = e >> 5, b = (e & 31) * 2;
-      *reinterpret_cast<double2*>(w.Z + (r0 + a) * w.K + ix(b)) = double2{T[a][b], T[a][b + 1]};
+      *reinterpret_cast<gptr<double2>>(as_global_w<double>(w.Z) + (r0 + a) * w.K + ix(b)) = double2{T[a][b], T[a][b + 1]};
     }
 }
 
@@ -1074,11 +1077,11 @@ RF_DEV void eig_apply_body(const EigWork& w, int round, int id, int slot) {
     const int Py = circle(round, y, np), Qy = circle(round, np - 1 - y, np);
     auto ix = [&](int a) -> int64_t { return a < JB ? (int64_t)Px * JB + a : (int64_t)Qx * JB + (a - JB); };
     auto iy = [&](int a) -> int64_t { return a < JB ? (int64_t)Py * JB + a : (int64_t)Qy * JB + (a - JB); };
-    if (!idy_) mm.load_b(Vr + (int64_t)y * JS * JS, opb);
-    if (!idx_) mm.load_at(Vr + (int64_t)x * JS * JS, opa);
+    if (!idy_) mm.load_b(as_global<double>(Vr) + (int64_t)y * JS * JS, opb);
+    if (!idx_) mm.load_at(as_global<double>(Vr) + (int64_t)x * JS * JS, opa);
     for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
       const int a = e >> 5, b = (e & 31) * 2;
-      const double2 g = *reinterpret_cast<const double2*>(w.Gp + ix(a) * w.K + iy(b));
+      const double2 g = *reinterpret_cast<gptr<const double2>>(as_global<double>(w.Gp) + ix(a) * w.K + iy(b));
       T[a][b] = g.x;
       T[a][b + 1] = g.y;
     }
@@ -1101,12 +1104,12 @@ RF_DEV void eig_apply_body(const EigWork& w, int round, int id, int slot) {
       // a diagonal tile is symmetrised from its upper half
       g.x = (x == y && a > b) ? T[b][a] : T[a][b];
       g.y = (x == y && a > b + 1) ? T[b + 1][a] : T[a][b + 1];
-      *reinterpret_cast<double2*>(w.Gp + ix(a) * w.K + iy(b)) = g;
+      *reinterpret_cast<gptr<double2>>(as_global_w<double>(w.Gp) + ix(a) * w.K + iy(b)) = g;
     }
     if (x != y) {
       for (int e = threadIdx.x; e < JS * JS / 2; e += blockDim.x) {
         const int b = e >> 5, a = (e & 31) * 2;
-        *reinterpret_cast<double2*>(w.Gp + iy(b) * w.K + ix(a)) = double2{T[a][b], T[a + 1][b]};
+        *reinterpret_cast<gptr<double2>>(as_global_w<double>(w.Gp) + iy(b) * w.K + ix(a)) = double2{T[a][b], T[a + 1][b]};
       }
     }
   } else {
