@@ -51,7 +51,10 @@ RF_DEV void store_out(const GemmArgs& g, int64_t i, int64_t j, float v) {
 }
 
 // ---------------- FP32 operands -------------------------------------------------------
-template <bool AKC, bool BKC>
+// VEC: the launcher has checked that both operands take the 16-byte form (the
+// element form is then not compiled in: two forms merging into the same registers
+// made the compiler wait for each 16-byte load before the next chunk's).
+template <bool AKC, bool BKC, bool VEC = false>
 RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
   constexpr int BK = 16;          // 32 (two workgroups per CU instead of three) measured slower
   constexpr int NPS = BK / 8;     // load passes per operand and step
@@ -92,8 +95,8 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
   // per-chunk mix of the two forms made the compiler wait for every outstanding
   // load before each 16-byte one (both write the same registers).
   const int64_t akx = AKC ? g.K : g.M, bkx = BKC ? g.K : g.N;  // contiguous extents
-  const bool avec = ((((uintptr_t)A) & 15) == 0) && (g.lda % 4 == 0) && (akx % 4 == 0) && (g.kps % 4 == 0);
-  const bool bvec = ((((uintptr_t)B) & 15) == 0) && (g.ldb % 4 == 0) && (bkx % 4 == 0) && (g.kps % 4 == 0);
+  const bool avec = VEC || (((((uintptr_t)A) & 15) == 0) && (g.lda % 4 == 0) && (akx % 4 == 0) && (g.kps % 4 == 0));
+  const bool bvec = VEC || (((((uintptr_t)B) & 15) == 0) && (g.ldb % 4 == 0) && (bkx % 4 == 0) && (g.kps % 4 == 0));
   // four consecutive elements of P along the contiguous index (x0 .. x0+3 < xmax)
   // of line y (< ymax: the other index), into d
   auto load4 = [&](gptr<const float> P, int64_t ld, int64_t y, int64_t ymax, int64_t x0, int64_t xmax, bool vec,
@@ -724,9 +727,15 @@ RF_DEV void gemm_bf16_big_body(const GemmArgs& g, int bid, int split) {
   big_epilogue(g, acc, i0, j0, split, wm, wn, lane, tid, smem);
 }
 
-template <bool AKC, bool BKC>
+template <bool AKC, bool BKC, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
-  gemm_f32_body<AKC, BKC>(g, blockIdx.x, blockIdx.y);
+  gemm_f32_body<AKC, BKC, VEC>(g, blockIdx.x, blockIdx.y);
+}
+// the operand test of gemm_f32_body, on the host
+static bool f32_vec_ok(const GemmArgs& g) {
+  const int64_t akx = g.a_kc ? g.K : g.M, bkx = g.b_kc ? g.K : g.N;
+  return ((uintptr_t)g.A % 16 == 0) && (g.lda % 4 == 0) && (akx % 4 == 0) && ((uintptr_t)g.B % 16 == 0) &&
+         (g.ldb % 4 == 0) && (bkx % 4 == 0) && (g.kps % 4 == 0);
 }
 template <bool AKC, bool BKC>
 __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
@@ -1103,10 +1112,17 @@ hipError_t launch_gemm(GemmArgs g, int dtype, float* partial, hipStream_t st) {
   dim3 grid((unsigned)tiles, (unsigned)splits);
   auto go = [&](auto kern) { hipLaunchKernelGGL(kern, grid, dim3(256), 0, st, g); };
   if (dtype == 0) {
-    if (g.a_kc && g.b_kc) go(k_gemm_f32<true, true>);
-    else if (g.a_kc && !g.b_kc) go(k_gemm_f32<true, false>);
-    else if (!g.a_kc && g.b_kc) go(k_gemm_f32<false, true>);
-    else go(k_gemm_f32<false, false>);
+    if (f32_vec_ok(g)) {
+      if (g.a_kc && g.b_kc) go(k_gemm_f32<true, true, true>);
+      else if (g.a_kc && !g.b_kc) go(k_gemm_f32<true, false, true>);
+      else if (!g.a_kc && g.b_kc) go(k_gemm_f32<false, true, true>);
+      else go(k_gemm_f32<false, false, true>);
+    } else {
+      if (g.a_kc && g.b_kc) go(k_gemm_f32<true, true, false>);
+      else if (g.a_kc && !g.b_kc) go(k_gemm_f32<true, false, false>);
+      else if (!g.a_kc && g.b_kc) go(k_gemm_f32<false, true, false>);
+      else go(k_gemm_f32<false, false, false>);
+    }
   } else if (dtype == 2 && big) {
     if (g.a_kc && g.b_kc) go_big<true, true, 0>(g, grid, st);
     else if (g.a_kc && !g.b_kc) go_big<true, false, 0>(g, grid, st);
