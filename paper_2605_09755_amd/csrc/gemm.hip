@@ -23,6 +23,11 @@ namespace rf {
 
 constexpr int GBM = 128, GBN = 128;
 
+// x where keep holds, else +0: a bit mask rather than a select, so the compiler
+// keeps the load unconditional (a select of a loaded value can become a branch
+// around the load, with a wait right after it)
+RF_DEV float keep_or_zero(float x, bool keep) { return __uint_as_float(__float_as_uint(x) & (keep ? ~0u : 0u)); }
+
 RF_DEV void tile_coords(int id, int ntm, int ntn, int& tm, int& tn) {
   // XCD-aware order: consecutive workgroup ids go to different XCDs (id % 8);
   // give each XCD whole M-panels and walk their N tiles back to back so the
@@ -51,10 +56,11 @@ RF_DEV void store_out(const GemmArgs& g, int64_t i, int64_t j, float v) {
 }
 
 // ---------------- FP32 operands -------------------------------------------------------
-// VEC: the launcher has checked that both operands take the 16-byte form (the
-// element form is then not compiled in: two forms merging into the same registers
-// made the compiler wait for each 16-byte load before the next chunk's).
-template <bool AKC, bool BKC, bool VEC = false>
+// VEC: the launcher has checked that both operands take the 16-byte form (true) or
+// runs the element form for both (false); each instance compiles one form only:
+// with both forms, the compiler merged them into the same registers and waited for
+// each chunk's loads before issuing the next chunk's.
+template <bool AKC, bool BKC, bool VEC>
 RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
   constexpr int BK = 16;          // 32 (two workgroups per CU instead of three) measured slower
   constexpr int NPS = BK / 8;     // load passes per operand and step
@@ -94,9 +100,7 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
   // element loads, zero past the edge.  The choice is uniform over the launch: a
   // per-chunk mix of the two forms made the compiler wait for every outstanding
   // load before each 16-byte one (both write the same registers).
-  const int64_t akx = AKC ? g.K : g.M, bkx = BKC ? g.K : g.N;  // contiguous extents
-  const bool avec = VEC || (((((uintptr_t)A) & 15) == 0) && (g.lda % 4 == 0) && (akx % 4 == 0) && (g.kps % 4 == 0));
-  const bool bvec = VEC || (((((uintptr_t)B) & 15) == 0) && (g.ldb % 4 == 0) && (bkx % 4 == 0) && (g.kps % 4 == 0));
+  constexpr bool avec = VEC, bvec = VEC;
   // four consecutive elements of P along the contiguous index (x0 .. x0+3 < xmax)
   // of line y (< ymax: the other index), into d
   auto load4 = [&](gptr<const float> P, int64_t ld, int64_t y, int64_t ymax, int64_t x0, int64_t xmax, bool vec,
@@ -109,15 +113,20 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
         d[0] = d[1] = d[2] = d[3] = 0.f;
       }
     } else {
+      // raw loads from clamped addresses; the entries outside the operand are
+      // zeroed by mask4 when the stage is stored, so no load waits before the MFMAs
       const int64_t yc = min(y, ymax - 1);
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float x = P[yc * ld + min(x0 + e, xmax - 1)];
-        d[e] = (y < ymax && x0 + e < xmax) ? x : 0.f;
-      }
+      for (int e = 0; e < 4; ++e) d[e] = P[yc * ld + min(x0 + e, xmax - 1)];
     }
   };
+  auto mask4 = [&](int64_t y, int64_t ymax, int64_t x0, int64_t xmax, float* d) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e) d[e] = keep_or_zero(d[e], y < ymax && x0 + e < xmax);
+  };
+  int64_t kreg = 0;  // first k of the stage held in ra / rb
   auto gload = [&](int64_t k0) {
+    kreg = k0;
 #pragma unroll
     for (int ps = 0; ps < NPS; ++ps) {
       if (AKC) {
@@ -137,6 +146,15 @@ RF_DEV void gemm_f32_body(const GemmArgs& g, int bid, int split) {
     }
   };
   auto sstore = [&](int buf) {
+    if constexpr (!VEC) {
+#pragma unroll
+      for (int ps = 0; ps < NPS; ++ps) {
+        if (AKC) mask4(i0 + tid / TPR + RPP * ps, g.M, kreg + (tid % TPR) * 4, kend, ra[ps]);
+        else mask4(kreg + (tid >> 5) + 8 * ps, kend, i0 + (tid & 31) * 4, g.M, ra[ps]);
+        if (BKC) mask4(j0 + tid / TPR + RPP * ps, g.N, kreg + (tid % TPR) * 4, kend, rb[ps]);
+        else mask4(kreg + (tid >> 5) + 8 * ps, kend, j0 + (tid & 31) * 4, g.N, rb[ps]);
+      }
+    }
 #pragma unroll
     for (int ps = 0; ps < NPS; ++ps) {
       if (AKC) {
@@ -329,7 +347,7 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) t[e] = Af[rc * g.lda + min(k + e, kend - 1)];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) t[e] = (r < rmax && k + e < kend) ? t[e] : 0.f;
+        for (int e = 0; e < 8; ++e) t[e] = keep_or_zero(t[e], r < rmax && k + e < kend);
       }
       dst[ps] = make_uint4(pack2_bf16(t[0], t[1]), pack2_bf16(t[2], t[3]), pack2_bf16(t[4], t[5]),
                            pack2_bf16(t[6], t[7]));
@@ -358,8 +376,8 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
 #pragma unroll
       for (int e = 0; e < 8; ++e) {
         const bool kin = k0 + 8 * wave + e < kend;
-        lo[e] = (kin && r < rmax) ? lo[e] : 0.f;
-        hi[e] = (kin && r + 1 < rmax) ? hi[e] : 0.f;
+        lo[e] = keep_or_zero(lo[e], kin && r < rmax);
+        hi[e] = keep_or_zero(hi[e], kin && r + 1 < rmax);
       }
     }
 #pragma unroll
@@ -731,7 +749,8 @@ template <bool AKC, bool BKC, bool VEC>
 __global__ __launch_bounds__(256) void k_gemm_f32(GemmArgs g) {
   gemm_f32_body<AKC, BKC, VEC>(g, blockIdx.x, blockIdx.y);
 }
-// the operand test of gemm_f32_body, on the host
+// whether both operands allow the 16-byte form: aligned, and every chunk wholly inside
+// the operand or wholly past its edge
 static bool f32_vec_ok(const GemmArgs& g) {
   const int64_t akx = g.a_kc ? g.K : g.M, bkx = g.b_kc ? g.K : g.N;
   return ((uintptr_t)g.A % 16 == 0) && (g.lda % 4 == 0) && (akx % 4 == 0) && ((uintptr_t)g.B % 16 == 0) &&
@@ -957,13 +976,14 @@ RF_DEV int find_group(const int* __restrict__ start, int count, int bid) {
   }
   return lo;
 }
+// (the problems of a group launch take the element form: their shapes are ragged)
 template <bool AKC, bool BKC>
 __global__ __launch_bounds__(256) void k_gemm_f32_grouped(const GemmArgs* __restrict__ gs, const int* tile_start,
                                                           int count) {
   const int i = find_group(tile_start, count, blockIdx.x);
   const GemmArgs g = gs[i];
   if (g.M == 0 || g.N == 0) return;
-  gemm_f32_body<AKC, BKC>(g, blockIdx.x - tile_start[i], 0);
+  gemm_f32_body<AKC, BKC, false>(g, blockIdx.x - tile_start[i], 0);
 }
 template <bool AKC, bool BKC>
 __global__ __launch_bounds__(256) void k_gemm_bf16_grouped(const GemmArgs* __restrict__ gs, const int* tile_start,
