@@ -231,7 +231,10 @@ RF_DEV uint32_t pack_hi(uint32_t a, uint32_t b) { return (a >> 16) | (b & 0xffff
 RF_DEV uint32_t pack2_bf16(float a, float b) { return pk_bf16(a, b); }
 
 // AF32: the A operand is FP32 in memory and rounded to BF16 (RNE) as it is loaded.
-template <bool AKC, bool BKC, bool AF32 = false>
+// DEFER: every operand takes the element form, and the raw loads are masked,
+// rounded and packed only when the stage is stored (the loads stay in flight across
+// the MFMA phase); the grouped launches run it (their problems are ragged).
+template <bool AKC, bool BKC, bool AF32 = false, bool DEFER = false>
 RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
   constexpr int BK = 32;
   constexpr int ST = BK + 8;  // bf16 elements per LDS row (80 B)
@@ -394,7 +397,76 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
                                 : ((((uintptr_t)A) & 3) == 0 && (g.lda & 1) == 0 && (g.M % 2 == 0)));
   const bool bvec = BKC ? ((((uintptr_t)B) & 15) == 0 && (g.ldb & 7) == 0 && kwhole)
                         : ((((uintptr_t)B) & 3) == 0 && (g.ldb & 1) == 0 && (g.N % 2 == 0));
+  // deferred element form: raw 32-bit words (BF16 values or FP32 bits) at the
+  // positions load_kc / load_tc use, from clamped addresses
+  uint32_t raw_a[16], raw_b[16];
+  int64_t kreg = 0;
+  auto raw_kc = [&](auto P, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, uint32_t* raw) {
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+      const int64_t rc = min(r0 + (tid >> 2) + 64 * ps, rmax - 1), k = k0 + (tid & 3) * 8;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const auto v = P[rc * ld + min(k + e, kend - 1)];
+        if constexpr (sizeof(v) == 4) raw[8 * ps + e] = __float_as_uint(v);
+        else raw[8 * ps + e] = v;
+      }
+    }
+  };
+  auto raw_tc = [&](auto P, int64_t ld, int64_t r0, int64_t rmax, int64_t k0, uint32_t* raw) {
+    const int64_t r = r0 + 2 * lane, r0c = min(r, rmax - 1), r1c = min(r + 1, rmax - 1);
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t kc = min(k0 + 8 * wave + e, kend - 1);
+      const auto lo = P[kc * ld + r0c], hi = P[kc * ld + r1c];
+      if constexpr (sizeof(lo) == 4) {
+        raw[e] = __float_as_uint(lo);
+        raw[8 + e] = __float_as_uint(hi);
+      } else {
+        raw[e] = lo;
+        raw[8 + e] = hi;
+      }
+    }
+  };
+  // two entries (FP32 bits if F32) as a packed BF16 pair, each zero unless kept
+  auto pair = [&](uint32_t x, bool kx, uint32_t y, bool ky, bool f32) -> uint32_t {
+    if (f32) return pack2_bf16(keep_or_zero(__uint_as_float(x), kx), keep_or_zero(__uint_as_float(y), ky));
+    return (kx ? x : 0u) | ((ky ? y : 0u) << 16);
+  };
+  auto pack_kc = [&](const uint32_t* raw, int64_t r0, int64_t rmax, bool f32, uint4* dst) {
+#pragma unroll
+    for (int ps = 0; ps < 2; ++ps) {
+      const int64_t r = r0 + (tid >> 2) + 64 * ps, k = kreg + (tid & 3) * 8;
+      const bool rin = r < rmax;
+      uint32_t w[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        w[e] = pair(raw[8 * ps + 2 * e], rin && k + 2 * e < kend, raw[8 * ps + 2 * e + 1], rin && k + 2 * e + 1 < kend, f32);
+      dst[ps] = make_uint4(w[0], w[1], w[2], w[3]);
+    }
+  };
+  auto pack_tc = [&](const uint32_t* raw, int64_t r0, int64_t rmax, bool f32, uint4* dst) {
+    const int64_t r = r0 + 2 * lane;
+    uint32_t w[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const bool kin = kreg + 8 * wave + e < kend;
+      w[e] = pair(raw[e], kin && r < rmax, raw[8 + e], kin && r + 1 < rmax, f32);
+    }
+    dst[0] = make_uint4(pack_lo(w[0], w[1]), pack_lo(w[2], w[3]), pack_lo(w[4], w[5]), pack_lo(w[6], w[7]));
+    dst[1] = make_uint4(pack_hi(w[0], w[1]), pack_hi(w[2], w[3]), pack_hi(w[4], w[5]), pack_hi(w[6], w[7]));
+  };
   auto gload = [&](int64_t k0) {
+    if constexpr (DEFER) {
+      kreg = k0;
+      if constexpr (AF32) {
+        if (AKC) raw_kc(Af, g.lda, i0, g.M, k0, raw_a); else raw_tc(Af, g.lda, i0, g.M, k0, raw_a);
+      } else {
+        if (AKC) raw_kc(A, g.lda, i0, g.M, k0, raw_a); else raw_tc(A, g.lda, i0, g.M, k0, raw_a);
+      }
+      if (BKC) raw_kc(B, g.ldb, j0, g.N, k0, raw_b); else raw_tc(B, g.ldb, j0, g.N, k0, raw_b);
+      return;
+    }
     if constexpr (AF32) {
       if (AKC) load_kc_f32(i0, g.M, k0, sa, avec); else load_tc_f32(i0, g.M, k0, sa, avec);
     } else {
@@ -403,6 +475,10 @@ RF_DEV void gemm_bf16_body(const GemmArgs& g, int bid, int split) {
     if (BKC) load_kc(B, g.ldb, j0, g.N, k0, sb, bvec); else load_tc(B, g.ldb, j0, g.N, k0, sb, bvec);
   };
   auto sstore = [&](int buf) {
+    if constexpr (DEFER) {
+      if (AKC) pack_kc(raw_a, i0, g.M, AF32, sa); else pack_tc(raw_a, i0, g.M, AF32, sa);
+      if (BKC) pack_kc(raw_b, j0, g.N, false, sb); else pack_tc(raw_b, j0, g.N, false, sb);
+    }
     if (AKC) store_kc(As[buf], sa); else store_tc(As[buf], sa);
     if (BKC) store_kc(Bs[buf], sb); else store_tc(Bs[buf], sb);
   };
@@ -991,7 +1067,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16_grouped(const GemmArgs* __res
   const int i = find_group(tile_start, count, blockIdx.x);
   const GemmArgs g = gs[i];
   if (g.M == 0 || g.N == 0) return;
-  gemm_bf16_body<AKC, BKC>(g, blockIdx.x - tile_start[i], 0);
+  gemm_bf16_body<AKC, BKC, false, true>(g, blockIdx.x - tile_start[i], 0);
 }
 template <bool AKC, bool BKC>
 __global__ __launch_bounds__(256) void k_gemm_bf16a32_grouped(const GemmArgs* __restrict__ gs, const int* tile_start,
@@ -999,7 +1075,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16a32_grouped(const GemmArgs* __
   const int i = find_group(tile_start, count, blockIdx.x);
   const GemmArgs g = gs[i];
   if (g.M == 0 || g.N == 0) return;
-  gemm_bf16_body<AKC, BKC, true>(g, blockIdx.x - tile_start[i], 0);
+  gemm_bf16_body<AKC, BKC, true, true>(g, blockIdx.x - tile_start[i], 0);
 }
 template <bool AKC, bool BKC, int AMODE>
 __global__ __launch_bounds__(BT, 1) void k_gemm_bf16_big_grouped(const GemmArgs* __restrict__ gs,
