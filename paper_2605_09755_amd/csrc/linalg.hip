@@ -450,7 +450,7 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, bool full, int x, int sl
   } else {
     for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) {
       int a = e / JS, b = e % JS;
-      M[a][b] = w.Gp[gidx(a) * w.K + gidx(b)];
+      M[a][b] = as_global<double>(w.Gp)[gidx(a) * w.K + gidx(b)];
       V[a][b] = (a == b) ? 1.0 : 0.0;
     }
   }
@@ -656,7 +656,8 @@ RF_DEV void eig_solve_body(const EigWork& w, int round, bool full, int x, int sl
   }
   __syncthreads();
   double* out = Vout + (int64_t)x * JS * JS;
-  for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) out[(e / JS) * JS + rnk[e % JS]] = V[e / JS][e % JS];
+  const gptr<double> outg = as_global_w<double>(out);
+  for (int e = threadIdx.x; e < JS * JS; e += blockDim.x) outg[(e / JS) * JS + rnk[e % JS]] = V[e / JS][e % JS];
 }
 
 // 64 x 64 FP64 products on v_mfma_f64_16x16x4f64, 4 waves, each a 32 x 32
